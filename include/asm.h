@@ -1,0 +1,202 @@
+/*
+ * asm.h - C ABI of the MI355X Schwarz-preconditioned GMRES solver for 3x3
+ * block Jacobians (Jackson, Taroni, Ponting, "A Two-Level Variant of
+ * Additive Schwarz Preconditioning for Use in Reservoir Simulation",
+ * arXiv:1401.7227).
+ *
+ * The linear problem is the one of Section 2: r = b - A x with b = R (the
+ * non-linear residual) and A = -J (J the Jacobian of eq. (1.2)), so the
+ * solution x is the Newton update of eq. (1.1).  Unknowns are grouped per
+ * grid cell into 3-vectors (p, So, Sg) and A is stored with dense 3x3
+ * blocks (Section 1).
+ *
+ * Conventions for every call:
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP
+ *    device); pointers named *_host are host pointers.  The caller owns
+ *    them; the library never frees or retains them past the call.
+ *  - Cell c = (ix*ny + iy)*nz + iz (z fastest); unknown 3c + v.
+ *  - BSR: row_ptr[nb+1], col_idx[nnzb] (strictly increasing per row,
+ *    diagonal block present), vals[9*nnzb] with each 3x3 block row-major.
+ *  - Work is ordered on the given stream; calls that return host results
+ *    synchronise that stream before returning.
+ *  - Errors are returned as asm_status, never thrown; asm_last_error()
+ *    gives a thread-local message for the last failing call.
+ *  - A handle must not be used from two threads at once.  Handles hold
+ *    device memory until destroyed.
+ */
+#ifndef ASM_MI355X_H
+#define ASM_MI355X_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ASM_OK = 0,
+  ASM_NOT_CONVERGED = 1,        /* warning: x holds the last iterate        */
+  ASM_ERR_INVALID = -1,         /* bad argument, shape or BSR structure     */
+  ASM_ERR_OOM = -2,             /* device or host allocation failed         */
+  ASM_ERR_SINGULAR_PIVOT = -3,  /* a 3x3 ILU pivot is singular/non-finite   */
+  ASM_ERR_NONFINITE = -4,       /* NaN/Inf in A, b or x0                    */
+  ASM_ERR_HIP = -5              /* a HIP runtime call failed                */
+} asm_status;
+
+typedef struct asm_system_s *asm_system;   /* device copy of A, own layout */
+typedef struct asm_precond_s *asm_precond; /* partition, maps, factors     */
+
+typedef struct {
+  int32_t nx, ny, nz;
+} asm_grid;
+
+/* Preconditioner kinds and combinations. */
+enum { ASM_KIND_NONE = 0, ASM_KIND_CLASSICAL = 1, ASM_KIND_TWO_LEVEL = 2 };
+enum { ASM_COMBINE_ADDITIVE = 0, ASM_COMBINE_RESTRICTED = 1 };
+enum { ASM_PREC_FP64 = 0, ASM_PREC_FP32 = 1 };
+
+/*
+ * asm_create_system - take a device copy of A (Section 2's A = -J).
+ *   grid       : host; nx*ny*nz must equal nb.
+ *   nb, nnzb   : block rows and stored blocks.
+ *   row_ptr_dev, col_idx_dev, vals_dev : device BSR arrays (see above);
+ *                copied, the caller may free them after return.
+ *   Validates the structure (INVALID) and finiteness (NONFINITE); one
+ *   device-to-host copy of the pattern is made for the host-side setup.
+ *   out        : host; receives the handle.
+ */
+asm_status asm_create_system(const asm_grid *grid, int32_t nb, int64_t nnzb,
+                             const int32_t *row_ptr_dev, const int32_t *col_idx_dev,
+                             const double *vals_dev, hipStream_t stream, asm_system *out);
+
+/* New values on the same pattern (the next Newton iteration, Section 4:
+ * matrices are re-lumped once per non-linear iteration).  vals_dev as in
+ * asm_create_system.  Preconditioners built on the system must then be
+ * refreshed with asm_refactor. */
+asm_status asm_update_values(asm_system sys, const double *vals_dev, hipStream_t stream);
+
+/* y = A x (device vectors of 3*nb doubles). */
+asm_status asm_spmv(asm_system sys, const double *x_dev, double *y_dev, hipStream_t stream);
+
+/*
+ * Preconditioner options.
+ *   kind      NONE (B = I), CLASSICAL (eq. (3.3)-(3.4): A_i = R_i A R_i^T
+ *             with R_i restricting to the overlapping subdomain), or
+ *             TWO_LEVEL (Section 4, eq. (4.1): outside cells are lumped by
+ *             summation into near-field boxes on face-neighbour subdomains
+ *             and far-field boxes elsewhere; Appendix B, eq. (B.3)).
+ *   combine   ADDITIVE (eq. (3.3): overlapping contributions summed) or
+ *             RESTRICTED (eq. (4.2): each cell keeps its owner's value; the
+ *             coarse part of every local solution is discarded).
+ *   sx, sy    subdomains along x and y; each spans all of z.  Balanced
+ *             split: the first (n mod s) parts get one extra column.
+ *   overlap   algebraic overlap: cells within this graph distance of a
+ *             subdomain in A's (symmetrised) block graph.
+ *   near, far coarsening boxes (cells per box along x, y, z), two-level only.
+ *   precision FP64, or FP32: factors of fine rows stored and applied in
+ *             single precision, coarse rows kept in double; the outer GMRES
+ *             stays double.
+ * Local solver: block ILU(0) with 3x3 pivots inverted directly (Section 2;
+ * Section 6 names ILU as the approximate local solve).
+ */
+typedef struct {
+  int32_t kind;
+  int32_t combine;
+  int32_t sx, sy;
+  int32_t overlap;
+  int32_t near_box[3];
+  int32_t far_box[3];
+  int32_t precision;
+} asm_precond_opts;
+
+/* Builds the partition, overlap, coarse maps, extended patterns and level
+ * schedules on the host, then assembles and factorises every A_i on the
+ * device.  A singular pivot returns ASM_ERR_SINGULAR_PIVOT naming the
+ * subdomain and block row.  out: host; receives the handle. */
+asm_status asm_setup_precond(asm_system sys, const asm_precond_opts *opts, hipStream_t stream,
+                             asm_precond *out);
+
+/* Numeric re-assembly and re-factorisation after asm_update_values. */
+asm_status asm_refactor(asm_precond pc, hipStream_t stream);
+
+/* z = B^-1 r (device vectors of 3*nb doubles). */
+asm_status asm_precond_apply(asm_precond pc, const double *r_dev, double *z_dev, hipStream_t stream);
+
+/* Sizes of the preconditioner (host struct). */
+typedef struct {
+  int32_t nsub;
+  int64_t ext_rows;      /* sum over subdomains of rows of A_i           */
+  int64_t coarse_rows;   /* of which lumped (coarse) rows                */
+  int64_t factor_blocks; /* stored 3x3 blocks of all factors             */
+  int64_t fine_row_blocks; /* of which in fine rows (single precision   */
+                           /* when precision is FP32)                    */
+  int32_t max_levels;    /* longest forward or backward level schedule   */
+  int64_t device_bytes;  /* device memory held by the preconditioner     */
+} asm_precond_stats;
+asm_status asm_precond_get_stats(asm_precond pc, asm_precond_stats *stats_host);
+
+/* Copies subdomain s's local matrix and factors to host buffers, in the
+ * local ordering (fine cells ascending, then near boxes, then far boxes):
+ *   rp_host[n+1], ci_host[nnz], a_host[9*nnz] (assembled A_i),
+ *   f_host[9*nnz] (ILU(0): L below the diagonal, U above, D^-1 on it),
+ *   label_host[nb] (row of A_i each cell maps to, -1 if none).
+ * Any pointer may be NULL.  Query n and nnz first with all buffers NULL. */
+asm_status asm_precond_export_sub(asm_precond pc, int32_t s, int32_t *n, int32_t *nnz,
+                                  int32_t *rp_host, int32_t *ci_host, double *a_host,
+                                  double *f_host, int32_t *label_host);
+
+/* Restarted right-preconditioned GMRES(restart) (Section 2 names GMRES as
+ * the accelerator).  One iteration is one Arnoldi step.  Stops when the
+ * true residual satisfies ||b - A x|| <= rtol ||b||, or at max_iters
+ * (ASM_NOT_CONVERGED, x holds the last iterate).  fixed_iters > 0 runs
+ * exactly that many steps without convergence tests. */
+typedef struct {
+  int32_t restart;     /* default 30, at most 32 */
+  double rtol;         /* default 1e-6 */
+  int32_t max_iters;   /* default 10000 */
+  int32_t fixed_iters; /* 0 = off */
+} asm_solve_opts;
+
+typedef struct {
+  int32_t iters, cycles;
+  double rel_res_true, rel_res_est;
+} asm_solve_info;
+
+/* b_dev: device, 3*nb doubles.  x_dev: device, in: x0, out: solution.
+ * opts, info: host.  Synchronises the stream before returning. */
+asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
+                     const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
+
+/* Kernel-phase timing of asm_solve (HIP events on the solve stream).
+ * When enabled on a system, every launch of the phases below inside
+ * asm_solve is bracketed by events; asm_profile_read returns the launch
+ * counts and accumulated device milliseconds since the last reset. */
+enum {
+  ASM_PHASE_ILU_APPLY = 0,  /* subdomain gather + forward/backward sweeps     */
+  ASM_PHASE_LUMP = 1,       /* lumped (coarse) right-hand sides               */
+  ASM_PHASE_COMBINE = 2,    /* additive combination                           */
+  ASM_PHASE_SPMV = 3,       /* w = A z                                        */
+  ASM_PHASE_DOTS = 4,       /* Gram-Schmidt projections V^T w and ||w||       */
+  ASM_PHASE_UPDATE = 5,     /* w - V h and its norm                           */
+  ASM_PHASE_RESIDUAL = 6,   /* b - A x and its norm                           */
+  ASM_PHASE_OTHER = 7,      /* reductions, solution update                    */
+  ASM_NPHASE = 8
+};
+typedef struct {
+  int64_t launches[ASM_NPHASE];
+  double ms[ASM_NPHASE];
+} asm_profile;
+asm_status asm_profile_enable(asm_system sys, int32_t enable);
+asm_status asm_profile_read(asm_system sys, asm_profile *out_host, int32_t reset);
+
+void asm_destroy_precond(asm_precond pc);
+void asm_destroy_system(asm_system sys);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *asm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASM_MI355X_H */

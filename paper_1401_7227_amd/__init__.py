@@ -1,0 +1,15 @@
+"""MI355X-native Schwarz-preconditioned GMRES for 3x3-block reservoir Jacobians.
+
+Jackson, Taroni, Ponting, "A Two-Level Variant of Additive Schwarz
+Preconditioning for Use in Reservoir Simulation" (arXiv:1401.7227): the
+linear problem r = b - A x with A = -J (Section 2), classical additive
+Schwarz (eq. (3.3)-(3.4)) and the two-level coarsened-overlap variant
+(Section 4), block ILU(0) local solves, restarted GMRES.
+
+The compute path is the C-ABI library ``libasm_mi355x.so`` (HIP for gfx950,
+declared in ``include/asm.h``); this package only marshals arguments.
+"""
+from ._binding import (  # noqa: F401
+    ADDITIVE, ERR_HIP, ERR_INVALID, ERR_NONFINITE, ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FP32,
+    FP64, KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, NOT_CONVERGED, OK, RESTRICTED,
+    PHASES, AsmError, Info, Precond, System, load, solve)

@@ -1,0 +1,281 @@
+"""ctypes binding of libasm_mi355x.so (argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; torch is used only
+for device memory and the current HIP stream.  The library must be built
+(``paper_1401_7227_amd.build.build()``); importing fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasm_mi355x.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID, ERR_OOM, ERR_SINGULAR_PIVOT, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4, -5
+KIND_NONE, KIND_CLASSICAL, KIND_TWO_LEVEL = 0, 1, 2
+ADDITIVE, RESTRICTED = 0, 1
+FP64, FP32 = 0, 1
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
+                -3: "ERR_SINGULAR_PIVOT", -4: "ERR_NONFINITE", -5: "ERR_HIP"}
+
+EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_precond",
+            "asm_refactor", "asm_precond_apply", "asm_precond_get_stats",
+            "asm_precond_export_sub", "asm_solve", "asm_destroy_precond",
+            "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read"]
+
+PHASES = ["ilu_apply", "lump", "combine", "spmv", "dots", "update", "residual", "other"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("combine", C.c_int32), ("sx", C.c_int32),
+                ("sy", C.c_int32), ("overlap", C.c_int32), ("near_box", C.c_int32 * 3),
+                ("far_box", C.c_int32 * 3), ("precision", C.c_int32)]
+
+
+class PrecondStats(C.Structure):
+    _fields_ = [("nsub", C.c_int32), ("ext_rows", C.c_int64), ("coarse_rows", C.c_int64),
+                ("factor_blocks", C.c_int64), ("fine_row_blocks", C.c_int64),
+                ("max_levels", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("rtol", C.c_double), ("max_iters", C.c_int32),
+                ("fixed_iters", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("rel_res_true", C.c_double),
+                ("rel_res_est", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads the built library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1401_7227_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    V = C.c_void_p
+    L.asm_last_error.restype = C.c_char_p
+    L.asm_create_system.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int64, V, V, V, V,
+                                    C.POINTER(V)]
+    L.asm_update_values.argtypes = [V, V, V]
+    L.asm_spmv.argtypes = [V, V, V, V]
+    L.asm_setup_precond.argtypes = [V, C.POINTER(PrecondOpts), V, C.POINTER(V)]
+    L.asm_refactor.argtypes = [V, V]
+    L.asm_precond_apply.argtypes = [V, V, V, V]
+    L.asm_precond_get_stats.argtypes = [V, C.POINTER(PrecondStats)]
+    L.asm_precond_export_sub.argtypes = [V, C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), V, V, V, V, V]
+    L.asm_solve.argtypes = [V, V, V, V, C.POINTER(SolveOpts), V, C.POINTER(SolveInfo)]
+    L.asm_profile_enable.argtypes = [V, C.c_int32]
+    L.asm_profile_read.argtypes = [V, C.POINTER(Profile), C.c_int32]
+    L.asm_destroy_precond.argtypes = [V]
+    L.asm_destroy_system.argtypes = [V]
+    for name in EXPORTED:
+        if name != "asm_last_error":
+            getattr(L, name).restype = C.c_int
+    L.asm_destroy_precond.restype = None
+    L.asm_destroy_system.restype = None
+    _lib = L
+    return L
+
+
+class AsmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st: int) -> int:
+    if st < 0:
+        raise AsmError(st, load().asm_last_error().decode())
+    return st
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype) -> torch.Tensor:
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class System:
+    """Device copy of A (= -J) in the library's own layout."""
+
+    def __init__(self, nx, ny, nz, row_ptr, col_idx, vals):
+        L = load()
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        rp = _dev(row_ptr, torch.int32)
+        ci = _dev(col_idx, torch.int32)
+        v = _dev(vals, torch.float64).reshape(-1)
+        self.nnzb = int(ci.numel())
+        h = C.c_void_p()
+        g = Grid(nx, ny, nz)
+        _check(L.asm_create_system(C.byref(g), int(rp.numel()) - 1, self.nnzb, _ptr(rp),
+                                   _ptr(ci), _ptr(v), _stream(), C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def from_generated(s) -> "System":
+        return System(s.nx, s.ny, s.nz, s.row_ptr, s.col_idx, s.vals)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update_values(self, vals):
+        v = _dev(vals, torch.float64).reshape(-1)
+        _check(load().asm_update_values(self._h, _ptr(v), _stream()))
+
+    def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        x = _dev(x, torch.float64)
+        y = torch.empty_like(x) if out is None else out
+        _check(load().asm_spmv(self._h, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def profile(self, enable: bool = True):
+        """Turns HIP-event timing of solve phases on or off."""
+        _check(load().asm_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{phase: (launches, device ms)} accumulated since the last reset."""
+        p = Profile()
+        _check(load().asm_profile_read(self._h, C.byref(p), 1 if reset else 0))
+        return {name: (int(p.launches[k]), float(p.ms[k])) for k, name in enumerate(PHASES)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().asm_destroy_system(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Export:
+    n: int
+    rp: np.ndarray
+    ci: np.ndarray
+    a: np.ndarray
+    f: np.ndarray
+    label: np.ndarray
+
+
+class Precond:
+    """Schwarz preconditioner B (classical or two-level) on a System."""
+
+    def __init__(self, system: System, kind=KIND_CLASSICAL, combine=RESTRICTED, sx=1, sy=1,
+                 overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64):
+        L = load()
+        self.system = system
+        o = PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near),
+                        (C.c_int32 * 3)(*far), precision)
+        h = C.c_void_p()
+        _check(L.asm_setup_precond(system.handle, C.byref(o), _stream(), C.byref(h)))
+        self._h = h
+        self.kind = kind
+
+    @property
+    def handle(self):
+        return self._h
+
+    def refactor(self):
+        _check(load().asm_refactor(self._h, _stream()))
+
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        r = _dev(r, torch.float64)
+        z = torch.empty_like(r) if out is None else out
+        _check(load().asm_precond_apply(self._h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def stats(self) -> dict:
+        st = PrecondStats()
+        _check(load().asm_precond_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in PrecondStats._fields_}
+
+    def export_sub(self, s: int) -> Export:
+        L = load()
+        n, nnz = C.c_int32(), C.c_int32()
+        _check(L.asm_precond_export_sub(self._h, s, C.byref(n), C.byref(nnz), None, None, None,
+                                        None, None))
+        rp = np.empty(n.value + 1, np.int32)
+        ci = np.empty(max(nnz.value, 1), np.int32)
+        a = np.empty((max(nnz.value, 1), 3, 3))
+        f = np.empty((max(nnz.value, 1), 3, 3))
+        lab = np.empty(self.system.N, np.int32)
+        p = lambda arr: arr.ctypes.data_as(C.c_void_p)  # noqa: E731
+        _check(L.asm_precond_export_sub(self._h, s, C.byref(n), C.byref(nnz), p(rp), p(ci), p(a),
+                                        p(f), p(lab)))
+        k = nnz.value
+        return Export(n.value, rp, ci[:k], a[:k], f[:k], lab)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().asm_destroy_precond(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    cycles: int
+    rel_res_true: float
+    rel_res_est: float
+
+
+def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6,
+          max_iters=10000, fixed_iters=0, out: torch.Tensor | None = None):
+    """Solves A x = b; returns (x, Info).  b, x0: device tensors or arrays."""
+    b = _dev(b, torch.float64)
+    if out is not None:
+        x = out
+        if x0 is not None:
+            x.copy_(_dev(x0, torch.float64))
+    else:
+        x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64).clone()
+    o = SolveOpts(restart, rtol, max_iters, fixed_iters)
+    info = SolveInfo()
+    st = _check(load().asm_solve(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o),
+                                 _stream(), C.byref(info)))
+    return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)

@@ -1,0 +1,73 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace asmx {
+
+// Sliced ELL layout of A: slices of 64 block rows (one wavefront); slice s
+// holds groups sptr[s]..sptr[s+1]-1, group g holds one block per row of the
+// slice: cols[g*64 + lane], block entry e at vals[(g*9 + e)*64 + lane].
+struct SellDev {
+  int32_t N = 0, nslices = 0, ngroups = 0;
+  int32_t *sptr = nullptr;   // [nslices+1]
+  int32_t *cols = nullptr;   // [ngroups*64]
+  int32_t *src = nullptr;    // [ngroups*64] CSR entry feeding each slot, -1 pad
+  double *vals = nullptr;    // [ngroups*9*64]
+};
+
+constexpr int kReduceBlocks = 1024;  // partial-sum blocks of the Krylov kernels
+constexpr int kMaxRestart = 32;
+
+hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_t s);
+hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s);
+// r = b - A x; partial[kReduceBlocks-sized region] receives per-block sums of r.r
+hipError_t launch_residual(const SellDev &A, const double *x, const double *b, double *r,
+                           double *partial, int *nblocks_out, hipStream_t s);
+
+hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx,
+                              const double *srcA, int32_t nA, const double *srcB, double *dst,
+                              hipStream_t s);
+hipError_t launch_gather_sum3(int ndst, const int32_t *ptr, const int32_t *idx, const double *src,
+                              const double *scale, double *dst, hipStream_t s);
+
+// Level-scheduled block ILU(0) of every subdomain; singular pivots reported
+// through *bad as (subdomain << 32 | local row), minimum over all.
+hipError_t launch_ilu_factor(const DevPlan &p, unsigned long long *bad, hipStream_t s);
+// Copy factor blocks from CSR into the step layouts (FP64 and FP32 targets).
+hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base,
+                           const int32_t *stride, const uint8_t *to32, const double *fact,
+                           double *out64, float *out32, hipStream_t s);
+// z = B^-1 (scale * r) over all subdomains; restricted=1 writes owned rows
+// straight into z, restricted=0 leaves the local solutions in yext.
+hipError_t launch_ilu_apply(const DevPlan &p, const double *r, const double *scale, double *z,
+                            int restricted, bool any_fp32, hipStream_t s);
+hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx,
+                                   const double *yext, double *z, hipStream_t s);
+
+// Krylov kernels (n = scalar length).
+hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w,
+                           double *partial, int *nblocks_out, hipStream_t s);
+hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out,
+                              hipStream_t s);
+// After multidot of column j: H[j*ldh + i] = scale[i]*d[i] (i<=j), coef[i] =
+// H[j*ldh+i]*scale[i], wnorm = sqrt(d[nv]).
+hipError_t launch_finalize_dots(int nv, const double *d, const double *scale, double *Hcol,
+                                double *coef, double *wnorm, hipStream_t s);
+hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
+                         const double *w, double *unew, double *partial, int *nblocks_out,
+                         hipStream_t s);
+// hn = sqrt(nrm2[0]); *hout = hn; *scale_out = hn > 0 ? 1/hn : 0.
+hipError_t launch_finalize_norm(const double *nrm2, double *hout, double *scale_out, hipStream_t s);
+hipError_t launch_lincomb(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
+                          double *out, hipStream_t s);
+hipError_t launch_axpy(int64_t n, const double *z, double *x, hipStream_t s);
+
+hipError_t launch_check_finite(int64_t n, const double *v, int *flag, hipStream_t s);
+hipError_t launch_norm2(int64_t n, const double *v, double *partial, int *nblocks_out, hipStream_t s);
+hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s);
+
+}  // namespace asmx

@@ -1,0 +1,848 @@
+// Host-side symbolic setup: partition, algebraic overlap, the coarse maps of
+// the two-level variant, the extended patterns A_i = R_i A R_i^T with their
+// value sources, block ILU(0) update pairs and level schedules, and the
+// device layouts of the triangular solves.
+//
+// Method (Jackson, Taroni, Ponting, arXiv:1401.7227):
+//  - classical additive Schwarz, eq. (3.3)-(3.4): A_i = R_i A R_i^T with
+//    R_i restricting to the overlapping subdomain;
+//  - two-level variant, Section 4, eq. (4.1)-(4.5): R_i keeps subdomain i
+//    (with its overlap) and lumps every other cell by summation (App. B,
+//    eq. (B.3)) into near-field boxes on face-neighbour subdomains and
+//    far-field boxes elsewhere;
+//  - local solver: block ILU(0) (Section 2 and Section 6).
+//
+// Lumping is done in the shared way Section 4 asks for (matrix elements are
+// lumped once and shared, not re-summed per subdomain): cells are grouped
+// into atoms that every subdomain sees as wholly fine or wholly inside one
+// coarse variable, and each subdomain's coarse entries are sums of
+// atom-level lumped blocks.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace asmx {
+namespace {
+
+constexpr int kMode0MaxEntries = 8;  // rows with more entries use a wave per row
+
+struct Split {
+  std::vector<int32_t> part;   // part of each column index
+  std::vector<int32_t> start;  // first column of each part, size k+1
+};
+
+// Balanced split of n columns into k parts: the first (n mod k) parts are
+// one column wider.
+Split balanced(int n, int k) {
+  Split s;
+  s.start.resize(k + 1);
+  const int base = n / k, rem = n % k;
+  s.start[0] = 0;
+  for (int p = 0; p < k; ++p) s.start[p + 1] = s.start[p] + base + (p < rem ? 1 : 0);
+  s.part.resize(n);
+  for (int p = 0; p < k; ++p)
+    for (int i = s.start[p]; i < s.start[p + 1]; ++i) s.part[i] = p;
+  return s;
+}
+
+struct Csr {
+  std::vector<int32_t> ptr, idx;
+};
+
+// Undirected block graph (pattern of A plus its transpose, no self loops).
+Csr undirected(const HostPattern &A) {
+  Csr g;
+  g.ptr.assign(A.N + 1, 0);
+  for (int r = 0; r < A.N; ++r)
+    for (int e = A.rp[r]; e < A.rp[r + 1]; ++e) {
+      const int c = A.ci[e];
+      if (c == r) continue;
+      g.ptr[r + 1]++;
+      g.ptr[c + 1]++;
+    }
+  for (int r = 0; r < A.N; ++r) g.ptr[r + 1] += g.ptr[r];
+  g.idx.resize(g.ptr[A.N]);
+  std::vector<int32_t> fill(g.ptr.begin(), g.ptr.end() - 1);
+  for (int r = 0; r < A.N; ++r)
+    for (int e = A.rp[r]; e < A.rp[r + 1]; ++e) {
+      const int c = A.ci[e];
+      if (c == r) continue;
+      g.idx[fill[r]++] = c;
+      g.idx[fill[c]++] = r;
+    }
+  return g;
+}
+
+// Column view of A: for column d, the (row, entry) pairs holding it, rows
+// ascending.
+struct Transpose {
+  std::vector<int32_t> ptr, row, ent;
+};
+
+Transpose transpose(const HostPattern &A) {
+  Transpose t;
+  t.ptr.assign(A.N + 1, 0);
+  for (int64_t e = 0; e < A.nnzb; ++e) t.ptr[A.ci[e] + 1]++;
+  for (int d = 0; d < A.N; ++d) t.ptr[d + 1] += t.ptr[d];
+  t.row.resize(A.nnzb);
+  t.ent.resize(A.nnzb);
+  std::vector<int32_t> fill(t.ptr.begin(), t.ptr.end() - 1);
+  for (int r = 0; r < A.N; ++r)
+    for (int e = A.rp[r]; e < A.rp[r + 1]; ++e) {
+      const int d = A.ci[e];
+      t.row[fill[d]] = r;
+      t.ent[fill[d]] = e;
+      fill[d]++;
+    }
+  return t;
+}
+
+// Per-subdomain result of the symbolic phase (local indices).
+struct SubLocal {
+  int32_t n = 0, nfine = 0, ncoarse = 0;
+  std::vector<int32_t> cells;   // fine rows -> cell
+  std::vector<uint8_t> owned;   // fine rows owned by this subdomain
+  std::vector<int32_t> rp, ci;  // CSR of A_i
+  std::vector<int32_t> sptr, sidx;  // value sources per entry (pool indices)
+  std::vector<int32_t> diag;
+  std::vector<int32_t> tptr, tdst, tsrc;
+  std::vector<int32_t> cptr, cidx;  // coarse rows -> near/far atom sums
+  // level steps (local positions / slots)
+  std::vector<Step> fst, bst;
+  std::vector<int32_t> frow, brow, fcol, bcol, frptr, brptr;
+  std::vector<int32_t> fsrc, fbase, fstride, bsrc, bbase, bstride, dsrc, dbase, dstride;
+  std::vector<uint8_t> f32, b32, d32;
+  int32_t fslots = 0, bslots = 0, bpos = 0, fpos = 0;
+  int32_t levels = 0;
+  int32_t bad_row = -1;  // missing diagonal
+};
+
+// Everything about atoms that the per-subdomain pass needs.
+struct Atoms {
+  bool on = false;
+  int32_t nA = 0, nNa = 0, nFa = 0;
+  std::vector<int32_t> cell_atom;            // fine atom of each cell
+  std::vector<int32_t> a_near, a_far;        // fine atom -> N-atom, F-atom
+  std::vector<int32_t> na_box, na_owner, fa_box, fa_owner;
+  Csr na_sig, fa_sig;                         // subdomains for which the atom is fine
+  Csr owner_na, owner_fa;                     // owner -> its N-atoms / F-atoms
+  // L2 blocks: 4 matrices, CSR over row atoms, pool position of each entry
+  struct M {
+    std::vector<int32_t> ptr, col, pos;
+  } nn, nf, fn, ff;
+  std::vector<int32_t> nbox, fbox;            // per cell
+  int32_t nbn = 0, nbf = 0;
+};
+
+inline bool contains(const Csr &c, int row, int v) {
+  for (int t = c.ptr[row]; t < c.ptr[row + 1]; ++t)
+    if (c.idx[t] == v) return true;
+  return false;
+}
+
+// Assigns compact ids to keys (in sorted key order).  keys: (k1, k2) pairs.
+std::vector<int32_t> compact_ids(const std::vector<std::pair<int64_t, int64_t>> &keys, int32_t &nids) {
+  std::vector<int32_t> order(keys.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+  std::vector<int32_t> id(keys.size());
+  int32_t next = -1;
+  for (size_t i = 0; i < order.size(); ++i) {
+    if (i == 0 || keys[order[i]] != keys[order[i - 1]]) ++next;
+    id[order[i]] = next;
+  }
+  nids = next + 1;
+  return id;
+}
+
+// Builds a CSR "row -> (col, source)" lumped matrix from (row, col, src)
+// triples; returns pattern and gather list (sources in ascending order).
+void triples_to_csr(std::vector<std::array<int32_t, 3>> &t, int32_t nrows, std::vector<int32_t> &ptr,
+                    std::vector<int32_t> &col, GatherList &g) {
+  std::sort(t.begin(), t.end());
+  ptr.assign(nrows + 1, 0);
+  col.clear();
+  for (size_t i = 0; i < t.size(); ++i) {
+    const bool first = (i == 0 || t[i][0] != t[i - 1][0] || t[i][1] != t[i - 1][1]);
+    if (first) {
+      col.push_back(t[i][1]);
+      ptr[t[i][0] + 1]++;
+      g.ptr.push_back(g.ptr.back());
+    }
+    g.idx.push_back(t[i][2]);
+    g.ptr.back()++;
+  }
+  for (int r = 0; r < nrows; ++r) ptr[r + 1] += ptr[r];
+}
+
+}  // namespace
+
+asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost &P, std::string &err) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz, N = A.N;
+  const bool two = (o.kind == ASM_KIND_TWO_LEVEL);
+  const int sx = o.sx, sy = o.sy, nsub = sx * sy;
+  const int delta = o.overlap;
+  const bool restricted = (o.combine == ASM_COMBINE_RESTRICTED);
+  const bool fp32 = (o.precision == ASM_PREC_FP32);
+
+  const Split xs = balanced(nx, sx), ys = balanced(ny, sy);
+  std::vector<int32_t> owner(N);
+  for (int c = 0; c < N; ++c) {
+    const int ix = c / (ny * nz), iy = (c / nz) % ny;
+    owner[c] = xs.part[ix] * sy + ys.part[iy];
+  }
+  auto face_nbr = [&](int a, int b) {
+    const int ax = a / sy, ay = a % sy, bx = b / sy, by = b % sy;
+    return std::abs(ax - bx) + std::abs(ay - by) == 1;
+  };
+
+  const Csr G = undirected(A);
+
+  // ---------------------------------------------------------------- fine sets
+  std::vector<std::vector<int32_t>> F(nsub);
+#pragma omp parallel
+  {
+    std::vector<int32_t> dist(N, -1), queue;
+#pragma omp for schedule(dynamic)
+    for (int s = 0; s < nsub; ++s) {
+      const int px = s / sy, py = s % sy;
+      queue.clear();
+      for (int ix = xs.start[px]; ix < xs.start[px + 1]; ++ix)
+        for (int iy = ys.start[py]; iy < ys.start[py + 1]; ++iy)
+          for (int iz = 0; iz < nz; ++iz) {
+            const int c = (ix * ny + iy) * nz + iz;
+            dist[c] = 0;
+            queue.push_back(c);
+          }
+      for (size_t h = 0; h < queue.size(); ++h) {
+        const int c = queue[h];
+        if (dist[c] >= delta) continue;
+        for (int t = G.ptr[c]; t < G.ptr[c + 1]; ++t) {
+          const int d = G.idx[t];
+          if (dist[d] < 0) {
+            dist[d] = dist[c] + 1;
+            queue.push_back(d);
+          }
+        }
+      }
+      F[s] = queue;
+      std::sort(F[s].begin(), F[s].end());
+      for (int c : queue) dist[c] = -1;
+    }
+  }
+
+  // ---------------------------------------------------------------- atoms
+  Atoms at;
+  const Transpose T = two ? transpose(A) : Transpose{};
+  if (two) {
+    at.on = true;
+    const int *nb = o.near_box, *fb = o.far_box;
+    const int nbny = (ny + nb[1] - 1) / nb[1], nbnz = (nz + nb[2] - 1) / nb[2];
+    const int fbny = (ny + fb[1] - 1) / fb[1], fbnz = (nz + fb[2] - 1) / fb[2];
+    at.nbn = ((nx + nb[0] - 1) / nb[0]) * nbny * nbnz;
+    at.nbf = ((nx + fb[0] - 1) / fb[0]) * fbny * fbnz;
+    at.nbox.resize(N);
+    at.fbox.resize(N);
+    for (int c = 0; c < N; ++c) {
+      const int ix = c / (ny * nz), iy = (c / nz) % ny, iz = c % nz;
+      at.nbox[c] = ((ix / nb[0]) * nbny + iy / nb[1]) * nbnz + iz / nb[2];
+      at.fbox[c] = ((ix / fb[0]) * fbny + iy / fb[1]) * fbnz + iz / fb[2];
+    }
+    // membership of each cell in the fine sets of subdomains other than its owner
+    Csr sig;
+    sig.ptr.assign(N + 1, 0);
+    for (int s = 0; s < nsub; ++s)
+      for (int c : F[s])
+        if (owner[c] != s) sig.ptr[c + 1]++;
+    for (int c = 0; c < N; ++c) sig.ptr[c + 1] += sig.ptr[c];
+    sig.idx.resize(sig.ptr[N]);
+    {
+      std::vector<int32_t> fill(sig.ptr.begin(), sig.ptr.end() - 1);
+      for (int s = 0; s < nsub; ++s)
+        for (int c : F[s])
+          if (owner[c] != s) sig.idx[fill[c]++] = s;
+    }
+    // ids of the full / near-part / far-part signature lists
+    std::map<std::vector<int32_t>, int32_t> sig_ids;
+    sig_ids[{}] = 0;
+    std::vector<std::vector<int32_t>> sig_list{{}};
+    auto sig_id = [&](const std::vector<int32_t> &v) {
+      auto it = sig_ids.find(v);
+      if (it != sig_ids.end()) return it->second;
+      const int32_t id = (int32_t)sig_list.size();
+      sig_ids.emplace(v, id);
+      sig_list.push_back(v);
+      return id;
+    };
+    std::vector<int32_t> sfull(N), snear(N), sfar(N);
+    std::vector<int32_t> tmp, tn, tf;
+    for (int c = 0; c < N; ++c) {
+      if (sig.ptr[c] == sig.ptr[c + 1]) {
+        sfull[c] = snear[c] = sfar[c] = 0;
+        continue;
+      }
+      tmp.assign(sig.idx.begin() + sig.ptr[c], sig.idx.begin() + sig.ptr[c + 1]);
+      tn.clear();
+      tf.clear();
+      for (int s : tmp) (face_nbr(s, owner[c]) ? tn : tf).push_back(s);
+      sfull[c] = sig_id(tmp);
+      snear[c] = sig_id(tn);
+      sfar[c] = sig_id(tf);
+    }
+    const int64_t ns = nsub;
+    std::vector<std::pair<int64_t, int64_t>> kA(N), kN(N), kF(N);
+    for (int c = 0; c < N; ++c) {
+      kA[c] = {((int64_t)at.nbox[c] * at.nbf + at.fbox[c]) * ns + owner[c], sfull[c]};
+      kN[c] = {(int64_t)at.nbox[c] * ns + owner[c], snear[c]};
+      kF[c] = {(int64_t)at.fbox[c] * ns + owner[c], sfar[c]};
+    }
+    at.cell_atom = compact_ids(kA, at.nA);
+    const std::vector<int32_t> cN = compact_ids(kN, at.nNa);
+    const std::vector<int32_t> cF = compact_ids(kF, at.nFa);
+    at.a_near.assign(at.nA, -1);
+    at.a_far.assign(at.nA, -1);
+    at.na_box.assign(at.nNa, 0);
+    at.na_owner.assign(at.nNa, 0);
+    at.fa_box.assign(at.nFa, 0);
+    at.fa_owner.assign(at.nFa, 0);
+    std::vector<int32_t> na_sigid(at.nNa, 0), fa_sigid(at.nFa, 0);
+    for (int c = 0; c < N; ++c) {
+      const int a = at.cell_atom[c];
+      at.a_near[a] = cN[c];
+      at.a_far[a] = cF[c];
+      at.na_box[cN[c]] = at.nbox[c];
+      at.na_owner[cN[c]] = owner[c];
+      na_sigid[cN[c]] = snear[c];
+      at.fa_box[cF[c]] = at.fbox[c];
+      at.fa_owner[cF[c]] = owner[c];
+      fa_sigid[cF[c]] = sfar[c];
+    }
+    auto sig_csr = [&](const std::vector<int32_t> &ids, Csr &out) {
+      out.ptr.assign(ids.size() + 1, 0);
+      for (size_t i = 0; i < ids.size(); ++i) out.ptr[i + 1] = out.ptr[i] + (int32_t)sig_list[ids[i]].size();
+      out.idx.resize(out.ptr.back());
+      for (size_t i = 0; i < ids.size(); ++i)
+        std::copy(sig_list[ids[i]].begin(), sig_list[ids[i]].end(), out.idx.begin() + out.ptr[i]);
+    };
+    sig_csr(na_sigid, at.na_sig);
+    sig_csr(fa_sigid, at.fa_sig);
+    auto by_owner = [&](const std::vector<int32_t> &own, Csr &out) {
+      out.ptr.assign(nsub + 1, 0);
+      for (int32_t o2 : own) out.ptr[o2 + 1]++;
+      for (int s = 0; s < nsub; ++s) out.ptr[s + 1] += out.ptr[s];
+      out.idx.resize(own.size());
+      std::vector<int32_t> fill(out.ptr.begin(), out.ptr.end() - 1);
+      for (size_t i = 0; i < own.size(); ++i) out.idx[fill[own[i]]++] = (int32_t)i;
+    };
+    by_owner(at.na_owner, at.owner_na);
+    by_owner(at.fa_owner, at.owner_fa);
+
+    // L1: fine-atom lumped matrix, sources = A blocks
+    std::vector<std::array<int32_t, 3>> t1;
+    t1.reserve(A.nnzb);
+    for (int r = 0; r < N; ++r)
+      for (int e = A.rp[r]; e < A.rp[r + 1]; ++e) t1.push_back({at.cell_atom[r], at.cell_atom[A.ci[e]], e});
+    std::vector<int32_t> l1ptr, l1col;
+    triples_to_csr(t1, at.nA, l1ptr, l1col, P.l1);
+    t1.clear();
+    t1.shrink_to_fit();
+    // L2: near/far atom matrices, sources = L1 entries.  Pool order NN, NF, FN, FF.
+    Atoms::M *mats[4] = {&at.nn, &at.nf, &at.fn, &at.ff};
+    int32_t pool = 0;
+    for (int m = 0; m < 4; ++m) {
+      const bool rn = (m < 2), cn = (m % 2 == 0);
+      std::vector<std::array<int32_t, 3>> t2;
+      for (int a = 0; a < at.nA; ++a)
+        for (int q = l1ptr[a]; q < l1ptr[a + 1]; ++q) {
+          const int b = l1col[q];
+          t2.push_back({rn ? at.a_near[a] : at.a_far[a], cn ? at.a_near[b] : at.a_far[b], q});
+        }
+      GatherList g;
+      triples_to_csr(t2, rn ? at.nNa : at.nFa, mats[m]->ptr, mats[m]->col, g);
+      mats[m]->pos.resize(mats[m]->col.size());
+      for (size_t i = 0; i < mats[m]->col.size(); ++i) mats[m]->pos[i] = pool + (int32_t)i;
+      pool += (int32_t)mats[m]->col.size();
+      for (int32_t d = 0; d < g.size(); ++d) {
+        for (int q = g.ptr[d]; q < g.ptr[d + 1]; ++q) P.l2.idx.push_back(g.idx[q]);
+        P.l2.ptr.push_back((int32_t)P.l2.idx.size());
+      }
+    }
+    // right-hand side lumping: fine-atom sums of cells, then N/F atoms
+    {
+      std::vector<std::array<int32_t, 3>> tc;
+      tc.reserve(N);
+      for (int c = 0; c < N; ++c) tc.push_back({at.cell_atom[c], c, c});
+      std::sort(tc.begin(), tc.end());
+      P.c1.ptr.assign(1, 0);
+      int cur = 0;
+      for (int a = 0; a < at.nA; ++a) {
+        while (cur < (int)tc.size() && tc[cur][0] == a) P.c1.idx.push_back(tc[cur++][2]);
+        P.c1.ptr.push_back((int32_t)P.c1.idx.size());
+      }
+      // c2 destinations: [N-atoms | F-atoms]
+      std::vector<std::vector<int32_t>> nsrc(at.nNa), fsrc(at.nFa);
+      for (int a = 0; a < at.nA; ++a) {
+        nsrc[at.a_near[a]].push_back(a);
+        fsrc[at.a_far[a]].push_back(a);
+      }
+      for (auto &v : nsrc) {
+        P.c2.idx.insert(P.c2.idx.end(), v.begin(), v.end());
+        P.c2.ptr.push_back((int32_t)P.c2.idx.size());
+      }
+      for (auto &v : fsrc) {
+        P.c2.idx.insert(P.c2.idx.end(), v.begin(), v.end());
+        P.c2.ptr.push_back((int32_t)P.c2.idx.size());
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- per subdomain
+  std::vector<SubLocal> L(nsub);
+  const int64_t nnzbA = A.nnzb;
+#pragma omp parallel
+  {
+    std::vector<int32_t> loc(N, -1);
+    std::vector<int32_t> nvar(two ? at.nbn : 0, -1), fvar(two ? at.nbf : 0, -1);
+    std::vector<int32_t> pos;
+    std::vector<std::array<int32_t, 3>> trip;
+#pragma omp for schedule(dynamic)
+    for (int s = 0; s < nsub; ++s) {
+      SubLocal &S = L[s];
+      S.cells = F[s];
+      S.nfine = (int32_t)S.cells.size();
+      S.owned.resize(S.nfine);
+      for (int u = 0; u < S.nfine; ++u) {
+        loc[S.cells[u]] = u;
+        S.owned[u] = (owner[S.cells[u]] == s);
+      }
+      std::vector<int32_t> near_boxes, far_boxes;
+      std::vector<std::vector<int32_t>> near_members, far_members;  // atoms per var
+      if (two) {
+        // coarse variables: near boxes of face-neighbour owners, far boxes
+        // elsewhere, each restricted to atoms not fine for s
+        for (int o2 = 0; o2 < nsub; ++o2) {
+          if (o2 == s) continue;
+          if (face_nbr(o2, s)) {
+            for (int t = at.owner_na.ptr[o2]; t < at.owner_na.ptr[o2 + 1]; ++t) {
+              const int a = at.owner_na.idx[t];
+              if (!contains(at.na_sig, a, s)) near_boxes.push_back(at.na_box[a]);
+            }
+          } else {
+            for (int t = at.owner_fa.ptr[o2]; t < at.owner_fa.ptr[o2 + 1]; ++t) {
+              const int a = at.owner_fa.idx[t];
+              if (!contains(at.fa_sig, a, s)) far_boxes.push_back(at.fa_box[a]);
+            }
+          }
+        }
+        std::sort(near_boxes.begin(), near_boxes.end());
+        near_boxes.erase(std::unique(near_boxes.begin(), near_boxes.end()), near_boxes.end());
+        std::sort(far_boxes.begin(), far_boxes.end());
+        far_boxes.erase(std::unique(far_boxes.begin(), far_boxes.end()), far_boxes.end());
+        for (size_t i = 0; i < near_boxes.size(); ++i) nvar[near_boxes[i]] = S.nfine + (int32_t)i;
+        for (size_t i = 0; i < far_boxes.size(); ++i)
+          fvar[far_boxes[i]] = S.nfine + (int32_t)near_boxes.size() + (int32_t)i;
+        S.ncoarse = (int32_t)(near_boxes.size() + far_boxes.size());
+        near_members.assign(near_boxes.size(), {});
+        far_members.assign(far_boxes.size(), {});
+      }
+      S.n = S.nfine + S.ncoarse;
+      auto is_fine = [&](int c) { return loc[c] >= 0; };
+      auto label = [&](int c) -> int32_t {
+        if (loc[c] >= 0) return loc[c];
+        if (!two) return -1;
+        const int o2 = owner[c];
+        return face_nbr(o2, s) ? nvar[at.nbox[c]] : fvar[at.fbox[c]];
+      };
+      trip.clear();
+      // (a) fine rows: every block of the cell's row
+      for (int u = 0; u < S.nfine; ++u) {
+        const int a = S.cells[u];
+        for (int e = A.rp[a]; e < A.rp[a + 1]; ++e) {
+          const int v = label(A.ci[e]);
+          if (v >= 0) trip.push_back({u, v, e});
+        }
+      }
+      if (two) {
+        // (b) coarse rows against fine columns, from A's blocks
+        for (int u = 0; u < S.nfine; ++u) {
+          const int d = S.cells[u];
+          for (int t = T.ptr[d]; t < T.ptr[d + 1]; ++t) {
+            const int a = T.row[t];
+            if (is_fine(a)) continue;
+            trip.push_back({label(a), u, T.ent[t]});
+          }
+        }
+        // (c) coarse against coarse, from the shared lumped atom matrices
+        auto near_ok = [&](int na) { return face_nbr(at.na_owner[na], s) && !contains(at.na_sig, na, s); };
+        auto far_ok = [&](int fa) {
+          const int o2 = at.fa_owner[fa];
+          return o2 != s && !face_nbr(o2, s) && !contains(at.fa_sig, fa, s);
+        };
+        for (int o2 = 0; o2 < nsub; ++o2) {
+          if (o2 == s) continue;
+          if (face_nbr(o2, s)) {
+            for (int t = at.owner_na.ptr[o2]; t < at.owner_na.ptr[o2 + 1]; ++t) {
+              const int a = at.owner_na.idx[t];
+              if (!near_ok(a)) continue;
+              const int u = nvar[at.na_box[a]];
+              near_members[u - S.nfine].push_back(a);
+              for (int q = at.nn.ptr[a]; q < at.nn.ptr[a + 1]; ++q)
+                if (near_ok(at.nn.col[q])) trip.push_back({u, nvar[at.na_box[at.nn.col[q]]], (int32_t)(nnzbA + at.nn.pos[q])});
+              for (int q = at.nf.ptr[a]; q < at.nf.ptr[a + 1]; ++q)
+                if (far_ok(at.nf.col[q])) trip.push_back({u, fvar[at.fa_box[at.nf.col[q]]], (int32_t)(nnzbA + at.nf.pos[q])});
+            }
+          } else {
+            for (int t = at.owner_fa.ptr[o2]; t < at.owner_fa.ptr[o2 + 1]; ++t) {
+              const int a = at.owner_fa.idx[t];
+              if (!far_ok(a)) continue;
+              const int u = fvar[at.fa_box[a]];
+              far_members[u - S.nfine - near_boxes.size()].push_back(a);
+              for (int q = at.fn.ptr[a]; q < at.fn.ptr[a + 1]; ++q)
+                if (near_ok(at.fn.col[q])) trip.push_back({u, nvar[at.na_box[at.fn.col[q]]], (int32_t)(nnzbA + at.fn.pos[q])});
+              for (int q = at.ff.ptr[a]; q < at.ff.ptr[a + 1]; ++q)
+                if (far_ok(at.ff.col[q])) trip.push_back({u, fvar[at.fa_box[at.ff.col[q]]], (int32_t)(nnzbA + at.ff.pos[q])});
+            }
+          }
+        }
+        // coarse right-hand sides: sums of the member atoms' lumped values
+        S.cptr.assign(1, 0);
+        for (auto &m : near_members) {
+          std::sort(m.begin(), m.end());
+          S.cidx.insert(S.cidx.end(), m.begin(), m.end());
+          S.cptr.push_back((int32_t)S.cidx.size());
+        }
+        for (auto &m : far_members) {
+          std::sort(m.begin(), m.end());
+          for (int a : m) S.cidx.push_back(at.nNa + a);
+          S.cptr.push_back((int32_t)S.cidx.size());
+        }
+      }
+      // CSR of A_i with value sources
+      std::sort(trip.begin(), trip.end());
+      S.rp.assign(S.n + 1, 0);
+      S.sptr.assign(1, 0);
+      for (size_t i = 0; i < trip.size(); ++i) {
+        if (i == 0 || trip[i][0] != trip[i - 1][0] || trip[i][1] != trip[i - 1][1]) {
+          S.ci.push_back(trip[i][1]);
+          S.rp[trip[i][0] + 1]++;
+          S.sptr.push_back(S.sptr.back());
+        }
+        S.sidx.push_back(trip[i][2]);
+        S.sptr.back()++;
+      }
+      for (int u = 0; u < S.n; ++u) S.rp[u + 1] += S.rp[u];
+      // diagonal positions
+      S.diag.assign(S.n, -1);
+      for (int u = 0; u < S.n; ++u)
+        for (int e = S.rp[u]; e < S.rp[u + 1]; ++e)
+          if (S.ci[e] == u) S.diag[u] = e;
+      for (int u = 0; u < S.n; ++u)
+        if (S.diag[u] < 0 && S.bad_row < 0) S.bad_row = u;
+      // ILU(0) update pairs: row i, lower entry (i,k), upper entry (k,j)
+      // with j in row i
+      const int nnz = S.rp[S.n];
+      pos.assign(S.n, -1);
+      S.tptr.assign(nnz + 1, 0);
+      for (int i = 0; i < S.n && S.bad_row < 0; ++i) {
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) pos[S.ci[e]] = e;
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+          const int k = S.ci[e];
+          if (k >= i) break;
+          for (int ek = S.diag[k] + 1; ek < S.rp[k + 1]; ++ek) {
+            const int dst = pos[S.ci[ek]];
+            if (dst < 0) continue;
+            S.tdst.push_back(dst);
+            S.tsrc.push_back(ek);
+          }
+          S.tptr[e + 1] = (int32_t)S.tdst.size();
+        }
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) pos[S.ci[e]] = -1;
+      }
+      // entries without pairs still need a monotone pointer
+      for (int e = 0; e < nnz; ++e) S.tptr[e + 1] = std::max(S.tptr[e + 1], S.tptr[e]);
+      // level schedules
+      std::vector<int32_t> lf(S.n, 0), lb(S.n, 0);
+      int maxf = 0, maxb = 0;
+      for (int i = 0; i < S.n; ++i) {
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
+          if (S.ci[e] < i) lf[i] = std::max(lf[i], lf[S.ci[e]] + 1);
+        maxf = std::max(maxf, lf[i]);
+      }
+      for (int i = S.n - 1; i >= 0; --i) {
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
+          if (S.ci[e] > i) lb[i] = std::max(lb[i], lb[S.ci[e]] + 1);
+        maxb = std::max(maxb, lb[i]);
+      }
+      S.levels = std::max(maxf, maxb) + 1;
+      // steps: rows of one level, split by class (fine/coarse) and mode
+      auto make_steps = [&](bool fwd, const std::vector<int32_t> &lev, int maxl, std::vector<Step> &steps,
+                            std::vector<int32_t> &rows, std::vector<int32_t> &cols, std::vector<int32_t> &rptr,
+                            std::vector<int32_t> &src, std::vector<int32_t> &base, std::vector<int32_t> &stride,
+                            std::vector<uint8_t> &to32, int32_t &slots) {
+        std::vector<std::vector<int32_t>> bylev(maxl + 1);
+        for (int i = 0; i < S.n; ++i) bylev[lev[i]].push_back(i);
+        auto count = [&](int i) {
+          int c = 0;
+          for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) c += fwd ? (S.ci[e] < i) : (S.ci[e] > i);
+          return c;
+        };
+        for (int l = 0; l <= maxl; ++l) {
+          for (int cls = 0; cls < 2; ++cls)
+            for (int mode = 0; mode < 2; ++mode) {
+              std::vector<int32_t> rs;
+              for (int i : bylev[l]) {
+                if ((i >= S.nfine) != (cls == 1)) continue;
+                if ((count(i) > kMode0MaxEntries) != (mode == 1)) continue;
+                rs.push_back(i);
+              }
+              if (rs.empty()) continue;
+              Step st{};
+              st.pos = (int32_t)rows.size();
+              st.nrows = (int32_t)rs.size();
+              st.eoff = slots;
+              st.mode = mode;
+              st.fp32 = (fp32 && cls == 0) ? 1 : 0;
+              rows.insert(rows.end(), rs.begin(), rs.end());
+              const int nr = st.nrows;
+              if (mode == 0) {
+                int w = 0;
+                for (int i : rs) w = std::max(w, count(i));
+                st.width = w;
+                const size_t c0 = cols.size();
+                cols.resize(c0 + (size_t)w * nr, -1);
+                for (int j = 0; j < nr; ++j) {
+                  const int i = rs[j];
+                  int k = 0;
+                  for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+                    const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
+                    if (!take) continue;
+                    cols[c0 + (size_t)k * nr + j] = S.ci[e];
+                    ++k;
+                  }
+                }
+                for (int k = 0; k < w; ++k)
+                  for (int j = 0; j < nr; ++j) {
+                    // source entry of slot (k, j)
+                    const int i = rs[j];
+                    int kk = 0, ent = -1;
+                    for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+                      const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
+                      if (!take) continue;
+                      if (kk == k) { ent = e; break; }
+                      ++kk;
+                    }
+                    src.push_back(ent);
+                    base.push_back(9 * slots + k * 9 * nr + j);
+                    stride.push_back(nr);
+                    to32.push_back((uint8_t)st.fp32);
+                  }
+                slots += w * nr;
+              } else {
+                st.width = 0;
+                st.rptr = (int32_t)rptr.size();
+                rptr.push_back(0);
+                int t = 0;
+                for (int j = 0; j < nr; ++j) {
+                  const int i = rs[j];
+                  for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+                    const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
+                    if (!take) continue;
+                    cols.push_back(S.ci[e]);
+                    src.push_back(e);
+                    base.push_back(9 * (slots + t));
+                    stride.push_back(1);
+                    to32.push_back((uint8_t)st.fp32);
+                    ++t;
+                  }
+                  rptr.push_back(t);
+                }
+                slots += t;
+              }
+              steps.push_back(st);
+            }
+        }
+      };
+      make_steps(true, lf, maxf, S.fst, S.frow, S.fcol, S.frptr, S.fsrc, S.fbase, S.fstride, S.f32, S.fslots);
+      make_steps(false, lb, maxb, S.bst, S.brow, S.bcol, S.brptr, S.bsrc, S.bbase, S.bstride, S.b32, S.bslots);
+      S.fpos = (int32_t)S.frow.size();
+      S.bpos = (int32_t)S.brow.size();
+      // pivots: D^-1 of each backward position, SoA per step
+      for (const Step &st : S.bst)
+        for (int j = 0; j < st.nrows; ++j) {
+          S.dsrc.push_back(S.diag[S.brow[st.pos + j]]);
+          S.dbase.push_back(9 * st.pos + j);
+          S.dstride.push_back(st.nrows);
+          S.d32.push_back((uint8_t)st.fp32);
+        }
+      for (int u = 0; u < S.nfine; ++u) loc[S.cells[u]] = -1;
+      if (two) {
+        for (int b : near_boxes) nvar[b] = -1;
+        for (int b : far_boxes) fvar[b] = -1;
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- checks
+  for (int s = 0; s < nsub; ++s)
+    if (L[s].bad_row >= 0) {
+      err = "subdomain " + std::to_string(s) + " local row " + std::to_string(L[s].bad_row) +
+            " has no diagonal block";
+      return ASM_ERR_INVALID;
+    }
+
+  // ---------------------------------------------------------------- concatenate
+  P.nsub = nsub;
+  P.sub.resize(nsub);
+  int64_t ext = 0, ent = 0, tcount = 0, asrc = 0, fsl = 0, bsl = 0, fpos = 0, bpos = 0, frp = 0, brp = 0,
+          coarse = 0, csrc = 0;
+  std::vector<int64_t> o_ext(nsub), o_ent(nsub), o_t(nsub), o_as(nsub), o_fsl(nsub), o_bsl(nsub), o_fpos(nsub),
+      o_bpos(nsub), o_frp(nsub), o_brp(nsub), o_coarse(nsub), o_cs(nsub), o_fst(nsub), o_bst(nsub);
+  int64_t fst = 0, bst = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const SubLocal &S = L[s];
+    o_ext[s] = ext; o_ent[s] = ent; o_t[s] = tcount; o_as[s] = asrc; o_fsl[s] = fsl; o_bsl[s] = bsl;
+    o_fpos[s] = fpos; o_bpos[s] = bpos; o_frp[s] = frp; o_brp[s] = brp; o_coarse[s] = coarse; o_cs[s] = csrc;
+    o_fst[s] = fst; o_bst[s] = bst;
+    ext += S.n; ent += S.rp[S.n]; tcount += (int64_t)S.tdst.size(); asrc += (int64_t)S.sidx.size();
+    fsl += S.fslots; bsl += S.bslots; fpos += S.fpos; bpos += S.bpos;
+    frp += (int64_t)S.frptr.size(); brp += (int64_t)S.brptr.size(); coarse += S.ncoarse;
+    csrc += (int64_t)S.cidx.size(); fst += (int64_t)S.fst.size(); bst += (int64_t)S.bst.size();
+    P.max_levels = std::max(P.max_levels, S.levels);
+    P.fine_row_entries += S.rp[S.nfine];
+  }
+  const int64_t lim = (int64_t)1 << 31;
+  if (ext >= lim || ent >= lim || tcount >= lim || asrc >= lim || 9 * fsl >= lim || 9 * bsl >= lim ||
+      9 * bpos >= lim) {
+    err = "preconditioner too large for 32-bit indexing";
+    return ASM_ERR_INVALID;
+  }
+  P.total_ext = ext;
+  P.total_coarse = coarse;
+  P.total_entries = ent;
+  P.fslots = fsl;
+  P.bslots = bsl;
+  P.bpos = bpos;
+  P.fstep.resize(fst);
+  P.bstep.resize(bst);
+  P.frow.resize(fpos);
+  P.brow.resize(bpos);
+  P.fcol.resize(fsl);
+  P.bcol.resize(bsl);
+  P.frptr.resize(frp);
+  P.brptr.resize(brp);
+  P.rhs_src.resize(ext);
+  P.out_cell.resize(ext);
+  P.arp.resize(ext + 1);
+  P.aci.resize(ent);
+  P.adiag.resize(ext);
+  P.tptr.resize(ent + 1);
+  P.tdst.resize(tcount);
+  P.tsrc.resize(tcount);
+  P.asm_src.ptr.resize(ent + 1);
+  P.asm_src.idx.resize(asrc);
+  P.c3.ptr.resize(coarse + 1);
+  P.c3.idx.resize(csrc);
+  auto rl_resize = [](RelayoutMap &m, int64_t n) {
+    m.src.resize(n); m.base.resize(n); m.stride.resize(n); m.to32.resize(n);
+  };
+  rl_resize(P.rl_f, fsl);
+  rl_resize(P.rl_b, bsl);
+  rl_resize(P.rl_d, bpos);
+#pragma omp parallel for schedule(dynamic)
+  for (int s = 0; s < nsub; ++s) {
+    const SubLocal &S = L[s];
+    SubDesc &d = P.sub[s];
+    d.ext_off = (int32_t)o_ext[s];
+    d.n = S.n;
+    d.nfine = S.nfine;
+    d.fstep0 = (int32_t)o_fst[s];
+    d.fstep1 = (int32_t)(o_fst[s] + S.fst.size());
+    d.bstep0 = (int32_t)o_bst[s];
+    d.bstep1 = (int32_t)(o_bst[s] + S.bst.size());
+    for (size_t k = 0; k < S.fst.size(); ++k) {
+      Step st = S.fst[k];
+      st.pos += (int32_t)o_fpos[s];
+      st.eoff += (int32_t)o_fsl[s];
+      st.rptr += (int32_t)o_frp[s];
+      P.fstep[o_fst[s] + k] = st;
+    }
+    for (size_t k = 0; k < S.bst.size(); ++k) {
+      Step st = S.bst[k];
+      st.pos += (int32_t)o_bpos[s];
+      st.eoff += (int32_t)o_bsl[s];
+      st.rptr += (int32_t)o_brp[s];
+      P.bstep[o_bst[s] + k] = st;
+    }
+    std::copy(S.frow.begin(), S.frow.end(), P.frow.begin() + o_fpos[s]);
+    std::copy(S.brow.begin(), S.brow.end(), P.brow.begin() + o_bpos[s]);
+    std::copy(S.fcol.begin(), S.fcol.end(), P.fcol.begin() + o_fsl[s]);
+    std::copy(S.bcol.begin(), S.bcol.end(), P.bcol.begin() + o_bsl[s]);
+    std::copy(S.frptr.begin(), S.frptr.end(), P.frptr.begin() + o_frp[s]);
+    std::copy(S.brptr.begin(), S.brptr.end(), P.brptr.begin() + o_brp[s]);
+    for (int u = 0; u < S.n; ++u) {
+      const int64_t g = o_ext[s] + u;
+      if (u < S.nfine) {
+        P.rhs_src[g] = S.cells[u];
+        P.out_cell[g] = (restricted && S.owned[u]) ? S.cells[u] : -1;
+      } else {
+        P.rhs_src[g] = -(int32_t)(1 + o_coarse[s] + (u - S.nfine));
+        P.out_cell[g] = -1;
+      }
+      P.arp[g] = (int32_t)(o_ent[s] + S.rp[u]);
+      P.adiag[g] = (int32_t)(o_ent[s] + S.diag[u]);
+    }
+    const int nnz = S.rp[S.n];
+    for (int e = 0; e < nnz; ++e) {
+      P.aci[o_ent[s] + e] = S.ci[e];
+      P.tptr[o_ent[s] + e] = (int32_t)(o_t[s] + S.tptr[e]);
+      P.asm_src.ptr[o_ent[s] + e] = (int32_t)(o_as[s] + S.sptr[e]);
+    }
+    for (size_t t = 0; t < S.tdst.size(); ++t) {
+      P.tdst[o_t[s] + t] = (int32_t)(o_ent[s] + S.tdst[t]);
+      P.tsrc[o_t[s] + t] = (int32_t)(o_ent[s] + S.tsrc[t]);
+    }
+    std::copy(S.sidx.begin(), S.sidx.end(), P.asm_src.idx.begin() + o_as[s]);
+    for (int q = 0; q < S.ncoarse; ++q) P.c3.ptr[o_coarse[s] + q] = (int32_t)(o_cs[s] + S.cptr[q]);
+    std::copy(S.cidx.begin(), S.cidx.end(), P.c3.idx.begin() + o_cs[s]);
+    auto fill_rl = [&](RelayoutMap &m, int64_t off, int64_t base_off, const std::vector<int32_t> &src,
+                       const std::vector<int32_t> &base, const std::vector<int32_t> &stride,
+                       const std::vector<uint8_t> &to32) {
+      for (size_t t = 0; t < src.size(); ++t) {
+        m.src[off + t] = src[t] >= 0 ? (int32_t)(o_ent[s] + src[t]) : -1;
+        m.base[off + t] = (int32_t)(base[t] + 9 * base_off);
+        m.stride[off + t] = stride[t];
+        m.to32[off + t] = to32[t];
+      }
+    };
+    fill_rl(P.rl_f, o_fsl[s], o_fsl[s], S.fsrc, S.fbase, S.fstride, S.f32);
+    fill_rl(P.rl_b, o_bsl[s], o_bsl[s], S.bsrc, S.bbase, S.bstride, S.b32);
+    fill_rl(P.rl_d, o_bpos[s], o_bpos[s], S.dsrc, S.dbase, S.dstride, S.d32);
+  }
+  P.arp[ext] = (int32_t)ent;
+  P.tptr[ent] = (int32_t)tcount;
+  P.asm_src.ptr[ent] = (int32_t)asrc;
+  P.c3.ptr[coarse] = (int32_t)csrc;
+  // additive combine: contributors of each cell in subdomain order
+  P.cptr.assign(N + 1, 0);
+  for (int s = 0; s < nsub; ++s)
+    for (int c : L[s].cells) P.cptr[c + 1]++;
+  for (int c = 0; c < N; ++c) P.cptr[c + 1] += P.cptr[c];
+  P.cidx.resize(P.cptr[N]);
+  {
+    std::vector<int32_t> fill(P.cptr.begin(), P.cptr.end() - 1);
+    for (int s = 0; s < nsub; ++s)
+      for (int u = 0; u < L[s].nfine; ++u) P.cidx[fill[L[s].cells[u]]++] = (int32_t)(o_ext[s] + u);
+  }
+  P.any_fp32 = fp32;
+  return ASM_OK;
+}
+
+}  // namespace asmx

@@ -1,0 +1,60 @@
+// Host-side symbolic setup of the Schwarz preconditioner.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/asm.h"
+#include "plan.hpp"
+
+namespace asmx {
+
+struct HostPattern {
+  int32_t nx = 0, ny = 0, nz = 0, N = 0;
+  int64_t nnzb = 0;
+  std::vector<int32_t> rp, ci;
+};
+
+// Slots copied from the CSR factors into a step layout: component q of slot
+// t goes to out[base[t] + q*stride[t]] of the FP32 array if to32[t], else of
+// the FP64 array.
+struct RelayoutMap {
+  std::vector<int32_t> src, base, stride;
+  std::vector<uint8_t> to32;
+};
+
+// Gather-sum description: dst entry d sums sources idx[ptr[d] .. ptr[d+1]).
+struct GatherList {
+  std::vector<int32_t> ptr{0}, idx;
+  int32_t size() const { return (int32_t)ptr.size() - 1; }
+};
+
+struct PlanHost {
+  int32_t nsub = 0;
+  int64_t total_ext = 0, total_coarse = 0, total_entries = 0, fine_row_entries = 0;
+  int32_t max_levels = 0;
+  std::vector<SubDesc> sub;
+  std::vector<Step> fstep, bstep;
+  std::vector<int32_t> frow, brow, fcol, bcol, frptr, brptr;
+  int64_t fslots = 0, bslots = 0, bpos = 0;  // sizes of fval, bval (blocks), bdinv (rows)
+  int64_t fslots32 = 0, bslots32 = 0;
+  RelayoutMap rl_f, rl_b, rl_d;
+  std::vector<int32_t> rhs_src, out_cell;
+  std::vector<int32_t> arp, aci, adiag, tptr, tdst, tsrc;
+  // Assembly of A_i values: sources index the pool [A blocks | lumped L2].
+  GatherList asm_src;
+  // Lumped matrices: L1 (fine atoms) from A blocks; L2 (near/far atoms)
+  // from L1 blocks.
+  GatherList l1, l2;
+  // Lumped right-hand side: atom sums of cells, then near/far atom sums of
+  // fine atoms, then coarse rows of near/far atoms.
+  GatherList c1, c2, c3;
+  // Additive combine: per cell the extended rows holding its value.
+  std::vector<int32_t> cptr, cidx;
+  bool any_fp32 = false;
+};
+
+// Builds everything that depends only on the sparsity pattern and options.
+asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost &P, std::string &err);
+
+}  // namespace asmx
