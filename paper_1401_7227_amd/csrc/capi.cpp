@@ -161,16 +161,18 @@ struct asm_system_s {
 struct asm_precond_s {
   asm_system sys = nullptr;
   asm_precond_opts opts{};
-  PlanHost plan;  // small host-side parts kept for export
+  PlanHost plan;  // small host-side parts kept for export and messages
   DevMem mem;
-  DevPlan dp{};
+  DevPlan dp{};     // factorisation
+  ApplyPlan ap{};   // sweeps
   GatherDev l1, l2, asrc, c1, c2, c3;
   double *L1 = nullptr, *L2 = nullptr;  // lumped block values
   double *aval = nullptr;               // assembled A_i (CSR)
   double *PA = nullptr, *PNF = nullptr; // lumped residual sums
-  int32_t *rl_src[3] = {}, *rl_base[3] = {}, *rl_stride[3] = {};
-  uint8_t *rl_to32[3] = {};
-  int64_t rl_n[3] = {};
+  void *recbuf = nullptr;               // sweep records
+  int32_t *rl_src = nullptr, *rl_base = nullptr, *rl_stride = nullptr;
+  uint8_t *rl_to32 = nullptr;
+  int64_t rl_n = 0;
   int32_t *cptr = nullptr, *cidx = nullptr;
   unsigned long long *bad = nullptr;
   asm_precond_stats stats{};
@@ -265,13 +267,8 @@ asm_status numeric_setup(asm_precond pc, hipStream_t s) {
                          hipMemcpyDeviceToDevice, s));
   ASM_HIP(hipMemsetAsync(pc->bad, 0xff, sizeof(unsigned long long), s));
   ASM_HIP(launch_ilu_factor(pc->dp, pc->bad, s));
-  ASM_HIP(launch_relayout((int)pc->rl_n[0], pc->rl_src[0], pc->rl_base[0], pc->rl_stride[0], pc->rl_to32[0],
-                          pc->dp.fact, const_cast<double *>(pc->dp.fval), const_cast<float *>(pc->dp.fval32), s));
-  ASM_HIP(launch_relayout((int)pc->rl_n[1], pc->rl_src[1], pc->rl_base[1], pc->rl_stride[1], pc->rl_to32[1],
-                          pc->dp.fact, const_cast<double *>(pc->dp.bval), const_cast<float *>(pc->dp.bval32), s));
-  ASM_HIP(launch_relayout((int)pc->rl_n[2], pc->rl_src[2], pc->rl_base[2], pc->rl_stride[2], pc->rl_to32[2],
-                          pc->dp.fact, const_cast<double *>(pc->dp.bdinv), const_cast<float *>(pc->dp.bdinv32),
-                          s));
+  ASM_HIP(launch_relayout((int)pc->rl_n, pc->rl_src, pc->rl_base, pc->rl_stride, pc->rl_to32, pc->dp.fact,
+                          static_cast<double *>(pc->recbuf), static_cast<float *>(pc->recbuf), s));
   unsigned long long bad = 0;
   ASM_HIP(hipMemcpyAsync(&bad, pc->bad, sizeof bad, hipMemcpyDeviceToHost, s));
   ASM_HIP(hipStreamSynchronize(s));
@@ -302,16 +299,17 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
     ASM_HIP(launch_gather_sum3(pc->c1.n, pc->c1.ptr, pc->c1.idx, r, scale, pc->PA, s));
     ASM_HIP(launch_gather_sum3(pc->c2.n, pc->c2.ptr, pc->c2.idx, pc->PA, nullptr, pc->PNF, s));
     ASM_HIP(launch_gather_sum3(pc->c3.n, pc->c3.ptr, pc->c3.idx, pc->PNF, nullptr,
-                               const_cast<double *>(pc->dp.crhs), s));
+                               const_cast<double *>(pc->ap.crhs), s));
     pf.span(ASM_PHASE_LUMP, t0, s);
   }
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(s);
-  ASM_HIP(launch_ilu_apply(pc->dp, r, scale, z, restricted ? 1 : 0, pc->plan.any_fp32, s));
+  ASM_HIP(launch_gather_rhs((int)pc->plan.total_pos, pc->ap, r, scale, s));
+  ASM_HIP(launch_ilu_apply(pc->ap, r, scale, z, s));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
     const size_t t2 = pf.mark(s);
-    ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->dp.yext, z, s));
+    ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->ap.yx, z, s));
     pf.span(ASM_PHASE_COMBINE, t2, s);
   }
   return ASM_OK;
@@ -436,23 +434,15 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   auto up = [&](auto **dst, const auto &vec) { return M.upload(dst, vec, s); };
   hipError_t e = hipSuccess;
   SubDesc *dsub;
-  Step *dfst, *dbst;
   int32_t *t32;
 #define UP(dst, vec)                                                                           \
   if ((e = up(dst, vec)) != hipSuccess)                                                        \
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   d.nsub = P.nsub;
   UP(&dsub, P.sub); d.sub = dsub;
+  Step *dfst;
   UP(&dfst, P.fstep); d.fstep = dfst;
-  UP(&dbst, P.bstep); d.bstep = dbst;
   UP(&t32, P.frow); d.frow = t32;
-  UP(&t32, P.brow); d.brow = t32;
-  UP(&t32, P.fcol); d.fcol = t32;
-  UP(&t32, P.bcol); d.bcol = t32;
-  UP(&t32, P.frptr); d.frptr = t32;
-  UP(&t32, P.brptr); d.brptr = t32;
-  UP(&t32, P.rhs_src); d.rhs_src = t32;
-  UP(&t32, P.out_cell); d.out_cell = t32;
   UP(&t32, P.arp); d.arp = t32;
   UP(&t32, P.aci); d.aci = t32;
   UP(&t32, P.adiag); d.adiag = t32;
@@ -461,32 +451,39 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   UP(&t32, P.tsrc); d.tsrc = t32;
   UP(&pc->cptr, P.cptr);
   UP(&pc->cidx, P.cidx);
-  RelayoutMap *maps[3] = {&P.rl_f, &P.rl_b, &P.rl_d};
-  for (int k = 0; k < 3; ++k) {
-    UP(&pc->rl_src[k], maps[k]->src);
-    UP(&pc->rl_base[k], maps[k]->base);
-    UP(&pc->rl_stride[k], maps[k]->stride);
-    UP(&pc->rl_to32[k], maps[k]->to32);
-    pc->rl_n[k] = (int64_t)maps[k]->src.size();
-  }
+  UP(&pc->rl_src, P.rl.src);
+  UP(&pc->rl_base, P.rl.base);
+  UP(&pc->rl_stride, P.rl.stride);
+  UP(&pc->rl_to32, P.rl.to32);
+  pc->rl_n = (int64_t)P.rl.src.size();
+  RecStep *drf, *drb;
+  UP(&drf, P.rf);
+  UP(&drb, P.rb);
+  uint8_t *drec;
+  UP(&drec, P.rec);
+  UP(&t32, P.fsrc);
+  ApplyPlan &ap = pc->ap;
+  ap.nsub = P.nsub;
+  ap.sub = dsub;
+  ap.fstep = drf;
+  ap.bstep = drb;
+  ap.rec = drec;
+  pc->recbuf = drec;
+  ap.fsrc = t32;
 #undef UP
   auto ALLOC = [&](auto **dst, size_t n) { return M.alloc(dst, n); };
-  double *fv, *bv, *bd, *yext, *crhs, *fact;
-  float *fv32, *bv32, *bd32;
-  if ((e = ALLOC(&fv, (size_t)P.fslots * 9)) != hipSuccess || (e = ALLOC(&bv, (size_t)P.bslots * 9)) != hipSuccess ||
-      (e = ALLOC(&bd, (size_t)P.bpos * 9)) != hipSuccess ||
-      (e = ALLOC(&fv32, P.any_fp32 ? (size_t)P.fslots * 9 : 1)) != hipSuccess ||
-      (e = ALLOC(&bv32, P.any_fp32 ? (size_t)P.bslots * 9 : 1)) != hipSuccess ||
-      (e = ALLOC(&bd32, P.any_fp32 ? (size_t)P.bpos * 9 : 1)) != hipSuccess ||
-      (e = ALLOC(&yext, (size_t)P.total_ext * 3)) != hipSuccess ||
+  double *yx, *rs, *crhs, *fact;
+  if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
+      (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
       (e = ALLOC(&crhs, (size_t)std::max<int64_t>(1, P.total_coarse) * 3)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->bad, 1)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  d.fval = fv; d.bval = bv; d.bdinv = bd;
-  d.fval32 = fv32; d.bval32 = bv32; d.bdinv32 = bd32;
-  d.yext = yext; d.crhs = crhs; d.fact = fact;
+  ap.yx = yx;
+  ap.rs = rs;
+  ap.crhs = crhs;
+  d.fact = fact;
   if ((e = upload_gather(M, pc->asrc, P.asm_src, s)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   if (o->kind == ASM_KIND_TWO_LEVEL) {
@@ -500,11 +497,15 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
   // keep only what export and error messages need on the host
-  for (RelayoutMap *m : maps) *m = RelayoutMap{};
-  P.frow.clear(); P.brow.clear(); P.fcol.clear(); P.bcol.clear(); P.tdst.clear(); P.tsrc.clear();
-  P.asm_src = GatherList{}; P.l1 = GatherList{}; P.l2 = GatherList{};
-  P.frow.shrink_to_fit(); P.brow.shrink_to_fit(); P.fcol.shrink_to_fit(); P.bcol.shrink_to_fit();
-  P.tdst.shrink_to_fit(); P.tsrc.shrink_to_fit();
+  P.rl = RelayoutMap{};
+  P.rec = std::vector<uint8_t>();
+  P.frow = std::vector<int32_t>();
+  P.fsrc = std::vector<int32_t>();
+  P.tdst = std::vector<int32_t>();
+  P.tsrc = std::vector<int32_t>();
+  P.asm_src = GatherList{};
+  P.l1 = GatherList{};
+  P.l2 = GatherList{};
   st = numeric_setup(pc, s);
   if (st != ASM_OK) return cleanup(st);
   pc->stats.nsub = P.nsub;

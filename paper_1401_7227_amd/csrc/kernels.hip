@@ -275,168 +275,268 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 }
 
 // ---------------------------------------------------------------- ILU(0) apply
-// acc -= B y for a block stored with component stride S (FP64 or FP32).
+// One workgroup per subdomain runs its forward sweep y = L^-1 R_i r and
+// backward sweep x = U^-1 y (D^-1 applied per row).  Every level step is a
+// contiguous record (see RecStep) streamed HBM -> registers -> LDS two steps
+// ahead of its use, so each step waits only on LDS and one barrier; the
+// vector values live in an LDS slot pool, and only values without a slot
+// (long-range dependencies) go through the global work vector.
+constexpr int kRecU4 = kRecBytes / 16;
+constexpr int kStageU4 = kRecU4 / 256;
+static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct Stage {
+  u32x4 v[kStageU4];
+};
+
+// One record into registers: kStageU4 16-byte words per thread, every load
+// issued unconditionally (indices clamped to the record's last word), so
+// the in-order wait counts stay static and loads of later records remain in
+// flight across barriers.
+__device__ __forceinline__ void stage_load(const u32x4 *__restrict__ src, int len, Stage &st) {
+#pragma unroll
+  for (int i = 0; i < kStageU4; ++i) st.v[i] = src[min(i * 256 + (int)threadIdx.x, len - 1)];
+}
+
+__device__ __forceinline__ void stage_store(u32x4 *dst, int len, const Stage &st) {
+#pragma unroll
+  for (int i = 0; i < kStageU4; ++i) {
+    const int q = i * 256 + (int)threadIdx.x;
+    if (q < len) dst[q] = st.v[i];
+  }
+}
+
 template <typename T>
-__device__ inline void sub_block(const T *__restrict__ B, size_t S, double y0, double y1, double y2,
-                                 double &a0, double &a1, double &a2) {
-  a0 -= (double)B[0] * y0 + (double)B[S] * y1 + (double)B[2 * S] * y2;
-  a1 -= (double)B[3 * S] * y0 + (double)B[4 * S] * y1 + (double)B[5 * S] * y2;
-  a2 -= (double)B[6 * S] * y0 + (double)B[7 * S] * y1 + (double)B[8 * S] * y2;
+__device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) b[e] = v[e * S];
 }
 
-// Single-precision variant: the row's arithmetic runs in FP32.
-__device__ inline void sub_block32(const float *__restrict__ B, size_t S, float y0, float y1, float y2,
-                                   float &a0, float &a1, float &a2) {
-  a0 -= B[0] * y0 + B[S] * y1 + B[2 * S] * y2;
-  a1 -= B[3 * S] * y0 + B[4 * S] * y1 + B[5 * S] * y2;
-  a2 -= B[6 * S] * y0 + B[7 * S] * y1 + B[8 * S] * y2;
+// Value of a dependency: an LDS slot (d >= 0) or the global work vector.
+__device__ __forceinline__ void dep_value(int d, const double *vec, const double *__restrict__ yx, double &y0,
+                                          double &y1, double &y2) {
+  if (d >= 0) {
+    y0 = vec[3 * d]; y1 = vec[3 * d + 1]; y2 = vec[3 * d + 2];
+  } else {
+    const size_t g = 3 * (size_t)(-1 - d);
+    y0 = yx[g]; y1 = yx[g + 1]; y2 = yx[g + 2];
+  }
 }
 
-// Rows of one step of a sweep.  FWD: y_u = rhs_u - sum L_uk y_k.
-// !FWD: x_u = D_u^-1 (y_u - sum U_uj x_j), written over y_u.
+// Stores a row result: LDS slot, global work vector, restricted output.
 template <bool FWD>
-__device__ inline void sweep_step(const DevPlan &p, const SubDesc &sd, const Step &st, double *__restrict__ Y,
-                                  const double *__restrict__ r, double sc, double *__restrict__ z,
-                                  int restricted) {
-  const int32_t *rowl = FWD ? p.frow : p.brow;
-  const int32_t *coll = FWD ? p.fcol : p.bcol;
-  const double *val = FWD ? p.fval : p.bval;
-  const float *val32 = FWD ? p.fval32 : p.bval32;
-  const size_t S = (size_t)st.nrows;
-  if (st.mode == 0) {
-    for (int j = threadIdx.x; j < st.nrows; j += blockDim.x) {
-      const int u = rowl[st.pos + j];
+__device__ __forceinline__ void put_row(const int4 m, double a0, double a1, double a2, double *vec,
+                                        double *__restrict__ yx, double *__restrict__ z) {
+  if (m.x >= 0) { vec[3 * m.x] = a0; vec[3 * m.x + 1] = a1; vec[3 * m.x + 2] = a2; }
+  if (FWD || m.w) { const size_t g = 3 * (size_t)m.y; yx[g] = a0; yx[g + 1] = a1; yx[g + 2] = a2; }
+  if (!FWD && m.z >= 0) { const size_t g = 3 * (size_t)m.z; z[g] = a0; z[g + 1] = a1; z[g + 2] = a2; }
+}
+
+// Mode 0: one thread per row, entries in jagged diagonals.  (a0,a1,a2) is
+// the row's right-hand side (forward) or its forward result (backward).
+template <bool FWD, typename T>
+__device__ __forceinline__ void step_rows(const RecStep &st, const char *recp, double *vec, double *__restrict__ yx,
+                                          double *__restrict__ z, double a0, double a1, double a2) {
+  const int j = threadIdx.x;
+  if (j >= st.nrows) return;
+  const int32_t *koff = reinterpret_cast<const int32_t *>(recp);
+  const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
+  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + st.deps);
+  const T *vals = reinterpret_cast<const T *>(recp + st.vals);
+  T t0 = (T)a0, t1 = (T)a1, t2 = (T)a2;
+  int k0 = koff[0];
+  for (int k = 0; k < st.width; ++k) {
+    const int k1 = koff[k + 1];
+    if (j >= k1 - k0) break;
+    const int q = k0 + j;
+    k0 = k1;
+    double y0, y1, y2;
+    dep_value(deps[q], vec, yx, y0, y1, y2);
+    T b[9];
+    block9<T>(vals + q, st.nslots, b);
+    const T u0 = (T)y0, u1 = (T)y1, u2 = (T)y2;
+    t0 -= b[0] * u0 + b[1] * u1 + b[2] * u2;
+    t1 -= b[3] * u0 + b[4] * u1 + b[5] * u2;
+    t2 -= b[6] * u0 + b[7] * u1 + b[8] * u2;
+  }
+  if (!FWD) {
+    T d[9];
+    block9<T>(reinterpret_cast<const T *>(recp + st.dinv) + j, st.nrows, d);
+    const T x0 = d[0] * t0 + d[1] * t1 + d[2] * t2;
+    const T x1 = d[3] * t0 + d[4] * t1 + d[5] * t2;
+    const T x2 = d[6] * t0 + d[7] * t1 + d[8] * t2;
+    t0 = x0; t1 = x1; t2 = x2;
+  }
+  put_row<FWD>(m, (double)t0, (double)t1, (double)t2, vec, yx, z);
+}
+
+// Mode 1: one wavefront per (long) row; lanes stride over its entries.  A
+// piece of a split row starts from / leaves its partial sum in the row's
+// global position.
+template <bool FWD, typename T>
+__device__ __forceinline__ void step_long_rows(const RecStep &st, const char *recp, double *vec,
+                                               double *__restrict__ yx, double *__restrict__ z,
+                                               const double *__restrict__ r, double sc,
+                                               const int32_t *__restrict__ fsrc, const double *__restrict__ crhs) {
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + st.deps);
+  const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + st.rptr);
+  const T *vals = reinterpret_cast<const T *>(recp + st.vals);
+  for (int j = wv; j < st.nrows; j += nw) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int q = rptr[j] + lane; q < rptr[j + 1]; q += kWave) {
+      double y0, y1, y2;
+      dep_value(deps[q], vec, yx, y0, y1, y2);
+      const T *b = vals + 9 * q;
+      s0 += (double)b[0] * y0 + (double)b[1] * y1 + (double)b[2] * y2;
+      s1 += (double)b[3] * y0 + (double)b[4] * y1 + (double)b[5] * y2;
+      s2 += (double)b[6] * y0 + (double)b[7] * y1 + (double)b[8] * y2;
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
       double a0, a1, a2;
-      if (FWD) {
-        const int src = p.rhs_src[sd.ext_off + u];
+      if (st.piece == kPieceMiddle || st.piece == kPieceLast || !FWD) {
+        const size_t g = 3 * (size_t)m.y;  // partial sum, or the forward result
+        a0 = yx[g]; a1 = yx[g + 1]; a2 = yx[g + 2];
+      } else {
+        const int src = fsrc[st.pos + j];
         if (src >= 0) {
           a0 = sc * r[3 * (size_t)src]; a1 = sc * r[3 * (size_t)src + 1]; a2 = sc * r[3 * (size_t)src + 2];
         } else {
-          const double *q = p.crhs + 3 * (size_t)(-src - 1);
-          a0 = q[0]; a1 = q[1]; a2 = q[2];
+          const double *c = crhs + 3 * (size_t)(-src - 1);
+          a0 = c[0]; a1 = c[1]; a2 = c[2];
         }
-      } else {
-        a0 = Y[3 * u]; a1 = Y[3 * u + 1]; a2 = Y[3 * u + 2];
       }
-      if (st.fp32) {
-        float f0 = (float)a0, f1 = (float)a1, f2 = (float)a2;
-        for (int k = 0; k < st.width; ++k) {
-          const size_t slot = (size_t)st.eoff + (size_t)k * S + j;
-          const int c = coll[slot];
-          if (c < 0) continue;
-          sub_block32(val32 + (size_t)st.eoff * 9 + (size_t)k * 9 * S + j, S, (float)Y[3 * c],
-                      (float)Y[3 * c + 1], (float)Y[3 * c + 2], f0, f1, f2);
-        }
-        if (!FWD) {
-          const float *D = p.bdinv32 + (size_t)st.pos * 9 + j;
-          const float x0 = D[0] * f0 + D[S] * f1 + D[2 * S] * f2;
-          const float x1 = D[3 * S] * f0 + D[4 * S] * f1 + D[5 * S] * f2;
-          const float x2 = D[6 * S] * f0 + D[7 * S] * f1 + D[8 * S] * f2;
-          f0 = x0; f1 = x1; f2 = x2;
-        }
-        a0 = f0; a1 = f1; a2 = f2;
+      a0 -= s0; a1 -= s1; a2 -= s2;
+      if (st.piece == kPieceFirst || st.piece == kPieceMiddle) {
+        const size_t g = 3 * (size_t)m.y;
+        yx[g] = a0; yx[g + 1] = a1; yx[g + 2] = a2;
       } else {
-        for (int k = 0; k < st.width; ++k) {
-          const size_t slot = (size_t)st.eoff + (size_t)k * S + j;
-          const int c = coll[slot];
-          if (c < 0) continue;
-          sub_block<double>(val + (size_t)st.eoff * 9 + (size_t)k * 9 * S + j, S, Y[3 * c], Y[3 * c + 1],
-                            Y[3 * c + 2], a0, a1, a2);
-        }
         if (!FWD) {
-          const double *D = p.bdinv + (size_t)st.pos * 9 + j;
-          const double x0 = D[0] * a0 + D[S] * a1 + D[2 * S] * a2;
-          const double x1 = D[3 * S] * a0 + D[4 * S] * a1 + D[5 * S] * a2;
-          const double x2 = D[6 * S] * a0 + D[7 * S] * a1 + D[8 * S] * a2;
+          const T *dv = reinterpret_cast<const T *>(recp + st.dinv) + j;
+          const int S = st.nrows;
+          const double x0 = (double)dv[0] * a0 + (double)dv[S] * a1 + (double)dv[2 * S] * a2;
+          const double x1 = (double)dv[3 * S] * a0 + (double)dv[4 * S] * a1 + (double)dv[5 * S] * a2;
+          const double x2 = (double)dv[6 * S] * a0 + (double)dv[7 * S] * a1 + (double)dv[8 * S] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
-      }
-      Y[3 * u] = a0; Y[3 * u + 1] = a1; Y[3 * u + 2] = a2;
-      if (!FWD && restricted) {
-        const int cell = p.out_cell[sd.ext_off + u];
-        if (cell >= 0) {
-          z[3 * (size_t)cell] = a0; z[3 * (size_t)cell + 1] = a1; z[3 * (size_t)cell + 2] = a2;
-        }
-      }
-    }
-  } else {
-    // one wavefront per (long) row; lanes stride over its entries
-    const int32_t *rp = (FWD ? p.frptr : p.brptr) + st.rptr;
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int j = wv; j < st.nrows; j += nw) {
-      const int u = rowl[st.pos + j];
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (int t = rp[j] + lane; t < rp[j + 1]; t += kWave) {
-        const size_t slot = (size_t)st.eoff + t;
-        const int c = coll[slot];
-        if (st.fp32) sub_block<float>(val32 + slot * 9, 1, Y[3 * c], Y[3 * c + 1], Y[3 * c + 2], s0, s1, s2);
-        else sub_block<double>(val + slot * 9, 1, Y[3 * c], Y[3 * c + 1], Y[3 * c + 2], s0, s1, s2);
-      }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (lane == 0) {
-        double a0, a1, a2;
-        if (FWD) {
-          const int src = p.rhs_src[sd.ext_off + u];
-          if (src >= 0) {
-            a0 = sc * r[3 * (size_t)src]; a1 = sc * r[3 * (size_t)src + 1]; a2 = sc * r[3 * (size_t)src + 2];
-          } else {
-            const double *q = p.crhs + 3 * (size_t)(-src - 1);
-            a0 = q[0]; a1 = q[1]; a2 = q[2];
-          }
-        } else {
-          a0 = Y[3 * u]; a1 = Y[3 * u + 1]; a2 = Y[3 * u + 2];
-        }
-        a0 += s0; a1 += s1; a2 += s2;
-        if (!FWD) {
-          double x0, x1, x2;
-          if (st.fp32) {
-            const float *D = p.bdinv32 + (size_t)st.pos * 9 + j;
-            x0 = D[0] * a0 + D[S] * a1 + D[2 * S] * a2;
-            x1 = D[3 * S] * a0 + D[4 * S] * a1 + D[5 * S] * a2;
-            x2 = D[6 * S] * a0 + D[7 * S] * a1 + D[8 * S] * a2;
-          } else {
-            const double *D = p.bdinv + (size_t)st.pos * 9 + j;
-            x0 = D[0] * a0 + D[S] * a1 + D[2 * S] * a2;
-            x1 = D[3 * S] * a0 + D[4 * S] * a1 + D[5 * S] * a2;
-            x2 = D[6 * S] * a0 + D[7 * S] * a1 + D[8 * S] * a2;
-          }
-          a0 = x0; a1 = x1; a2 = x2;
-        }
-        Y[3 * u] = a0; Y[3 * u + 1] = a1; Y[3 * u + 2] = a2;
-        if (!FWD && restricted) {
-          const int cell = p.out_cell[sd.ext_off + u];
-          if (cell >= 0) {
-            z[3 * (size_t)cell] = a0; z[3 * (size_t)cell + 1] = a1; z[3 * (size_t)cell + 2] = a2;
-          }
-        }
+        put_row<FWD>(m, a0, a1, a2, vec, yx, z);
       }
     }
   }
 }
 
-// One workgroup per subdomain: gather (R_i), forward sweep, backward sweep,
-// restricted write-back, all inside the workgroup with barriers between
-// level steps.
-__global__ __launch_bounds__(256) void ilu_apply_kernel(DevPlan p, const double *__restrict__ r,
-                                                        const double *__restrict__ scale,
-                                                        double *__restrict__ z, int restricted) {
+// Input of row j of a mode-0 step: its right-hand side (forward, from the
+// gathered stream) or its forward result (backward).  Loaded three steps
+// ahead; rows past the step clamp to its last row.
+__device__ __forceinline__ void fetch_in(const RecStep &st, const double *__restrict__ src, double &g0, double &g1,
+                                         double &g2) {
+  const size_t g = 3 * (size_t)(st.pos + min((int)threadIdx.x, st.nrows - 1));
+  g0 = src[g]; g1 = src[g + 1]; g2 = src[g + 2];
+}
+
+struct SweepLds {
+  u32x4 buf[3][kRecU4];
+  double vec[3 * kVecSlots];
+};
+
+struct In3 {
+  double a, b, c;
+};
+
+// One pipeline iteration for step s.  Register stage `hold` has record s+1
+// (loaded two iterations ago) and `load` receives record s+3; input set `g`
+// has step s's inputs and, after the compute, receives step s+3's.  Loads
+// past the last step re-read the last step so every iteration issues the
+// same loads.
+template <bool FWD>
+__device__ __forceinline__ void sweep_iter(int s, int S, const RecStep *__restrict__ steps,
+                                           const u32x4 *__restrict__ rec, SweepLds &L, Stage &hold, Stage &load,
+                                           In3 &g, const double *__restrict__ in, const double *__restrict__ r,
+                                           double sc, const int32_t *__restrict__ fsrc,
+                                           const double *__restrict__ crhs, double *__restrict__ yx,
+                                           double *__restrict__ z) {
+  const RecStep cur = steps[s];
+  const RecStep n3 = steps[min(s + 3, S - 1)];
+  stage_load(rec + n3.rec, n3.len, load);
+  const char *recp = reinterpret_cast<const char *>(L.buf[s % 3]);
+  if (cur.mode == 0) {
+    if (cur.fp32) step_rows<FWD, float>(cur, recp, L.vec, yx, z, g.a, g.b, g.c);
+    else step_rows<FWD, double>(cur, recp, L.vec, yx, z, g.a, g.b, g.c);
+  } else {
+    if (cur.fp32) step_long_rows<FWD, float>(cur, recp, L.vec, yx, z, r, sc, fsrc, crhs);
+    else step_long_rows<FWD, double>(cur, recp, L.vec, yx, z, r, sc, fsrc, crhs);
+  }
+  fetch_in(n3, in, g.a, g.b, g.c);
+  if (s + 1 < S) stage_store(L.buf[(s + 1) % 3], steps[s + 1].len, hold);
+  __syncthreads();
+}
+
+template <bool FWD>
+__device__ __forceinline__ void sweep(const RecStep *__restrict__ steps, int S, const u32x4 *__restrict__ rec,
+                                      SweepLds &L, const double *__restrict__ in, const double *__restrict__ r,
+                                      double sc, const int32_t *__restrict__ fsrc, const double *__restrict__ crhs,
+                                      double *__restrict__ yx, double *__restrict__ z) {
+  if (S == 0) return;
+  Stage A, B, C;
+  In3 g0, g1, g2;
+  // prologue: record 0 into LDS; records 1 and 2 and the inputs of steps
+  // 0..2 in flight
+  {
+    const RecStep s0 = steps[0];
+    stage_load(rec + s0.rec, s0.len, A);
+    fetch_in(s0, in, g0.a, g0.b, g0.c);
+    const RecStep s1 = steps[min(1, S - 1)];
+    stage_load(rec + s1.rec, s1.len, B);
+    fetch_in(s1, in, g1.a, g1.b, g1.c);
+    const RecStep s2 = steps[min(2, S - 1)];
+    stage_load(rec + s2.rec, s2.len, C);
+    fetch_in(s2, in, g2.a, g2.b, g2.c);
+    stage_store(L.buf[0], s0.len, A);
+  }
+  __syncthreads();
+  // stage k%3 and input set k%3 hold record / inputs of step k
+  for (int s = 0; s < S; s += 3) {
+    sweep_iter<FWD>(s, S, steps, rec, L, B, A, g0, in, r, sc, fsrc, crhs, yx, z);
+    if (s + 1 < S) sweep_iter<FWD>(s + 1, S, steps, rec, L, C, B, g1, in, r, sc, fsrc, crhs, yx, z);
+    if (s + 2 < S) sweep_iter<FWD>(s + 2, S, steps, rec, L, A, C, g2, in, r, sc, fsrc, crhs, yx, z);
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void ilu_apply_kernel(ApplyPlan p, const double *__restrict__ r,
+                                                           const double *__restrict__ scale, double *__restrict__ z) {
+  __shared__ SweepLds L;
   const SubDesc sd = p.sub[blockIdx.x];
-  double *Y = p.yext + 3 * (size_t)sd.ext_off;
   const double sc = scale ? *scale : 1.0;
-  for (int si = sd.fstep0; si < sd.fstep1; ++si) {
-    const Step st = p.fstep[si];
-    sweep_step<true>(p, sd, st, Y, r, sc, z, restricted);
-    __threadfence_block();
-    __syncthreads();
+  const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
+  sweep<true>(p.fstep + sd.rf0, sd.rf1 - sd.rf0, rec, L, p.rs, r, sc, p.fsrc, p.crhs, p.yx, z);
+  __syncthreads();
+  sweep<false>(p.bstep + sd.rb0, sd.rb1 - sd.rb0, rec, L, p.yx, r, sc, p.fsrc, p.crhs, p.yx, z);
+}
+
+// Forward right-hand sides in sweep order: the restriction R_i r of every
+// subdomain (fine rows gather r, coarse rows take the lumped sums).
+__global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t *__restrict__ fsrc,
+                                                         const double *__restrict__ r,
+                                                         const double *__restrict__ scale,
+                                                         const double *__restrict__ crhs, double *__restrict__ rs) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= npos) return;
+  const int src = fsrc[q];
+  double a0, a1, a2;
+  if (src >= 0) {
+    const double sc = scale ? *scale : 1.0;
+    a0 = sc * r[3 * (size_t)src]; a1 = sc * r[3 * (size_t)src + 1]; a2 = sc * r[3 * (size_t)src + 2];
+  } else {
+    const double *c = crhs + 3 * (size_t)(-src - 1);
+    a0 = c[0]; a1 = c[1]; a2 = c[2];
   }
-  for (int si = sd.bstep0; si < sd.bstep1; ++si) {
-    const Step st = p.bstep[si];
-    sweep_step<false>(p, sd, st, Y, r, sc, z, restricted);
-    __threadfence_block();
-    __syncthreads();
-  }
+  rs[3 * (size_t)q] = a0; rs[3 * (size_t)q + 1] = a1; rs[3 * (size_t)q + 2] = a2;
 }
 
 __global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int32_t *__restrict__ cptr,
@@ -625,10 +725,15 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base, 
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(const DevPlan &p, const double *r, const double *scale, double *z, int restricted,
-                            bool, hipStream_t s) {
+hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s) {
+  if (npos == 0) return hipSuccess;
+  gather_rhs_kernel<<<blocks_for(npos, 256), 256, 0, s>>>(npos, p.fsrc, r, scale, p.crhs, p.rs);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s) {
   if (p.nsub == 0) return hipSuccess;
-  ilu_apply_kernel<<<p.nsub, 256, 0, s>>>(p, r, scale, z, restricted);
+  ilu_apply_kernel<<<p.nsub, 256, 0, s>>>(p, r, scale, z);
   return hipGetLastError();
 }
 

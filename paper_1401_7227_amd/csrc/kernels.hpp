@@ -41,10 +41,12 @@ hipError_t launch_ilu_factor(const DevPlan &p, unsigned long long *bad, hipStrea
 hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base,
                            const int32_t *stride, const uint8_t *to32, const double *fact,
                            double *out64, float *out32, hipStream_t s);
-// z = B^-1 (scale * r) over all subdomains; restricted=1 writes owned rows
-// straight into z, restricted=0 leaves the local solutions in yext.
-hipError_t launch_ilu_apply(const DevPlan &p, const double *r, const double *scale, double *z,
-                            int restricted, bool any_fp32, hipStream_t s);
+// z = B^-1 (scale * r) over all subdomains: owned rows of a restricted
+// combine go straight into z; values needed by the additive combine are in
+// the plan's global work vector.
+// Forward right-hand sides of all subdomains in sweep order (p.rs).
+hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s);
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s);
 hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx,
                                    const double *yext, double *z, hipStream_t s);
 

@@ -9,51 +9,86 @@
 
 namespace asmx {
 
-// Rows of one level-schedule step.  All rows of a step share one level, so
-// they can be processed concurrently; consecutive steps are separated by a
-// workgroup barrier.
-//   mode 0: one thread per row; entries stored ELL-style, slot (k, j) of
-//           the step's rows in structure-of-arrays order (coalesced).
-//   mode 1: one 64-wide wavefront per row; entries of each row contiguous,
-//           located by a per-step relative row pointer.
+// Rows of one factorisation step: one level of the forward schedule (or a
+// chunk of it); consecutive steps are separated by a workgroup barrier.
 struct Step {
   int32_t pos;    // first position in the step row list
   int32_t nrows;  // rows in the step
-  int32_t width;  // mode 0: max entries per row
-  int32_t eoff;   // first block slot of the step's entries
-  int32_t mode;   // 0 or 1
-  int32_t rptr;   // mode 1: offset of the relative row pointer (nrows+1)
-  int32_t fp32;   // 1 if the step's blocks are held in single precision
-  int32_t pad;
+};
+
+// Apply-sweep layout: every level step of a sweep is one contiguous record
+// in a global buffer, streamed into LDS ahead of its use.
+#ifndef ASM_REC_BYTES
+#define ASM_REC_BYTES 32768
+#endif
+constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (3 buffers)
+#ifndef ASM_VEC_SLOTS
+#define ASM_VEC_SLOTS 2560
+#endif
+constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
+constexpr int kMaxJdsWidth = 8;    // mode-0 rows have at most this many entries
+constexpr int kMaxStepRows = 256;  // rows per step (one thread per row)
+
+// One step of a sweep.  Record sections (byte offsets from the record
+// start, each 16-byte aligned):
+//   head  int koff[kMaxJdsWidth + 1] (mode 0: first entry of each jagged
+//         diagonal; koff[width] = nslots), padded to kRecHead bytes.
+//   meta  int4 per row.  Forward: {LDS slot or -1, spill position, -, -};
+//         backward: {LDS slot or -1, own position, output cell or -1,
+//         1 if the value must also be stored to the global vector}.
+//   deps  int per entry: >= 0 an LDS slot, < 0 the global position -1-d.
+//   rptr  mode 1: nrows+1 relative entry offsets.
+//   vals  mode 0: jagged-diagonal SoA, component e of entry q at
+//         [e*nslots + q], entry q = koff[k] + j for row j's k-th entry
+//         (rows sorted by entry count, descending); mode 1: 9 per entry.
+//   dinv  backward: component e of row j at [e*nrows + j].
+// A mode-1 row whose record would not fit one LDS buffer is split into
+// pieces in consecutive one-row steps; pieces carry the partial sum through
+// the row's global position.
+constexpr int kRecHead = 48;
+enum { kPieceWhole = 0, kPieceFirst = 1, kPieceMiddle = 2, kPieceLast = 3 };
+
+struct RecStep {
+  int32_t rec;     // record start, in 16-byte units
+  int32_t len;     // record length, in 16-byte units
+  int32_t pos;     // position of the step's first row (forward / backward order)
+  int32_t nrows;
+  int32_t nslots;  // dependency entries
+  int32_t mode;    // 0: thread per row (jagged diagonals); 1: wavefront per row
+  int32_t fp32;    // blocks stored in single precision
+  int32_t piece;   // mode 1: kPiece* of a split row
+  int32_t deps, vals, dinv, rptr;
+  int32_t width;
+  int32_t pad[3];
+};
+
+struct ApplyPlan {
+  int32_t nsub;
+  const struct SubDesc *sub;
+  const RecStep *fstep, *bstep;
+  const void *rec;              // all records (16-byte aligned)
+  const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
+  double *rs;                   // 3 doubles per forward position: gathered rhs
+  double *yx;                   // 3 doubles per backward position
+  const double *crhs;           // 3 doubles per coarse row
 };
 
 struct SubDesc {
-  int32_t ext_off;    // first extended row (global)
-  int32_t n;          // rows of A_i
-  int32_t nfine;      // fine rows of A_i
-  int32_t fstep0, fstep1;  // forward steps [fstep0, fstep1)
-  int32_t bstep0, bstep1;  // backward steps
-  int32_t pad;
+  int32_t ext_off;         // first extended row (global)
+  int32_t n;               // rows of A_i
+  int32_t nfine;           // fine rows of A_i
+  int32_t fstep0, fstep1;  // factorisation level steps [fstep0, fstep1)
+  int32_t rf0, rf1;        // forward sweep records
+  int32_t rb0, rb1;        // backward sweep records
+  int32_t pad[3];
 };
 
-// Pointers handed to the apply / factor kernels.
+// Pointers handed to the factorisation kernel.
 struct DevPlan {
   int32_t nsub;
   const SubDesc *sub;
-  const Step *fstep, *bstep;
-  const int32_t *frow, *brow;    // local row of each step position
-  const int32_t *fcol, *bcol;    // local column of each block slot, -1 pad
-  const int32_t *frptr, *brptr;  // mode-1 relative row pointers
-  const double *fval, *bval;     // block values (FP64 steps)
-  const float *fval32, *bval32;  // block values (FP32 steps)
-  const double *bdinv;           // D^-1 per backward position, SoA per step
-  const float *bdinv32;
-  const int32_t *rhs_src;        // per ext row: cell >= 0, or -(1+coarse row)
-  const int32_t *out_cell;       // per ext row: cell written by a restricted
-                                 // combine, -1 if none
-  double *yext;                  // 3 doubles per ext row (work vector)
-  const double *crhs;            // 3 doubles per coarse row (lumped rhs)
-  // factorisation
+  const Step *fstep;             // factorisation level steps (pos, nrows)
+  const int32_t *frow;           // local row of each step position
   const int32_t *arp;            // per ext row: first CSR entry (global)
   const int32_t *aci;            // per entry: local column
   const int32_t *adiag;          // per ext row: CSR entry of the diagonal

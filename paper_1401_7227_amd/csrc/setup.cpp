@@ -32,7 +32,6 @@
 namespace asmx {
 namespace {
 
-constexpr int kMode0MaxEntries = 8;  // rows with more entries use a wave per row
 
 struct Split {
   std::vector<int32_t> part;   // part of each column index
@@ -115,13 +114,17 @@ struct SubLocal {
   std::vector<int32_t> diag;
   std::vector<int32_t> tptr, tdst, tsrc;
   std::vector<int32_t> cptr, cidx;  // coarse rows -> near/far atom sums
-  // level steps (local positions / slots)
-  std::vector<Step> fst, bst;
-  std::vector<int32_t> frow, brow, fcol, bcol, frptr, brptr;
-  std::vector<int32_t> fsrc, fbase, fstride, bsrc, bbase, bstride, dsrc, dbase, dstride;
-  std::vector<uint8_t> f32, b32, d32;
-  int32_t fslots = 0, bslots = 0, bpos = 0, fpos = 0;
+  // factorisation steps (forward chunks) and sweep records, local offsets
+  std::vector<Step> fst;
+  std::vector<int32_t> frow;             // rows in forward order
+  std::vector<int32_t> bpos;             // backward position of each row
+  std::vector<RecStep> rf, rb;           // rec/pos fields local (rec in bytes)
+  std::vector<uint8_t> rec;
+  std::vector<int32_t> fsrc;             // per forward position (coarse: local index)
+  std::vector<int32_t> rl_src, rl_base, rl_stride;  // base in elements, local
+  std::vector<uint8_t> rl_to32;
   int32_t levels = 0;
+  int64_t spilled = 0;
   int32_t bad_row = -1;  // missing diagonal
 };
 
@@ -181,6 +184,255 @@ void triples_to_csr(std::vector<std::array<int32_t, 3>> &t, int32_t nrows, std::
     g.ptr.back()++;
   }
   for (int r = 0; r < nrows; ++r) ptr[r + 1] += ptr[r];
+}
+
+inline int32_t align16(int64_t b) { return (int32_t)((b + 15) & ~int64_t(15)); }
+
+// Record section offsets for a step of nrows rows and nslots entries.
+struct RecLayout {
+  int32_t deps, rptr, vals, dinv, total;
+};
+
+RecLayout rec_layout(int nrows, int nslots, int mode, bool fwd, bool f32) {
+  const int sz = f32 ? 4 : 8;
+  RecLayout L{};
+  L.deps = kRecHead + align16((int64_t)16 * nrows);
+  int32_t at = L.deps + align16((int64_t)4 * nslots);
+  L.rptr = at;
+  if (mode == 1) at += align16((int64_t)4 * (nrows + 1));
+  L.vals = at;
+  at += align16((int64_t)9 * nslots * sz);
+  L.dinv = at;
+  if (!fwd) at += align16((int64_t)9 * nrows * sz);
+  L.total = at;
+  return L;
+}
+
+// Level steps of both sweeps of one subdomain: rows of a level grouped by
+// mode (short rows: one thread each, jagged diagonals; long rows: one
+// wavefront each) and, in FP32 mode, by precision class; chunked so that a
+// step has at most kMaxStepRows rows and its record fits one LDS buffer.
+// LDS vector slots are assigned by a linear scan over live ranges; rows
+// that get no slot pass their values through the global vector.
+void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const std::vector<int32_t> &lb, int maxb,
+                  bool fp32, bool restricted, const std::vector<int32_t> &owner, int sub) {
+  struct Chunk {
+    std::vector<int32_t> rows;
+    int mode, f32;
+    int piece = kPieceWhole;  // split row: which piece
+    int e0 = 0, e1 = 0;       // split row: entry range (of the row's entries)
+  };
+  auto count = [&](int i, bool fwd) {
+    int c = 0;
+    for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) c += fwd ? (S.ci[e] < i) : (S.ci[e] > i);
+    return c;
+  };
+  auto make_chunks = [&](bool fwd, const std::vector<int32_t> &lev, int maxl) {
+    std::vector<Chunk> out;
+    std::vector<std::vector<int32_t>> bylev(maxl + 1);
+    for (int i = 0; i < S.n; ++i) bylev[lev[i]].push_back(i);
+    for (int l = 0; l <= maxl; ++l)
+      for (int cls = 0; cls < (fp32 ? 2 : 1); ++cls)
+        for (int mode = 0; mode < 2; ++mode) {
+          std::vector<int32_t> rows;
+          for (int i : bylev[l]) {
+            if (fp32 && (i >= S.nfine) != (cls == 1)) continue;
+            if ((count(i, fwd) > kMaxJdsWidth) != (mode == 1)) continue;
+            rows.push_back(i);
+          }
+          if (rows.empty()) continue;
+          if (mode == 0)
+            std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return count(a, fwd) > count(b, fwd); });
+          const bool f32 = fp32 && cls == 0;
+          Chunk cur{{}, mode, f32 ? 1 : 0};
+          int slots = 0;
+          for (int i : rows) {
+            const int c = count(i, fwd);
+            const int nr = (int)cur.rows.size() + 1;
+            const bool fits = nr <= kMaxStepRows && rec_layout(nr, slots + c, mode, fwd, f32).total <= kRecBytes;
+            if (!fits && !cur.rows.empty()) {
+              out.push_back(cur);
+              cur.rows.clear();
+              slots = 0;
+            }
+            if (rec_layout(1, c, mode, fwd, f32).total > kRecBytes) {
+              // a row too long for one buffer: consecutive one-row pieces
+              int per = c;
+              while (rec_layout(1, per, mode, fwd, f32).total > kRecBytes) per = (per + 1) / 2;
+              const int np = (c + per - 1) / per;
+              for (int k = 0; k < np; ++k) {
+                Chunk pc{{i}, mode, f32 ? 1 : 0};
+                pc.piece = (k == 0) ? kPieceFirst : (k == np - 1 ? kPieceLast : kPieceMiddle);
+                pc.e0 = k * per;
+                pc.e1 = std::min(c, (k + 1) * per);
+                out.push_back(pc);
+              }
+              continue;
+            }
+            cur.rows.push_back(i);
+            slots += c;
+          }
+          if (!cur.rows.empty()) out.push_back(cur);
+        }
+    return out;
+  };
+  const std::vector<Chunk> fch = make_chunks(true, lf, maxf), bch = make_chunks(false, lb, maxb);
+  // positions
+  std::vector<int32_t> fpos(S.n), bpos(S.n);
+  int p = 0;
+  for (const Chunk &c : fch) {
+    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
+    S.fst.push_back(Step{p, (int32_t)c.rows.size()});
+    for (int i : c.rows) {
+      fpos[i] = p++;
+      S.frow.push_back(i);
+      S.fsrc.push_back(i < S.nfine ? S.cells[i] : -(1 + (i - S.nfine)));
+    }
+  }
+  p = 0;
+  for (const Chunk &c : bch) {
+    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
+    for (int i : c.rows) bpos[i] = p++;
+  }
+  S.bpos = bpos;
+  // LDS slots by linear scan over steps
+  auto allocate = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<int32_t> &slot, std::vector<int32_t> &last) {
+    std::vector<int32_t> stp(S.n);
+    for (size_t k = 0; k < ch.size(); ++k)
+      for (int i : ch[k].rows) stp[i] = (int32_t)k;
+    last.assign(S.n, -1);
+    for (int i = 0; i < S.n; ++i)
+      for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+        const int c = S.ci[e];
+        if (fwd ? c < i : c > i) last[c] = std::max(last[c], stp[i]);
+      }
+    slot.assign(S.n, -1);
+    std::vector<std::pair<int32_t, int32_t>> heap;  // (last use, slot), min-heap
+    std::vector<int32_t> freel;
+    for (int q = kVecSlots - 1; q >= 0; --q) freel.push_back(q);
+    auto cmp = [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) { return a > b; };
+    for (size_t k = 0; k < ch.size(); ++k) {
+      while (!heap.empty() && heap.front().first < (int32_t)k) {
+        freel.push_back(heap.front().second);
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        heap.pop_back();
+      }
+      for (int i : ch[k].rows) {
+        if (last[i] <= (int32_t)k) continue;
+        if (freel.empty()) {
+          ++S.spilled;
+          continue;
+        }
+        slot[i] = freel.back();
+        freel.pop_back();
+        heap.push_back({last[i], slot[i]});
+        std::push_heap(heap.begin(), heap.end(), cmp);
+      }
+    }
+  };
+  std::vector<int32_t> fslot, flast, bslot, blast;
+  allocate(fch, true, fslot, flast);
+  allocate(bch, false, bslot, blast);
+  // records
+  auto emit = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<RecStep> &out) {
+    const std::vector<int32_t> &slot = fwd ? fslot : bslot;
+    const std::vector<int32_t> &last = fwd ? flast : blast;
+    for (const Chunk &c : ch) {
+      const int nr = (int)c.rows.size();
+      std::vector<std::vector<int32_t>> ent(nr);
+      int nslots = 0;
+      for (int j = 0; j < nr; ++j) {
+        const int i = c.rows[j];
+        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
+          if (fwd ? S.ci[e] < i : S.ci[e] > i) ent[j].push_back(e);
+        if (c.piece != kPieceWhole)
+          ent[j] = std::vector<int32_t>(ent[j].begin() + c.e0, ent[j].begin() + c.e1);
+        nslots += (int)ent[j].size();
+      }
+      const bool f32 = c.f32 != 0;
+      const int sz = f32 ? 4 : 8;
+      const RecLayout L = rec_layout(nr, nslots, c.mode, fwd, f32);
+      RecStep st{};
+      st.rec = (int32_t)S.rec.size();
+      st.len = L.total / 16;
+      st.pos = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
+      st.nrows = nr;
+      st.nslots = nslots;
+      st.mode = c.mode;
+      st.fp32 = c.f32;
+      st.piece = c.piece;
+      st.deps = L.deps;
+      st.vals = L.vals;
+      st.dinv = L.dinv;
+      st.rptr = L.rptr;
+      S.rec.resize(S.rec.size() + L.total, 0);
+      uint8_t *base = S.rec.data() + st.rec;
+      int32_t *head = reinterpret_cast<int32_t *>(base);
+      int32_t *meta = reinterpret_cast<int32_t *>(base + kRecHead);
+      int32_t *deps = reinterpret_cast<int32_t *>(base + L.deps);
+      auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : -1 - bpos[col]; };
+      for (int j = 0; j < nr; ++j) {
+        const int i = c.rows[j];
+        meta[4 * j] = slot[i];
+        meta[4 * j + 1] = bpos[i];
+        if (fwd) {
+          meta[4 * j + 2] = 0;
+          meta[4 * j + 3] = 0;
+        } else {
+          const bool fine = i < S.nfine;
+          meta[4 * j + 2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
+          meta[4 * j + 3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
+        }
+      }
+      const int64_t vbase = (st.rec + L.vals) / sz;  // element index of the vals section
+      if (c.mode == 0) {
+        int width = 0;
+        for (int j = 0; j < nr; ++j) width = std::max(width, (int)ent[j].size());
+        st.width = width;
+        int q = 0;
+        for (int k = 0; k < width; ++k) {
+          head[k] = q;
+          for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) {
+            const int e = ent[j][k];
+            deps[q] = dep_of(S.ci[e]);
+            S.rl_src.push_back(e);
+            S.rl_base.push_back((int32_t)(vbase + q));
+            S.rl_stride.push_back(nslots);
+            S.rl_to32.push_back((uint8_t)f32);
+            ++q;
+          }
+        }
+        head[width] = q;
+      } else {
+        int32_t *rptr = reinterpret_cast<int32_t *>(base + L.rptr);
+        int q = 0;
+        for (int j = 0; j < nr; ++j) {
+          rptr[j] = q;
+          for (int e : ent[j]) {
+            deps[q] = dep_of(S.ci[e]);
+            S.rl_src.push_back(e);
+            S.rl_base.push_back((int32_t)(vbase + 9 * q));
+            S.rl_stride.push_back(1);
+            S.rl_to32.push_back((uint8_t)f32);
+            ++q;
+          }
+        }
+        rptr[nr] = q;
+      }
+      if (!fwd) {
+        const int64_t dbase = (st.rec + L.dinv) / sz;
+        for (int j = 0; j < nr; ++j) {
+          S.rl_src.push_back(S.diag[c.rows[j]]);
+          S.rl_base.push_back((int32_t)(dbase + j));
+          S.rl_stride.push_back(nr);
+          S.rl_to32.push_back((uint8_t)f32);
+        }
+      }
+      out.push_back(st);
+    }
+  };
+  emit(fch, true, S.rf);
+  emit(bch, false, S.rb);
 }
 
 }  // namespace
@@ -582,106 +834,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         maxb = std::max(maxb, lb[i]);
       }
       S.levels = std::max(maxf, maxb) + 1;
-      // steps: rows of one level, split by class (fine/coarse) and mode
-      auto make_steps = [&](bool fwd, const std::vector<int32_t> &lev, int maxl, std::vector<Step> &steps,
-                            std::vector<int32_t> &rows, std::vector<int32_t> &cols, std::vector<int32_t> &rptr,
-                            std::vector<int32_t> &src, std::vector<int32_t> &base, std::vector<int32_t> &stride,
-                            std::vector<uint8_t> &to32, int32_t &slots) {
-        std::vector<std::vector<int32_t>> bylev(maxl + 1);
-        for (int i = 0; i < S.n; ++i) bylev[lev[i]].push_back(i);
-        auto count = [&](int i) {
-          int c = 0;
-          for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) c += fwd ? (S.ci[e] < i) : (S.ci[e] > i);
-          return c;
-        };
-        for (int l = 0; l <= maxl; ++l) {
-          for (int cls = 0; cls < 2; ++cls)
-            for (int mode = 0; mode < 2; ++mode) {
-              std::vector<int32_t> rs;
-              for (int i : bylev[l]) {
-                if ((i >= S.nfine) != (cls == 1)) continue;
-                if ((count(i) > kMode0MaxEntries) != (mode == 1)) continue;
-                rs.push_back(i);
-              }
-              if (rs.empty()) continue;
-              Step st{};
-              st.pos = (int32_t)rows.size();
-              st.nrows = (int32_t)rs.size();
-              st.eoff = slots;
-              st.mode = mode;
-              st.fp32 = (fp32 && cls == 0) ? 1 : 0;
-              rows.insert(rows.end(), rs.begin(), rs.end());
-              const int nr = st.nrows;
-              if (mode == 0) {
-                int w = 0;
-                for (int i : rs) w = std::max(w, count(i));
-                st.width = w;
-                const size_t c0 = cols.size();
-                cols.resize(c0 + (size_t)w * nr, -1);
-                for (int j = 0; j < nr; ++j) {
-                  const int i = rs[j];
-                  int k = 0;
-                  for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
-                    const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
-                    if (!take) continue;
-                    cols[c0 + (size_t)k * nr + j] = S.ci[e];
-                    ++k;
-                  }
-                }
-                for (int k = 0; k < w; ++k)
-                  for (int j = 0; j < nr; ++j) {
-                    // source entry of slot (k, j)
-                    const int i = rs[j];
-                    int kk = 0, ent = -1;
-                    for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
-                      const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
-                      if (!take) continue;
-                      if (kk == k) { ent = e; break; }
-                      ++kk;
-                    }
-                    src.push_back(ent);
-                    base.push_back(9 * slots + k * 9 * nr + j);
-                    stride.push_back(nr);
-                    to32.push_back((uint8_t)st.fp32);
-                  }
-                slots += w * nr;
-              } else {
-                st.width = 0;
-                st.rptr = (int32_t)rptr.size();
-                rptr.push_back(0);
-                int t = 0;
-                for (int j = 0; j < nr; ++j) {
-                  const int i = rs[j];
-                  for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) {
-                    const bool take = fwd ? (S.ci[e] < i) : (S.ci[e] > i);
-                    if (!take) continue;
-                    cols.push_back(S.ci[e]);
-                    src.push_back(e);
-                    base.push_back(9 * (slots + t));
-                    stride.push_back(1);
-                    to32.push_back((uint8_t)st.fp32);
-                    ++t;
-                  }
-                  rptr.push_back(t);
-                }
-                slots += t;
-              }
-              steps.push_back(st);
-            }
-        }
-      };
-      make_steps(true, lf, maxf, S.fst, S.frow, S.fcol, S.frptr, S.fsrc, S.fbase, S.fstride, S.f32, S.fslots);
-      make_steps(false, lb, maxb, S.bst, S.brow, S.bcol, S.brptr, S.bsrc, S.bbase, S.bstride, S.b32, S.bslots);
-      S.fpos = (int32_t)S.frow.size();
-      S.bpos = (int32_t)S.brow.size();
-      // pivots: D^-1 of each backward position, SoA per step
-      for (const Step &st : S.bst)
-        for (int j = 0; j < st.nrows; ++j) {
-          S.dsrc.push_back(S.diag[S.brow[st.pos + j]]);
-          S.dbase.push_back(9 * st.pos + j);
-          S.dstride.push_back(st.nrows);
-          S.d32.push_back((uint8_t)st.fp32);
-        }
+      build_sweeps(S, lf, maxf, lb, maxb, fp32, restricted, owner, s);
       for (int u = 0; u < S.nfine; ++u) loc[S.cells[u]] = -1;
       if (two) {
         for (int b : near_boxes) nvar[b] = -1;
@@ -701,45 +854,38 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
   // ---------------------------------------------------------------- concatenate
   P.nsub = nsub;
   P.sub.resize(nsub);
-  int64_t ext = 0, ent = 0, tcount = 0, asrc = 0, fsl = 0, bsl = 0, fpos = 0, bpos = 0, frp = 0, brp = 0,
-          coarse = 0, csrc = 0;
-  std::vector<int64_t> o_ext(nsub), o_ent(nsub), o_t(nsub), o_as(nsub), o_fsl(nsub), o_bsl(nsub), o_fpos(nsub),
-      o_bpos(nsub), o_frp(nsub), o_brp(nsub), o_coarse(nsub), o_cs(nsub), o_fst(nsub), o_bst(nsub);
-  int64_t fst = 0, bst = 0;
+  std::vector<int64_t> o_ext(nsub), o_ent(nsub), o_t(nsub), o_as(nsub), o_coarse(nsub), o_cs(nsub), o_fst(nsub),
+      o_rf(nsub), o_rb(nsub), o_rec(nsub), o_rl(nsub);
+  int64_t ext = 0, ent = 0, tcount = 0, asrc = 0, coarse = 0, csrc = 0, fst = 0, nrf = 0, nrb = 0, recb = 0, nrl = 0;
   for (int s = 0; s < nsub; ++s) {
     const SubLocal &S = L[s];
-    o_ext[s] = ext; o_ent[s] = ent; o_t[s] = tcount; o_as[s] = asrc; o_fsl[s] = fsl; o_bsl[s] = bsl;
-    o_fpos[s] = fpos; o_bpos[s] = bpos; o_frp[s] = frp; o_brp[s] = brp; o_coarse[s] = coarse; o_cs[s] = csrc;
-    o_fst[s] = fst; o_bst[s] = bst;
+    o_ext[s] = ext; o_ent[s] = ent; o_t[s] = tcount; o_as[s] = asrc; o_coarse[s] = coarse; o_cs[s] = csrc;
+    o_fst[s] = fst; o_rf[s] = nrf; o_rb[s] = nrb; o_rec[s] = recb; o_rl[s] = nrl;
     ext += S.n; ent += S.rp[S.n]; tcount += (int64_t)S.tdst.size(); asrc += (int64_t)S.sidx.size();
-    fsl += S.fslots; bsl += S.bslots; fpos += S.fpos; bpos += S.bpos;
-    frp += (int64_t)S.frptr.size(); brp += (int64_t)S.brptr.size(); coarse += S.ncoarse;
-    csrc += (int64_t)S.cidx.size(); fst += (int64_t)S.fst.size(); bst += (int64_t)S.bst.size();
+    coarse += S.ncoarse; csrc += (int64_t)S.cidx.size(); fst += (int64_t)S.fst.size();
+    nrf += (int64_t)S.rf.size(); nrb += (int64_t)S.rb.size(); recb += (int64_t)S.rec.size();
+    nrl += (int64_t)S.rl_src.size();
     P.max_levels = std::max(P.max_levels, S.levels);
     P.fine_row_entries += S.rp[S.nfine];
+    P.lds_spilled_rows += S.spilled;
   }
   const int64_t lim = (int64_t)1 << 31;
-  if (ext >= lim || ent >= lim || tcount >= lim || asrc >= lim || 9 * fsl >= lim || 9 * bsl >= lim ||
-      9 * bpos >= lim) {
+  if (ext >= lim || ent >= lim || tcount >= lim || asrc >= lim || recb / 4 >= lim || nrl >= lim) {
     err = "preconditioner too large for 32-bit indexing";
     return ASM_ERR_INVALID;
   }
   P.total_ext = ext;
   P.total_coarse = coarse;
   P.total_entries = ent;
-  P.fslots = fsl;
-  P.bslots = bsl;
-  P.bpos = bpos;
+  P.total_pos = ext;
+  P.sweep_steps = nrf + nrb;
   P.fstep.resize(fst);
-  P.bstep.resize(bst);
-  P.frow.resize(fpos);
-  P.brow.resize(bpos);
-  P.fcol.resize(fsl);
-  P.bcol.resize(bsl);
-  P.frptr.resize(frp);
-  P.brptr.resize(brp);
+  P.frow.resize(ext);
+  P.rf.resize(nrf);
+  P.rb.resize(nrb);
+  P.rec.assign(recb, 0);
+  P.fsrc.resize(ext);
   P.rhs_src.resize(ext);
-  P.out_cell.resize(ext);
   P.arp.resize(ext + 1);
   P.aci.resize(ent);
   P.adiag.resize(ext);
@@ -750,52 +896,58 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
   P.asm_src.idx.resize(asrc);
   P.c3.ptr.resize(coarse + 1);
   P.c3.idx.resize(csrc);
-  auto rl_resize = [](RelayoutMap &m, int64_t n) {
-    m.src.resize(n); m.base.resize(n); m.stride.resize(n); m.to32.resize(n);
-  };
-  rl_resize(P.rl_f, fsl);
-  rl_resize(P.rl_b, bsl);
-  rl_resize(P.rl_d, bpos);
+  P.rl.src.resize(nrl);
+  P.rl.base.resize(nrl);
+  P.rl.stride.resize(nrl);
+  P.rl.to32.resize(nrl);
 #pragma omp parallel for schedule(dynamic)
   for (int s = 0; s < nsub; ++s) {
-    const SubLocal &S = L[s];
+    SubLocal &S = L[s];
     SubDesc &d = P.sub[s];
+    const int32_t pos_off = (int32_t)o_ext[s];  // forward / backward positions share the ext range
     d.ext_off = (int32_t)o_ext[s];
     d.n = S.n;
     d.nfine = S.nfine;
     d.fstep0 = (int32_t)o_fst[s];
     d.fstep1 = (int32_t)(o_fst[s] + S.fst.size());
-    d.bstep0 = (int32_t)o_bst[s];
-    d.bstep1 = (int32_t)(o_bst[s] + S.bst.size());
-    for (size_t k = 0; k < S.fst.size(); ++k) {
-      Step st = S.fst[k];
-      st.pos += (int32_t)o_fpos[s];
-      st.eoff += (int32_t)o_fsl[s];
-      st.rptr += (int32_t)o_frp[s];
-      P.fstep[o_fst[s] + k] = st;
+    d.rf0 = (int32_t)o_rf[s];
+    d.rf1 = (int32_t)(o_rf[s] + S.rf.size());
+    d.rb0 = (int32_t)o_rb[s];
+    d.rb1 = (int32_t)(o_rb[s] + S.rb.size());
+    for (size_t k = 0; k < S.fst.size(); ++k) P.fstep[o_fst[s] + k] = Step{S.fst[k].pos + pos_off, S.fst[k].nrows};
+    for (int q = 0; q < S.n; ++q) {
+      P.frow[pos_off + q] = S.frow[q];
+      const int32_t f = S.fsrc[q];
+      P.fsrc[pos_off + q] = f >= 0 ? f : -(int32_t)(1 + o_coarse[s] + (-f - 1));
     }
-    for (size_t k = 0; k < S.bst.size(); ++k) {
-      Step st = S.bst[k];
-      st.pos += (int32_t)o_bpos[s];
-      st.eoff += (int32_t)o_bsl[s];
-      st.rptr += (int32_t)o_brp[s];
-      P.bstep[o_bst[s] + k] = st;
+    // records: shift positions and global dependencies by the subdomain offset
+    uint8_t *rb = P.rec.data() + o_rec[s];
+    std::copy(S.rec.begin(), S.rec.end(), rb);
+    auto place = [&](const std::vector<RecStep> &loc, std::vector<RecStep> &glob, int64_t off) {
+      for (size_t k = 0; k < loc.size(); ++k) {
+        RecStep st = loc[k];
+        int32_t *meta = reinterpret_cast<int32_t *>(rb + st.rec + kRecHead);
+        int32_t *deps = reinterpret_cast<int32_t *>(rb + st.rec + st.deps);
+        for (int j = 0; j < st.nrows; ++j) meta[4 * j + 1] += pos_off;
+        for (int q = 0; q < st.nslots; ++q)
+          if (deps[q] < 0) deps[q] -= pos_off;
+        st.rec = (int32_t)((o_rec[s] + st.rec) / 16);
+        st.pos += pos_off;
+        glob[off + k] = st;
+      }
+    };
+    place(S.rf, P.rf, o_rf[s]);
+    place(S.rb, P.rb, o_rb[s]);
+    for (size_t t = 0; t < S.rl_src.size(); ++t) {
+      const int sz = S.rl_to32[t] ? 4 : 8;
+      P.rl.src[o_rl[s] + t] = (int32_t)(o_ent[s] + S.rl_src[t]);
+      P.rl.base[o_rl[s] + t] = (int32_t)(S.rl_base[t] + o_rec[s] / sz);
+      P.rl.stride[o_rl[s] + t] = S.rl_stride[t];
+      P.rl.to32[o_rl[s] + t] = S.rl_to32[t];
     }
-    std::copy(S.frow.begin(), S.frow.end(), P.frow.begin() + o_fpos[s]);
-    std::copy(S.brow.begin(), S.brow.end(), P.brow.begin() + o_bpos[s]);
-    std::copy(S.fcol.begin(), S.fcol.end(), P.fcol.begin() + o_fsl[s]);
-    std::copy(S.bcol.begin(), S.bcol.end(), P.bcol.begin() + o_bsl[s]);
-    std::copy(S.frptr.begin(), S.frptr.end(), P.frptr.begin() + o_frp[s]);
-    std::copy(S.brptr.begin(), S.brptr.end(), P.brptr.begin() + o_brp[s]);
     for (int u = 0; u < S.n; ++u) {
       const int64_t g = o_ext[s] + u;
-      if (u < S.nfine) {
-        P.rhs_src[g] = S.cells[u];
-        P.out_cell[g] = (restricted && S.owned[u]) ? S.cells[u] : -1;
-      } else {
-        P.rhs_src[g] = -(int32_t)(1 + o_coarse[s] + (u - S.nfine));
-        P.out_cell[g] = -1;
-      }
+      P.rhs_src[g] = (u < S.nfine) ? S.cells[u] : -(int32_t)(1 + o_coarse[s] + (u - S.nfine));
       P.arp[g] = (int32_t)(o_ent[s] + S.rp[u]);
       P.adiag[g] = (int32_t)(o_ent[s] + S.diag[u]);
     }
@@ -812,25 +964,14 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     std::copy(S.sidx.begin(), S.sidx.end(), P.asm_src.idx.begin() + o_as[s]);
     for (int q = 0; q < S.ncoarse; ++q) P.c3.ptr[o_coarse[s] + q] = (int32_t)(o_cs[s] + S.cptr[q]);
     std::copy(S.cidx.begin(), S.cidx.end(), P.c3.idx.begin() + o_cs[s]);
-    auto fill_rl = [&](RelayoutMap &m, int64_t off, int64_t base_off, const std::vector<int32_t> &src,
-                       const std::vector<int32_t> &base, const std::vector<int32_t> &stride,
-                       const std::vector<uint8_t> &to32) {
-      for (size_t t = 0; t < src.size(); ++t) {
-        m.src[off + t] = src[t] >= 0 ? (int32_t)(o_ent[s] + src[t]) : -1;
-        m.base[off + t] = (int32_t)(base[t] + 9 * base_off);
-        m.stride[off + t] = stride[t];
-        m.to32[off + t] = to32[t];
-      }
-    };
-    fill_rl(P.rl_f, o_fsl[s], o_fsl[s], S.fsrc, S.fbase, S.fstride, S.f32);
-    fill_rl(P.rl_b, o_bsl[s], o_bsl[s], S.bsrc, S.bbase, S.bstride, S.b32);
-    fill_rl(P.rl_d, o_bpos[s], o_bpos[s], S.dsrc, S.dbase, S.dstride, S.d32);
+    // free the local copies early
+    std::vector<uint8_t>().swap(S.rec);
   }
   P.arp[ext] = (int32_t)ent;
   P.tptr[ent] = (int32_t)tcount;
   P.asm_src.ptr[ent] = (int32_t)asrc;
   P.c3.ptr[coarse] = (int32_t)csrc;
-  // additive combine: contributors of each cell in subdomain order
+  // additive combine: backward positions of each cell's fine rows, in subdomain order
   P.cptr.assign(N + 1, 0);
   for (int s = 0; s < nsub; ++s)
     for (int c : L[s].cells) P.cptr[c + 1]++;
@@ -839,7 +980,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
   {
     std::vector<int32_t> fill(P.cptr.begin(), P.cptr.end() - 1);
     for (int s = 0; s < nsub; ++s)
-      for (int u = 0; u < L[s].nfine; ++u) P.cidx[fill[L[s].cells[u]]++] = (int32_t)(o_ext[s] + u);
+      for (int u = 0; u < L[s].nfine; ++u) P.cidx[fill[L[s].cells[u]]++] = (int32_t)(o_ext[s] + L[s].bpos[u]);
   }
   P.any_fp32 = fp32;
   return ASM_OK;

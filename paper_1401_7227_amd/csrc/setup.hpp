@@ -33,13 +33,19 @@ struct PlanHost {
   int32_t nsub = 0;
   int64_t total_ext = 0, total_coarse = 0, total_entries = 0, fine_row_entries = 0;
   int32_t max_levels = 0;
+  int64_t sweep_steps = 0;       // forward + backward records
+  int64_t lds_spilled_rows = 0;  // rows whose values went through global memory
   std::vector<SubDesc> sub;
-  std::vector<Step> fstep, bstep;
-  std::vector<int32_t> frow, brow, fcol, bcol, frptr, brptr;
-  int64_t fslots = 0, bslots = 0, bpos = 0;  // sizes of fval, bval (blocks), bdinv (rows)
-  int64_t fslots32 = 0, bslots32 = 0;
-  RelayoutMap rl_f, rl_b, rl_d;
-  std::vector<int32_t> rhs_src, out_cell;
+  // factorisation level steps
+  std::vector<Step> fstep;
+  std::vector<int32_t> frow;
+  // sweep records
+  std::vector<RecStep> rf, rb;
+  std::vector<uint8_t> rec;      // all records, 16-byte aligned
+  std::vector<int32_t> fsrc;     // forward position -> cell or -(1+coarse row)
+  int64_t total_pos = 0;         // rows in forward (= backward) order
+  RelayoutMap rl;                // factor blocks -> record value slots
+  std::vector<int32_t> rhs_src;  // per ext row: cell or -(1+coarse row)
   std::vector<int32_t> arp, aci, adiag, tptr, tdst, tsrc;
   // Assembly of A_i values: sources index the pool [A blocks | lumped L2].
   GatherList asm_src;
@@ -49,7 +55,7 @@ struct PlanHost {
   // Lumped right-hand side: atom sums of cells, then near/far atom sums of
   // fine atoms, then coarse rows of near/far atoms.
   GatherList c1, c2, c3;
-  // Additive combine: per cell the extended rows holding its value.
+  // Additive combine: per cell the backward positions holding its value.
   std::vector<int32_t> cptr, cidx;
   bool any_fp32 = false;
 };
