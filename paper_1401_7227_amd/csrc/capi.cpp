@@ -305,7 +305,7 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(s);
   ASM_HIP(launch_gather_rhs((int)pc->plan.total_pos, pc->ap, r, scale, s));
-  ASM_HIP(launch_ilu_apply(pc->ap, r, scale, z, s));
+  ASM_HIP(launch_ilu_apply(pc->ap, z, s));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
     const size_t t2 = pf.mark(s);
@@ -472,9 +472,10 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   ap.fsrc = t32;
 #undef UP
   auto ALLOC = [&](auto **dst, size_t n) { return M.alloc(dst, n); };
-  double *yx, *rs, *crhs, *fact;
+  double *yx, *rs, *trash, *crhs, *fact;
   if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
       (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
+      (e = ALLOC(&trash, (size_t)P.nsub * 256 * 3)) != hipSuccess ||
       (e = ALLOC(&crhs, (size_t)std::max<int64_t>(1, P.total_coarse) * 3)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
@@ -482,6 +483,7 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   ap.yx = yx;
   ap.rs = rs;
+  ap.trash = trash;
   ap.crhs = crhs;
   d.fact = fact;
   if ((e = upload_gather(M, pc->asrc, P.asm_src, s)) != hipSuccess)

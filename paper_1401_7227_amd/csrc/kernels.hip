@@ -286,27 +286,11 @@ constexpr int kStageU4 = kRecU4 / 256;
 static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kConsumerThreads = 256;  // one thread per row of a step
 
 struct Stage {
   u32x4 v[kStageU4];
 };
-
-// One record into registers: kStageU4 16-byte words per thread, every load
-// issued unconditionally (indices clamped to the record's last word), so
-// the in-order wait counts stay static and loads of later records remain in
-// flight across barriers.
-__device__ __forceinline__ void stage_load(const u32x4 *__restrict__ src, int len, Stage &st) {
-#pragma unroll
-  for (int i = 0; i < kStageU4; ++i) st.v[i] = src[min(i * 256 + (int)threadIdx.x, len - 1)];
-}
-
-__device__ __forceinline__ void stage_store(u32x4 *dst, int len, const Stage &st) {
-#pragma unroll
-  for (int i = 0; i < kStageU4; ++i) {
-    const int q = i * 256 + (int)threadIdx.x;
-    if (q < len) dst[q] = st.v[i];
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
@@ -325,70 +309,75 @@ __device__ __forceinline__ void dep_value(int d, const double *vec, const double
   }
 }
 
-// Stores a row result: LDS slot, global work vector, restricted output.
-template <bool FWD>
-__device__ __forceinline__ void put_row(const int4 m, double a0, double a1, double a2, double *vec,
-                                        double *__restrict__ yx, double *__restrict__ z) {
-  if (m.x >= 0) { vec[3 * m.x] = a0; vec[3 * m.x + 1] = a1; vec[3 * m.x + 2] = a2; }
-  if (FWD || m.w) { const size_t g = 3 * (size_t)m.y; yx[g] = a0; yx[g + 1] = a1; yx[g + 2] = a2; }
-  if (!FWD && m.z >= 0) { const size_t g = 3 * (size_t)m.z; z[g] = a0; z[g + 1] = a1; z[g + 2] = a2; }
-}
+struct SweepLds {
+  u32x4 buf[3][kRecU4];        // records of steps s, s+1 (and s-1 until overwritten)
+  double vec[3 * kVecSlots];    // vector slot pool
+  double stg[2][3 * 256];       // row results awaiting their global stores
+  double part[4];               // partial sum of a split row
+};
 
 // Mode 0: one thread per row, entries in jagged diagonals.  (a0,a1,a2) is
 // the row's right-hand side (forward) or its forward result (backward).
+// All entries' LDS reads are issued before any is used: dependency
+// indices, then the dependency values, then the blocks.
 template <bool FWD, typename T>
-__device__ __forceinline__ void step_rows(const RecStep &st, const char *recp, double *vec, double *__restrict__ yx,
-                                          double *__restrict__ z, double a0, double a1, double a2) {
+__device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, SweepLds &L, double *stg,
+                                          const double *__restrict__ yx, double a0, double a1, double a2) {
   const int j = threadIdx.x;
-  if (j >= st.nrows) return;
-  const int32_t *koff = reinterpret_cast<const int32_t *>(recp);
+  if (j >= h.nrows) return;
   const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
-  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + st.deps);
-  const T *vals = reinterpret_cast<const T *>(recp + st.vals);
+  const int cnt = m.w >> 8;
+  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + h.deps);
+  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
+  const int4 ka = *reinterpret_cast<const int4 *>(reinterpret_cast<const RecHead *>(recp)->koff);
+  const int4 kb = *reinterpret_cast<const int4 *>(reinterpret_cast<const RecHead *>(recp)->koff + 4);
+  const int ko[kMaxJdsWidth] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+  int d[kMaxJdsWidth];
+#pragma unroll
+  for (int k = 0; k < kMaxJdsWidth; ++k) d[k] = (k < cnt) ? deps[ko[k] + j] : 0;
+  double y[kMaxJdsWidth][3];
+#pragma unroll
+  for (int k = 0; k < kMaxJdsWidth; ++k)
+    if (k < cnt) dep_value(d[k], L.vec, yx, y[k][0], y[k][1], y[k][2]);
   T t0 = (T)a0, t1 = (T)a1, t2 = (T)a2;
-  int k0 = koff[0];
-  for (int k = 0; k < st.width; ++k) {
-    const int k1 = koff[k + 1];
-    if (j >= k1 - k0) break;
-    const int q = k0 + j;
-    k0 = k1;
-    double y0, y1, y2;
-    dep_value(deps[q], vec, yx, y0, y1, y2);
-    T b[9];
-    block9<T>(vals + q, st.nslots, b);
-    const T u0 = (T)y0, u1 = (T)y1, u2 = (T)y2;
-    t0 -= b[0] * u0 + b[1] * u1 + b[2] * u2;
-    t1 -= b[3] * u0 + b[4] * u1 + b[5] * u2;
-    t2 -= b[6] * u0 + b[7] * u1 + b[8] * u2;
+#pragma unroll
+  for (int k = 0; k < kMaxJdsWidth; ++k) {
+    if (k < cnt) {
+      T b[9];
+      block9<T>(vals + ko[k] + j, h.nslots, b);
+      const T u0 = (T)y[k][0], u1 = (T)y[k][1], u2 = (T)y[k][2];
+      t0 -= b[0] * u0 + b[1] * u1 + b[2] * u2;
+      t1 -= b[3] * u0 + b[4] * u1 + b[5] * u2;
+      t2 -= b[6] * u0 + b[7] * u1 + b[8] * u2;
+    }
   }
   if (!FWD) {
-    T d[9];
-    block9<T>(reinterpret_cast<const T *>(recp + st.dinv) + j, st.nrows, d);
-    const T x0 = d[0] * t0 + d[1] * t1 + d[2] * t2;
-    const T x1 = d[3] * t0 + d[4] * t1 + d[5] * t2;
-    const T x2 = d[6] * t0 + d[7] * t1 + d[8] * t2;
+    T dv[9];
+    block9<T>(reinterpret_cast<const T *>(recp + h.dinv) + j, h.nrows, dv);
+    const T x0 = dv[0] * t0 + dv[1] * t1 + dv[2] * t2;
+    const T x1 = dv[3] * t0 + dv[4] * t1 + dv[5] * t2;
+    const T x2 = dv[6] * t0 + dv[7] * t1 + dv[8] * t2;
     t0 = x0; t1 = x1; t2 = x2;
   }
-  put_row<FWD>(m, (double)t0, (double)t1, (double)t2, vec, yx, z);
+  if (m.x >= 0) { L.vec[3 * m.x] = (double)t0; L.vec[3 * m.x + 1] = (double)t1; L.vec[3 * m.x + 2] = (double)t2; }
+  stg[3 * j] = (double)t0; stg[3 * j + 1] = (double)t1; stg[3 * j + 2] = (double)t2;
 }
 
-// Mode 1: one wavefront per (long) row; lanes stride over its entries.  A
-// piece of a split row starts from / leaves its partial sum in the row's
-// global position.
+// Mode 1: one wavefront per (long) row; lanes stride over its entries.
+// Pieces of a split row carry their partial sum in LDS.
 template <bool FWD, typename T>
-__device__ __forceinline__ void step_long_rows(const RecStep &st, const char *recp, double *vec,
-                                               double *__restrict__ yx, double *__restrict__ z,
-                                               const double *__restrict__ r, double sc,
-                                               const int32_t *__restrict__ fsrc, const double *__restrict__ crhs) {
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + st.deps);
-  const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + st.rptr);
-  const T *vals = reinterpret_cast<const T *>(recp + st.vals);
-  for (int j = wv; j < st.nrows; j += nw) {
+__device__ __forceinline__ void step_long_rows(const RecHead &h, const char *recp, SweepLds &L, double *stg,
+                                               const double *__restrict__ in, const double *__restrict__ yx) {
+  // consumer waves only (the producer waves stream records)
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = kConsumerThreads / kWave;
+  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + h.deps);
+  const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + h.rptr);
+  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
+  for (int j = wv; j < h.nrows; j += nw) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = rptr[j] + lane; q < rptr[j + 1]; q += kWave) {
       double y0, y1, y2;
-      dep_value(deps[q], vec, yx, y0, y1, y2);
+      dep_value(deps[q], L.vec, yx, y0, y1, y2);
       const T *b = vals + 9 * q;
       s0 += (double)b[0] * y0 + (double)b[1] * y1 + (double)b[2] * y2;
       s1 += (double)b[3] * y0 + (double)b[4] * y1 + (double)b[5] * y2;
@@ -398,125 +387,196 @@ __device__ __forceinline__ void step_long_rows(const RecStep &st, const char *re
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
     if (lane == 0) {
-      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
       double a0, a1, a2;
-      if (st.piece == kPieceMiddle || st.piece == kPieceLast || !FWD) {
-        const size_t g = 3 * (size_t)m.y;  // partial sum, or the forward result
-        a0 = yx[g]; a1 = yx[g + 1]; a2 = yx[g + 2];
+      if (h.piece == kPieceMiddle || h.piece == kPieceLast) {
+        a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
       } else {
-        const int src = fsrc[st.pos + j];
-        if (src >= 0) {
-          a0 = sc * r[3 * (size_t)src]; a1 = sc * r[3 * (size_t)src + 1]; a2 = sc * r[3 * (size_t)src + 2];
-        } else {
-          const double *c = crhs + 3 * (size_t)(-src - 1);
-          a0 = c[0]; a1 = c[1]; a2 = c[2];
-        }
+        const size_t g = 3 * (size_t)(h.pos + j);
+        a0 = in[g]; a1 = in[g + 1]; a2 = in[g + 2];
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
-      if (st.piece == kPieceFirst || st.piece == kPieceMiddle) {
-        const size_t g = 3 * (size_t)m.y;
-        yx[g] = a0; yx[g + 1] = a1; yx[g + 2] = a2;
+      if (h.piece == kPieceFirst || h.piece == kPieceMiddle) {
+        L.part[0] = a0; L.part[1] = a1; L.part[2] = a2;
       } else {
         if (!FWD) {
-          const T *dv = reinterpret_cast<const T *>(recp + st.dinv) + j;
-          const int S = st.nrows;
+          const T *dv = reinterpret_cast<const T *>(recp + h.dinv) + j;
+          const int S = h.nrows;
           const double x0 = (double)dv[0] * a0 + (double)dv[S] * a1 + (double)dv[2 * S] * a2;
           const double x1 = (double)dv[3 * S] * a0 + (double)dv[4 * S] * a1 + (double)dv[5 * S] * a2;
           const double x2 = (double)dv[6 * S] * a0 + (double)dv[7 * S] * a1 + (double)dv[8 * S] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
-        put_row<FWD>(m, a0, a1, a2, vec, yx, z);
+        const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
+        if (m.x >= 0) { L.vec[3 * m.x] = a0; L.vec[3 * m.x + 1] = a1; L.vec[3 * m.x + 2] = a2; }
+        stg[3 * j] = a0; stg[3 * j + 1] = a1; stg[3 * j + 2] = a2;
       }
     }
   }
 }
 
-// Input of row j of a mode-0 step: its right-hand side (forward, from the
-// gathered stream) or its forward result (backward).  Loaded three steps
-// ahead; rows past the step clamp to its last row.
-__device__ __forceinline__ void fetch_in(const RecStep &st, const double *__restrict__ src, double &g0, double &g1,
-                                         double &g2) {
-  const size_t g = 3 * (size_t)(st.pos + min((int)threadIdx.x, st.nrows - 1));
-  g0 = src[g]; g1 = src[g + 1]; g2 = src[g + 2];
+// Global stores of the previous step's results: thread t stores row t, every
+// thread issues the same two stores (rows without a destination, and threads
+// past the step, write to their own discard slot), keeping the memory
+// operation count of an iteration independent of the data.
+__device__ __forceinline__ void epilogue(const char *recp, int nrows, const double *stg, double *__restrict__ yx,
+                                         double *__restrict__ z, double *__restrict__ trash) {
+  const int t = threadIdx.x;
+  double *dA = trash, *dB = trash;
+  if (t < nrows) {
+    const RecHead *h = reinterpret_cast<const RecHead *>(recp);
+    if (h->piece == kPieceWhole || h->piece == kPieceLast) {
+      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[t];
+      if (m.w & 1) dA = yx + 3 * (size_t)m.y;
+      if (m.z >= 0) dB = z + 3 * (size_t)m.z;
+    }
+  }
+  const double v0 = stg[3 * t], v1 = stg[3 * t + 1], v2 = stg[3 * t + 2];
+  dA[0] = v0; dA[1] = v1; dA[2] = v2;
+  dB[0] = v0; dB[1] = v1; dB[2] = v2;
 }
 
-struct SweepLds {
-  u32x4 buf[3][kRecU4];
-  double vec[3 * kVecSlots];
-};
+// Input of row j of a mode-0 step: its right-hand side (forward, from the
+// gathered stream) or its forward result (backward).  Rows past the step
+// read its first row.
+__device__ __forceinline__ void fetch_in(const RecStep &st, const double *__restrict__ src, double &g0, double &g1,
+                                         double &g2) {
+  const size_t g = 3 * (size_t)(st.pos + max(0, min((int)threadIdx.x, st.nrows - 1)));
+  g0 = src[g]; g1 = src[g + 1]; g2 = src[g + 2];
+}
 
 struct In3 {
   double a, b, c;
 };
 
-// One pipeline iteration for step s.  Register stage `hold` has record s+1
-// (loaded two iterations ago) and `load` receives record s+3; input set `g`
-// has step s's inputs and, after the compute, receives step s+3's.  Loads
-// past the last step re-read the last step so every iteration issues the
-// same loads.
-template <bool FWD>
-__device__ __forceinline__ void sweep_iter(int s, int S, const RecStep *__restrict__ steps,
-                                           const u32x4 *__restrict__ rec, SweepLds &L, Stage &hold, Stage &load,
-                                           In3 &g, const double *__restrict__ in, const double *__restrict__ r,
-                                           double sc, const int32_t *__restrict__ fsrc,
-                                           const double *__restrict__ crhs, double *__restrict__ yx,
-                                           double *__restrict__ z) {
-  const RecStep cur = steps[s];
-  const RecStep n3 = steps[min(s + 3, S - 1)];
-  stage_load(rec + n3.rec, n3.len, load);
-  const char *recp = reinterpret_cast<const char *>(L.buf[s % 3]);
-  if (cur.mode == 0) {
-    if (cur.fp32) step_rows<FWD, float>(cur, recp, L.vec, yx, z, g.a, g.b, g.c);
-    else step_rows<FWD, double>(cur, recp, L.vec, yx, z, g.a, g.b, g.c);
-  } else {
-    if (cur.fp32) step_long_rows<FWD, float>(cur, recp, L.vec, yx, z, r, sc, fsrc, crhs);
-    else step_long_rows<FWD, double>(cur, recp, L.vec, yx, z, r, sc, fsrc, crhs);
-  }
-  fetch_in(n3, in, g.a, g.b, g.c);
-  if (s + 1 < S) stage_store(L.buf[(s + 1) % 3], steps[s + 1].len, hold);
+// The sweep runs with wave-specialised roles.  Waves 0-3 (one thread per
+// row) compute the steps; waves 4-7 only stream records: each producer
+// thread keeps kAhead future records in registers and moves the next one
+// into LDS every step, so several records are in flight while the
+// consumers compute.  Both roles execute the same sequence of barriers.
+constexpr int kAhead = 4;
+
+struct Producer {
+  Stage st[kAhead];
+  int len[kAhead];
+};
+
+// Producer: load record k of the sweep (clamped to the last step) into
+// stage slot k % kAhead.
+__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec, Stage &st, int &len,
+                                          int t) {
+#pragma unroll
+  for (int i = 0; i < kStageU4; ++i) st.v[i] = rec[d.rec + min(i * 256 + t, d.len - 1)];
+  len = d.len;
+}
+
+// Stores the whole buffer unconditionally: words past the record are
+// copies of its last word and land in the unused tail of the buffer.
+__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int, int t) {
+#pragma unroll
+  for (int i = 0; i < kStageU4; ++i) dst[i * 256 + t] = st.v[i];
+}
+
+template <int K>
+__device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restrict__ steps,
+                                          const u32x4 *__restrict__ rec, SweepLds &L, Producer &P, RecStep &dn,
+                                          int t) {
+  // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
+  // the stage for record s+1+kAhead (descriptor loaded last iteration)
+  prod_store(L.buf[(s + 1) % 3], P.st[K], P.len[K], t);
+  const RecStep d = dn;
+  prod_load(d, rec, P.st[K], P.len[K], t);
+  dn = steps[min(s + 2 + kAhead, S - 1)];
   __syncthreads();
 }
 
-template <bool FWD>
-__device__ __forceinline__ void sweep(const RecStep *__restrict__ steps, int S, const u32x4 *__restrict__ rec,
-                                      SweepLds &L, const double *__restrict__ in, const double *__restrict__ r,
-                                      double sc, const int32_t *__restrict__ fsrc, const double *__restrict__ crhs,
-                                      double *__restrict__ yx, double *__restrict__ z) {
+__device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
+                                               const u32x4 *__restrict__ rec, SweepLds &L) {
   if (S == 0) return;
-  Stage A, B, C;
-  In3 g0, g1, g2;
-  // prologue: record 0 into LDS; records 1 and 2 and the inputs of steps
-  // 0..2 in flight
-  {
-    const RecStep s0 = steps[0];
-    stage_load(rec + s0.rec, s0.len, A);
-    fetch_in(s0, in, g0.a, g0.b, g0.c);
-    const RecStep s1 = steps[min(1, S - 1)];
-    stage_load(rec + s1.rec, s1.len, B);
-    fetch_in(s1, in, g1.a, g1.b, g1.c);
-    const RecStep s2 = steps[min(2, S - 1)];
-    stage_load(rec + s2.rec, s2.len, C);
-    fetch_in(s2, in, g2.a, g2.b, g2.c);
-    stage_store(L.buf[0], s0.len, A);
-  }
+  const int t = threadIdx.x - kConsumerThreads;
+  Producer P;
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) prod_load(steps[min(k, S - 1)], rec, P.st[k], P.len[k], t);
+  prod_store(L.buf[0], P.st[0], P.len[0], t);
+  prod_load(steps[min(kAhead, S - 1)], rec, P.st[0], P.len[0], t);
+  RecStep dn = steps[min(1 + kAhead, S - 1)];
   __syncthreads();
-  // stage k%3 and input set k%3 hold record / inputs of step k
-  for (int s = 0; s < S; s += 3) {
-    sweep_iter<FWD>(s, S, steps, rec, L, B, A, g0, in, r, sc, fsrc, crhs, yx, z);
-    if (s + 1 < S) sweep_iter<FWD>(s + 1, S, steps, rec, L, C, B, g1, in, r, sc, fsrc, crhs, yx, z);
-    if (s + 2 < S) sweep_iter<FWD>(s + 2, S, steps, rec, L, A, C, g2, in, r, sc, fsrc, crhs, yx, z);
+  static_assert(kAhead == 4, "the unrolled producer loop assumes four stages");
+  // full groups of kAhead steps without conditions (exact wait counts),
+  // then the remaining steps in straight-line code
+  int s = 0;
+  for (; s + kAhead <= S; s += kAhead) {
+    prod_iter<1>(s, S, steps, rec, L, P, dn, t);
+    prod_iter<2>(s + 1, S, steps, rec, L, P, dn, t);
+    prod_iter<3>(s + 2, S, steps, rec, L, P, dn, t);
+    prod_iter<0>(s + 3, S, steps, rec, L, P, dn, t);
   }
+  if (s < S) prod_iter<1>(s, S, steps, rec, L, P, dn, t);
+  if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, L, P, dn, t);
+  if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, L, P, dn, t);
+  __syncthreads();  // matches the consumers' final epilogue barrier
 }
 
-__global__ __launch_bounds__(256, 1) void ilu_apply_kernel(ApplyPlan p, const double *__restrict__ r,
-                                                           const double *__restrict__ scale, double *__restrict__ z) {
+// Consumer iteration for step s: global stores of step s-1, compute of step
+// s from LDS, inputs of step s+3 (descriptor loaded last iteration).
+template <bool FWD>
+__device__ __forceinline__ void cons_iter(int s, int S, const RecStep *__restrict__ steps, SweepLds &L, In3 &g,
+                                          RecStep &dn, const double *__restrict__ in, double *__restrict__ yx,
+                                          double *__restrict__ z, double *__restrict__ trash) {
+  const int prev_rows = (s > 0) ? reinterpret_cast<const RecHead *>(L.buf[(s + 2) % 3])->nrows : 0;
+  epilogue(reinterpret_cast<const char *>(L.buf[(s + 2) % 3]), prev_rows, L.stg[(s + 1) & 1], yx, z, trash);
+  const char *recp = reinterpret_cast<const char *>(L.buf[s % 3]);
+  const RecHead h = *reinterpret_cast<const RecHead *>(recp);
+  double *stg = L.stg[s & 1];
+  if (h.mode == 0) {
+    if (h.fp32) step_rows<FWD, float>(h, recp, L, stg, yx, g.a, g.b, g.c);
+    else step_rows<FWD, double>(h, recp, L, stg, yx, g.a, g.b, g.c);
+  } else {
+    if (h.fp32) step_long_rows<FWD, float>(h, recp, L, stg, in, yx);
+    else step_long_rows<FWD, double>(h, recp, L, stg, in, yx);
+  }
+  const RecStep d3 = dn;
+  fetch_in(d3, in, g.a, g.b, g.c);
+  dn = steps[min(s + 4, S - 1)];
+  __syncthreads();
+}
+
+template <bool FWD>
+__device__ __forceinline__ void consumer_sweep(const RecStep *__restrict__ steps, int S, SweepLds &L,
+                                               const double *__restrict__ in, double *__restrict__ yx,
+                                               double *__restrict__ z, double *__restrict__ trash) {
+  if (S == 0) return;
+  In3 g0, g1, g2;
+  fetch_in(steps[0], in, g0.a, g0.b, g0.c);
+  fetch_in(steps[min(1, S - 1)], in, g1.a, g1.b, g1.c);
+  fetch_in(steps[min(2, S - 1)], in, g2.a, g2.b, g2.c);
+  RecStep dn = steps[min(3, S - 1)];
+  __syncthreads();
+  int s = 0;
+  for (; s + 3 <= S; s += 3) {
+    cons_iter<FWD>(s, S, steps, L, g0, dn, in, yx, z, trash);
+    cons_iter<FWD>(s + 1, S, steps, L, g1, dn, in, yx, z, trash);
+    cons_iter<FWD>(s + 2, S, steps, L, g2, dn, in, yx, z, trash);
+  }
+  if (s < S) cons_iter<FWD>(s, S, steps, L, g0, dn, in, yx, z, trash);
+  if (s + 1 < S) cons_iter<FWD>(s + 1, S, steps, L, g1, dn, in, yx, z, trash);
+  const char *lastp = reinterpret_cast<const char *>(L.buf[(S - 1) % 3]);
+  epilogue(lastp, reinterpret_cast<const RecHead *>(lastp)->nrows, L.stg[(S - 1) & 1], yx, z, trash);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
   __shared__ SweepLds L;
   const SubDesc sd = p.sub[blockIdx.x];
-  const double sc = scale ? *scale : 1.0;
   const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
-  sweep<true>(p.fstep + sd.rf0, sd.rf1 - sd.rf0, rec, L, p.rs, r, sc, p.fsrc, p.crhs, p.yx, z);
-  __syncthreads();
-  sweep<false>(p.bstep + sd.rb0, sd.rb1 - sd.rb0, rec, L, p.yx, r, sc, p.fsrc, p.crhs, p.yx, z);
+  const int nf = sd.rf1 - sd.rf0, nb = sd.rb1 - sd.rb0;
+  if (threadIdx.x < kConsumerThreads) {
+    double *trash = p.trash + 3 * ((size_t)blockIdx.x * 256 + threadIdx.x);
+    consumer_sweep<true>(p.fstep + sd.rf0, nf, L, p.rs, p.yx, z, trash);
+    consumer_sweep<false>(p.bstep + sd.rb0, nb, L, p.yx, p.yx, z, trash);
+  } else {
+    producer_sweep(p.fstep + sd.rf0, nf, rec, L);
+    producer_sweep(p.bstep + sd.rb0, nb, rec, L);
+  }
 }
 
 // Forward right-hand sides in sweep order: the restriction R_i r of every
@@ -731,9 +791,9 @@ hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, cons
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s) {
+hipError_t launch_ilu_apply(const ApplyPlan &p, double *z, hipStream_t s) {
   if (p.nsub == 0) return hipSuccess;
-  ilu_apply_kernel<<<p.nsub, 256, 0, s>>>(p, r, scale, z);
+  ilu_apply_kernel<<<p.nsub, 512, 0, s>>>(p, z);
   return hipGetLastError();
 }
 

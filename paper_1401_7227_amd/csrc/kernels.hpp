@@ -46,7 +46,7 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base,
 // the plan's global work vector.
 // Forward right-hand sides of all subdomains in sweep order (p.rs).
 hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s);
-hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s);
+hipError_t launch_ilu_apply(const ApplyPlan &p, double *z, hipStream_t s);
 hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx,
                                    const double *yext, double *z, hipStream_t s);
 

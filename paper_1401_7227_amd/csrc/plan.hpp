@@ -23,19 +23,21 @@ struct Step {
 #endif
 constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (3 buffers)
 #ifndef ASM_VEC_SLOTS
-#define ASM_VEC_SLOTS 2560
+#define ASM_VEC_SLOTS 2048
 #endif
 constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
 constexpr int kMaxJdsWidth = 8;    // mode-0 rows have at most this many entries
 constexpr int kMaxStepRows = 256;  // rows per step (one thread per row)
 
-// One step of a sweep.  Record sections (byte offsets from the record
-// start, each 16-byte aligned):
-//   head  int koff[kMaxJdsWidth + 1] (mode 0: first entry of each jagged
-//         diagonal; koff[width] = nslots), padded to kRecHead bytes.
-//   meta  int4 per row.  Forward: {LDS slot or -1, spill position, -, -};
-//         backward: {LDS slot or -1, own position, output cell or -1,
-//         1 if the value must also be stored to the global vector}.
+// One step of a sweep.  The record starts with its own descriptor (read
+// from LDS once the record has arrived); a compact {rec, len, pos, nrows}
+// array per sweep drives the prefetch.  Record sections (byte offsets from
+// the record start, each 16-byte aligned):
+//   head  RecHead (kRecHead bytes).
+//   meta  int4 per row: {LDS slot or -1, own position, output cell or -1,
+//         flags}; flags bit 0 = store the value to the global vector at the
+//         own position (always in the forward sweep), bits 8.. = the row's
+//         entry count.
 //   deps  int per entry: >= 0 an LDS slot, < 0 the global position -1-d.
 //   rptr  mode 1: nrows+1 relative entry offsets.
 //   vals  mode 0: jagged-diagonal SoA, component e of entry q at
@@ -43,23 +45,26 @@ constexpr int kMaxStepRows = 256;  // rows per step (one thread per row)
 //         (rows sorted by entry count, descending); mode 1: 9 per entry.
 //   dinv  backward: component e of row j at [e*nrows + j].
 // A mode-1 row whose record would not fit one LDS buffer is split into
-// pieces in consecutive one-row steps; pieces carry the partial sum through
-// the row's global position.
-constexpr int kRecHead = 48;
+// pieces in consecutive one-row steps that carry the partial sum in LDS.
+// Values read through the global vector are produced at least two steps
+// before their use (the host inserts empty steps where needed), because
+// results reach global memory one step after they are computed.
 enum { kPieceWhole = 0, kPieceFirst = 1, kPieceMiddle = 2, kPieceLast = 3 };
 
+struct RecHead {
+  int32_t nrows, nslots, mode, fp32, piece, width;
+  int32_t deps, vals, dinv, rptr, pos, pad;
+  int32_t koff[kMaxJdsWidth + 1];  // mode 0: first entry of each jagged diagonal
+  int32_t pad2[3];
+};
+constexpr int kRecHead = (int)sizeof(RecHead);
+static_assert(kRecHead % 16 == 0, "record head must keep 16-byte alignment");
+
 struct RecStep {
-  int32_t rec;     // record start, in 16-byte units
-  int32_t len;     // record length, in 16-byte units
-  int32_t pos;     // position of the step's first row (forward / backward order)
+  int32_t rec;    // record start, in 16-byte units
+  int32_t len;    // record length, in 16-byte units
+  int32_t pos;    // position of the step's first row (forward / backward order)
   int32_t nrows;
-  int32_t nslots;  // dependency entries
-  int32_t mode;    // 0: thread per row (jagged diagonals); 1: wavefront per row
-  int32_t fp32;    // blocks stored in single precision
-  int32_t piece;   // mode 1: kPiece* of a split row
-  int32_t deps, vals, dinv, rptr;
-  int32_t width;
-  int32_t pad[3];
 };
 
 struct ApplyPlan {
@@ -67,9 +72,10 @@ struct ApplyPlan {
   const struct SubDesc *sub;
   const RecStep *fstep, *bstep;
   const void *rec;              // all records (16-byte aligned)
-  const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
   double *rs;                   // 3 doubles per forward position: gathered rhs
   double *yx;                   // 3 doubles per backward position
+  double *trash;                // 3 doubles per thread of the grid (discarded stores)
+  const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
   const double *crhs;           // 3 doubles per coarse row
 };
 

@@ -333,14 +333,29 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
   std::vector<int32_t> fslot, flast, bslot, blast;
   allocate(fch, true, fslot, flast);
   allocate(bch, false, bslot, blast);
-  // records
+  // records; an empty step is inserted wherever a value read through the
+  // global vector would be needed one step after the step producing it
   auto emit = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<RecStep> &out) {
     const std::vector<int32_t> &slot = fwd ? fslot : bslot;
     const std::vector<int32_t> &last = fwd ? flast : blast;
+    std::vector<int32_t> made(S.n, -1);  // emitted step that produced each row
+    auto push_record = [&](const RecHead &h, int32_t total, int32_t pos, int32_t nrows) -> uint8_t * {
+      RecStep st{};
+      st.rec = (int32_t)S.rec.size();
+      st.len = total / 16;
+      st.pos = pos;
+      st.nrows = nrows;
+      S.rec.resize(S.rec.size() + total, 0);
+      uint8_t *base = S.rec.data() + st.rec;
+      std::memcpy(base, &h, sizeof h);
+      out.push_back(st);
+      return base;
+    };
     for (const Chunk &c : ch) {
       const int nr = (int)c.rows.size();
       std::vector<std::vector<int32_t>> ent(nr);
       int nslots = 0;
+      bool near_global = false;
       for (int j = 0; j < nr; ++j) {
         const int i = c.rows[j];
         for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
@@ -348,26 +363,46 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         if (c.piece != kPieceWhole)
           ent[j] = std::vector<int32_t>(ent[j].begin() + c.e0, ent[j].begin() + c.e1);
         nslots += (int)ent[j].size();
+        for (int e : ent[j]) {
+          const int col = S.ci[e];
+          if (slot[col] < 0 && made[col] >= (int)out.size() - 1) near_global = true;
+        }
+      }
+      if (near_global) {
+        RecHead h{};
+        const int32_t pos = out.empty() ? (fwd ? fpos[c.rows[0]] : bpos[c.rows[0]]) : out.back().pos;
+        push_record(h, kRecHead, pos, 0);
+        h.pos = pos;
+        std::memcpy(S.rec.data() + out.back().rec, &h, sizeof h);
       }
       const bool f32 = c.f32 != 0;
       const int sz = f32 ? 4 : 8;
       const RecLayout L = rec_layout(nr, nslots, c.mode, fwd, f32);
-      RecStep st{};
-      st.rec = (int32_t)S.rec.size();
-      st.len = L.total / 16;
-      st.pos = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
-      st.nrows = nr;
-      st.nslots = nslots;
-      st.mode = c.mode;
-      st.fp32 = c.f32;
-      st.piece = c.piece;
-      st.deps = L.deps;
-      st.vals = L.vals;
-      st.dinv = L.dinv;
-      st.rptr = L.rptr;
-      S.rec.resize(S.rec.size() + L.total, 0);
-      uint8_t *base = S.rec.data() + st.rec;
-      int32_t *head = reinterpret_cast<int32_t *>(base);
+      RecHead h{};
+      h.nrows = nr;
+      h.nslots = nslots;
+      h.mode = c.mode;
+      h.fp32 = c.f32;
+      h.piece = c.piece;
+      h.deps = L.deps;
+      h.vals = L.vals;
+      h.dinv = L.dinv;
+      h.rptr = L.rptr;
+      h.pos = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
+      std::vector<int32_t> koff(kMaxJdsWidth + 1, 0);
+      if (c.mode == 0) {
+        int width = 0;
+        for (int j = 0; j < nr; ++j) width = std::max(width, (int)ent[j].size());
+        h.width = width;
+        int q = 0;
+        for (int k = 0; k < width; ++k) {
+          h.koff[k] = q;
+          for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) ++q;
+        }
+        h.koff[width] = q;
+      }
+      uint8_t *base = push_record(h, L.total, h.pos, nr);
+      const int32_t rec0 = out.back().rec;
       int32_t *meta = reinterpret_cast<int32_t *>(base + kRecHead);
       int32_t *deps = reinterpret_cast<int32_t *>(base + L.deps);
       auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : -1 - bpos[col]; };
@@ -375,23 +410,22 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         const int i = c.rows[j];
         meta[4 * j] = slot[i];
         meta[4 * j + 1] = bpos[i];
+        // w: bit 0 = store to the global vector, bits 8.. = entry count
         if (fwd) {
-          meta[4 * j + 2] = 0;
-          meta[4 * j + 3] = 0;
+          meta[4 * j + 2] = -1;
+          meta[4 * j + 3] = 1;
         } else {
           const bool fine = i < S.nfine;
           meta[4 * j + 2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
           meta[4 * j + 3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
         }
+        meta[4 * j + 3] |= (int32_t)ent[j].size() << 8;
+        if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
       }
-      const int64_t vbase = (st.rec + L.vals) / sz;  // element index of the vals section
+      const int64_t vbase = (rec0 + L.vals) / sz;  // element index of the vals section
       if (c.mode == 0) {
-        int width = 0;
-        for (int j = 0; j < nr; ++j) width = std::max(width, (int)ent[j].size());
-        st.width = width;
         int q = 0;
-        for (int k = 0; k < width; ++k) {
-          head[k] = q;
+        for (int k = 0; k < h.width; ++k)
           for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) {
             const int e = ent[j][k];
             deps[q] = dep_of(S.ci[e]);
@@ -401,8 +435,6 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
             S.rl_to32.push_back((uint8_t)f32);
             ++q;
           }
-        }
-        head[width] = q;
       } else {
         int32_t *rptr = reinterpret_cast<int32_t *>(base + L.rptr);
         int q = 0;
@@ -420,7 +452,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         rptr[nr] = q;
       }
       if (!fwd) {
-        const int64_t dbase = (st.rec + L.dinv) / sz;
+        const int64_t dbase = (rec0 + L.dinv) / sz;
         for (int j = 0; j < nr; ++j) {
           S.rl_src.push_back(S.diag[c.rows[j]]);
           S.rl_base.push_back((int32_t)(dbase + j));
@@ -428,7 +460,6 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
           S.rl_to32.push_back((uint8_t)f32);
         }
       }
-      out.push_back(st);
     }
   };
   emit(fch, true, S.rf);
@@ -926,11 +957,15 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     auto place = [&](const std::vector<RecStep> &loc, std::vector<RecStep> &glob, int64_t off) {
       for (size_t k = 0; k < loc.size(); ++k) {
         RecStep st = loc[k];
+        RecHead h;
+        std::memcpy(&h, rb + st.rec, sizeof h);
         int32_t *meta = reinterpret_cast<int32_t *>(rb + st.rec + kRecHead);
-        int32_t *deps = reinterpret_cast<int32_t *>(rb + st.rec + st.deps);
-        for (int j = 0; j < st.nrows; ++j) meta[4 * j + 1] += pos_off;
-        for (int q = 0; q < st.nslots; ++q)
+        int32_t *deps = reinterpret_cast<int32_t *>(rb + st.rec + h.deps);
+        for (int j = 0; j < h.nrows; ++j) meta[4 * j + 1] += pos_off;
+        for (int q = 0; q < h.nslots; ++q)
           if (deps[q] < 0) deps[q] -= pos_off;
+        h.pos += pos_off;
+        std::memcpy(rb + st.rec, &h, sizeof h);
         st.rec = (int32_t)((o_rec[s] + st.rec) / 16);
         st.pos += pos_off;
         glob[off + k] = st;
