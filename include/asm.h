@@ -133,6 +133,9 @@ typedef struct {
                            /* when precision is FP32)                    */
   int32_t max_levels;    /* longest forward or backward level schedule   */
   int64_t device_bytes;  /* device memory held by the preconditioner     */
+  int64_t sweep_steps;   /* forward + backward sweep steps, all subdomains */
+  int64_t reloaded_rows; /* rows whose values are reloaded from global
+                            memory (no on-chip slot) during a sweep      */
 } asm_precond_stats;
 asm_status asm_precond_get_stats(asm_precond pc, asm_precond_stats *stats_host);
 

@@ -47,7 +47,7 @@ class PrecondStats(C.Structure):
     _fields_ = [("nsub", C.c_int32), ("ext_rows", C.c_int64), ("coarse_rows", C.c_int64),
                 ("factor_blocks", C.c_int64), ("fine_row_blocks", C.c_int64),
                 ("max_levels", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("sweep_steps", C.c_int64), ("reloaded_rows", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

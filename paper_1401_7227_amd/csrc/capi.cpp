@@ -472,10 +472,9 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   ap.fsrc = t32;
 #undef UP
   auto ALLOC = [&](auto **dst, size_t n) { return M.alloc(dst, n); };
-  double *yx, *rs, *trash, *crhs, *fact;
+  double *yx, *rs, *crhs, *fact;
   if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
       (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
-      (e = ALLOC(&trash, (size_t)P.nsub * 256 * 3)) != hipSuccess ||
       (e = ALLOC(&crhs, (size_t)std::max<int64_t>(1, P.total_coarse) * 3)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
@@ -483,7 +482,6 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   ap.yx = yx;
   ap.rs = rs;
-  ap.trash = trash;
   ap.crhs = crhs;
   d.fact = fact;
   if ((e = upload_gather(M, pc->asrc, P.asm_src, s)) != hipSuccess)
@@ -517,6 +515,8 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   pc->stats.fine_row_blocks = P.fine_row_entries;
   pc->stats.max_levels = P.max_levels;
   pc->stats.device_bytes = (int64_t)M.bytes;
+  pc->stats.sweep_steps = P.sweep_steps;
+  pc->stats.reloaded_rows = P.lds_spilled_rows;
   *out = pc;
   return ASM_OK;
 }

@@ -277,19 +277,30 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 // ---------------------------------------------------------------- ILU(0) apply
 // One workgroup per subdomain runs its forward sweep y = L^-1 R_i r and
 // backward sweep x = U^-1 y (D^-1 applied per row).  Every level step is a
-// contiguous record (see RecStep) streamed HBM -> registers -> LDS two steps
-// ahead of its use, so each step waits only on LDS and one barrier; the
-// vector values live in an LDS slot pool, and only values without a slot
-// (long-range dependencies) go through the global work vector.
+// contiguous record (see RecStep) that the streaming waves copy from HBM,
+// together with the step's row inputs, into one of three LDS buffers
+// several steps ahead of its use.  The computing waves then touch global
+// memory only to store results: vector values live in an LDS slot pool,
+// and values without a slot are reloaded into LDS by "fill" steps.
 constexpr int kRecU4 = kRecBytes / 16;
 constexpr int kStageU4 = kRecU4 / 256;
 static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
+static_assert(kMaxStepRows * 3 <= 3 * 256, "row inputs: three doubles per streaming thread");
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kConsumerThreads = 256;  // one thread per row of a step
 
+// Explicit address spaces: LDS reads must never become generic (flat)
+// accesses, whose completion is tracked together with global memory.
+#define ASMX_LDS __attribute__((address_space(3)))
+#define ASMX_GLB __attribute__((address_space(1)))
+typedef ASMX_LDS double lds_double;
+typedef const ASMX_LDS double lds_cdouble;
+typedef const ASMX_GLB double glb_cdouble;
+
 struct Stage {
   u32x4 v[kStageU4];
+  double x[3];
 };
 
 template <typename T>
@@ -298,53 +309,54 @@ __device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
   for (int e = 0; e < 9; ++e) b[e] = v[e * S];
 }
 
-// Value of a dependency: an LDS slot (d >= 0) or the global work vector.
-__device__ __forceinline__ void dep_value(int d, const double *vec, const double *__restrict__ yx, double &y0,
-                                          double &y1, double &y2) {
-  if (d >= 0) {
-    y0 = vec[3 * d]; y1 = vec[3 * d + 1]; y2 = vec[3 * d + 2];
-  } else {
-    const size_t g = 3 * (size_t)(-1 - d);
-    y0 = yx[g]; y1 = yx[g + 1]; y2 = yx[g + 2];
-  }
-}
-
 struct SweepLds {
   u32x4 buf[3][kRecU4];        // records of steps s, s+1 (and s-1 until overwritten)
-  double vec[3 * kVecSlots];    // vector slot pool
-  double stg[2][3 * 256];       // row results awaiting their global stores
+  double vec[3 * kVecSlots];    // vector slot pool (top kFillSlots: reloaded values)
   double part[4];               // partial sum of a split row
 };
 
-// Mode 0: one thread per row, entries in jagged diagonals.  (a0,a1,a2) is
-// the row's right-hand side (forward) or its forward result (backward).
-// All entries' LDS reads are issued before any is used: dependency
-// indices, then the dependency values, then the blocks.
+// A finished row: its LDS slot (later steps read it there) and its global
+// copies (the work vector, and the output cell of the restricted combine).
+__device__ __forceinline__ void row_out(const int4 &m, double t0, double t1, double t2, SweepLds &L,
+                                        double *__restrict__ yx, double *__restrict__ z) {
+  lds_double *w = (lds_double *)L.vec;
+  if (m.x >= 0) { w[3 * m.x] = t0; w[3 * m.x + 1] = t1; w[3 * m.x + 2] = t2; }
+  if (m.w & 1) {
+    double *g = yx + 3 * (size_t)m.y;
+    g[0] = t0; g[1] = t1; g[2] = t2;
+  }
+  if (m.z >= 0) {
+    double *g = z + 3 * (size_t)m.z;
+    g[0] = t0; g[1] = t1; g[2] = t2;
+  }
+}
+
+// Mode 0: one thread per row, entries in jagged diagonals.  The row header
+// holds the dependencies' slots, so the slot values are read right after
+// it; the blocks and the input need the step descriptor.
 template <bool FWD, typename T>
-__device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, SweepLds &L, double *stg,
-                                          const double *__restrict__ yx, double a0, double a1, double a2) {
+__device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, SweepLds &L, double *__restrict__ yx,
+                                          double *__restrict__ z) {
   const int j = threadIdx.x;
   if (j >= h.nrows) return;
-  const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
+  lds_cdouble *vec = (lds_cdouble *)L.vec;
+  const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead) + 2 * j;
+  const int4 m = hdr[0], dp = hdr[1];
   const int cnt = m.w >> 8;
-  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + h.deps);
-  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
-  const int4 ka = *reinterpret_cast<const int4 *>(reinterpret_cast<const RecHead *>(recp)->koff);
-  const int4 kb = *reinterpret_cast<const int4 *>(reinterpret_cast<const RecHead *>(recp)->koff + 4);
-  const int ko[kMaxJdsWidth] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
-  int d[kMaxJdsWidth];
-#pragma unroll
-  for (int k = 0; k < kMaxJdsWidth; ++k) d[k] = (k < cnt) ? deps[ko[k] + j] : 0;
+  const int d[kMaxJdsWidth] = {dp.x & 0xffff, (int)((unsigned)dp.x >> 16), dp.y & 0xffff, (int)((unsigned)dp.y >> 16),
+                               dp.z & 0xffff, (int)((unsigned)dp.z >> 16), dp.w & 0xffff, (int)((unsigned)dp.w >> 16)};
   double y[kMaxJdsWidth][3];
 #pragma unroll
   for (int k = 0; k < kMaxJdsWidth; ++k)
-    if (k < cnt) dep_value(d[k], L.vec, yx, y[k][0], y[k][1], y[k][2]);
-  T t0 = (T)a0, t1 = (T)a1, t2 = (T)a2;
+    if (k < cnt) { y[k][0] = vec[3 * d[k]]; y[k][1] = vec[3 * d[k] + 1]; y[k][2] = vec[3 * d[k] + 2]; }
+  const double *inp = reinterpret_cast<const double *>(recp + h.in) + 3 * j;
+  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
+  T t0 = (T)inp[0], t1 = (T)inp[1], t2 = (T)inp[2];
 #pragma unroll
   for (int k = 0; k < kMaxJdsWidth; ++k) {
     if (k < cnt) {
       T b[9];
-      block9<T>(vals + ko[k] + j, h.nslots, b);
+      block9<T>(vals + h.koff[k] + j, h.nslots, b);
       const T u0 = (T)y[k][0], u1 = (T)y[k][1], u2 = (T)y[k][2];
       t0 -= b[0] * u0 + b[1] * u1 + b[2] * u2;
       t1 -= b[3] * u0 + b[4] * u1 + b[5] * u2;
@@ -359,25 +371,24 @@ __device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, Sw
     const T x2 = dv[6] * t0 + dv[7] * t1 + dv[8] * t2;
     t0 = x0; t1 = x1; t2 = x2;
   }
-  if (m.x >= 0) { L.vec[3 * m.x] = (double)t0; L.vec[3 * m.x + 1] = (double)t1; L.vec[3 * m.x + 2] = (double)t2; }
-  stg[3 * j] = (double)t0; stg[3 * j + 1] = (double)t1; stg[3 * j + 2] = (double)t2;
+  row_out(m, (double)t0, (double)t1, (double)t2, L, yx, z);
 }
 
 // Mode 1: one wavefront per (long) row; lanes stride over its entries.
 // Pieces of a split row carry their partial sum in LDS.
 template <bool FWD, typename T>
-__device__ __forceinline__ void step_long_rows(const RecHead &h, const char *recp, SweepLds &L, double *stg,
-                                               const double *__restrict__ in, const double *__restrict__ yx) {
-  // consumer waves only (the producer waves stream records)
+__device__ __forceinline__ void step_long_rows(const RecHead &h, const char *recp, SweepLds &L,
+                                               double *__restrict__ yx, double *__restrict__ z) {
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = kConsumerThreads / kWave;
+  lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int32_t *deps = reinterpret_cast<const int32_t *>(recp + h.deps);
   const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + h.rptr);
   const T *vals = reinterpret_cast<const T *>(recp + h.vals);
   for (int j = wv; j < h.nrows; j += nw) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = rptr[j] + lane; q < rptr[j + 1]; q += kWave) {
-      double y0, y1, y2;
-      dep_value(deps[q], L.vec, yx, y0, y1, y2);
+      const int d = deps[q];
+      const double y0 = vec[3 * d], y1 = vec[3 * d + 1], y2 = vec[3 * d + 2];
       const T *b = vals + 9 * q;
       s0 += (double)b[0] * y0 + (double)b[1] * y1 + (double)b[2] * y2;
       s1 += (double)b[3] * y0 + (double)b[4] * y1 + (double)b[5] * y2;
@@ -391,8 +402,8 @@ __device__ __forceinline__ void step_long_rows(const RecHead &h, const char *rec
       if (h.piece == kPieceMiddle || h.piece == kPieceLast) {
         a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
       } else {
-        const size_t g = 3 * (size_t)(h.pos + j);
-        a0 = in[g]; a1 = in[g + 1]; a2 = in[g + 2];
+        const double *inp = reinterpret_cast<const double *>(recp + h.in) + 3 * j;
+        a0 = inp[0]; a1 = inp[1]; a2 = inp[2];
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
       if (h.piece == kPieceFirst || h.piece == kPieceMiddle) {
@@ -406,162 +417,132 @@ __device__ __forceinline__ void step_long_rows(const RecHead &h, const char *rec
           const double x2 = (double)dv[6 * S] * a0 + (double)dv[7 * S] * a1 + (double)dv[8 * S] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
-        const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[j];
-        if (m.x >= 0) { L.vec[3 * m.x] = a0; L.vec[3 * m.x + 1] = a1; L.vec[3 * m.x + 2] = a2; }
-        stg[3 * j] = a0; stg[3 * j + 1] = a1; stg[3 * j + 2] = a2;
+        const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
+        row_out(m, a0, a1, a2, L, yx, z);
       }
     }
   }
 }
 
-// Global stores of the previous step's results: thread t stores row t, every
-// thread issues the same two stores (rows without a destination, and threads
-// past the step, write to their own discard slot), keeping the memory
-// operation count of an iteration independent of the data.
-__device__ __forceinline__ void epilogue(const char *recp, int nrows, const double *stg, double *__restrict__ yx,
-                                         double *__restrict__ z, double *__restrict__ trash) {
-  const int t = threadIdx.x;
-  double *dA = trash, *dB = trash;
-  if (t < nrows) {
-    const RecHead *h = reinterpret_cast<const RecHead *>(recp);
-    if (h->piece == kPieceWhole || h->piece == kPieceLast) {
-      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[t];
-      if (m.w & 1) dA = yx + 3 * (size_t)m.y;
-      if (m.z >= 0) dB = z + 3 * (size_t)m.z;
-    }
+// Fill step: reloads values of the next step that have no LDS slot of
+// their own from the global vector (stored before an earlier barrier).
+__device__ __forceinline__ void fill_values(const RecHead &h, const char *recp, SweepLds &L,
+                                            const double *__restrict__ yx) {
+  const ASMX_LDS int32_t *fl = (const ASMX_LDS int32_t *)(recp + h.fill);
+  lds_double *w = (lds_double *)L.vec;
+  for (int q = threadIdx.x; q < h.nfill; q += kConsumerThreads) {
+    const int gpos = fl[2 * q], slot = fl[2 * q + 1];
+    glb_cdouble *src = (glb_cdouble *)yx + 3 * (size_t)gpos;
+    const double v0 = src[0], v1 = src[1], v2 = src[2];
+    w[3 * slot] = v0; w[3 * slot + 1] = v1; w[3 * slot + 2] = v2;
   }
-  const double v0 = stg[3 * t], v1 = stg[3 * t + 1], v2 = stg[3 * t + 2];
-  dA[0] = v0; dA[1] = v1; dA[2] = v2;
-  dB[0] = v0; dB[1] = v1; dB[2] = v2;
 }
-
-// Input of row j of a mode-0 step: its right-hand side (forward, from the
-// gathered stream) or its forward result (backward).  Rows past the step
-// read its first row.
-__device__ __forceinline__ void fetch_in(const RecStep &st, const double *__restrict__ src, double &g0, double &g1,
-                                         double &g2) {
-  const size_t g = 3 * (size_t)(st.pos + max(0, min((int)threadIdx.x, st.nrows - 1)));
-  g0 = src[g]; g1 = src[g + 1]; g2 = src[g + 2];
-}
-
-struct In3 {
-  double a, b, c;
-};
 
 // The sweep runs with wave-specialised roles.  Waves 0-3 (one thread per
-// row) compute the steps; waves 4-7 only stream records: each producer
-// thread keeps kAhead future records in registers and moves the next one
-// into LDS every step, so several records are in flight while the
-// consumers compute.  Both roles execute the same sequence of barriers.
+// row) compute the steps; waves 4-7 only stream: each streaming thread
+// keeps kAhead future records (and their row inputs) in registers and
+// moves the next one into LDS every step, so several steps are in flight
+// while the computing waves work.  Both roles execute the same sequence of
+// barriers.
 constexpr int kAhead = 4;
 
 struct Producer {
   Stage st[kAhead];
   int len[kAhead];
+  int xlast[kAhead];
 };
 
-// Producer: load record k of the sweep (clamped to the last step) into
-// stage slot k % kAhead.
-__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec, Stage &st, int &len,
-                                          int t) {
+// Streamer: load record k of the sweep and its row inputs (3 doubles per
+// row from src at the step's positions) into a stage.  Loads are clamped
+// to the record / the input segment, never conditional.
+__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec,
+                                          const double *__restrict__ src, Stage &st, int &len, int &xlast, int t) {
 #pragma unroll
   for (int i = 0; i < kStageU4; ++i) st.v[i] = rec[d.rec + min(i * 256 + t, d.len - 1)];
+  const int last = 3 * max(d.nrows, 1) - 1;
+  const double *xs = src + 3 * (size_t)d.pos;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) st.x[i] = xs[min(i * 256 + t, last)];
   len = d.len;
+  xlast = last;
 }
 
-// Stores the whole buffer unconditionally: words past the record are
-// copies of its last word and land in the unused tail of the buffer.
-__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int, int t) {
+// Stores a stage into an LDS buffer: the record words, then the inputs
+// right behind the record.
+__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len, int xlast, int t) {
 #pragma unroll
-  for (int i = 0; i < kStageU4; ++i) dst[i * 256 + t] = st.v[i];
+  for (int i = 0; i < kStageU4; ++i)
+    if (i * 256 + t < len) dst[i * 256 + t] = st.v[i];
+  double *xd = reinterpret_cast<double *>(dst + len);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (i * 256 + t <= xlast) xd[i * 256 + t] = st.x[i];
 }
 
 template <int K>
 __device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restrict__ steps,
-                                          const u32x4 *__restrict__ rec, SweepLds &L, Producer &P, RecStep &dn,
-                                          int t) {
+                                          const u32x4 *__restrict__ rec, const double *__restrict__ src,
+                                          SweepLds &L, Producer &P, RecStep &dn, int t) {
   // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
   // the stage for record s+1+kAhead (descriptor loaded last iteration)
-  prod_store(L.buf[(s + 1) % 3], P.st[K], P.len[K], t);
+  prod_store(L.buf[(s + 1) % 3], P.st[K], P.len[K], P.xlast[K], t);
   const RecStep d = dn;
-  prod_load(d, rec, P.st[K], P.len[K], t);
+  prod_load(d, rec, src, P.st[K], P.len[K], P.xlast[K], t);
   dn = steps[min(s + 2 + kAhead, S - 1)];
   __syncthreads();
 }
 
 __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
-                                               const u32x4 *__restrict__ rec, SweepLds &L) {
+                                               const u32x4 *__restrict__ rec, const double *__restrict__ src,
+                                               SweepLds &L) {
   if (S == 0) return;
   const int t = threadIdx.x - kConsumerThreads;
   Producer P;
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) prod_load(steps[min(k, S - 1)], rec, P.st[k], P.len[k], t);
-  prod_store(L.buf[0], P.st[0], P.len[0], t);
-  prod_load(steps[min(kAhead, S - 1)], rec, P.st[0], P.len[0], t);
+  for (int k = 0; k < kAhead; ++k) prod_load(steps[min(k, S - 1)], rec, src, P.st[k], P.len[k], P.xlast[k], t);
+  prod_store(L.buf[0], P.st[0], P.len[0], P.xlast[0], t);
+  prod_load(steps[min(kAhead, S - 1)], rec, src, P.st[0], P.len[0], P.xlast[0], t);
   RecStep dn = steps[min(1 + kAhead, S - 1)];
   __syncthreads();
-  static_assert(kAhead == 4, "the unrolled producer loop assumes four stages");
+  static_assert(kAhead == 4, "the unrolled streaming loop assumes four stages");
   // full groups of kAhead steps without conditions (exact wait counts),
   // then the remaining steps in straight-line code
   int s = 0;
   for (; s + kAhead <= S; s += kAhead) {
-    prod_iter<1>(s, S, steps, rec, L, P, dn, t);
-    prod_iter<2>(s + 1, S, steps, rec, L, P, dn, t);
-    prod_iter<3>(s + 2, S, steps, rec, L, P, dn, t);
-    prod_iter<0>(s + 3, S, steps, rec, L, P, dn, t);
+    prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+    prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+    prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
+    prod_iter<0>(s + 3, S, steps, rec, src, L, P, dn, t);
   }
-  if (s < S) prod_iter<1>(s, S, steps, rec, L, P, dn, t);
-  if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, L, P, dn, t);
-  if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, L, P, dn, t);
-  __syncthreads();  // matches the consumers' final epilogue barrier
+  if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+  if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+  if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
+  __syncthreads();  // matches the computing waves' final epilogue barrier
 }
 
-// Consumer iteration for step s: global stores of step s-1, compute of step
-// s from LDS, inputs of step s+3 (descriptor loaded last iteration).
+// Computing iteration for step s: step s from LDS (or the reloads of a
+// fill step), results stored at once.
 template <bool FWD>
-__device__ __forceinline__ void cons_iter(int s, int S, const RecStep *__restrict__ steps, SweepLds &L, In3 &g,
-                                          RecStep &dn, const double *__restrict__ in, double *__restrict__ yx,
-                                          double *__restrict__ z, double *__restrict__ trash) {
-  const int prev_rows = (s > 0) ? reinterpret_cast<const RecHead *>(L.buf[(s + 2) % 3])->nrows : 0;
-  epilogue(reinterpret_cast<const char *>(L.buf[(s + 2) % 3]), prev_rows, L.stg[(s + 1) & 1], yx, z, trash);
+__device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
   const char *recp = reinterpret_cast<const char *>(L.buf[s % 3]);
   const RecHead h = *reinterpret_cast<const RecHead *>(recp);
-  double *stg = L.stg[s & 1];
   if (h.mode == 0) {
-    if (h.fp32) step_rows<FWD, float>(h, recp, L, stg, yx, g.a, g.b, g.c);
-    else step_rows<FWD, double>(h, recp, L, stg, yx, g.a, g.b, g.c);
+    if (h.fp32) step_rows<FWD, float>(h, recp, L, yx, z);
+    else step_rows<FWD, double>(h, recp, L, yx, z);
   } else {
-    if (h.fp32) step_long_rows<FWD, float>(h, recp, L, stg, in, yx);
-    else step_long_rows<FWD, double>(h, recp, L, stg, in, yx);
+    if (h.fp32) step_long_rows<FWD, float>(h, recp, L, yx, z);
+    else step_long_rows<FWD, double>(h, recp, L, yx, z);
   }
-  const RecStep d3 = dn;
-  fetch_in(d3, in, g.a, g.b, g.c);
-  dn = steps[min(s + 4, S - 1)];
+  if (h.nfill > 0) fill_values(h, recp, L, yx);
   __syncthreads();
 }
 
 template <bool FWD>
-__device__ __forceinline__ void consumer_sweep(const RecStep *__restrict__ steps, int S, SweepLds &L,
-                                               const double *__restrict__ in, double *__restrict__ yx,
-                                               double *__restrict__ z, double *__restrict__ trash) {
+__device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
   if (S == 0) return;
-  In3 g0, g1, g2;
-  fetch_in(steps[0], in, g0.a, g0.b, g0.c);
-  fetch_in(steps[min(1, S - 1)], in, g1.a, g1.b, g1.c);
-  fetch_in(steps[min(2, S - 1)], in, g2.a, g2.b, g2.c);
-  RecStep dn = steps[min(3, S - 1)];
   __syncthreads();
-  int s = 0;
-  for (; s + 3 <= S; s += 3) {
-    cons_iter<FWD>(s, S, steps, L, g0, dn, in, yx, z, trash);
-    cons_iter<FWD>(s + 1, S, steps, L, g1, dn, in, yx, z, trash);
-    cons_iter<FWD>(s + 2, S, steps, L, g2, dn, in, yx, z, trash);
-  }
-  if (s < S) cons_iter<FWD>(s, S, steps, L, g0, dn, in, yx, z, trash);
-  if (s + 1 < S) cons_iter<FWD>(s + 1, S, steps, L, g1, dn, in, yx, z, trash);
-  const char *lastp = reinterpret_cast<const char *>(L.buf[(S - 1) % 3]);
-  epilogue(lastp, reinterpret_cast<const RecHead *>(lastp)->nrows, L.stg[(S - 1) & 1], yx, z, trash);
-  __syncthreads();
+  for (int s = 0; s < S; ++s) cons_iter<FWD>(s, L, yx, z);
+  __syncthreads();  // matches the streaming waves' final barrier
 }
 
 __global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
@@ -570,12 +551,11 @@ __global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *
   const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
   const int nf = sd.rf1 - sd.rf0, nb = sd.rb1 - sd.rb0;
   if (threadIdx.x < kConsumerThreads) {
-    double *trash = p.trash + 3 * ((size_t)blockIdx.x * 256 + threadIdx.x);
-    consumer_sweep<true>(p.fstep + sd.rf0, nf, L, p.rs, p.yx, z, trash);
-    consumer_sweep<false>(p.bstep + sd.rb0, nb, L, p.yx, p.yx, z, trash);
+    consumer_sweep<true>(nf, L, p.yx, z);
+    consumer_sweep<false>(nb, L, p.yx, z);
   } else {
-    producer_sweep(p.fstep + sd.rf0, nf, rec, L);
-    producer_sweep(p.bstep + sd.rb0, nb, rec, L);
+    producer_sweep(p.fstep + sd.rf0, nf, rec, p.rs, L);
+    producer_sweep(p.bstep + sd.rb0, nb, rec, p.yx, L);
   }
 }
 

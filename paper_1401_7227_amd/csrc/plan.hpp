@@ -26,36 +26,51 @@ constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (3 b
 #define ASM_VEC_SLOTS 2048
 #endif
 constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
+static_assert(kVecSlots <= 65536, "slots are stored as 16-bit indices");
 constexpr int kMaxJdsWidth = 8;    // mode-0 rows have at most this many entries
 constexpr int kMaxStepRows = 256;  // rows per step (one thread per row)
+
+#ifndef ASM_FILL_SLOTS
+#define ASM_FILL_SLOTS 256
+#endif
+constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values reloaded from global memory
 
 // One step of a sweep.  The record starts with its own descriptor (read
 // from LDS once the record has arrived); a compact {rec, len, pos, nrows}
 // array per sweep drives the prefetch.  Record sections (byte offsets from
 // the record start, each 16-byte aligned):
 //   head  RecHead (kRecHead bytes).
-//   meta  int4 per row: {LDS slot or -1, own position, output cell or -1,
-//         flags}; flags bit 0 = store the value to the global vector at the
-//         own position (always in the forward sweep), bits 8.. = the row's
-//         entry count.
-//   deps  int per entry: >= 0 an LDS slot, < 0 the global position -1-d.
+//   rows  32 bytes per row: int4 {LDS slot or -1, own position, output
+//         cell or -1, flags}, flags bit 0 = store the value to the global
+//         vector at the own position (always in the forward sweep), bits
+//         8.. = the row's entry count; then (mode 0) the LDS slots of the
+//         row's dependencies, 8 x uint16.
+//   deps  mode 1: int per entry, the LDS slot of the dependency's value.
 //   rptr  mode 1: nrows+1 relative entry offsets.
 //   vals  mode 0: jagged-diagonal SoA, component e of entry q at
 //         [e*nslots + q], entry q = koff[k] + j for row j's k-th entry
 //         (rows sorted by entry count, descending); mode 1: 9 per entry.
 //   dinv  backward: component e of row j at [e*nrows + j].
+//   fill  int2 per value {global position, slot}: values of the NEXT step
+//         that have no LDS slot of their own, reloaded from the global
+//         vector into the fill slots (only in empty "fill" steps).
+// The stored record ends there (len 16-byte units); in LDS it is followed
+// by the "in" section, 3 doubles per row (at least one row): the rows'
+// inputs (forward: gathered right-hand side; backward: forward result),
+// which the streaming waves copy from the global vectors at the step's
+// positions.
 // A mode-1 row whose record would not fit one LDS buffer is split into
 // pieces in consecutive one-row steps that carry the partial sum in LDS.
-// Values read through the global vector are produced at least two steps
-// before their use (the host inserts empty steps where needed), because
-// results reach global memory one step after they are computed.
+// A value reloaded by a fill step is produced at least two steps before
+// it (the host inserts empty steps where needed), because results reach
+// global memory one step after they are computed.
 enum { kPieceWhole = 0, kPieceFirst = 1, kPieceMiddle = 2, kPieceLast = 3 };
 
 struct RecHead {
   int32_t nrows, nslots, mode, fp32, piece, width;
-  int32_t deps, vals, dinv, rptr, pos, pad;
+  int32_t deps, vals, dinv, rptr, pos, in;
   int32_t koff[kMaxJdsWidth + 1];  // mode 0: first entry of each jagged diagonal
-  int32_t pad2[3];
+  int32_t nfill, fill, pad;
 };
 constexpr int kRecHead = (int)sizeof(RecHead);
 static_assert(kRecHead % 16 == 0, "record head must keep 16-byte alignment");
@@ -74,7 +89,6 @@ struct ApplyPlan {
   const void *rec;              // all records (16-byte aligned)
   double *rs;                   // 3 doubles per forward position: gathered rhs
   double *yx;                   // 3 doubles per backward position
-  double *trash;                // 3 doubles per thread of the grid (discarded stores)
   const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
   const double *crhs;           // 3 doubles per coarse row
 };

@@ -189,15 +189,19 @@ void triples_to_csr(std::vector<std::array<int32_t, 3>> &t, int32_t nrows, std::
 inline int32_t align16(int64_t b) { return (int32_t)((b + 15) & ~int64_t(15)); }
 
 // Record section offsets for a step of nrows rows and nslots entries.
+// total: bytes stored in global memory; lds: bytes the record occupies in
+// an LDS buffer (stored part plus the rows' inputs).
 struct RecLayout {
-  int32_t deps, rptr, vals, dinv, total;
+  int32_t deps, rptr, vals, dinv, total, lds;
 };
+
+inline int32_t in_bytes(int nrows) { return align16((int64_t)24 * std::max(nrows, 1)); }
 
 RecLayout rec_layout(int nrows, int nslots, int mode, bool fwd, bool f32) {
   const int sz = f32 ? 4 : 8;
   RecLayout L{};
-  L.deps = kRecHead + align16((int64_t)16 * nrows);
-  int32_t at = L.deps + align16((int64_t)4 * nslots);
+  L.deps = kRecHead + 32 * nrows;
+  int32_t at = L.deps + (mode == 1 ? align16((int64_t)4 * nslots) : 0);
   L.rptr = at;
   if (mode == 1) at += align16((int64_t)4 * (nrows + 1));
   L.vals = at;
@@ -205,6 +209,7 @@ RecLayout rec_layout(int nrows, int nslots, int mode, bool fwd, bool f32) {
   L.dinv = at;
   if (!fwd) at += align16((int64_t)9 * nrows * sz);
   L.total = at;
+  L.lds = at + in_bytes(nrows);
   return L;
 }
 
@@ -249,16 +254,16 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
           for (int i : rows) {
             const int c = count(i, fwd);
             const int nr = (int)cur.rows.size() + 1;
-            const bool fits = nr <= kMaxStepRows && rec_layout(nr, slots + c, mode, fwd, f32).total <= kRecBytes;
+            const bool fits = nr <= kMaxStepRows && rec_layout(nr, slots + c, mode, fwd, f32).lds <= kRecBytes;
             if (!fits && !cur.rows.empty()) {
               out.push_back(cur);
               cur.rows.clear();
               slots = 0;
             }
-            if (rec_layout(1, c, mode, fwd, f32).total > kRecBytes) {
+            if (rec_layout(1, c, mode, fwd, f32).lds > kRecBytes) {
               // a row too long for one buffer: consecutive one-row pieces
               int per = c;
-              while (rec_layout(1, per, mode, fwd, f32).total > kRecBytes) per = (per + 1) / 2;
+              while (rec_layout(1, per, mode, fwd, f32).lds > kRecBytes) per = (per + 1) / 2;
               const int np = (c + per - 1) / per;
               for (int k = 0; k < np; ++k) {
                 Chunk pc{{i}, mode, f32 ? 1 : 0};
@@ -309,7 +314,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
     slot.assign(S.n, -1);
     std::vector<std::pair<int32_t, int32_t>> heap;  // (last use, slot), min-heap
     std::vector<int32_t> freel;
-    for (int q = kVecSlots - 1; q >= 0; --q) freel.push_back(q);
+    for (int q = kVecSlots - kFillSlots - 1; q >= 0; --q) freel.push_back(q);
     auto cmp = [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) { return a > b; };
     for (size_t k = 0; k < ch.size(); ++k) {
       while (!heap.empty() && heap.front().first < (int32_t)k) {
@@ -333,12 +338,103 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
   std::vector<int32_t> fslot, flast, bslot, blast;
   allocate(fch, true, fslot, flast);
   allocate(bch, false, bslot, blast);
-  // records; an empty step is inserted wherever a value read through the
-  // global vector would be needed one step after the step producing it
-  auto emit = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<RecStep> &out) {
+  // Entries of a chunk (row-relative CSR entry lists, piece ranges applied).
+  auto chunk_entries = [&](const Chunk &c, bool fwd) {
+    std::vector<std::vector<int32_t>> ent(c.rows.size());
+    for (size_t j = 0; j < c.rows.size(); ++j) {
+      const int i = c.rows[j];
+      for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
+        if (fwd ? S.ci[e] < i : S.ci[e] > i) ent[j].push_back(e);
+      if (c.piece != kPieceWhole) ent[j] = std::vector<int32_t>(ent[j].begin() + c.e0, ent[j].begin() + c.e1);
+    }
+    return ent;
+  };
+  // Splits a chunk so that no part reads more than kFillSlots values that
+  // have no LDS slot: rows of a step are independent, and a long row splits
+  // into further pieces.
+  auto split_for_fills = [&](const Chunk &c, bool fwd, const std::vector<int32_t> &slot) {
+    auto add_spilled = [&](int e, std::vector<int32_t> &set) {
+      const int col = S.ci[e];
+      if (slot[col] < 0 && std::find(set.begin(), set.end(), col) == set.end()) set.push_back(col);
+    };
+    std::vector<Chunk> out;
+    auto split_row = [&](const Chunk &c1) {
+      const int i = c1.rows[0];
+      std::vector<int32_t> all;
+      for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
+        if (fwd ? S.ci[e] < i : S.ci[e] > i) all.push_back(e);
+      const int lo = c1.piece == kPieceWhole ? 0 : c1.e0;
+      const int hi = c1.piece == kPieceWhole ? (int)all.size() : c1.e1;
+      std::vector<std::pair<int, int>> ranges;
+      std::vector<int32_t> set;
+      int start = lo;
+      for (int q = lo; q < hi; ++q) {
+        std::vector<int32_t> t = set;
+        add_spilled(all[q], t);
+        if ((int)t.size() > kFillSlots) {
+          ranges.push_back({start, q});
+          start = q;
+          t.clear();
+          add_spilled(all[q], t);
+        }
+        set = t;
+      }
+      ranges.push_back({start, hi});
+      if (ranges.size() == 1) {
+        out.push_back(c1);
+        return;
+      }
+      const bool open = (c1.piece == kPieceWhole || c1.piece == kPieceFirst);
+      const bool close = (c1.piece == kPieceWhole || c1.piece == kPieceLast);
+      for (size_t k = 0; k < ranges.size(); ++k) {
+        Chunk p = c1;
+        p.e0 = ranges[k].first;
+        p.e1 = ranges[k].second;
+        p.piece = (k == 0 && open) ? kPieceFirst : ((k + 1 == ranges.size() && close) ? kPieceLast : kPieceMiddle);
+        out.push_back(p);
+      }
+    };
+    const auto ent = chunk_entries(c, fwd);
+    std::vector<int32_t> total;
+    for (const auto &es : ent)
+      for (int e : es) add_spilled(e, total);
+    if ((int)total.size() <= kFillSlots) return std::vector<Chunk>{c};
+    if (c.rows.size() == 1) {
+      split_row(c);
+      return out;
+    }
+    // several whole rows: greedy groups of consecutive rows
+    Chunk cur{{}, c.mode, c.f32};
+    std::vector<int32_t> set;
+    auto flush = [&]() {
+      if (cur.rows.size() == 1) split_row(cur);
+      else if (!cur.rows.empty()) out.push_back(cur);
+      cur.rows.clear();
+    };
+    for (size_t j = 0; j < c.rows.size(); ++j) {
+      std::vector<int32_t> t = set;
+      for (int e : ent[j]) add_spilled(e, t);
+      if ((int)t.size() > kFillSlots && !cur.rows.empty()) {
+        flush();
+        t.clear();
+        for (int e : ent[j]) add_spilled(e, t);
+      }
+      cur.rows.push_back(c.rows[j]);
+      set = t;
+    }
+    flush();
+    return out;
+  };
+  // Records.  Before a step that reads values without an LDS slot, a fill
+  // step reloads them from the global vector into the fill slots; empty
+  // steps keep that reload at least two steps after the values' producers.
+  auto emit = [&](const std::vector<Chunk> &ch0, bool fwd, std::vector<RecStep> &out) {
     const std::vector<int32_t> &slot = fwd ? fslot : bslot;
     const std::vector<int32_t> &last = fwd ? flast : blast;
     std::vector<int32_t> made(S.n, -1);  // emitted step that produced each row
+    std::vector<Chunk> ch;
+    for (const Chunk &c : ch0)
+      for (Chunk &p : split_for_fills(c, fwd, slot)) ch.push_back(std::move(p));
     auto push_record = [&](const RecHead &h, int32_t total, int32_t pos, int32_t nrows) -> uint8_t * {
       RecStep st{};
       st.rec = (int32_t)S.rec.size();
@@ -351,29 +447,45 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       out.push_back(st);
       return base;
     };
+    std::vector<int32_t> fill_of(S.n, -1);  // fill slot of a value for the current step
     for (const Chunk &c : ch) {
       const int nr = (int)c.rows.size();
-      std::vector<std::vector<int32_t>> ent(nr);
+      const auto ent = chunk_entries(c, fwd);
+      const int32_t pos0 = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
       int nslots = 0;
-      bool near_global = false;
+      std::vector<int32_t> fills;  // columns to reload, in first-use order
+      int32_t newest = -1;
       for (int j = 0; j < nr; ++j) {
-        const int i = c.rows[j];
-        for (int e = S.rp[i]; e < S.rp[i + 1]; ++e)
-          if (fwd ? S.ci[e] < i : S.ci[e] > i) ent[j].push_back(e);
-        if (c.piece != kPieceWhole)
-          ent[j] = std::vector<int32_t>(ent[j].begin() + c.e0, ent[j].begin() + c.e1);
         nslots += (int)ent[j].size();
         for (int e : ent[j]) {
           const int col = S.ci[e];
-          if (slot[col] < 0 && made[col] >= (int)out.size() - 1) near_global = true;
+          if (slot[col] >= 0 || fill_of[col] >= 0) continue;
+          fill_of[col] = (int32_t)fills.size();
+          fills.push_back(col);
+          newest = std::max(newest, made[col]);
         }
       }
-      if (near_global) {
-        RecHead h{};
-        const int32_t pos = out.empty() ? (fwd ? fpos[c.rows[0]] : bpos[c.rows[0]]) : out.back().pos;
-        push_record(h, kRecHead, pos, 0);
-        h.pos = pos;
-        std::memcpy(S.rec.data() + out.back().rec, &h, sizeof h);
+      if (!fills.empty()) {
+        // the fill step (index out.size()) must come two steps after the
+        // newest producer
+        while ((int32_t)out.size() < newest + 2) {
+          RecHead e{};
+          e.pos = out.empty() ? pos0 : out.back().pos;
+          e.in = kRecHead;
+          push_record(e, kRecHead, e.pos, 0);
+        }
+        RecHead f{};
+        f.pos = out.empty() ? pos0 : out.back().pos;
+        f.nfill = (int32_t)fills.size();
+        f.fill = kRecHead;
+        const int32_t total = kRecHead + align16((int64_t)8 * fills.size());
+        f.in = total;
+        uint8_t *fb = push_record(f, total, f.pos, 0);
+        int32_t *fl = reinterpret_cast<int32_t *>(fb + kRecHead);
+        for (size_t q = 0; q < fills.size(); ++q) {
+          fl[2 * q] = bpos[fills[q]];
+          fl[2 * q + 1] = kVecSlots - kFillSlots + (int32_t)q;
+        }
       }
       const bool f32 = c.f32 != 0;
       const int sz = f32 ? 4 : 8;
@@ -388,8 +500,8 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       h.vals = L.vals;
       h.dinv = L.dinv;
       h.rptr = L.rptr;
-      h.pos = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
-      std::vector<int32_t> koff(kMaxJdsWidth + 1, 0);
+      h.in = L.total;
+      h.pos = pos0;
       if (c.mode == 0) {
         int width = 0;
         for (int j = 0; j < nr; ++j) width = std::max(width, (int)ent[j].size());
@@ -405,21 +517,26 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       const int32_t rec0 = out.back().rec;
       int32_t *meta = reinterpret_cast<int32_t *>(base + kRecHead);
       int32_t *deps = reinterpret_cast<int32_t *>(base + L.deps);
-      auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : -1 - bpos[col]; };
+      auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : kVecSlots - kFillSlots + fill_of[col]; };
       for (int j = 0; j < nr; ++j) {
         const int i = c.rows[j];
-        meta[4 * j] = slot[i];
-        meta[4 * j + 1] = bpos[i];
-        // w: bit 0 = store to the global vector, bits 8.. = entry count
+        int32_t *m = meta + 8 * j;
+        m[0] = slot[i];
+        m[1] = bpos[i];
+        // flags: bit 0 = store to the global vector, bits 8.. = entry count
         if (fwd) {
-          meta[4 * j + 2] = -1;
-          meta[4 * j + 3] = 1;
+          m[2] = -1;
+          m[3] = 1;
         } else {
           const bool fine = i < S.nfine;
-          meta[4 * j + 2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
-          meta[4 * j + 3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
+          m[2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
+          m[3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
         }
-        meta[4 * j + 3] |= (int32_t)ent[j].size() << 8;
+        m[3] |= (int32_t)ent[j].size() << 8;
+        if (c.mode == 0) {
+          uint16_t *dp = reinterpret_cast<uint16_t *>(m + 4);
+          for (size_t k = 0; k < ent[j].size(); ++k) dp[k] = (uint16_t)dep_of(S.ci[ent[j][k]]);
+        }
         if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
       }
       const int64_t vbase = (rec0 + L.vals) / sz;  // element index of the vals section
@@ -428,7 +545,6 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         for (int k = 0; k < h.width; ++k)
           for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) {
             const int e = ent[j][k];
-            deps[q] = dep_of(S.ci[e]);
             S.rl_src.push_back(e);
             S.rl_base.push_back((int32_t)(vbase + q));
             S.rl_stride.push_back(nslots);
@@ -451,6 +567,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         }
         rptr[nr] = q;
       }
+      for (int col : fills) fill_of[col] = -1;
       if (!fwd) {
         const int64_t dbase = (rec0 + L.dinv) / sz;
         for (int j = 0; j < nr; ++j) {
@@ -951,7 +1068,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
       const int32_t f = S.fsrc[q];
       P.fsrc[pos_off + q] = f >= 0 ? f : -(int32_t)(1 + o_coarse[s] + (-f - 1));
     }
-    // records: shift positions and global dependencies by the subdomain offset
+    // records: shift positions (rows and reloads) by the subdomain offset
     uint8_t *rb = P.rec.data() + o_rec[s];
     std::copy(S.rec.begin(), S.rec.end(), rb);
     auto place = [&](const std::vector<RecStep> &loc, std::vector<RecStep> &glob, int64_t off) {
@@ -960,10 +1077,9 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         RecHead h;
         std::memcpy(&h, rb + st.rec, sizeof h);
         int32_t *meta = reinterpret_cast<int32_t *>(rb + st.rec + kRecHead);
-        int32_t *deps = reinterpret_cast<int32_t *>(rb + st.rec + h.deps);
-        for (int j = 0; j < h.nrows; ++j) meta[4 * j + 1] += pos_off;
-        for (int q = 0; q < h.nslots; ++q)
-          if (deps[q] < 0) deps[q] -= pos_off;
+        for (int j = 0; j < h.nrows; ++j) meta[8 * j + 1] += pos_off;
+        int32_t *fl = reinterpret_cast<int32_t *>(rb + st.rec + h.fill);
+        for (int q = 0; q < h.nfill; ++q) fl[2 * q] += pos_off;
         h.pos += pos_off;
         std::memcpy(rb + st.rec, &h, sizeof h);
         st.rec = (int32_t)((o_rec[s] + st.rec) / 16);
