@@ -15,6 +15,7 @@ region; the dominant kernel's algorithmic bytes per launch divided by its
 mean launch time give the roofline figure (HBM peak 8 TB/s).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,28 @@ SPLIT = dict(sx=16, sy=16, overlap=1)
 NEAR, FAR = (4, 4, 4), (16, 16, 16)
 HBM_PEAK_GBS = 8000.0
 RESTART = 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ilu_apply_two_level_1M_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_7227_amd", "csrc", "kernels.hip")
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
+
+
+def kernel_source_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter runs (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by what the same counter reads
+    for a copy of known size), or None if the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return (t["fetch_kib_per_dispatch"] * t["copy_fetch_factor"]
+            + t["write_kib_per_dispatch"] * t["copy_write_factor"]) * 1024.0
 
 
 def ilu_apply_bytes(st, N, fp32=False):
@@ -108,6 +131,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--counter-workload", choices=["apply", "copy"], default=None,
+                    help="run only a short workload for hardware-counter collection: five preconditioner "
+                         "applications of the benchmark configuration, or a plain 1 GiB device copy")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,6 +148,15 @@ def main():
     import paper_1401_7227_amd as P
 
     torch.cuda.set_device(0)
+    if args.counter_workload == "copy":
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_workload": "copy", "bytes_read_per_launch": COPY_BYTES,
+                          "bytes_written_per_launch": COPY_BYTES, "launches": 5}))
+        return
     s = gen.generate(*GRID, seed=SEED)
     N, n = s.N, s.n
     t0 = time.perf_counter()
@@ -133,6 +168,14 @@ def main():
     t2 = time.perf_counter()
     st = B.stats()
     b = torch.from_numpy(s.b).cuda()
+    if args.counter_workload == "apply":
+        z = torch.empty_like(b)
+        for _ in range(5):
+            B.apply(b, out=z)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_workload": "apply", "launches": 5,
+                          "alg_bytes_per_launch": ilu_apply_bytes(st, N)}))
+        return
 
     ms, info, prof, x = timed_solves(P, torch, G, B, b, args.steps, args.warmup, profile=True)
     # kernel phases measured inside the timed region
@@ -150,8 +193,10 @@ def main():
     dominant = max(alg, key=lambda k: phase[k]["ms_total"])
     avg_ms = phase[dominant]["ms_avg"]
     achieved = alg[dominant] / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic() if dominant == "ilu_apply" else None
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "alg_bytes_per_launch": int(alg[dominant]), "avg_launch_ms": round(avg_ms, 4)}
     # algorithmic bytes of the whole solve over the wall time
     total_bytes = (alg["ilu_apply"] * per_solve_launch["ilu_apply"] + alg["spmv"] * per_solve_launch["spmv"]
