@@ -172,12 +172,15 @@ asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double
                      const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
 
 /* Kernel-phase timing of asm_solve (HIP events on the solve stream).
- * When enabled on a system, every launch of the phases below inside
- * asm_solve is bracketed by events; asm_profile_read returns the launch
- * counts and accumulated device milliseconds since the last reset. */
+ * asm_profile_enable(sys, phase_mask): bit k of phase_mask times phase k
+ * (0 = off, 0xff = all): inside asm_solve every launch of a timed phase
+ * is bracketed by events, which add a little time per launch, so time
+ * only what is needed.  asm_profile_read returns the launch counts and
+ * accumulated device milliseconds since the last reset. */
 enum {
-  ASM_PHASE_ILU_APPLY = 0,  /* subdomain gather + forward/backward sweeps     */
-  ASM_PHASE_LUMP = 1,       /* lumped (coarse) right-hand sides               */
+  ASM_PHASE_ILU_APPLY = 0,  /* forward/backward sweeps (one kernel launch)   */
+  ASM_PHASE_LUMP = 1,       /* restriction: lumped coarse sums, subdomain
+                               right-hand sides in sweep order             */
   ASM_PHASE_COMBINE = 2,    /* additive combination                           */
   ASM_PHASE_SPMV = 3,       /* w = A z                                        */
   ASM_PHASE_DOTS = 4,       /* Gram-Schmidt projections V^T w and ||w||       */
@@ -190,7 +193,7 @@ typedef struct {
   int64_t launches[ASM_NPHASE];
   double ms[ASM_NPHASE];
 } asm_profile;
-asm_status asm_profile_enable(asm_system sys, int32_t enable);
+asm_status asm_profile_enable(asm_system sys, int32_t phase_mask);
 asm_status asm_profile_read(asm_system sys, asm_profile *out_host, int32_t reset);
 
 void asm_destroy_precond(asm_precond pc);

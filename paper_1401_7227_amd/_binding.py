@@ -163,9 +163,13 @@ class System:
         _check(load().asm_spmv(self._h, _ptr(x), _ptr(y), _stream()))
         return y
 
-    def profile(self, enable: bool = True):
-        """Turns HIP-event timing of solve phases on or off."""
-        _check(load().asm_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, phases=None):
+        """Turns HIP-event timing of solve phases on (all, or the named
+        phases) or off."""
+        mask = 0
+        if enable:
+            mask = 0xFF if phases is None else sum(1 << PHASES.index(p) for p in phases)
+        _check(load().asm_profile_enable(self._h, mask))
 
     def profile_read(self, reset: bool = True) -> dict:
         """{phase: (launches, device ms)} accumulated since the last reset."""

@@ -63,11 +63,15 @@ struct DevMem {
 
 struct GatherDev {
   int32_t n = 0;
+  int32_t lanes = 1;  // threads per destination (about the mean fan-in)
   int32_t *ptr = nullptr, *idx = nullptr;
 };
 
 hipError_t upload_gather(DevMem &m, GatherDev &g, const GatherList &h, hipStream_t s) {
   g.n = h.size();
+  const double mean = g.n > 0 ? (double)h.idx.size() / g.n : 0.0;
+  g.lanes = 1;
+  while (g.lanes < 16 && g.lanes < mean) g.lanes *= 2;
   hipError_t e = m.upload(&g.ptr, h.ptr, s);
   if (e == hipSuccess) e = m.upload(&g.idx, h.idx, s);
   return e;
@@ -76,6 +80,7 @@ hipError_t upload_gather(DevMem &m, GatherDev &g, const GatherList &h, hipStream
 // HIP-event timing of solve phases (enabled per system).
 struct Profiler {
   bool on = false;
+  uint32_t mask = 0;  // phases timed (bit k = phase k)
   std::vector<hipEvent_t> pool;
   size_t next = 0;
   struct Span {
@@ -88,9 +93,13 @@ struct Profiler {
   ~Profiler() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
-  // Records an event; returns its pool index, or SIZE_MAX when off.
-  size_t mark(hipStream_t s) {
-    if (!on) return SIZE_MAX;
+  // Records an event if the phase is timed; returns its pool index, or
+  // SIZE_MAX when not timed.
+  size_t mark(int phase, hipStream_t s) {
+    if (!on || !(mask >> phase & 1u)) return SIZE_MAX;
+    return record(s);
+  }
+  size_t record(hipStream_t s) {
     if (next == pool.size()) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
@@ -102,7 +111,7 @@ struct Profiler {
   }
   void span(int phase, size_t a, hipStream_t s) {
     if (!on || a == SIZE_MAX) return;
-    const size_t b = mark(s);
+    const size_t b = record(s);
     if (b != SIZE_MAX) pend.push_back({phase, a, b});
   }
   // Only after the stream has been synchronised.
@@ -127,7 +136,8 @@ struct Profiler {
 struct Workspace {
   DevMem mem;
   int m = 0;
-  double *U = nullptr;        // (m+1) x n basis (unnormalised columns)
+  double *U = nullptr;        // (m+1) columns of n (stride ldu) basis (unnormalised)
+  int64_t ldu = 0;
   double *w = nullptr, *z = nullptr, *t = nullptr;
   double *partial = nullptr;  // kReduceBlocks x (kMaxRestart+2)
   double *dvec = nullptr;     // reduced dot products
@@ -136,11 +146,19 @@ struct Workspace {
   double *coef = nullptr;
   double *misc = nullptr;     // [0] wnorm, [1] beta, [2] scratch norm
   int *flag = nullptr;
-  double *pinned = nullptr;   // host staging
+  double *pinned = nullptr;   // host staging: scalars, then one published column per step
+  double *pinned_dev = nullptr;  // the same memory as seen by kernels
+  hipEvent_t step_done[kMaxRestart] = {};
   ~Workspace() {
     if (pinned) (void)hipHostFree(pinned);
+    for (hipEvent_t e : step_done)
+      if (e) (void)hipEventDestroy(e);
   }
 };
+
+// Pinned layout: [0, 16) scalars; column j of a cycle at kPubBase + j*kPubStride
+// holds H(0..j+1, j) and then ||w|| (the breakdown reference).
+constexpr int kPubBase = 16, kPubStride = kMaxRestart + 4;
 
 }  // namespace
 }  // namespace asmx
@@ -189,7 +207,8 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
     W.pinned = nullptr;
   }
   const size_t n = 3 * (size_t)S->pat.N;
-  ASM_HIP(W.mem.alloc(&W.U, (size_t)(m + 1) * n));
+  W.ldu = (int64_t)((n + 1) & ~(size_t)1);  // even: 16-byte aligned columns
+  ASM_HIP(W.mem.alloc(&W.U, (size_t)(m + 1) * W.ldu));
   ASM_HIP(W.mem.alloc(&W.w, n));
   ASM_HIP(W.mem.alloc(&W.z, n));
   ASM_HIP(W.mem.alloc(&W.t, n));
@@ -200,7 +219,11 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   ASM_HIP(W.mem.alloc(&W.coef, m + 1));
   ASM_HIP(W.mem.alloc(&W.misc, 8));
   ASM_HIP(W.mem.alloc(&W.flag, 4));
-  ASM_HIP(hipHostMalloc((void **)&W.pinned, sizeof(double) * (2 * kMaxRestart + 16), hipHostMallocDefault));
+  ASM_HIP(hipHostMalloc((void **)&W.pinned, sizeof(double) * (kPubBase + (size_t)kMaxRestart * kPubStride),
+                        hipHostMallocCoherent));
+  ASM_HIP(hipHostGetDevicePointer((void **)&W.pinned_dev, W.pinned, 0));
+  for (hipEvent_t &e : W.step_done)
+    if (!e) ASM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   W.m = m;
   (void)s;
   return ASM_OK;
@@ -289,26 +312,24 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   Profiler dummy;
   Profiler &pf = prof ? *prof : dummy;
   if (pc->opts.kind == ASM_KIND_NONE) {
-    const size_t t0 = pf.mark(s);
+    const size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
     ASM_HIP(launch_scale_copy(n, r, scale, z, s));
     pf.span(ASM_PHASE_OTHER, t0, s);
     return ASM_OK;
   }
+  const size_t t0 = pf.mark(ASM_PHASE_LUMP, s);
   if (pc->c1.n > 0) {
-    const size_t t0 = pf.mark(s);
-    ASM_HIP(launch_gather_sum3(pc->c1.n, pc->c1.ptr, pc->c1.idx, r, scale, pc->PA, s));
-    ASM_HIP(launch_gather_sum3(pc->c2.n, pc->c2.ptr, pc->c2.idx, pc->PA, nullptr, pc->PNF, s));
-    ASM_HIP(launch_gather_sum3(pc->c3.n, pc->c3.ptr, pc->c3.idx, pc->PNF, nullptr,
-                               const_cast<double *>(pc->ap.crhs), s));
-    pf.span(ASM_PHASE_LUMP, t0, s);
+    ASM_HIP(launch_gather_sum3(pc->c1.n, pc->c1.lanes, pc->c1.ptr, pc->c1.idx, r, scale, pc->PA, s));
+    ASM_HIP(launch_gather_sum3(pc->c2.n, pc->c2.lanes, pc->c2.ptr, pc->c2.idx, pc->PA, nullptr, pc->PNF, s));
   }
-  const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
-  const size_t t1 = pf.mark(s);
   ASM_HIP(launch_gather_rhs((int)pc->plan.total_pos, pc->ap, r, scale, s));
+  pf.span(ASM_PHASE_LUMP, t0, s);
+  const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
+  const size_t t1 = pf.mark(ASM_PHASE_ILU_APPLY, s);
   ASM_HIP(launch_ilu_apply(pc->ap, z, s));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
-    const size_t t2 = pf.mark(s);
+    const size_t t2 = pf.mark(ASM_PHASE_COMBINE, s);
     ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->ap.yx, z, s));
     pf.span(ASM_PHASE_COMBINE, t2, s);
   }
@@ -472,17 +493,15 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   ap.fsrc = t32;
 #undef UP
   auto ALLOC = [&](auto **dst, size_t n) { return M.alloc(dst, n); };
-  double *yx, *rs, *crhs, *fact;
+  double *yx, *rs, *fact;
   if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
       (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
-      (e = ALLOC(&crhs, (size_t)std::max<int64_t>(1, P.total_coarse) * 3)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->bad, 1)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   ap.yx = yx;
   ap.rs = rs;
-  ap.crhs = crhs;
   d.fact = fact;
   if ((e = upload_gather(M, pc->asrc, P.asm_src, s)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
@@ -494,6 +513,9 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
         (e = ALLOC(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
         (e = ALLOC(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess)
       return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    ap.cptr3 = pc->c3.ptr;
+    ap.cidx3 = pc->c3.idx;
+    ap.pnf = pc->PNF;
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
   // keep only what export and error messages need on the host
@@ -613,12 +635,12 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   const double tol = o->rtol * bnorm;
   auto true_residual = [&](double *beta) -> asm_status {
     int nbr = 0;
-    const size_t t0 = pf.mark(s);
+    const size_t t0 = pf.mark(ASM_PHASE_RESIDUAL, s);
     ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
     pf.span(ASM_PHASE_RESIDUAL, t0, s);
-    const size_t t1 = pf.mark(s);
+    const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
     ASM_HIP(launch_reduce_cols(nbr, 1, W.partial, W.misc + 2, s));
-    ASM_HIP(launch_finalize_norm(W.misc + 2, W.misc + 1, W.scale, s));
+    ASM_HIP(launch_finalize_norm(0, W.misc + 2, W.misc + 1, W.scale, nullptr, nullptr, s));
     pf.span(ASM_PHASE_OTHER, t1, s);
     ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
@@ -634,42 +656,57 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   std::vector<double> H((size_t)ld * m), cs(m), sn(m), g(m + 1), y(m), sc(m + 1), coef(m + 1);
   auto Hh = [&](int i, int j) -> double & { return H[(size_t)j * ld + i]; };
   asm_status result = ASM_NOT_CONVERGED;
+  // One Arnoldi step on the stream: z = B^-1 v_j, w = A z, CGS projections,
+  // the new basis vector and its norm; the step's Hessenberg column is then
+  // published to pinned memory and an event marks the step's end.
+  auto enqueue_step = [&](int j) -> asm_status {
+    const double *Uj = W.U + (size_t)j * W.ldu;
+    asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
+    if (e2 != ASM_OK) return e2;
+    size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
+    ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
+    pf.span(ASM_PHASE_SPMV, t0, s);
+    int nbd = 0;
+    t0 = pf.mark(ASM_PHASE_DOTS, s);
+    ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
+    pf.span(ASM_PHASE_DOTS, t0, s);
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
+    ASM_HIP(launch_finalize_dots(j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.coef, W.misc, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    int nbu = 0;
+    t0 = pf.mark(ASM_PHASE_UPDATE, s);
+    ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.coef, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial, &nbu, s));
+    pf.span(ASM_PHASE_UPDATE, t0, s);
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_reduce_cols(nbu, 1, W.partial, W.misc + 2, s));
+    ASM_HIP(launch_finalize_norm(j + 1, W.misc + 2, W.H + (size_t)j * ld, W.scale + j + 1, W.misc,
+                                 W.pinned_dev + kPubBase + (size_t)j * kPubStride, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    ASM_HIP(hipEventRecord(W.step_done[j], s));
+    return ASM_OK;
+  };
   while (true) {
     if (beta == 0.0) { result = ASM_OK; break; }
     info->cycles++;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     sc[0] = 1.0 / beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      const double *Uj = W.U + (size_t)j * n;
-      if ((st = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf)) != ASM_OK) return st;
-      size_t t0 = pf.mark(s);
-      ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
-      pf.span(ASM_PHASE_SPMV, t0, s);
-      info->iters++;
-      int nbd = 0;
-      t0 = pf.mark(s);
-      ASM_HIP(launch_multidot(n, j + 1, W.U, n, W.w, W.partial, &nbd, s));
-      pf.span(ASM_PHASE_DOTS, t0, s);
-      t0 = pf.mark(s);
-      ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
-      ASM_HIP(launch_finalize_dots(j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.coef, W.misc, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      int nbu = 0;
-      t0 = pf.mark(s);
-      ASM_HIP(launch_update(n, j + 1, W.U, n, W.coef, W.w, W.U + (size_t)(j + 1) * n, W.partial, &nbu, s));
-      pf.span(ASM_PHASE_UPDATE, t0, s);
-      t0 = pf.mark(s);
-      ASM_HIP(launch_reduce_cols(nbu, 1, W.partial, W.misc + 2, s));
-      ASM_HIP(launch_finalize_norm(W.misc + 2, W.H + (size_t)j * ld + j + 1, W.scale + j + 1, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      ASM_HIP(hipMemcpyAsync(hp, W.H + (size_t)j * ld, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      ASM_HIP(hipMemcpyAsync(hp + kMaxRestart + 2, W.misc, sizeof(double), hipMemcpyDeviceToHost, s));
-      ASM_HIP(hipStreamSynchronize(s));
-      pf.flush();
-      for (int i = 0; i <= j + 1; ++i) Hh(i, j) = hp[i];
-      const double w0 = hp[kMaxRestart + 2];
+    // steps of this cycle: at most m, and never past the iteration limit
+    const int kmax = std::min(m, limit - info->iters);
+    int k = 0, queued = 0;
+    if ((st = enqueue_step(0)) != ASM_OK) return st;
+    queued = 1;
+    for (int j = 0; j < kmax; ++j) {
+      // keep the next step queued while step j's column is read back
+      if (queued < kmax) {
+        if ((st = enqueue_step(queued)) != ASM_OK) return st;
+        ++queued;
+      }
+      ASM_HIP(hipEventSynchronize(W.step_done[j]));
+      const double *col = hp + kPubBase + (size_t)j * kPubStride;
+      for (int i = 0; i <= j + 1; ++i) Hh(i, j) = col[i];
+      const double w0 = col[j + 2];
       const double hn = Hh(j + 1, j);
       sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
       // previous rotations, then a new one annihilating h_{j+1,j}
@@ -694,8 +731,8 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
       info->rel_res_est = std::fabs(g[j + 1]) / scl;
       if (hn <= 1e-14 * w0) break;
       if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
-      if (info->iters >= limit) break;
     }
+    info->iters += k;
     for (int i = k - 1; i >= 0; --i) {
       double acc = g[i];
       for (int j = i + 1; j < k; ++j) acc -= Hh(i, j) * y[j];
@@ -703,11 +740,11 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
     }
     for (int i = 0; i < k; ++i) coef[i] = y[i] * sc[i];
     ASM_HIP(hipMemcpyAsync(W.coef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-    size_t t0 = pf.mark(s);
-    ASM_HIP(launch_lincomb(n, k, W.U, n, W.coef, W.t, s));
+    size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_lincomb(n, k, W.U, W.ldu, W.coef, W.t, s));
     pf.span(ASM_PHASE_OTHER, t0, s);
     if ((st = apply_precond(pc, W.t, nullptr, W.z, s, &pf)) != ASM_OK) return st;
-    t0 = pf.mark(s);
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
     ASM_HIP(launch_axpy(n, W.z, x, s));
     pf.span(ASM_PHASE_OTHER, t0, s);
     if ((st = true_residual(&beta)) != ASM_OK) return st;
@@ -724,10 +761,11 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   return result;
 }
 
-asm_status asm_profile_enable(asm_system S, int32_t enable) {
+asm_status asm_profile_enable(asm_system S, int32_t phase_mask) {
   g_err.clear();
   if (!S) return fail(ASM_ERR_INVALID, "NULL argument");
-  S->prof.on = (enable != 0);
+  S->prof.on = (phase_mask != 0);
+  S->prof.mask = (uint32_t)phase_mask;
   return ASM_OK;
 }
 

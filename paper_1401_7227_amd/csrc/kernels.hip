@@ -127,24 +127,38 @@ __global__ __launch_bounds__(256) void gather_sum9_kernel(int ndst, const int32_
   for (int q = 0; q < 9; ++q) dst[(size_t)d * 9 + q] = acc[q];
 }
 
+// dst[d] = scale * sum of src over idx[ptr[d] .. ptr[d+1]), 3 doubles per
+// entry; G lanes share a destination and combine their partial sums in a
+// fixed butterfly order (deterministic).
+template <int G>
 __global__ __launch_bounds__(256) void gather_sum3_kernel(int ndst, const int32_t *__restrict__ ptr,
                                                           const int32_t *__restrict__ idx,
                                                           const double *__restrict__ src,
                                                           const double *__restrict__ scale,
                                                           double *__restrict__ dst) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= ndst) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int d = gid / G, lane = gid % G;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int t = ptr[d]; t < ptr[d + 1]; ++t) {
-    const size_t q = (size_t)idx[t] * 3;
-    a0 += src[q];
-    a1 += src[q + 1];
-    a2 += src[q + 2];
+  if (d < ndst) {
+    for (int t = ptr[d] + lane; t < ptr[d + 1]; t += G) {
+      const size_t q = (size_t)idx[t] * 3;
+      a0 += src[q];
+      a1 += src[q + 1];
+      a2 += src[q + 2];
+    }
   }
-  const double s = scale ? *scale : 1.0;
-  dst[(size_t)d * 3] = s * a0;
-  dst[(size_t)d * 3 + 1] = s * a1;
-  dst[(size_t)d * 3 + 2] = s * a2;
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) {
+    a0 += __shfl_xor(a0, off, G);
+    a1 += __shfl_xor(a1, off, G);
+    a2 += __shfl_xor(a2, off, G);
+  }
+  if (d < ndst && lane == 0) {
+    const double s = scale ? *scale : 1.0;
+    dst[(size_t)d * 3] = s * a0;
+    dst[(size_t)d * 3 + 1] = s * a1;
+    dst[(size_t)d * 3 + 2] = s * a2;
+  }
 }
 
 // ---------------------------------------------------------------- 3x3 block math
@@ -560,21 +574,27 @@ __global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *
 }
 
 // Forward right-hand sides in sweep order: the restriction R_i r of every
-// subdomain (fine rows gather r, coarse rows take the lumped sums).
+// subdomain.  Fine rows gather r (times the basis scale); a coarse row sums
+// its near/far atoms' lumped residuals (App. B, eq. (B.2)).
 __global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t *__restrict__ fsrc,
                                                          const double *__restrict__ r,
                                                          const double *__restrict__ scale,
-                                                         const double *__restrict__ crhs, double *__restrict__ rs) {
+                                                         const int32_t *__restrict__ cptr3,
+                                                         const int32_t *__restrict__ cidx3,
+                                                         const double *__restrict__ pnf, double *__restrict__ rs) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= npos) return;
   const int src = fsrc[q];
-  double a0, a1, a2;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (src >= 0) {
     const double sc = scale ? *scale : 1.0;
     a0 = sc * r[3 * (size_t)src]; a1 = sc * r[3 * (size_t)src + 1]; a2 = sc * r[3 * (size_t)src + 2];
   } else {
-    const double *c = crhs + 3 * (size_t)(-src - 1);
-    a0 = c[0]; a1 = c[1]; a2 = c[2];
+    const int c = -src - 1;
+    for (int t = cptr3[c]; t < cptr3[c + 1]; ++t) {
+      const double *p = pnf + 3 * (size_t)cidx3[t];
+      a0 += p[0]; a1 += p[1]; a2 += p[2];
+    }
   }
   rs[3 * (size_t)q] = a0; rs[3 * (size_t)q + 1] = a1; rs[3 * (size_t)q + 2] = a2;
 }
@@ -596,6 +616,8 @@ __global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int3
 // ---------------------------------------------------------------- Krylov
 // partial[b*(NV+1) + i] = sum over the block's elements of U_i . w (i < NV),
 // partial[b*(NV+1) + NV] = w . w.
+// Krylov vectors are processed two doubles per thread (16-byte loads); an
+// odd last element is handled by thread 0 of block 0.
 template <int NV>
 __global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
                                                        const double *__restrict__ w,
@@ -604,10 +626,21 @@ __global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const double we = w[e];
+  const int64_t n2 = n / 2;
+  const double2 *w2 = reinterpret_cast<const double2 *>(w);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (int64_t)gridDim.x * 256) {
+    const double2 we = w2[e];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += U[i * ldu + e] * we;
+    for (int i = 0; i < NV; ++i) {
+      const double2 u = reinterpret_cast<const double2 *>(U + i * ldu)[e];
+      acc[i] += u.x * we.x + u.y * we.y;
+    }
+    acc[NV] += we.x * we.x + we.y * we.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double we = w[n - 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += U[i * ldu + n - 1] * we;
     acc[NV] += we * we;
   }
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -647,31 +680,59 @@ __global__ void finalize_dots_kernel(int nv, const double *__restrict__ d, const
   if (i == 0) *wnorm = sqrt(d[nv]);
 }
 
-__global__ __launch_bounds__(256) void update_kernel(int64_t n, int nv, const double *__restrict__ U, int64_t ldu,
+// unew = w - sum_i coef[i] U_i and per-block partial sums of ||unew||^2.
+template <int NV>
+__global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
                                                      const double *__restrict__ coef,
                                                      const double *__restrict__ w, double *__restrict__ unew,
                                                      double *__restrict__ partial) {
-  __shared__ double cs[kMaxRestart + 1];
   __shared__ double red[4];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) cs[i] = coef[i];
-  __syncthreads();
+  double cs[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) cs[i] = coef[i];
   double nrm = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    double a = w[e];
-    for (int i = 0; i < nv; ++i) a -= cs[i] * U[i * ldu + e];
-    unew[e] = a;
+  const int64_t n2 = n / 2;
+  const double2 *w2 = reinterpret_cast<const double2 *>(w);
+  double2 *o2 = reinterpret_cast<double2 *>(unew);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (int64_t)gridDim.x * 256) {
+    double2 a = w2[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double2 u = reinterpret_cast<const double2 *>(U + i * ldu)[e];
+      a.x -= cs[i] * u.x;
+      a.y -= cs[i] * u.y;
+    }
+    o2[e] = a;
+    nrm += a.x * a.x + a.y * a.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = w[n - 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a -= cs[i] * U[i * ldu + n - 1];
+    unew[n - 1] = a;
     nrm += a * a;
   }
   const double s = block_sum<256>(nrm, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void finalize_norm_kernel(const double *__restrict__ nrm2, double *__restrict__ hout,
-                                     double *__restrict__ scale_out) {
-  if (threadIdx.x == 0) {
-    const double h = sqrt(nrm2[0]);
-    *hout = h;
+// h = ||u_new|| into hcol[nv] and its inverse into scale_out; optionally
+// publishes hcol[0..nv] and *wnorm to pinned host memory (pub).
+__global__ void finalize_norm_kernel(int nv, const double *__restrict__ nrm2, double *__restrict__ hcol,
+                                     double *__restrict__ scale_out, const double *__restrict__ wnorm,
+                                     double *__restrict__ pub) {
+  const int i = threadIdx.x;
+  const double h = sqrt(nrm2[0]);
+  if (i == 0) {
+    hcol[nv] = h;
     *scale_out = (h > 0.0) ? 1.0 / h : 0.0;
+  }
+  if (pub) {
+    for (int q = i; q < nv; q += blockDim.x) pub[q] = hcol[q];
+    if (i == 0) {
+      pub[nv] = h;
+      pub[nv + 1] = *wnorm;
+    }
   }
 }
 
@@ -745,10 +806,19 @@ hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx, 
   return hipGetLastError();
 }
 
-hipError_t launch_gather_sum3(int ndst, const int32_t *ptr, const int32_t *idx, const double *src,
+hipError_t launch_gather_sum3(int ndst, int lanes, const int32_t *ptr, const int32_t *idx, const double *src,
                               const double *scale, double *dst, hipStream_t s) {
   if (ndst == 0) return hipSuccess;
-  gather_sum3_kernel<<<blocks_for(ndst, 256), 256, 0, s>>>(ndst, ptr, idx, src, scale, dst);
+  const int64_t threads = (int64_t)ndst * lanes;
+  const int grid = (int)((threads + 255) / 256);
+  switch (lanes) {
+    case 1: gather_sum3_kernel<1><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
+    case 2: gather_sum3_kernel<2><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
+    case 4: gather_sum3_kernel<4><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
+    case 8: gather_sum3_kernel<8><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
+    case 16: gather_sum3_kernel<16><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -767,7 +837,7 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base, 
 
 hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s) {
   if (npos == 0) return hipSuccess;
-  gather_rhs_kernel<<<blocks_for(npos, 256), 256, 0, s>>>(npos, p.fsrc, r, scale, p.crhs, p.rs);
+  gather_rhs_kernel<<<blocks_for(npos, 256), 256, 0, s>>>(npos, p.fsrc, r, scale, p.cptr3, p.cidx3, p.pnf, p.rs);
   return hipGetLastError();
 }
 
@@ -799,7 +869,7 @@ static bool multidot_dispatch(int nv, int64_t n, const double *U, int64_t ldu, c
 
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w, double *partial,
                            int *nblocks_out, hipStream_t s) {
-  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > 32) return hipErrorInvalidValue;
   multidot_dispatch(nv, n, U, ldu, w, partial, grid, s, std::make_integer_sequence<int, 32>{});
   *nblocks_out = grid;
@@ -817,16 +887,32 @@ hipError_t launch_finalize_dots(int nv, const double *d, const double *scale, do
   return hipGetLastError();
 }
 
+template <int NV>
+static void update_launch(int64_t n, const double *U, int64_t ldu, const double *coef, const double *w, double *unew,
+                          double *partial, int grid, hipStream_t s) {
+  update_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, coef, w, unew, partial);
+}
+
+template <int... Is>
+static bool update_dispatch(int nv, int64_t n, const double *U, int64_t ldu, const double *coef, const double *w,
+                            double *unew, double *partial, int grid, hipStream_t s, std::integer_sequence<int, Is...>) {
+  bool done = false;
+  ((nv == Is + 1 ? (update_launch<Is + 1>(n, U, ldu, coef, w, unew, partial, grid, s), done = true) : false), ...);
+  return done;
+}
+
 hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *coef, const double *w,
                          double *unew, double *partial, int *nblocks_out, hipStream_t s) {
-  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
-  update_kernel<<<grid, 256, 0, s>>>(n, nv, U, ldu, coef, w, unew, partial);
+  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
+  if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  update_dispatch(nv, n, U, ldu, coef, w, unew, partial, grid, s, std::make_integer_sequence<int, kMaxRestart>{});
   *nblocks_out = grid;
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_norm(const double *nrm2, double *hout, double *scale_out, hipStream_t s) {
-  finalize_norm_kernel<<<1, 64, 0, s>>>(nrm2, hout, scale_out);
+hipError_t launch_finalize_norm(int nv, const double *nrm2, double *hcol, double *scale_out, const double *wnorm,
+                                double *pub, hipStream_t s) {
+  finalize_norm_kernel<<<1, 64, 0, s>>>(nv, nrm2, hcol, scale_out, wnorm, pub);
   return hipGetLastError();
 }
 

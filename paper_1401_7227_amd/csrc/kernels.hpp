@@ -31,7 +31,8 @@ hipError_t launch_residual(const SellDev &A, const double *x, const double *b, d
 hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx,
                               const double *srcA, int32_t nA, const double *srcB, double *dst,
                               hipStream_t s);
-hipError_t launch_gather_sum3(int ndst, const int32_t *ptr, const int32_t *idx, const double *src,
+// lanes (1, 2, 4, 8 or 16) threads share each destination.
+hipError_t launch_gather_sum3(int ndst, int lanes, const int32_t *ptr, const int32_t *idx, const double *src,
                               const double *scale, double *dst, hipStream_t s);
 
 // Level-scheduled block ILU(0) of every subdomain; singular pivots reported
@@ -51,6 +52,7 @@ hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *ci
                                    const double *yext, double *z, hipStream_t s);
 
 // Krylov kernels (n = scalar length).
+// U columns (stride ldu, even) and w must be 16-byte aligned.
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w,
                            double *partial, int *nblocks_out, hipStream_t s);
 hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out,
@@ -63,7 +65,10 @@ hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const 
                          const double *w, double *unew, double *partial, int *nblocks_out,
                          hipStream_t s);
 // hn = sqrt(nrm2[0]); *hout = hn; *scale_out = hn > 0 ? 1/hn : 0.
-hipError_t launch_finalize_norm(const double *nrm2, double *hout, double *scale_out, hipStream_t s);
+// h = sqrt(*nrm2) into hcol[nv], 1/h into *scale_out; if pub is not NULL,
+// hcol[0..nv] and *wnorm are also written to pub[0..nv+1] (pinned host).
+hipError_t launch_finalize_norm(int nv, const double *nrm2, double *hcol, double *scale_out, const double *wnorm,
+                                double *pub, hipStream_t s);
 hipError_t launch_lincomb(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
                           double *out, hipStream_t s);
 hipError_t launch_axpy(int64_t n, const double *z, double *x, hipStream_t s);

@@ -90,7 +90,8 @@ struct ApplyPlan {
   double *rs;                   // 3 doubles per forward position: gathered rhs
   double *yx;                   // 3 doubles per backward position
   const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
-  const double *crhs;           // 3 doubles per coarse row
+  const int32_t *cptr3, *cidx3;  // coarse row -> its near/far atom sums (two-level only)
+  const double *pnf;             // 3 doubles per near/far atom: lumped residual sums
 };
 
 struct SubDesc {
