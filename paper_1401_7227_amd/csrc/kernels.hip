@@ -36,6 +36,48 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Cross-lane moves inside the VALU (DPP), no LDS traffic.  CTRL is a DPP
+// control: quad_perm 0xB1 (lanes xor 1), 0x4E (xor 2), 0x141 row half
+// mirror (lane i <-> 7-i within 8), 0x140 row mirror (i <-> 15-i within 16).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_any(double v) { return dpp64<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ float dpp_any(float v) { return dpp32<CTRL>(v); }
+
+// Sum over each group of 4 lanes (every lane of the group gets it); all
+// lanes of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v += dpp_any<0xB1>(v);
+  v += dpp_any<0x4E>(v);
+  return v;
+}
+
+__device__ __forceinline__ double readlane64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Wave-wide sum without LDS: sums within rows of 16 lanes by DPP, then the
+// four row sums in lane order.  All lanes must be active; the result is
+// uniform.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = quad_sum(v);
+  v += dpp64<0x141>(v);
+  v += dpp64<0x140>(v);
+  return ((readlane64(v, 0) + readlane64(v, 16)) + readlane64(v, 32)) + readlane64(v, 48);
+}
+
 // Fixed-order block reduction (deterministic): wave butterflies, then the
 // per-wave sums in wave order.  Result valid in thread 0.
 template <int NT>
@@ -292,8 +334,9 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 // One workgroup per subdomain runs its forward sweep y = L^-1 R_i r and
 // backward sweep x = U^-1 y (D^-1 applied per row).  Every level step is a
 // contiguous record (see RecStep) that the streaming waves copy from HBM,
-// together with the step's row inputs, into one of three LDS buffers
-// several steps ahead of its use.  The computing waves then touch global
+// together with the step's row inputs, into one of two LDS buffers (step s
+// is computed from one while step s+1 is written into the other); the
+// loads run several steps ahead in registers.  The computing waves then touch global
 // memory only to store results: vector values live in an LDS slot pool,
 // and values without a slot are reloaded into LDS by "fill" steps.
 constexpr int kRecU4 = kRecBytes / 16;
@@ -324,7 +367,7 @@ __device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
 }
 
 struct SweepLds {
-  u32x4 buf[3][kRecU4];        // records of steps s, s+1 (and s-1 until overwritten)
+  u32x4 buf[2][kRecU4];        // record of step s (read) and of step s+1 (being written)
   double vec[3 * kVecSlots];    // vector slot pool (top kFillSlots: reloaded values)
   double part[4];               // partial sum of a split row
 };
@@ -345,47 +388,68 @@ __device__ __forceinline__ void row_out(const int4 &m, double t0, double t1, dou
   }
 }
 
-// Mode 0: one thread per row, entries in jagged diagonals.  The row header
-// holds the dependencies' slots, so the slot values are read right after
-// it; the blocks and the input need the step descriptor.
+// Mode 0: four threads per row.  Thread r of a row takes the row's entries
+// r and r+4 (jagged diagonals), the four partial sums are combined inside
+// the quad (DPP), and thread r < 3 finishes component r of the result.
+// A step with more than 64 rows takes several passes.
 template <bool FWD, typename T>
 __device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, SweepLds &L, double *__restrict__ yx,
                                           double *__restrict__ z) {
-  const int j = threadIdx.x;
-  if (j >= h.nrows) return;
+  constexpr int kRowsPerPass = kConsumerThreads / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
-  const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead) + 2 * j;
-  const int4 m = hdr[0], dp = hdr[1];
-  const int cnt = m.w >> 8;
-  const int d[kMaxJdsWidth] = {dp.x & 0xffff, (int)((unsigned)dp.x >> 16), dp.y & 0xffff, (int)((unsigned)dp.y >> 16),
-                               dp.z & 0xffff, (int)((unsigned)dp.z >> 16), dp.w & 0xffff, (int)((unsigned)dp.w >> 16)};
-  double y[kMaxJdsWidth][3];
-#pragma unroll
-  for (int k = 0; k < kMaxJdsWidth; ++k)
-    if (k < cnt) { y[k][0] = vec[3 * d[k]]; y[k][1] = vec[3 * d[k] + 1]; y[k][2] = vec[3 * d[k] + 2]; }
-  const double *inp = reinterpret_cast<const double *>(recp + h.in) + 3 * j;
+  const int r = threadIdx.x & 3;
+  const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead);
   const T *vals = reinterpret_cast<const T *>(recp + h.vals);
-  T t0 = (T)inp[0], t1 = (T)inp[1], t2 = (T)inp[2];
-#pragma unroll
-  for (int k = 0; k < kMaxJdsWidth; ++k) {
-    if (k < cnt) {
+  const double *inb = reinterpret_cast<const double *>(recp + h.in);
+  const int k0 = r, k1 = r + 4;
+  // lane-dependent diagonal starts, read from the record in LDS (indexing
+  // the register copy of the head by lane would move it to scratch)
+  const int32_t *koff = reinterpret_cast<const RecHead *>(recp)->koff;
+  const int q0 = koff[k0], q1 = koff[k1];
+  for (int j0 = 0; j0 < h.nrows; j0 += kRowsPerPass) {
+    const int j = j0 + (int)(threadIdx.x >> 2);
+    const bool act = j < h.nrows;
+    const int jc = act ? j : 0;
+    const int4 m = hdr[2 * jc], dp = hdr[2 * jc + 1];
+    const int cnt = act ? (m.w >> 8) : 0;
+    const unsigned w0 = (unsigned)((r < 2) ? dp.x : dp.y), w1 = (unsigned)((r < 2) ? dp.z : dp.w);
+    const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
+    const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
+    T s0 = 0, s1 = 0, s2 = 0;
+    if (k0 < cnt) {
+      const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
       T b[9];
-      block9<T>(vals + h.koff[k] + j, h.nslots, b);
-      const T u0 = (T)y[k][0], u1 = (T)y[k][1], u2 = (T)y[k][2];
-      t0 -= b[0] * u0 + b[1] * u1 + b[2] * u2;
-      t1 -= b[3] * u0 + b[4] * u1 + b[5] * u2;
-      t2 -= b[6] * u0 + b[7] * u1 + b[8] * u2;
+      block9<T>(vals + q0 + j, h.nslots, b);
+      s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
+      s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
+      s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
+    }
+    if (k1 < cnt) {
+      const T u0 = (T)vec[3 * d1], u1 = (T)vec[3 * d1 + 1], u2 = (T)vec[3 * d1 + 2];
+      T b[9];
+      block9<T>(vals + q1 + j, h.nslots, b);
+      s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
+      s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
+      s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
+    }
+    s0 = quad_sum(s0);
+    s1 = quad_sum(s1);
+    s2 = quad_sum(s2);
+    if (act && r < 3) {
+      T o;
+      if (FWD) {
+        o = (T)inb[3 * j + r] - (r == 0 ? s0 : (r == 1 ? s1 : s2));
+      } else {
+        const T t0 = (T)inb[3 * j] - s0, t1 = (T)inb[3 * j + 1] - s1, t2 = (T)inb[3 * j + 2] - s2;
+        const T *dv = reinterpret_cast<const T *>(recp + h.dinv) + j + 3 * r * h.nrows;
+        o = dv[0] * t0 + dv[h.nrows] * t1 + dv[2 * h.nrows] * t2;
+      }
+      const double od = (double)o;
+      if (m.x >= 0) ((lds_double *)L.vec)[3 * m.x + r] = od;
+      if (m.w & 1) yx[3 * (size_t)m.y + r] = od;
+      if (m.z >= 0) z[3 * (size_t)m.z + r] = od;
     }
   }
-  if (!FWD) {
-    T dv[9];
-    block9<T>(reinterpret_cast<const T *>(recp + h.dinv) + j, h.nrows, dv);
-    const T x0 = dv[0] * t0 + dv[1] * t1 + dv[2] * t2;
-    const T x1 = dv[3] * t0 + dv[4] * t1 + dv[5] * t2;
-    const T x2 = dv[6] * t0 + dv[7] * t1 + dv[8] * t2;
-    t0 = x0; t1 = x1; t2 = x2;
-  }
-  row_out(m, (double)t0, (double)t1, (double)t2, L, yx, z);
 }
 
 // Mode 1: one wavefront per (long) row; lanes stride over its entries.
@@ -408,9 +472,9 @@ __device__ __forceinline__ void step_long_rows(const RecHead &h, const char *rec
       s1 += (double)b[3] * y0 + (double)b[4] * y1 + (double)b[5] * y2;
       s2 += (double)b[6] * y0 + (double)b[7] * y1 + (double)b[8] * y2;
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
+    s0 = wave_sum_dpp(s0);
+    s1 = wave_sum_dpp(s1);
+    s2 = wave_sum_dpp(s2);
     if (lane == 0) {
       double a0, a1, a2;
       if (h.piece == kPieceMiddle || h.piece == kPieceLast) {
@@ -468,11 +532,12 @@ struct Producer {
 
 // Streamer: load record k of the sweep and its row inputs (3 doubles per
 // row from src at the step's positions) into a stage.  Loads are clamped
-// to the record / the input segment, never conditional.
+// to the record / the input segment, never conditional; records are read
+// once per application, so they are loaded non-temporally.
 __device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec,
                                           const double *__restrict__ src, Stage &st, int &len, int &xlast, int t) {
 #pragma unroll
-  for (int i = 0; i < kStageU4; ++i) st.v[i] = rec[d.rec + min(i * 256 + t, d.len - 1)];
+  for (int i = 0; i < kStageU4; ++i) st.v[i] = __builtin_nontemporal_load(rec + d.rec + min(i * 256 + t, d.len - 1));
   const int last = 3 * max(d.nrows, 1) - 1;
   const double *xs = src + 3 * (size_t)d.pos;
 #pragma unroll
@@ -499,7 +564,7 @@ __device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restric
                                           SweepLds &L, Producer &P, RecStep &dn, int t) {
   // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
   // the stage for record s+1+kAhead (descriptor loaded last iteration)
-  prod_store(L.buf[(s + 1) % 3], P.st[K], P.len[K], P.xlast[K], t);
+  prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.xlast[K], t);
   const RecStep d = dn;
   prod_load(d, rec, src, P.st[K], P.len[K], P.xlast[K], t);
   dn = steps[min(s + 2 + kAhead, S - 1)];
@@ -538,7 +603,7 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
 // fill step), results stored at once.
 template <bool FWD>
 __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
-  const char *recp = reinterpret_cast<const char *>(L.buf[s % 3]);
+  const char *recp = reinterpret_cast<const char *>(L.buf[s & 1]);
   const RecHead h = *reinterpret_cast<const RecHead *>(recp);
   if (h.mode == 0) {
     if (h.fp32) step_rows<FWD, float>(h, recp, L, yx, z);
