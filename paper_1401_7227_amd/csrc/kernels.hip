@@ -372,62 +372,46 @@ struct SweepLds {
   double part[4];               // partial sum of a split row
 };
 
-// A finished row: its LDS slot (later steps read it there) and its global
-// copies (the work vector, and the output cell of the restricted combine).
-__device__ __forceinline__ void row_out(const int4 &m, double t0, double t1, double t2, SweepLds &L,
-                                        double *__restrict__ yx, double *__restrict__ z) {
-  lds_double *w = (lds_double *)L.vec;
-  if (m.x >= 0) { w[3 * m.x] = t0; w[3 * m.x + 1] = t1; w[3 * m.x + 2] = t2; }
-  if (m.w & 1) {
-    double *g = yx + 3 * (size_t)m.y;
-    g[0] = t0; g[1] = t1; g[2] = t2;
-  }
-  if (m.z >= 0) {
-    double *g = z + 3 * (size_t)m.z;
-    g[0] = t0; g[1] = t1; g[2] = t2;
-  }
-}
-
-// Mode 0: four threads per row.  Thread r of a row takes the row's entries
-// r and r+4 (jagged diagonals), the four partial sums are combined inside
-// the quad (DPP), and thread r < 3 finishes component r of the result.
-// A step with more than 64 rows takes several passes.
+// Short rows of one section: four threads per row.  Thread r of a row
+// takes the row's entries r and r+4 (jagged diagonals), the four partial
+// sums are combined inside the quad (DPP), and thread r < 3 finishes
+// component r of the result.  Sections with more than 64 rows take
+// several passes.  j0: first step row of the section; n: its rows;
+// koff: its diagonal starts (LDS); dinv rows of the section start at
+// index doff of a plane of dstride rows.
 template <bool FWD, typename T>
-__device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, SweepLds &L, double *__restrict__ yx,
-                                          double *__restrict__ z) {
+__device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
+                                           double *__restrict__ z, int j0, int n, const int32_t *koff, int nslots,
+                                           int vals_off, int dinv_off, int dstride, int doff, int in_off) {
   constexpr int kRowsPerPass = kConsumerThreads / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int r = threadIdx.x & 3;
   const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead);
-  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
-  const double *inb = reinterpret_cast<const double *>(recp + h.in);
-  const int k0 = r, k1 = r + 4;
-  // lane-dependent diagonal starts, read from the record in LDS (indexing
-  // the register copy of the head by lane would move it to scratch)
-  const int32_t *koff = reinterpret_cast<const RecHead *>(recp)->koff;
-  const int q0 = koff[k0], q1 = koff[k1];
-  for (int j0 = 0; j0 < h.nrows; j0 += kRowsPerPass) {
-    const int j = j0 + (int)(threadIdx.x >> 2);
-    const bool act = j < h.nrows;
-    const int jc = act ? j : 0;
-    const int4 m = hdr[2 * jc], dp = hdr[2 * jc + 1];
+  const T *vals = reinterpret_cast<const T *>(recp + vals_off);
+  const double *inb = reinterpret_cast<const double *>(recp + in_off);
+  const int q0 = koff[r], q1 = koff[r + 4];
+  for (int i0 = 0; i0 < n; i0 += kRowsPerPass) {
+    const int i = i0 + (int)(threadIdx.x >> 2);
+    const bool act = i < n;
+    const int j = j0 + (act ? i : 0);
+    const int4 m = hdr[2 * j], dp = hdr[2 * j + 1];
     const int cnt = act ? (m.w >> 8) : 0;
     const unsigned w0 = (unsigned)((r < 2) ? dp.x : dp.y), w1 = (unsigned)((r < 2) ? dp.z : dp.w);
     const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
     const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
     T s0 = 0, s1 = 0, s2 = 0;
-    if (k0 < cnt) {
+    if (r < cnt) {
       const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
       T b[9];
-      block9<T>(vals + q0 + j, h.nslots, b);
+      block9<T>(vals + q0 + i, nslots, b);
       s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
       s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
       s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
     }
-    if (k1 < cnt) {
+    if (r + 4 < cnt) {
       const T u0 = (T)vec[3 * d1], u1 = (T)vec[3 * d1 + 1], u2 = (T)vec[3 * d1 + 2];
       T b[9];
-      block9<T>(vals + q1 + j, h.nslots, b);
+      block9<T>(vals + q1 + i, nslots, b);
       s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
       s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
       s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
@@ -441,8 +425,8 @@ __device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, Sw
         o = (T)inb[3 * j + r] - (r == 0 ? s0 : (r == 1 ? s1 : s2));
       } else {
         const T t0 = (T)inb[3 * j] - s0, t1 = (T)inb[3 * j + 1] - s1, t2 = (T)inb[3 * j + 2] - s2;
-        const T *dv = reinterpret_cast<const T *>(recp + h.dinv) + j + 3 * r * h.nrows;
-        o = dv[0] * t0 + dv[h.nrows] * t1 + dv[2 * h.nrows] * t2;
+        const T *dv = reinterpret_cast<const T *>(recp + dinv_off) + doff + i + 3 * r * dstride;
+        o = dv[0] * t0 + dv[dstride] * t1 + dv[2 * dstride] * t2;
       }
       const double od = (double)o;
       if (m.x >= 0) ((lds_double *)L.vec)[3 * m.x + r] = od;
@@ -452,51 +436,63 @@ __device__ __forceinline__ void step_rows(const RecHead &h, const char *recp, Sw
   }
 }
 
-// Mode 1: one wavefront per (long) row; lanes stride over its entries.
+// Long rows (FP64): one wavefront per row; lanes stride over its entries.
 // Pieces of a split row carry their partial sum in LDS.
-template <bool FWD, typename T>
-__device__ __forceinline__ void step_long_rows(const RecHead &h, const char *recp, SweepLds &L,
-                                               double *__restrict__ yx, double *__restrict__ z) {
+template <bool FWD>
+__device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
+                                          double *__restrict__ z, int j0, int n, int piece, int deps_off,
+                                          int rptr_off, int vals_off, int dinv_off, int dstride, int doff,
+                                          int in_off) {
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = kConsumerThreads / kWave;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
-  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + h.deps);
-  const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + h.rptr);
-  const T *vals = reinterpret_cast<const T *>(recp + h.vals);
-  for (int j = wv; j < h.nrows; j += nw) {
+  const int32_t *deps = reinterpret_cast<const int32_t *>(recp + deps_off);
+  const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + rptr_off);
+  const double *vals = reinterpret_cast<const double *>(recp + vals_off);
+  for (int i = wv; i < n; i += nw) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int q = rptr[j] + lane; q < rptr[j + 1]; q += kWave) {
+    for (int q = rptr[i] + lane; q < rptr[i + 1]; q += kWave) {
       const int d = deps[q];
       const double y0 = vec[3 * d], y1 = vec[3 * d + 1], y2 = vec[3 * d + 2];
-      const T *b = vals + 9 * q;
-      s0 += (double)b[0] * y0 + (double)b[1] * y1 + (double)b[2] * y2;
-      s1 += (double)b[3] * y0 + (double)b[4] * y1 + (double)b[5] * y2;
-      s2 += (double)b[6] * y0 + (double)b[7] * y1 + (double)b[8] * y2;
+      const double *b = vals + 9 * q;
+      s0 += b[0] * y0 + b[1] * y1 + b[2] * y2;
+      s1 += b[3] * y0 + b[4] * y1 + b[5] * y2;
+      s2 += b[6] * y0 + b[7] * y1 + b[8] * y2;
     }
     s0 = wave_sum_dpp(s0);
     s1 = wave_sum_dpp(s1);
     s2 = wave_sum_dpp(s2);
     if (lane == 0) {
+      const int j = j0 + i;
       double a0, a1, a2;
-      if (h.piece == kPieceMiddle || h.piece == kPieceLast) {
+      if (piece == kPieceMiddle || piece == kPieceLast) {
         a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
       } else {
-        const double *inp = reinterpret_cast<const double *>(recp + h.in) + 3 * j;
+        const double *inp = reinterpret_cast<const double *>(recp + in_off) + 3 * j;
         a0 = inp[0]; a1 = inp[1]; a2 = inp[2];
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
-      if (h.piece == kPieceFirst || h.piece == kPieceMiddle) {
+      if (piece == kPieceFirst || piece == kPieceMiddle) {
         L.part[0] = a0; L.part[1] = a1; L.part[2] = a2;
       } else {
         if (!FWD) {
-          const T *dv = reinterpret_cast<const T *>(recp + h.dinv) + j;
-          const int S = h.nrows;
-          const double x0 = (double)dv[0] * a0 + (double)dv[S] * a1 + (double)dv[2 * S] * a2;
-          const double x1 = (double)dv[3 * S] * a0 + (double)dv[4 * S] * a1 + (double)dv[5 * S] * a2;
-          const double x2 = (double)dv[6 * S] * a0 + (double)dv[7 * S] * a1 + (double)dv[8 * S] * a2;
+          const double *dv = reinterpret_cast<const double *>(recp + dinv_off) + doff + i;
+          const int S = dstride;
+          const double x0 = dv[0] * a0 + dv[S] * a1 + dv[2 * S] * a2;
+          const double x1 = dv[3 * S] * a0 + dv[4 * S] * a1 + dv[5 * S] * a2;
+          const double x2 = dv[6 * S] * a0 + dv[7 * S] * a1 + dv[8 * S] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
         const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
-        row_out(m, a0, a1, a2, L, yx, z);
+        lds_double *w = (lds_double *)L.vec;
+        if (m.x >= 0) { w[3 * m.x] = a0; w[3 * m.x + 1] = a1; w[3 * m.x + 2] = a2; }
+        if (m.w & 1) {
+          double *g = yx + 3 * (size_t)m.y;
+          g[0] = a0; g[1] = a1; g[2] = a2;
+        }
+        if (m.z >= 0) {
+          double *g = z + 3 * (size_t)m.z;
+          g[0] = a0; g[1] = a1; g[2] = a2;
+        }
       }
     }
   }
@@ -604,14 +600,17 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
 template <bool FWD>
 __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
   const char *recp = reinterpret_cast<const char *>(L.buf[s & 1]);
-  const RecHead h = *reinterpret_cast<const RecHead *>(recp);
-  if (h.mode == 0) {
-    if (h.fp32) step_rows<FWD, float>(h, recp, L, yx, z);
-    else step_rows<FWD, double>(h, recp, L, yx, z);
-  } else {
-    if (h.fp32) step_long_rows<FWD, float>(h, recp, L, yx, z);
-    else step_long_rows<FWD, double>(h, recp, L, yx, z);
-  }
+  const RecHead *hp = reinterpret_cast<const RecHead *>(recp);
+  const RecHead h = *hp;
+  const int nlong = h.nrows - h.n32 - h.n64;
+  if (h.n32 > 0)
+    short_rows<FWD, float>(recp, L, yx, z, 0, h.n32, hp->koff32, h.nslots32, h.vals32, h.dinv32, h.n32, 0, h.in);
+  if (h.n64 > 0)
+    short_rows<FWD, double>(recp, L, yx, z, h.n32, h.n64, hp->koff64, h.nslots64, h.vals64, h.dinv64,
+                            h.n64 + nlong, 0, h.in);
+  if (nlong > 0)
+    long_rows<FWD>(recp, L, yx, z, h.n32 + h.n64, nlong, h.piece, h.ldeps, h.lrptr, h.lvals, h.dinv64,
+                   h.n64 + nlong, h.n64, h.in);
   if (h.nfill > 0) fill_values(h, recp, L, yx);
   __syncthreads();
 }

@@ -37,40 +37,52 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 
 // One step of a sweep.  The record starts with its own descriptor (read
 // from LDS once the record has arrived); a compact {rec, len, pos, nrows}
-// array per sweep drives the prefetch.  Record sections (byte offsets from
-// the record start, each 16-byte aligned):
-//   head  RecHead (kRecHead bytes).
-//   rows  32 bytes per row: int4 {LDS slot or -1, own position, output
-//         cell or -1, flags}, flags bit 0 = store the value to the global
-//         vector at the own position (always in the forward sweep), bits
-//         8.. = the row's entry count; then (mode 0) the LDS slots of the
-//         row's dependencies, 8 x uint16.
-//   deps  mode 1: int per entry, the LDS slot of the dependency's value.
-//   rptr  mode 1: nrows+1 relative entry offsets.
-//   vals  mode 0: jagged-diagonal SoA, component e of entry q at
-//         [e*nslots + q], entry q = koff[k] + j for row j's k-th entry
-//         (rows sorted by entry count, descending); mode 1: 9 per entry.
-//   dinv  backward: component e of row j at [e*nrows + j].
-//   fill  int2 per value {global position, slot}: values of the NEXT step
-//         that have no LDS slot of their own, reloaded from the global
-//         vector into the fill slots (only in empty "fill" steps).
+// array per sweep drives the prefetch.  A step holds the rows of one level
+// (or part of one), in up to three sections, stored in this order:
+//   short FP32 rows [0, n32)      (FP32 factors; fine rows in FP32 mode)
+//   short FP64 rows [n32, n32+n64)
+//   long rows       [n32+n64, nrows), FP64
+// A short row has at most kMaxJdsWidth entries (four lanes per row); a
+// long row takes a whole wavefront.  Record sections (byte offsets from the
+// record start, each 16-byte aligned):
+//   head    RecHead (kRecHead bytes).
+//   rows    32 bytes per row: int4 {LDS slot or -1, own position, output
+//           cell or -1, flags}, flags bit 0 = store the value to the global
+//           vector at the own position (always in the forward sweep), bits
+//           8.. = the row's entry count; then (short rows) the LDS slots of
+//           the row's dependencies, 8 x uint16.
+//   ldeps   long rows: int per entry, the LDS slot of the dependency.
+//   lrptr   long rows: relative entry offsets (nlong+1).
+//   vals32, vals64  short rows: jagged diagonals, structure of arrays:
+//           component e of entry q at [e*nslots + q] (nslots = entries of
+//           the section); entry q = koff[k] + i for the k-th entry of the
+//           section's row i (rows sorted by entry count, descending).
+//   lvals   long rows: 9 values per entry.
+//   dinv32, dinv64  backward: component e of section row i at
+//           [e*rows + i] (dinv64 covers the short FP64 and the long rows).
+//   fill    int2 per value {global position, slot}: values of the NEXT step
+//           that have no LDS slot of their own, reloaded from the global
+//           vector into the fill slots (only in empty "fill" steps).
 // The stored record ends there (len 16-byte units); in LDS it is followed
 // by the "in" section, 3 doubles per row (at least one row): the rows'
 // inputs (forward: gathered right-hand side; backward: forward result),
 // which the streaming waves copy from the global vectors at the step's
 // positions.
-// A mode-1 row whose record would not fit one LDS buffer is split into
+// A long row whose record would not fit one LDS buffer is split into
 // pieces in consecutive one-row steps that carry the partial sum in LDS.
 // A value reloaded by a fill step is produced at least two steps before
-// it (the host inserts empty steps where needed), because results reach
-// global memory one step after they are computed.
+// it (the host inserts empty steps where needed).
 enum { kPieceWhole = 0, kPieceFirst = 1, kPieceMiddle = 2, kPieceLast = 3 };
 
 struct RecHead {
-  int32_t nrows, nslots, mode, fp32, piece, width;
-  int32_t deps, vals, dinv, rptr, pos, in;
-  int32_t koff[kMaxJdsWidth + 1];  // mode 0: first entry of each jagged diagonal
-  int32_t nfill, fill, pad;
+  int32_t nrows, n32, n64, piece;
+  int32_t nslots32, nslots64, pos, in;
+  int32_t vals32, vals64, lvals, ldeps;
+  int32_t lrptr, dinv32, dinv64, nfill;
+  int32_t fill, pad0, pad1, pad2;
+  int32_t koff32[kMaxJdsWidth + 1];  // first entry of each jagged diagonal
+  int32_t koff64[kMaxJdsWidth + 1];
+  int32_t pad3[2];
 };
 constexpr int kRecHead = (int)sizeof(RecHead);
 static_assert(kRecHead % 16 == 0, "record head must keep 16-byte alignment");

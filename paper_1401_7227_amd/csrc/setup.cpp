@@ -188,118 +188,130 @@ void triples_to_csr(std::vector<std::array<int32_t, 3>> &t, int32_t nrows, std::
 
 inline int32_t align16(int64_t b) { return (int32_t)((b + 15) & ~int64_t(15)); }
 
-// Record section offsets for a step of nrows rows and nslots entries.
-// total: bytes stored in global memory; lds: bytes the record occupies in
-// an LDS buffer (stored part plus the rows' inputs).
+// Record section offsets of a step.  total: bytes stored in global memory;
+// lds: bytes the record occupies in an LDS buffer (stored part plus the
+// rows' inputs).
+struct StepShape {
+  int n32 = 0, n64 = 0, nlong = 0;  // rows per section
+  int e32 = 0, e64 = 0, elong = 0;  // entries per section
+  int nrows() const { return n32 + n64 + nlong; }
+};
 struct RecLayout {
-  int32_t deps, rptr, vals, dinv, total, lds;
+  int32_t ldeps, lrptr, vals32, vals64, lvals, dinv32, dinv64, total, lds;
 };
 
 inline int32_t in_bytes(int nrows) { return align16((int64_t)24 * std::max(nrows, 1)); }
 
-RecLayout rec_layout(int nrows, int nslots, int mode, bool fwd, bool f32) {
-  const int sz = f32 ? 4 : 8;
+RecLayout rec_layout(const StepShape &k, bool fwd) {
   RecLayout L{};
-  L.deps = kRecHead + 32 * nrows;
-  int32_t at = L.deps + (mode == 1 ? align16((int64_t)4 * nslots) : 0);
-  L.rptr = at;
-  if (mode == 1) at += align16((int64_t)4 * (nrows + 1));
-  L.vals = at;
-  at += align16((int64_t)9 * nslots * sz);
-  L.dinv = at;
-  if (!fwd) at += align16((int64_t)9 * nrows * sz);
-  L.total = at;
-  L.lds = at + in_bytes(nrows);
+  int64_t at = kRecHead + 32 * (int64_t)k.nrows();
+  L.ldeps = (int32_t)at;
+  at += align16((int64_t)4 * k.elong);
+  L.lrptr = (int32_t)at;
+  if (k.nlong > 0) at += align16((int64_t)4 * (k.nlong + 1));
+  L.vals32 = (int32_t)at;
+  at += align16((int64_t)36 * k.e32);
+  L.vals64 = (int32_t)at;
+  at += align16((int64_t)72 * k.e64);
+  L.lvals = (int32_t)at;
+  at += align16((int64_t)72 * k.elong);
+  L.dinv32 = (int32_t)at;
+  if (!fwd) at += align16((int64_t)36 * k.n32);
+  L.dinv64 = (int32_t)at;
+  if (!fwd) at += align16((int64_t)72 * (k.n64 + k.nlong));
+  const int64_t lim = (int64_t)1 << 30;
+  L.total = (int32_t)std::min(at, lim);
+  L.lds = (int32_t)std::min(at + in_bytes(k.nrows()), lim);
   return L;
 }
 
-// Level steps of both sweeps of one subdomain: rows of a level grouped by
-// mode (short rows: one thread each, jagged diagonals; long rows: one
-// wavefront each) and, in FP32 mode, by precision class; chunked so that a
-// step has at most kMaxStepRows rows and its record fits one LDS buffer.
-// LDS vector slots are assigned by a linear scan over live ranges; rows
-// that get no slot pass their values through the global vector.
+// Level steps of both sweeps of one subdomain.  The rows of a level form
+// steps of at most kMaxStepRows rows whose record fits one LDS buffer; a
+// step holds short FP32 rows, short FP64 rows and long rows (sections in
+// that order; short rows sorted by entry count, descending).  A long row
+// too big for a buffer on its own becomes one-row pieces.  LDS vector
+// slots are assigned by a linear scan over live ranges; rows that get no
+// slot pass their values through the global vector and are reloaded by
+// fill steps.
 void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const std::vector<int32_t> &lb, int maxb,
                   bool fp32, bool restricted, const std::vector<int32_t> &owner, int sub) {
   struct Chunk {
-    std::vector<int32_t> rows;
-    int mode, f32;
-    int piece = kPieceWhole;  // split row: which piece
-    int e0 = 0, e1 = 0;       // split row: entry range (of the row's entries)
+    std::vector<int32_t> rows;  // section order
+    int n32 = 0, n64 = 0;       // short rows of each precision (the rest are long)
+    int piece = kPieceWhole;    // split row: which piece
+    int e0 = 0, e1 = 0;         // split row: entry range (of the row's entries)
   };
   auto count = [&](int i, bool fwd) {
     int c = 0;
     for (int e = S.rp[i]; e < S.rp[i + 1]; ++e) c += fwd ? (S.ci[e] < i) : (S.ci[e] > i);
     return c;
   };
+  // section of a row: 0 short FP32, 1 short FP64, 2 long
+  auto section = [&](int i, bool fwd) {
+    if (count(i, fwd) > kMaxJdsWidth) return 2;
+    return (fp32 && i < S.nfine) ? 0 : 1;
+  };
   auto make_chunks = [&](bool fwd, const std::vector<int32_t> &lev, int maxl) {
     std::vector<Chunk> out;
     std::vector<std::vector<int32_t>> bylev(maxl + 1);
     for (int i = 0; i < S.n; ++i) bylev[lev[i]].push_back(i);
-    for (int l = 0; l <= maxl; ++l)
-      for (int cls = 0; cls < (fp32 ? 2 : 1); ++cls)
-        for (int mode = 0; mode < 2; ++mode) {
-          std::vector<int32_t> rows;
-          for (int i : bylev[l]) {
-            if (fp32 && (i >= S.nfine) != (cls == 1)) continue;
-            if ((count(i, fwd) > kMaxJdsWidth) != (mode == 1)) continue;
-            rows.push_back(i);
+    for (int l = 0; l <= maxl; ++l) {
+      std::vector<int32_t> rows[3];
+      for (int i : bylev[l]) rows[section(i, fwd)].push_back(i);
+      for (int sc = 0; sc < 2; ++sc)
+        std::stable_sort(rows[sc].begin(), rows[sc].end(), [&](int a, int b) { return count(a, fwd) > count(b, fwd); });
+      Chunk cur;
+      StepShape shp;
+      auto flush = [&]() {
+        if (!cur.rows.empty()) out.push_back(cur);
+        cur = Chunk{};
+        shp = StepShape{};
+      };
+      for (int sc = 0; sc < 3; ++sc)
+        for (int i : rows[sc]) {
+          const int c = count(i, fwd);
+          StepShape t = shp;
+          if (sc == 0) { ++t.n32; t.e32 += c; }
+          if (sc == 1) { ++t.n64; t.e64 += c; }
+          if (sc == 2) { ++t.nlong; t.elong += c; }
+          if (t.nrows() > kMaxStepRows || rec_layout(t, fwd).lds > kRecBytes) {
+            flush();
+            t = StepShape{};
+            if (sc == 0) { t.n32 = 1; t.e32 = c; }
+            if (sc == 1) { t.n64 = 1; t.e64 = c; }
+            if (sc == 2) { t.nlong = 1; t.elong = c; }
           }
-          if (rows.empty()) continue;
-          if (mode == 0)
-            std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return count(a, fwd) > count(b, fwd); });
-          const bool f32 = fp32 && cls == 0;
-          Chunk cur{{}, mode, f32 ? 1 : 0};
-          int slots = 0;
-          for (int i : rows) {
-            const int c = count(i, fwd);
-            const int nr = (int)cur.rows.size() + 1;
-            const bool fits = nr <= kMaxStepRows && rec_layout(nr, slots + c, mode, fwd, f32).lds <= kRecBytes;
-            if (!fits && !cur.rows.empty()) {
-              out.push_back(cur);
-              cur.rows.clear();
-              slots = 0;
+          if (rec_layout(t, fwd).lds > kRecBytes) {
+            // a long row too big for one buffer: consecutive one-row pieces
+            int per = c;
+            StepShape one;
+            one.nlong = 1;
+            do {
+              one.elong = per;
+              if (rec_layout(one, fwd).lds <= kRecBytes) break;
+              per = (per + 1) / 2;
+            } while (true);
+            const int np = (c + per - 1) / per;
+            for (int k = 0; k < np; ++k) {
+              Chunk pc;
+              pc.rows = {i};
+              pc.piece = (k == 0) ? kPieceFirst : (k == np - 1 ? kPieceLast : kPieceMiddle);
+              pc.e0 = k * per;
+              pc.e1 = std::min(c, (k + 1) * per);
+              out.push_back(pc);
             }
-            if (rec_layout(1, c, mode, fwd, f32).lds > kRecBytes) {
-              // a row too long for one buffer: consecutive one-row pieces
-              int per = c;
-              while (rec_layout(1, per, mode, fwd, f32).lds > kRecBytes) per = (per + 1) / 2;
-              const int np = (c + per - 1) / per;
-              for (int k = 0; k < np; ++k) {
-                Chunk pc{{i}, mode, f32 ? 1 : 0};
-                pc.piece = (k == 0) ? kPieceFirst : (k == np - 1 ? kPieceLast : kPieceMiddle);
-                pc.e0 = k * per;
-                pc.e1 = std::min(c, (k + 1) * per);
-                out.push_back(pc);
-              }
-              continue;
-            }
-            cur.rows.push_back(i);
-            slots += c;
+            continue;
           }
-          if (!cur.rows.empty()) out.push_back(cur);
+          cur.rows.push_back(i);
+          if (sc == 0) ++cur.n32;
+          if (sc == 1) ++cur.n64;
+          shp = t;
         }
+      flush();
+    }
     return out;
   };
-  const std::vector<Chunk> fch = make_chunks(true, lf, maxf), bch = make_chunks(false, lb, maxb);
-  // positions
-  std::vector<int32_t> fpos(S.n), bpos(S.n);
-  int p = 0;
-  for (const Chunk &c : fch) {
-    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
-    S.fst.push_back(Step{p, (int32_t)c.rows.size()});
-    for (int i : c.rows) {
-      fpos[i] = p++;
-      S.frow.push_back(i);
-      S.fsrc.push_back(i < S.nfine ? S.cells[i] : -(1 + (i - S.nfine)));
-    }
-  }
-  p = 0;
-  for (const Chunk &c : bch) {
-    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
-    for (int i : c.rows) bpos[i] = p++;
-  }
-  S.bpos = bpos;
+  const std::vector<Chunk> fch0 = make_chunks(true, lf, maxf), bch0 = make_chunks(false, lb, maxb);
   // LDS slots by linear scan over steps
   auto allocate = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<int32_t> &slot, std::vector<int32_t> &last) {
     std::vector<int32_t> stp(S.n);
@@ -336,8 +348,8 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
     }
   };
   std::vector<int32_t> fslot, flast, bslot, blast;
-  allocate(fch, true, fslot, flast);
-  allocate(bch, false, bslot, blast);
+  allocate(fch0, true, fslot, flast);
+  allocate(bch0, false, bslot, blast);
   // Entries of a chunk (row-relative CSR entry lists, piece ranges applied).
   auto chunk_entries = [&](const Chunk &c, bool fwd) {
     std::vector<std::vector<int32_t>> ent(c.rows.size());
@@ -387,7 +399,8 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       const bool open = (c1.piece == kPieceWhole || c1.piece == kPieceFirst);
       const bool close = (c1.piece == kPieceWhole || c1.piece == kPieceLast);
       for (size_t k = 0; k < ranges.size(); ++k) {
-        Chunk p = c1;
+        Chunk p;
+        p.rows = c1.rows;
         p.e0 = ranges[k].first;
         p.e1 = ranges[k].second;
         p.piece = (k == 0 && open) ? kPieceFirst : ((k + 1 == ranges.size() && close) ? kPieceLast : kPieceMiddle);
@@ -400,16 +413,18 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       for (int e : es) add_spilled(e, total);
     if ((int)total.size() <= kFillSlots) return std::vector<Chunk>{c};
     if (c.rows.size() == 1) {
-      split_row(c);
+      Chunk one = c;
+      one.n32 = one.n64 = 0;  // a split row is always handled as a long row
+      split_row(one);
       return out;
     }
     // several whole rows: greedy groups of consecutive rows
-    Chunk cur{{}, c.mode, c.f32};
+    Chunk cur;
     std::vector<int32_t> set;
     auto flush = [&]() {
-      if (cur.rows.size() == 1) split_row(cur);
+      if (cur.rows.size() == 1 && cur.n32 + cur.n64 == 0) split_row(cur);
       else if (!cur.rows.empty()) out.push_back(cur);
-      cur.rows.clear();
+      cur = Chunk{};
     };
     for (size_t j = 0; j < c.rows.size(); ++j) {
       std::vector<int32_t> t = set;
@@ -420,21 +435,43 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         for (int e : ent[j]) add_spilled(e, t);
       }
       cur.rows.push_back(c.rows[j]);
+      if ((int)j < c.n32) ++cur.n32;
+      else if ((int)j < c.n32 + c.n64) ++cur.n64;
       set = t;
     }
     flush();
     return out;
   };
+  std::vector<Chunk> fch, bch;
+  for (const Chunk &c : fch0)
+    for (Chunk &q : split_for_fills(c, true, fslot)) fch.push_back(std::move(q));
+  for (const Chunk &c : bch0)
+    for (Chunk &q : split_for_fills(c, false, bslot)) bch.push_back(std::move(q));
+  // positions: rows of a step are consecutive, in the step's row order
+  std::vector<int32_t> fpos(S.n), bpos(S.n);
+  int p = 0;
+  for (const Chunk &c : fch) {
+    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
+    S.fst.push_back(Step{p, (int32_t)c.rows.size()});
+    for (int i : c.rows) {
+      fpos[i] = p++;
+      S.frow.push_back(i);
+      S.fsrc.push_back(i < S.nfine ? S.cells[i] : -(1 + (i - S.nfine)));
+    }
+  }
+  p = 0;
+  for (const Chunk &c : bch) {
+    if (c.piece != kPieceWhole && c.piece != kPieceFirst) continue;
+    for (int i : c.rows) bpos[i] = p++;
+  }
+  S.bpos = bpos;
   // Records.  Before a step that reads values without an LDS slot, a fill
   // step reloads them from the global vector into the fill slots; empty
   // steps keep that reload at least two steps after the values' producers.
-  auto emit = [&](const std::vector<Chunk> &ch0, bool fwd, std::vector<RecStep> &out) {
+  auto emit = [&](const std::vector<Chunk> &ch, bool fwd, std::vector<RecStep> &out) {
     const std::vector<int32_t> &slot = fwd ? fslot : bslot;
     const std::vector<int32_t> &last = fwd ? flast : blast;
     std::vector<int32_t> made(S.n, -1);  // emitted step that produced each row
-    std::vector<Chunk> ch;
-    for (const Chunk &c : ch0)
-      for (Chunk &p : split_for_fills(c, fwd, slot)) ch.push_back(std::move(p));
     auto push_record = [&](const RecHead &h, int32_t total, int32_t pos, int32_t nrows) -> uint8_t * {
       RecStep st{};
       st.rec = (int32_t)S.rec.size();
@@ -447,16 +484,28 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       out.push_back(st);
       return base;
     };
+    auto add_slot = [&](int32_t e, int64_t base, int32_t stride, bool f32) {
+      S.rl_src.push_back(e);
+      S.rl_base.push_back((int32_t)base);
+      S.rl_stride.push_back(stride);
+      S.rl_to32.push_back((uint8_t)f32);
+    };
     std::vector<int32_t> fill_of(S.n, -1);  // fill slot of a value for the current step
     for (const Chunk &c : ch) {
       const int nr = (int)c.rows.size();
       const auto ent = chunk_entries(c, fwd);
       const int32_t pos0 = fwd ? fpos[c.rows[0]] : bpos[c.rows[0]];
-      int nslots = 0;
+      StepShape shp;
+      shp.n32 = c.n32;
+      shp.n64 = c.n64;
+      shp.nlong = nr - c.n32 - c.n64;
       std::vector<int32_t> fills;  // columns to reload, in first-use order
       int32_t newest = -1;
       for (int j = 0; j < nr; ++j) {
-        nslots += (int)ent[j].size();
+        const int ne = (int)ent[j].size();
+        if (j < c.n32) shp.e32 += ne;
+        else if (j < c.n32 + c.n64) shp.e64 += ne;
+        else shp.elong += ne;
         for (int e : ent[j]) {
           const int col = S.ci[e];
           if (slot[col] >= 0 || fill_of[col] >= 0) continue;
@@ -487,36 +536,41 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
           fl[2 * q + 1] = kVecSlots - kFillSlots + (int32_t)q;
         }
       }
-      const bool f32 = c.f32 != 0;
-      const int sz = f32 ? 4 : 8;
-      const RecLayout L = rec_layout(nr, nslots, c.mode, fwd, f32);
+      const RecLayout L = rec_layout(shp, fwd);
       RecHead h{};
       h.nrows = nr;
-      h.nslots = nslots;
-      h.mode = c.mode;
-      h.fp32 = c.f32;
+      h.n32 = c.n32;
+      h.n64 = c.n64;
       h.piece = c.piece;
-      h.deps = L.deps;
-      h.vals = L.vals;
-      h.dinv = L.dinv;
-      h.rptr = L.rptr;
-      h.in = L.total;
+      h.nslots32 = shp.e32;
+      h.nslots64 = shp.e64;
       h.pos = pos0;
-      if (c.mode == 0) {
+      h.in = L.total;
+      h.vals32 = L.vals32;
+      h.vals64 = L.vals64;
+      h.lvals = L.lvals;
+      h.ldeps = L.ldeps;
+      h.lrptr = L.lrptr;
+      h.dinv32 = L.dinv32;
+      h.dinv64 = L.dinv64;
+      // jagged-diagonal starts of the short sections
+      auto diag_starts = [&](int j0, int j1, int32_t *koff) {
         int width = 0;
-        for (int j = 0; j < nr; ++j) width = std::max(width, (int)ent[j].size());
-        h.width = width;
+        for (int j = j0; j < j1; ++j) width = std::max(width, (int)ent[j].size());
         int q = 0;
-        for (int k = 0; k < width; ++k) {
-          h.koff[k] = q;
-          for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) ++q;
+        for (int k = 0; k <= kMaxJdsWidth; ++k) {
+          koff[k] = q;
+          if (k < width)
+            for (int j = j0; j < j1 && k < (int)ent[j].size(); ++j) ++q;
         }
-        h.koff[width] = q;
-      }
+      };
+      diag_starts(0, c.n32, h.koff32);
+      diag_starts(c.n32, c.n32 + c.n64, h.koff64);
       uint8_t *base = push_record(h, L.total, h.pos, nr);
       const int32_t rec0 = out.back().rec;
       int32_t *meta = reinterpret_cast<int32_t *>(base + kRecHead);
-      int32_t *deps = reinterpret_cast<int32_t *>(base + L.deps);
+      int32_t *ldeps = reinterpret_cast<int32_t *>(base + L.ldeps);
+      int32_t *lrptr = reinterpret_cast<int32_t *>(base + L.lrptr);
       auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : kVecSlots - kFillSlots + fill_of[col]; };
       for (int j = 0; j < nr; ++j) {
         const int i = c.rows[j];
@@ -533,48 +587,43 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
           m[3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
         }
         m[3] |= (int32_t)ent[j].size() << 8;
-        if (c.mode == 0) {
+        if (j < c.n32 + c.n64) {
           uint16_t *dp = reinterpret_cast<uint16_t *>(m + 4);
           for (size_t k = 0; k < ent[j].size(); ++k) dp[k] = (uint16_t)dep_of(S.ci[ent[j][k]]);
         }
         if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
       }
-      const int64_t vbase = (rec0 + L.vals) / sz;  // element index of the vals section
-      if (c.mode == 0) {
+      // short sections: jagged diagonals, structure of arrays
+      auto short_vals = [&](int j0, int j1, const int32_t *koff, int32_t off, int nslots, bool f32) {
+        const int sz = f32 ? 4 : 8;
+        const int64_t vbase = (rec0 + off) / sz;
+        for (int k = 0; k < kMaxJdsWidth; ++k)
+          for (int j = j0; j < j1 && k < (int)ent[j].size(); ++j)
+            add_slot(ent[j][k], vbase + koff[k] + (j - j0), nslots, f32);
+      };
+      short_vals(0, c.n32, h.koff32, L.vals32, shp.e32, true);
+      short_vals(c.n32, c.n32 + c.n64, h.koff64, L.vals64, shp.e64, false);
+      // long section: 9 values per entry
+      {
+        const int64_t vbase = (rec0 + L.lvals) / 8;
         int q = 0;
-        for (int k = 0; k < h.width; ++k)
-          for (int j = 0; j < nr && k < (int)ent[j].size(); ++j) {
-            const int e = ent[j][k];
-            S.rl_src.push_back(e);
-            S.rl_base.push_back((int32_t)(vbase + q));
-            S.rl_stride.push_back(nslots);
-            S.rl_to32.push_back((uint8_t)f32);
-            ++q;
-          }
-      } else {
-        int32_t *rptr = reinterpret_cast<int32_t *>(base + L.rptr);
-        int q = 0;
-        for (int j = 0; j < nr; ++j) {
-          rptr[j] = q;
+        for (int j = c.n32 + c.n64; j < nr; ++j) {
+          lrptr[j - c.n32 - c.n64] = q;
           for (int e : ent[j]) {
-            deps[q] = dep_of(S.ci[e]);
-            S.rl_src.push_back(e);
-            S.rl_base.push_back((int32_t)(vbase + 9 * q));
-            S.rl_stride.push_back(1);
-            S.rl_to32.push_back((uint8_t)f32);
+            ldeps[q] = dep_of(S.ci[e]);
+            add_slot(e, vbase + 9 * q, 1, false);
             ++q;
           }
         }
-        rptr[nr] = q;
+        if (shp.nlong > 0) lrptr[shp.nlong] = q;
       }
       for (int col : fills) fill_of[col] = -1;
       if (!fwd) {
-        const int64_t dbase = (rec0 + L.dinv) / sz;
+        const int64_t d32 = (rec0 + L.dinv32) / 4, d64 = (rec0 + L.dinv64) / 8;
         for (int j = 0; j < nr; ++j) {
-          S.rl_src.push_back(S.diag[c.rows[j]]);
-          S.rl_base.push_back((int32_t)(dbase + j));
-          S.rl_stride.push_back(nr);
-          S.rl_to32.push_back((uint8_t)f32);
+          const int32_t dg = S.diag[c.rows[j]];
+          if (j < c.n32) add_slot(dg, d32 + j, c.n32, true);
+          else add_slot(dg, d64 + (j - c.n32), nr - c.n32, false);
         }
       }
     }
