@@ -309,10 +309,17 @@ __global__ __launch_bounds__(256) void ilu_factor_kernel(DevPlan p, unsigned lon
   }
 }
 
+// Copies factor blocks into their record slots.  kind bit 0: FP32
+// destination; bit 1: "granule" layout of a short-row section, where
+// stride packs the section's entry count S (low 16 bits) and the entry q
+// (high 16 bits): components are grouped in 16-byte granules (2 doubles
+// or 4 floats) stored plane by plane, granule g of entry q at
+// [g*W*S + W*q], the ninth component at [8*S + q] (W values per granule);
+// otherwise component c goes to base + c*stride.
 __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t *__restrict__ src,
                                                        const int32_t *__restrict__ base,
                                                        const int32_t *__restrict__ stride,
-                                                       const uint8_t *__restrict__ to32,
+                                                       const uint8_t *__restrict__ kind,
                                                        const double *__restrict__ fact,
                                                        double *__restrict__ out64,
                                                        float *__restrict__ out32) {
@@ -320,13 +327,21 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
   if (t >= nslots) return;
   const int e = src[t];
   const size_t b0 = (size_t)base[t];
-  const size_t st = (size_t)stride[t];
-  const bool f32 = to32 && to32[t];
+  const int k = kind ? kind[t] : 0;
+  const bool f32 = k & 1;
+  const int st = stride[t];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const double v = (e >= 0) ? fact[(size_t)e * 9 + q] : 0.0;
-    if (f32) out32[b0 + q * st] = (float)v;
-    else out64[b0 + q * st] = v;
+  for (int c = 0; c < 9; ++c) {
+    size_t off;
+    if (k & 2) {
+      const int S = st & 0xffff, q = (int)((unsigned)st >> 16), W = f32 ? 4 : 2;
+      off = (c < 8) ? b0 + (size_t)(c / W) * W * S + (size_t)W * q + c % W : b0 + 8 * (size_t)S + q;
+    } else {
+      off = b0 + (size_t)c * st;
+    }
+    const double v = (e >= 0) ? fact[(size_t)e * 9 + c] : 0.0;
+    if (f32) out32[off] = (float)v;
+    else out64[off] = v;
   }
 }
 
@@ -366,6 +381,31 @@ __device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
   for (int e = 0; e < 9; ++e) b[e] = v[e * S];
 }
 
+// Block q of a short-row section in the granule layout (see relayout_kernel):
+// 16-byte reads, five per FP64 block, three per FP32 block.
+__device__ __forceinline__ void granule9(const double *sec, int S, int q, double (&b)[9]) {
+  const double2 *g = reinterpret_cast<const double2 *>(sec);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 v = g[u * S + q];
+    b[2 * u] = v.x;
+    b[2 * u + 1] = v.y;
+  }
+  b[8] = sec[8 * S + q];
+}
+__device__ __forceinline__ void granule9(const float *sec, int S, int q, float (&b)[9]) {
+  const float4 *g = reinterpret_cast<const float4 *>(sec);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const float4 v = g[u * S + q];
+    b[4 * u] = v.x;
+    b[4 * u + 1] = v.y;
+    b[4 * u + 2] = v.z;
+    b[4 * u + 3] = v.w;
+  }
+  b[8] = sec[8 * S + q];
+}
+
 struct SweepLds {
   u32x4 buf[2][kRecU4];        // record of step s (read) and of step s+1 (being written)
   double vec[3 * kVecSlots];    // vector slot pool (top kFillSlots: reloaded values)
@@ -395,23 +435,34 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     const bool act = i < n;
     const int j = j0 + (act ? i : 0);
     const int4 m = hdr[2 * j], dp = hdr[2 * j + 1];
+    // inputs and this lane's row of D^-1 do not depend on earlier steps
+    const int rc = r < 3 ? r : 2;
+    T a0, a1, a2, e0 = 0, e1 = 0, e2 = 0;
+    if (FWD) {
+      a0 = (T)inb[3 * j + rc];
+      a1 = a2 = 0;
+    } else {
+      a0 = (T)inb[3 * j]; a1 = (T)inb[3 * j + 1]; a2 = (T)inb[3 * j + 2];
+      const T *dv = reinterpret_cast<const T *>(recp + dinv_off) + doff + (j - j0) + 3 * rc * dstride;
+      e0 = dv[0]; e1 = dv[dstride]; e2 = dv[2 * dstride];
+    }
     const int cnt = act ? (m.w >> 8) : 0;
     const unsigned w0 = (unsigned)((r < 2) ? dp.x : dp.y), w1 = (unsigned)((r < 2) ? dp.z : dp.w);
     const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
     const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
     T s0 = 0, s1 = 0, s2 = 0;
     if (r < cnt) {
-      const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
       T b[9];
-      block9<T>(vals + q0 + i, nslots, b);
+      granule9(vals, nslots, q0 + i, b);
+      const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
       s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
       s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
       s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
     }
     if (r + 4 < cnt) {
-      const T u0 = (T)vec[3 * d1], u1 = (T)vec[3 * d1 + 1], u2 = (T)vec[3 * d1 + 2];
       T b[9];
-      block9<T>(vals + q1 + i, nslots, b);
+      granule9(vals, nslots, q1 + i, b);
+      const T u0 = (T)vec[3 * d1], u1 = (T)vec[3 * d1 + 1], u2 = (T)vec[3 * d1 + 2];
       s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
       s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
       s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
@@ -422,11 +473,9 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     if (act && r < 3) {
       T o;
       if (FWD) {
-        o = (T)inb[3 * j + r] - (r == 0 ? s0 : (r == 1 ? s1 : s2));
+        o = a0 - (r == 0 ? s0 : (r == 1 ? s1 : s2));
       } else {
-        const T t0 = (T)inb[3 * j] - s0, t1 = (T)inb[3 * j + 1] - s1, t2 = (T)inb[3 * j + 2] - s2;
-        const T *dv = reinterpret_cast<const T *>(recp + dinv_off) + doff + i + 3 * r * dstride;
-        o = dv[0] * t0 + dv[dstride] * t1 + dv[2 * dstride] * t2;
+        o = e0 * (a0 - s0) + e1 * (a1 - s1) + e2 * (a2 - s2);
       }
       const double od = (double)o;
       if (m.x >= 0) ((lds_double *)L.vec)[3 * m.x + r] = od;

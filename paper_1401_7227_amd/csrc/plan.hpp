@@ -28,7 +28,8 @@ constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (2 b
 constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
 static_assert(kVecSlots <= 65536, "slots are stored as 16-bit indices");
 constexpr int kMaxJdsWidth = 8;    // mode-0 rows have at most this many entries
-constexpr int kMaxStepRows = 256;  // rows per step (one thread per row)
+constexpr int kMaxStepRows = 256;  // rows per step
+static_assert(kMaxStepRows * kMaxJdsWidth < 65536, "section entries are packed in 16 bits");
 
 #ifndef ASM_FILL_SLOTS
 #define ASM_FILL_SLOTS 256
@@ -53,10 +54,13 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 //           the row's dependencies, 8 x uint16.
 //   ldeps   long rows: int per entry, the LDS slot of the dependency.
 //   lrptr   long rows: relative entry offsets (nlong+1).
-//   vals32, vals64  short rows: jagged diagonals, structure of arrays:
-//           component e of entry q at [e*nslots + q] (nslots = entries of
-//           the section); entry q = koff[k] + i for the k-th entry of the
-//           section's row i (rows sorted by entry count, descending).
+//   vals32, vals64  short rows: jagged diagonals; entry q = koff[k] + i for
+//           the k-th entry of the section's row i (rows sorted by entry
+//           count, descending).  Granule layout (S = entries of the
+//           section, W = values per 16 bytes: 2 doubles or 4 floats):
+//           component c < 8 of entry q at [(c/W)*W*S + W*q + c%W], the
+//           ninth at [8*S + q], so a block takes five (FP64) or three
+//           (FP32) 16-byte-or-smaller reads.
 //   lvals   long rows: 9 values per entry.
 //   dinv32, dinv64  backward: component e of section row i at
 //           [e*rows + i] (dinv64 covers the short FP64 and the long rows).

@@ -594,12 +594,18 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
       }
       // short sections: jagged diagonals, structure of arrays
+      // (granule layout: the relayout stride packs the entry count and the entry)
       auto short_vals = [&](int j0, int j1, const int32_t *koff, int32_t off, int nslots, bool f32) {
         const int sz = f32 ? 4 : 8;
         const int64_t vbase = (rec0 + off) / sz;
         for (int k = 0; k < kMaxJdsWidth; ++k)
-          for (int j = j0; j < j1 && k < (int)ent[j].size(); ++j)
-            add_slot(ent[j][k], vbase + koff[k] + (j - j0), nslots, f32);
+          for (int j = j0; j < j1 && k < (int)ent[j].size(); ++j) {
+            const int32_t q = koff[k] + (j - j0);
+            S.rl_src.push_back(ent[j][k]);
+            S.rl_base.push_back((int32_t)vbase);
+            S.rl_stride.push_back(nslots | (q << 16));
+            S.rl_to32.push_back((uint8_t)((f32 ? 1 : 0) | 2));
+          }
       };
       short_vals(0, c.n32, h.koff32, L.vals32, shp.e32, true);
       short_vals(c.n32, c.n32 + c.n64, h.koff64, L.vals64, shp.e64, false);
@@ -1139,7 +1145,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     place(S.rf, P.rf, o_rf[s]);
     place(S.rb, P.rb, o_rb[s]);
     for (size_t t = 0; t < S.rl_src.size(); ++t) {
-      const int sz = S.rl_to32[t] ? 4 : 8;
+      const int sz = (S.rl_to32[t] & 1) ? 4 : 8;
       P.rl.src[o_rl[s] + t] = (int32_t)(o_ent[s] + S.rl_src[t]);
       P.rl.base[o_rl[s] + t] = (int32_t)(S.rl_base[t] + o_rec[s] / sz);
       P.rl.stride[o_rl[s] + t] = S.rl_stride[t];

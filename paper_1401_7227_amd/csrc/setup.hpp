@@ -15,9 +15,10 @@ struct HostPattern {
   std::vector<int32_t> rp, ci;
 };
 
-// Slots copied from the CSR factors into a step layout: component q of slot
-// t goes to out[base[t] + q*stride[t]] of the FP32 array if to32[t], else of
-// the FP64 array.
+// Slots copied from the CSR factors into a step layout: to32[t] bit 0 selects
+// the FP32 array; bit 1 the granule layout of short-row sections (stride[t]
+// = entries of the section | entry << 16); otherwise component q of slot t
+// goes to out[base[t] + q*stride[t]].
 struct RelayoutMap {
   std::vector<int32_t> src, base, stride;
   std::vector<uint8_t> to32;
