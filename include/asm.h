@@ -171,6 +171,22 @@ typedef struct {
 asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
                      const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
 
+/* Solves `count` independent systems together: systems[i] x[i] = b[i] with
+ * preconds[i] (built on systems[i]), all with the same options.  Every
+ * kernel launch serves all systems still iterating (one sweep launch covers
+ * the subdomains of all of them, and so on), so many small systems fill the
+ * GPU; each system's arithmetic is exactly that of asm_solve, so every x[i]
+ * and infos[i] equal what asm_solve returns for that system alone.
+ * systems, preconds, b, x: host arrays of `count` handles / device vector
+ * pointers (each 3*nb_i doubles; x[i] in: x0, out: solution); a system may
+ * appear only once.  infos, status: host arrays of `count` (status[i] is
+ * ASM_OK or ASM_NOT_CONVERGED).  Returns ASM_OK if all converged,
+ * ASM_NOT_CONVERGED if any did not, or an error (nothing solved).  Uses the
+ * systems' own workspaces; synchronises the stream before returning. */
+asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
+                           const double *const *b_dev, double *const *x_dev, const asm_solve_opts *opts,
+                           hipStream_t stream, asm_solve_info *infos, int32_t *status);
+
 /* Kernel-phase timing of asm_solve (HIP events on the solve stream).
  * asm_profile_enable(sys, phase_mask): bit k of phase_mask times phase k
  * (0 = off, 0xff = all): inside asm_solve every launch of a timed phase

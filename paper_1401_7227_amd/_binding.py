@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
 
 EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_precond",
             "asm_refactor", "asm_precond_apply", "asm_precond_get_stats",
-            "asm_precond_export_sub", "asm_solve", "asm_destroy_precond",
+            "asm_precond_export_sub", "asm_solve", "asm_solve_batch", "asm_destroy_precond",
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read"]
 
 PHASES = ["ilu_apply", "lump", "combine", "spmv", "dots", "update", "residual", "other"]
@@ -88,6 +88,8 @@ def load() -> C.CDLL:
     L.asm_precond_export_sub.argtypes = [V, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32), V, V, V, V, V]
     L.asm_solve.argtypes = [V, V, V, V, C.POINTER(SolveOpts), V, C.POINTER(SolveInfo)]
+    L.asm_solve_batch.argtypes = [C.c_int32, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V),
+                                  C.POINTER(SolveOpts), V, C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
     L.asm_profile_enable.argtypes = [V, C.c_int32]
     L.asm_profile_read.argtypes = [V, C.POINTER(Profile), C.c_int32]
     L.asm_destroy_precond.argtypes = [V]
@@ -283,3 +285,29 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
     st = _check(load().asm_solve(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o),
                                  _stream(), C.byref(info)))
     return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)
+
+
+def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_iters=10000, fixed_iters=0):
+    """Solves independent systems together (one set of launches per step for
+    all of them).  Returns ([x], [Info]); each equals solve() of that system."""
+    n = len(systems)
+    if n == 0:
+        return [], []
+    bs = [_dev(b, torch.float64) for b in bs]
+    xs = []
+    for i in range(n):
+        if x0s is None or x0s[i] is None:
+            xs.append(torch.zeros_like(bs[i]))
+        else:
+            xs.append(_dev(x0s[i], torch.float64).clone())
+    V = C.c_void_p
+    hs = (V * n)(*[s.handle.value for s in systems])
+    ps = (V * n)(*[p.handle.value for p in preconds])
+    bp = (V * n)(*[b.data_ptr() for b in bs])
+    xp = (V * n)(*[x.data_ptr() for x in xs])
+    o = SolveOpts(restart, rtol, max_iters, fixed_iters)
+    infos = (SolveInfo * n)()
+    stat = (C.c_int32 * n)()
+    _check(load().asm_solve_batch(n, hs, ps, bp, xp, C.byref(o), _stream(), infos, stat))
+    return xs, [Info(int(stat[i]), infos[i].iters, infos[i].cycles, infos[i].rel_res_true,
+                     infos[i].rel_res_est) for i in range(n)]

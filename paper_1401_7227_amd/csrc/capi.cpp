@@ -761,6 +761,315 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   return result;
 }
 
+asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
+                           const double *const *b, double *const *x, const asm_solve_opts *o, hipStream_t s,
+                           asm_solve_info *infos, int32_t *status) {
+  g_err.clear();
+  if (count < 1 || !systems || !preconds || !b || !x || !o || !infos || !status)
+    return fail(ASM_ERR_INVALID, "NULL argument or empty batch");
+  const int m = o->restart;
+  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
+    return fail(ASM_ERR_INVALID, "bad solver option");
+  for (int i = 0; i < count; ++i) {
+    if (!systems[i] || !preconds[i] || !b[i] || !x[i]) return fail(ASM_ERR_INVALID, "NULL system, preconditioner or vector");
+    if (preconds[i]->sys != systems[i]) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+    for (int k = 0; k < i; ++k)
+      if (systems[k] == systems[i]) return fail(ASM_ERR_INVALID, "a system appears twice in the batch");
+  }
+  asm_status st;
+  for (int i = 0; i < count; ++i)
+    if ((st = ensure_workspace(systems[i], m, s)) != ASM_OK) return st;
+  const int ld = m + 1;
+  // pinned area per system: [beta][m published columns][1 + m coefficients]
+  const size_t region = 1 + (size_t)m * kPubStride + 1 + m;
+  double *pin = nullptr, *pin_dev = nullptr;
+  int32_t *segh = nullptr, *segd = nullptr;
+  BatchSys *tabd = nullptr;
+  struct Guard {
+    double *&pin;
+    int32_t *&segh, *&segd;
+    BatchSys *&tabd;
+    ~Guard() {
+      if (pin) (void)hipHostFree(pin);
+      if (segh) (void)hipHostFree(segh);
+      if (segd) (void)hipFree(segd);
+      if (tabd) (void)hipFree(tabd);
+    }
+  } guard{pin, segh, segd, tabd};
+  ASM_HIP(hipHostMalloc((void **)&pin, sizeof(double) * (region * count + 16), hipHostMallocCoherent));
+  ASM_HIP(hipHostGetDevicePointer((void **)&pin_dev, pin, 0));
+  // per-system finiteness of b and x0, and ||b||
+  for (int i = 0; i < count; ++i) {
+    Workspace &W = systems[i]->ws;
+    const int64_t n = 3 * (int64_t)systems[i]->pat.N;
+    ASM_HIP(hipMemsetAsync(W.flag, 0, sizeof(int), s));
+    ASM_HIP(launch_check_finite(n, b[i], W.flag, s));
+    ASM_HIP(launch_check_finite(n, x[i], W.flag, s));
+    int nb = 0;
+    ASM_HIP(launch_norm2(n, b[i], W.partial, &nb, s));
+    ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
+    ASM_HIP(hipMemcpyAsync(pin + region * i, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipMemcpyAsync(pin + region * i + 1, W.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+  ASM_HIP(hipStreamSynchronize(s));
+  std::vector<double> scl(count), tol(count), beta(count, 0.0);
+  for (int i = 0; i < count; ++i) {
+    int flag = 0;
+    std::memcpy(&flag, pin + region * i + 1, sizeof(int));
+    if (flag) return fail(ASM_ERR_NONFINITE, "non-finite b or x0 in batch entry " + std::to_string(i));
+    const double bn = std::sqrt(pin[region * i]);
+    scl[i] = bn > 0.0 ? bn : 1.0;
+    tol[i] = o->rtol * bn;
+    std::memset(&infos[i], 0, sizeof infos[i]);
+    status[i] = ASM_NOT_CONVERGED;
+  }
+  // device table of the systems
+  std::vector<BatchSys> tab(count);
+  for (int i = 0; i < count; ++i) {
+    asm_system S = systems[i];
+    asm_precond pc = preconds[i];
+    Workspace &W = S->ws;
+    BatchSys &T = tab[i];
+    std::memset(&T, 0, sizeof T);
+    T.n = 3 * (int64_t)S->pat.N;
+    T.ldu = W.ldu;
+    T.U = W.U; T.w = W.w; T.z = W.z; T.t = W.t;
+    T.partial = W.partial; T.dvec = W.dvec; T.H = W.H; T.scale = W.scale; T.coef = W.coef; T.misc = W.misc;
+    T.pub = pin_dev + region * i + 1;
+    T.coefh = pin_dev + region * i + 1 + (size_t)m * kPubStride;
+    T.b = b[i];
+    T.x = x[i];
+    T.N = S->pat.N;
+    T.nlog = (S->pat.N + 255) / 256;
+    T.sptr = S->sell.sptr; T.cols = S->sell.cols; T.vals = S->sell.vals;
+    T.kind = pc->opts.kind;
+    T.restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
+    T.npos = (int32_t)pc->plan.total_pos;
+    T.nsub = pc->ap.nsub;
+    T.ap = pc->ap;
+    T.c1n = pc->c1.n; T.c1lanes = pc->c1.lanes; T.c1ptr = pc->c1.ptr; T.c1idx = pc->c1.idx;
+    T.c2n = pc->c2.n; T.c2lanes = pc->c2.lanes; T.c2ptr = pc->c2.ptr; T.c2idx = pc->c2.idx;
+    T.PA = pc->PA; T.PNF = pc->PNF;
+    T.cptr = pc->cptr; T.cidx = pc->cidx;
+  }
+  ASM_HIP(hipMalloc((void **)&tabd, sizeof(BatchSys) * count));
+  ASM_HIP(hipMemcpyAsync(tabd, tab.data(), sizeof(BatchSys) * count, hipMemcpyHostToDevice, s));
+  // Segment tables: one ring slot per launch group (a step, or a cycle
+  // end), each holding the tables of every kernel kind for its systems.
+  const int nslot = kMaxRestart + 4;
+  const size_t slot_ints = (size_t)kBkCount * (2 * (size_t)count + 1);
+  ASM_HIP(hipHostMalloc((void **)&segh, sizeof(int32_t) * slot_ints * nslot, hipHostMallocDefault));
+  ASM_HIP(hipMalloc((void **)&segd, sizeof(int32_t) * slot_ints * nslot));
+  int slot_next = 0;
+  // Uploads the tables for the systems in `act`; fills seg[kBkCount].
+  auto make_segs = [&](const std::vector<int> &act, BatchSeg *seg) -> asm_status {
+    const int sl = slot_next;
+    slot_next = (slot_next + 1) % nslot;
+    int32_t *h = segh + slot_ints * sl, *d = segd + slot_ints * sl;
+    const int na = (int)act.size();
+    for (int k = 0; k < kBkCount; ++k) {
+      int32_t *st0 = h + (size_t)k * (2 * count + 1), *sy = st0 + count + 1;
+      int nseg = 0, tot = 0;
+      for (int a = 0; a < na; ++a) {
+        const BatchSys &T = tab[act[a]];
+        int nb = batch_blocks((BatchKernel)k, T);
+        if (k == kBkCopy && T.kind != ASM_KIND_NONE) nb = 0;
+        if ((k == kBkC1 || k == kBkC2 || k == kBkRhs || k == kBkApply || k == kBkCombine) && T.kind == ASM_KIND_NONE) nb = 0;
+        if (k == kBkCombine && T.restricted) nb = 0;
+        if (nb <= 0) continue;
+        st0[nseg] = tot;
+        sy[nseg] = act[a];
+        ++nseg;
+        tot += nb;
+      }
+      st0[nseg] = tot;
+      seg[k].start = d + (size_t)k * (2 * count + 1);
+      seg[k].sys = seg[k].start + count + 1;
+      seg[k].n = nseg;
+      seg[k].total = tot;
+    }
+    ASM_HIP(hipMemcpyAsync(d, h, sizeof(int32_t) * slot_ints, hipMemcpyHostToDevice, s));
+    return ASM_OK;
+  };
+  // the one-step-late readback needs the previous copy of a slot to have
+  // run before the host rewrites it: ring slots are reused only after the
+  // stream passed an event recorded after their last use
+  std::vector<hipEvent_t> slot_ev(nslot, nullptr);
+  struct EvGuard {
+    std::vector<hipEvent_t> &v;
+    ~EvGuard() {
+      for (hipEvent_t e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } evguard{slot_ev};
+  for (hipEvent_t &e : slot_ev) ASM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto segs_for = [&](const std::vector<int> &act, BatchSeg *seg) -> asm_status {
+    ASM_HIP(hipEventSynchronize(slot_ev[slot_next]));
+    const int sl = slot_next;
+    asm_status e2 = make_segs(act, seg);
+    if (e2 != ASM_OK) return e2;
+    (void)sl;
+    return ASM_OK;
+  };
+  auto mark_slot = [&](int sl) -> asm_status {
+    ASM_HIP(hipEventRecord(slot_ev[sl], s));
+    return ASM_OK;
+  };
+  // true residuals of the systems in act (published as beta)
+  auto residuals = [&](const std::vector<int> &act) -> asm_status {
+    BatchSeg seg[kBkCount];
+    const int sl = slot_next;
+    asm_status e2 = segs_for(act, seg);
+    if (e2 != ASM_OK) return e2;
+    ASM_HIP(launch_batch_spmv(tabd, seg[kBkSpmv], true, s));
+    ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], 1, false, 1, s));
+    ASM_HIP(launch_batch_finalize_norm(tabd, seg[kBkOne], -1, ld, kPubStride, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    (void)mark_slot(sl);
+    for (int i : act) beta[i] = pin[region * i];
+    return ASM_OK;
+  };
+  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+  std::vector<int> active;
+  for (int i = 0; i < count; ++i) active.push_back(i);
+  if ((st = residuals(active)) != ASM_OK) return st;
+  {
+    std::vector<int> keep;
+    for (int i : active) {
+      infos[i].rel_res_true = infos[i].rel_res_est = beta[i] / scl[i];
+      if ((o->fixed_iters == 0 && beta[i] <= tol[i]) || beta[i] == 0.0) status[i] = ASM_OK;
+      else keep.push_back(i);
+    }
+    active.swap(keep);
+  }
+  // host-side Arnoldi state per system
+  std::vector<std::vector<double>> H(count), cs(count), sn(count), g(count), sc(count);
+  std::vector<int> k(count, 0), kmax(count, 0);
+  std::vector<char> in_cycle(count, 0);
+  while (!active.empty()) {
+    int K = 0;
+    for (int i : active) {
+      H[i].assign((size_t)ld * m, 0.0);
+      cs[i].assign(m, 0.0);
+      sn[i].assign(m, 0.0);
+      g[i].assign(m + 1, 0.0);
+      sc[i].assign(m + 1, 0.0);
+      g[i][0] = beta[i];
+      sc[i][0] = 1.0 / beta[i];
+      k[i] = 0;
+      kmax[i] = std::min(m, limit - infos[i].iters);
+      in_cycle[i] = 1;
+      infos[i].cycles++;
+      K = std::max(K, kmax[i]);
+    }
+    std::vector<std::vector<int>> ran(K);  // systems that ran step j
+    std::vector<int> ran_slot(K, 0);
+    auto enqueue_step = [&](int j) -> asm_status {
+      std::vector<int> act;
+      for (int i : active)
+        if (in_cycle[i] && kmax[i] > j) act.push_back(i);
+      ran[j] = act;
+      if (act.empty()) return ASM_OK;
+      BatchSeg seg[kBkCount];
+      const int sl = slot_next;
+      asm_status e2 = segs_for(act, seg);
+      if (e2 != ASM_OK) return e2;
+      ran_slot[j] = sl;
+      ASM_HIP(launch_batch_precond(tabd, seg, j, s));
+      ASM_HIP(launch_batch_spmv(tabd, seg[kBkSpmv], false, s));
+      ASM_HIP(launch_batch_multidot(tabd, seg[kBkRed], j + 1, s));
+      ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], j + 2, true, 0, s));
+      ASM_HIP(launch_batch_finalize_dots(tabd, seg[kBkOne], j, ld, s));
+      ASM_HIP(launch_batch_update(tabd, seg[kBkRed], j + 1, ld, s));
+      ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], 1, false, 0, s));
+      ASM_HIP(launch_batch_finalize_norm(tabd, seg[kBkOne], j, ld, kPubStride, s));
+      ASM_HIP(hipEventRecord(systems[0]->ws.step_done[j], s));
+      return mark_slot(sl);
+    };
+    (void)ran_slot;
+    if ((st = enqueue_step(0)) != ASM_OK) return st;
+    for (int j = 0; j < K; ++j) {
+      if (j + 1 < K && (st = enqueue_step(j + 1)) != ASM_OK) return st;
+      if (ran[j].empty()) continue;
+      ASM_HIP(hipEventSynchronize(systems[0]->ws.step_done[j]));
+      for (int i : ran[j]) {
+        if (!in_cycle[i]) continue;  // left the cycle at an earlier step; this step is discarded
+        auto Hh = [&](int r, int c) -> double & { return H[i][(size_t)c * ld + r]; };
+        const double *col = pin + region * i + 1 + (size_t)j * kPubStride;
+        for (int r = 0; r <= j + 1; ++r) Hh(r, j) = col[r];
+        const double w0 = col[j + 2];
+        const double hn = Hh(j + 1, j);
+        sc[i][j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        for (int r = 0; r < j; ++r) {
+          const double a = Hh(r, j), c = Hh(r + 1, j);
+          Hh(r, j) = cs[i][r] * a + sn[i][r] * c;
+          Hh(r + 1, j) = -sn[i][r] * a + cs[i][r] * c;
+        }
+        const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
+        if (rho == 0.0) {
+          cs[i][j] = 1.0;
+          sn[i][j] = 0.0;
+        } else {
+          cs[i][j] = Hh(j, j) / rho;
+          sn[i][j] = Hh(j + 1, j) / rho;
+        }
+        Hh(j, j) = rho;
+        Hh(j + 1, j) = 0.0;
+        g[i][j + 1] = -sn[i][j] * g[i][j];
+        g[i][j] = cs[i][j] * g[i][j];
+        k[i] = j + 1;
+        infos[i].rel_res_est = std::fabs(g[i][j + 1]) / scl[i];
+        if (hn <= 1e-14 * w0 || (o->fixed_iters == 0 && std::fabs(g[i][j + 1]) <= tol[i]) || k[i] >= kmax[i])
+          in_cycle[i] = 0;
+      }
+    }
+    // cycle end: x += B^-1 (V y) for every system of the cycle
+    for (int i : active) {
+      infos[i].iters += k[i];
+      auto Hh = [&](int r, int c) -> double & { return H[i][(size_t)c * ld + r]; };
+      std::vector<double> y(k[i]);
+      for (int r = k[i] - 1; r >= 0; --r) {
+        double acc = g[i][r];
+        for (int c = r + 1; c < k[i]; ++c) acc -= Hh(r, c) * y[c];
+        y[r] = acc / Hh(r, r);
+      }
+      double *coefh = pin + region * i + 1 + (size_t)m * kPubStride;
+      coefh[0] = (double)k[i];
+      for (int r = 0; r < k[i]; ++r) coefh[1 + r] = y[r] * sc[i][r];
+    }
+    {
+      BatchSeg seg[kBkCount];
+      const int sl = slot_next;
+      if ((st = segs_for(active, seg)) != ASM_OK) return st;
+      ASM_HIP(launch_batch_lincomb(tabd, seg[kBkVec], s));
+      ASM_HIP(launch_batch_precond(tabd, seg, -1, s));
+      ASM_HIP(launch_batch_axpy(tabd, seg[kBkVec], s));
+      if ((st = mark_slot(sl)) != ASM_OK) return st;
+    }
+    if ((st = residuals(active)) != ASM_OK) return st;
+    std::vector<int> keep;
+    for (int i : active) {
+      infos[i].rel_res_true = beta[i] / scl[i];
+      if (o->fixed_iters > 0) {
+        if (infos[i].iters >= o->fixed_iters) { status[i] = ASM_OK; continue; }
+      } else if (beta[i] <= tol[i]) {
+        status[i] = ASM_OK;
+        continue;
+      }
+      if (infos[i].iters >= limit || beta[i] == 0.0) {
+        status[i] = beta[i] == 0.0 ? ASM_OK : ASM_NOT_CONVERGED;
+        continue;
+      }
+      keep.push_back(i);
+    }
+    active.swap(keep);
+  }
+  ASM_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i)
+    if (status[i] != ASM_OK) return ASM_NOT_CONVERGED;
+  return ASM_OK;
+}
+
 asm_status asm_profile_enable(asm_system S, int32_t phase_mask) {
   g_err.clear();
   if (!S) return fail(ASM_ERR_INVALID, "NULL argument");

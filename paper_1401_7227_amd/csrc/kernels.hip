@@ -22,9 +22,8 @@ constexpr int kWave = 64;
 // XCD b % 8).  Remap so that each XCD walks a contiguous range of logical
 // blocks: neighbouring rows then share that XCD's L2.  The grid is launched
 // with 8 * ceil(nlogical / 8) blocks; logical indices >= nlogical are idle.
-__device__ inline int xcd_logical_block(int nlogical) {
+__device__ inline int xcd_logical_block(int nlogical, int b) {
   const int per = (nlogical + 7) >> 3;
-  const int b = blockIdx.x;
   return (b & 7) * per + (b >> 3);
 }
 
@@ -110,14 +109,11 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(int nslots, const int32_
 // y = A x, or (RESID) y = b - A x with per-block partial sums of y.y.
 // One thread per block row; the 64 lanes of a wave cover one slice.
 template <bool RESID>
-__global__ __launch_bounds__(256) void spmv_kernel(int N, int nlogical, const int32_t *__restrict__ sptr,
-                                                   const int32_t *__restrict__ cols,
-                                                   const double *__restrict__ vals,
-                                                   const double *__restrict__ x,
-                                                   const double *__restrict__ b, double *__restrict__ y,
-                                                   double *__restrict__ partial) {
-  __shared__ double red[4];
-  const int lb = xcd_logical_block(nlogical);
+__device__ __forceinline__ void spmv_body(int bid, int N, int nlogical, const int32_t *__restrict__ sptr,
+                                          const int32_t *__restrict__ cols, const double *__restrict__ vals,
+                                          const double *__restrict__ x, const double *__restrict__ b,
+                                          double *__restrict__ y, double *__restrict__ partial, double *red) {
+  const int lb = xcd_logical_block(nlogical, bid);
   double nrm = 0.0;
   const int row = lb * 256 + (int)threadIdx.x;
   if (lb < nlogical && row < N) {
@@ -144,8 +140,19 @@ __global__ __launch_bounds__(256) void spmv_kernel(int N, int nlogical, const in
   }
   if (RESID) {
     const double s = block_sum<256>(nrm, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[bid] = s;
   }
+}
+
+template <bool RESID>
+__global__ __launch_bounds__(256) void spmv_kernel(int N, int nlogical, const int32_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ cols,
+                                                   const double *__restrict__ vals,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ b, double *__restrict__ y,
+                                                   double *__restrict__ partial) {
+  __shared__ double red[4];
+  spmv_body<RESID>(blockIdx.x, N, nlogical, sptr, cols, vals, x, b, y, partial, red);
 }
 
 // ---------------------------------------------------------------- gathers
@@ -170,15 +177,12 @@ __global__ __launch_bounds__(256) void gather_sum9_kernel(int ndst, const int32_
 }
 
 // dst[d] = scale * sum of src over idx[ptr[d] .. ptr[d+1]), 3 doubles per
-// entry; G lanes share a destination and combine their partial sums in a
-// fixed butterfly order (deterministic).
-template <int G>
-__global__ __launch_bounds__(256) void gather_sum3_kernel(int ndst, const int32_t *__restrict__ ptr,
-                                                          const int32_t *__restrict__ idx,
-                                                          const double *__restrict__ src,
-                                                          const double *__restrict__ scale,
-                                                          double *__restrict__ dst) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+// entry; G lanes (1, 2, 4, 8 or 16) share a destination and combine their
+// partial sums in a fixed butterfly order (deterministic).
+__device__ __forceinline__ void gather_sum3_body(int bid, int G, int ndst, const int32_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ src,
+                                                 const double *__restrict__ scale, double *__restrict__ dst) {
+  const int gid = bid * 256 + (int)threadIdx.x;
   const int d = gid / G, lane = gid % G;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (d < ndst) {
@@ -189,7 +193,6 @@ __global__ __launch_bounds__(256) void gather_sum3_kernel(int ndst, const int32_
       a2 += src[q + 2];
     }
   }
-#pragma unroll
   for (int off = G / 2; off >= 1; off >>= 1) {
     a0 += __shfl_xor(a0, off, G);
     a1 += __shfl_xor(a1, off, G);
@@ -201,6 +204,14 @@ __global__ __launch_bounds__(256) void gather_sum3_kernel(int ndst, const int32_
     dst[(size_t)d * 3 + 1] = s * a1;
     dst[(size_t)d * 3 + 2] = s * a2;
   }
+}
+
+__global__ __launch_bounds__(256) void gather_sum3_kernel(int G, int ndst, const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ idx,
+                                                          const double *__restrict__ src,
+                                                          const double *__restrict__ scale,
+                                                          double *__restrict__ dst) {
+  gather_sum3_body(blockIdx.x, G, ndst, ptr, idx, src, scale, dst);
 }
 
 // ---------------------------------------------------------------- 3x3 block math
@@ -672,9 +683,8 @@ __device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__res
   __syncthreads();  // matches the streaming waves' final barrier
 }
 
-__global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
-  __shared__ SweepLds L;
-  const SubDesc sd = p.sub[blockIdx.x];
+__device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, double *__restrict__ z, SweepLds &L) {
+  const SubDesc sd = p.sub[sub];
   const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
   const int nf = sd.rf1 - sd.rf0, nb = sd.rb1 - sd.rb0;
   if (threadIdx.x < kConsumerThreads) {
@@ -686,16 +696,19 @@ __global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *
   }
 }
 
+__global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
+  __shared__ SweepLds L;
+  ilu_apply_body(p, blockIdx.x, z, L);
+}
+
 // Forward right-hand sides in sweep order: the restriction R_i r of every
 // subdomain.  Fine rows gather r (times the basis scale); a coarse row sums
 // its near/far atoms' lumped residuals (App. B, eq. (B.2)).
-__global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t *__restrict__ fsrc,
-                                                         const double *__restrict__ r,
-                                                         const double *__restrict__ scale,
-                                                         const int32_t *__restrict__ cptr3,
-                                                         const int32_t *__restrict__ cidx3,
-                                                         const double *__restrict__ pnf, double *__restrict__ rs) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_rhs_body(int bid, int npos, const int32_t *__restrict__ fsrc,
+                                                const double *__restrict__ r, const double *__restrict__ scale,
+                                                const int32_t *__restrict__ cptr3, const int32_t *__restrict__ cidx3,
+                                                const double *__restrict__ pnf, double *__restrict__ rs) {
+  const int q = bid * 256 + (int)threadIdx.x;
   if (q >= npos) return;
   const int src = fsrc[q];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -712,11 +725,19 @@ __global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t
   rs[3 * (size_t)q] = a0; rs[3 * (size_t)q + 1] = a1; rs[3 * (size_t)q + 2] = a2;
 }
 
-__global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int32_t *__restrict__ cptr,
-                                                               const int32_t *__restrict__ cidx,
-                                                               const double *__restrict__ yext,
-                                                               double *__restrict__ z) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t *__restrict__ fsrc,
+                                                         const double *__restrict__ r,
+                                                         const double *__restrict__ scale,
+                                                         const int32_t *__restrict__ cptr3,
+                                                         const int32_t *__restrict__ cidx3,
+                                                         const double *__restrict__ pnf, double *__restrict__ rs) {
+  gather_rhs_body(blockIdx.x, npos, fsrc, r, scale, cptr3, cidx3, pnf, rs);
+}
+
+__device__ __forceinline__ void additive_combine_body(int bid, int N, const int32_t *__restrict__ cptr,
+                                                      const int32_t *__restrict__ cidx,
+                                                      const double *__restrict__ yext, double *__restrict__ z) {
+  const int c = bid * 256 + (int)threadIdx.x;
   if (c >= N) return;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int t = cptr[c]; t < cptr[c + 1]; ++t) {
@@ -726,22 +747,28 @@ __global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int3
   z[3 * (size_t)c] = a0; z[3 * (size_t)c + 1] = a1; z[3 * (size_t)c + 2] = a2;
 }
 
+__global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int32_t *__restrict__ cptr,
+                                                               const int32_t *__restrict__ cidx,
+                                                               const double *__restrict__ yext,
+                                                               double *__restrict__ z) {
+  additive_combine_body(blockIdx.x, N, cptr, cidx, yext, z);
+}
+
 // ---------------------------------------------------------------- Krylov
 // partial[b*(NV+1) + i] = sum over the block's elements of U_i . w (i < NV),
 // partial[b*(NV+1) + NV] = w . w.
 // Krylov vectors are processed two doubles per thread (16-byte loads); an
 // odd last element is handled by thread 0 of block 0.
 template <int NV>
-__global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
-                                                       const double *__restrict__ w,
-                                                       double *__restrict__ partial) {
-  __shared__ double red[4 * (NV + 1)];
+__device__ __forceinline__ void multidot_body(int bid, int nblk, int64_t n, const double *__restrict__ U, int64_t ldu,
+                                              const double *__restrict__ w, double *__restrict__ partial,
+                                              double *red) {
   double acc[NV + 1];
 #pragma unroll
   for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
   const int64_t n2 = n / 2;
   const double2 *w2 = reinterpret_cast<const double2 *>(w);
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (int64_t)gridDim.x * 256) {
+  for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n2; e += (int64_t)nblk * 256) {
     const double2 we = w2[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -750,7 +777,7 @@ __global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *
     }
     acc[NV] += we.x * we.x + we.y * we.y;
   }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((n & 1) && bid == 0 && threadIdx.x == 0) {
     const double we = w[n - 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] += U[i * ldu + n - 1] * we;
@@ -766,24 +793,36 @@ __global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *
   if (threadIdx.x <= NV) {
     const double s = red[threadIdx.x] + red[(NV + 1) + threadIdx.x] + red[2 * (NV + 1) + threadIdx.x] +
                      red[3 * (NV + 1) + threadIdx.x];
-    partial[(size_t)blockIdx.x * (NV + 1) + threadIdx.x] = s;
+    partial[(size_t)bid * (NV + 1) + threadIdx.x] = s;
   }
 }
 
+template <int NV>
+__global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
+                                                       const double *__restrict__ w,
+                                                       double *__restrict__ partial) {
+  __shared__ double red[4 * (NV + 1)];
+  multidot_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, w, partial, red);
+}
+
 // out[c] = sum_b partial[b*ncols + c], fixed order: one workgroup per column.
-__global__ __launch_bounds__(256) void reduce_cols_kernel(int nblocks, int ncols, const double *__restrict__ partial,
-                                                          double *__restrict__ out) {
-  __shared__ double red[4];
-  const int c = blockIdx.x;
+__device__ __forceinline__ void reduce_cols_body(int c, int nblocks, int ncols, const double *__restrict__ partial,
+                                                 double *__restrict__ out, double *red) {
   double s = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(size_t)b * ncols + c];
   s = block_sum<256>(s, red);
   if (threadIdx.x == 0) out[c] = s;
 }
 
-__global__ void finalize_dots_kernel(int nv, const double *__restrict__ d, const double *__restrict__ scale,
-                                     double *__restrict__ Hcol, double *__restrict__ coef,
-                                     double *__restrict__ wnorm) {
+__global__ __launch_bounds__(256) void reduce_cols_kernel(int nblocks, int ncols, const double *__restrict__ partial,
+                                                          double *__restrict__ out) {
+  __shared__ double red[4];
+  reduce_cols_body(blockIdx.x, nblocks, ncols, partial, out, red);
+}
+
+__device__ __forceinline__ void finalize_dots_body(int nv, const double *__restrict__ d,
+                                                   const double *__restrict__ scale, double *__restrict__ Hcol,
+                                                   double *__restrict__ coef, double *__restrict__ wnorm) {
   const int i = threadIdx.x;
   if (i < nv) {
     const double h = scale[i] * d[i];
@@ -793,13 +832,17 @@ __global__ void finalize_dots_kernel(int nv, const double *__restrict__ d, const
   if (i == 0) *wnorm = sqrt(d[nv]);
 }
 
+__global__ void finalize_dots_kernel(int nv, const double *__restrict__ d, const double *__restrict__ scale,
+                                     double *__restrict__ Hcol, double *__restrict__ coef,
+                                     double *__restrict__ wnorm) {
+  finalize_dots_body(nv, d, scale, Hcol, coef, wnorm);
+}
+
 // unew = w - sum_i coef[i] U_i and per-block partial sums of ||unew||^2.
 template <int NV>
-__global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
-                                                     const double *__restrict__ coef,
-                                                     const double *__restrict__ w, double *__restrict__ unew,
-                                                     double *__restrict__ partial) {
-  __shared__ double red[4];
+__device__ __forceinline__ void update_body(int bid, int nblk, int64_t n, const double *__restrict__ U, int64_t ldu,
+                                            const double *__restrict__ coef, const double *__restrict__ w,
+                                            double *__restrict__ unew, double *__restrict__ partial, double *red) {
   double cs[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) cs[i] = coef[i];
@@ -807,7 +850,7 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__
   const int64_t n2 = n / 2;
   const double2 *w2 = reinterpret_cast<const double2 *>(w);
   double2 *o2 = reinterpret_cast<double2 *>(unew);
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (int64_t)gridDim.x * 256) {
+  for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n2; e += (int64_t)nblk * 256) {
     double2 a = w2[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -818,7 +861,7 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__
     o2[e] = a;
     nrm += a.x * a.x + a.y * a.y;
   }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+  if ((n & 1) && bid == 0 && threadIdx.x == 0) {
     double a = w[n - 1];
 #pragma unroll
     for (int i = 0; i < NV; ++i) a -= cs[i] * U[i * ldu + n - 1];
@@ -826,14 +869,23 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__
     nrm += a * a;
   }
   const double s = block_sum<256>(nrm, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) partial[bid] = s;
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
+                                                     const double *__restrict__ coef,
+                                                     const double *__restrict__ w, double *__restrict__ unew,
+                                                     double *__restrict__ partial) {
+  __shared__ double red[4];
+  update_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, coef, w, unew, partial, red);
 }
 
 // h = ||u_new|| into hcol[nv] and its inverse into scale_out; optionally
 // publishes hcol[0..nv] and *wnorm to pinned host memory (pub).
-__global__ void finalize_norm_kernel(int nv, const double *__restrict__ nrm2, double *__restrict__ hcol,
-                                     double *__restrict__ scale_out, const double *__restrict__ wnorm,
-                                     double *__restrict__ pub) {
+__device__ __forceinline__ void finalize_norm_body(int nv, const double *__restrict__ nrm2,
+                                                   double *__restrict__ hcol, double *__restrict__ scale_out,
+                                                   const double *__restrict__ wnorm, double *__restrict__ pub) {
   const int i = threadIdx.x;
   const double h = sqrt(nrm2[0]);
   if (i == 0) {
@@ -849,20 +901,37 @@ __global__ void finalize_norm_kernel(int nv, const double *__restrict__ nrm2, do
   }
 }
 
-__global__ __launch_bounds__(256) void lincomb_kernel(int64_t n, int nv, const double *__restrict__ U, int64_t ldu,
-                                                      const double *__restrict__ coef, double *__restrict__ out) {
-  __shared__ double cs[kMaxRestart + 1];
+__global__ void finalize_norm_kernel(int nv, const double *__restrict__ nrm2, double *__restrict__ hcol,
+                                     double *__restrict__ scale_out, const double *__restrict__ wnorm,
+                                     double *__restrict__ pub) {
+  finalize_norm_body(nv, nrm2, hcol, scale_out, wnorm, pub);
+}
+
+__device__ __forceinline__ void lincomb_body(int bid, int nblk, int64_t n, int nv, const double *__restrict__ U,
+                                             int64_t ldu, const double *__restrict__ coef, double *__restrict__ out,
+                                             double *cs) {
   for (int i = threadIdx.x; i < nv; i += blockDim.x) cs[i] = coef[i];
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+  for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) {
     double a = 0.0;
     for (int i = 0; i < nv; ++i) a += cs[i] * U[i * ldu + e];
     out[e] = a;
   }
 }
 
+__global__ __launch_bounds__(256) void lincomb_kernel(int64_t n, int nv, const double *__restrict__ U, int64_t ldu,
+                                                      const double *__restrict__ coef, double *__restrict__ out) {
+  __shared__ double cs[kMaxRestart + 1];
+  lincomb_body(blockIdx.x, gridDim.x, n, nv, U, ldu, coef, out, cs);
+}
+
+__device__ __forceinline__ void axpy_body(int bid, int nblk, int64_t n, const double *__restrict__ z,
+                                          double *__restrict__ x) {
+  for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) x[e] += z[e];
+}
+
 __global__ __launch_bounds__(256) void axpy_kernel(int64_t n, const double *__restrict__ z, double *__restrict__ x) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) x[e] += z[e];
+  axpy_body(blockIdx.x, gridDim.x, n, z, x);
 }
 
 __global__ __launch_bounds__(256) void check_finite_kernel(int64_t n, const double *__restrict__ v, int *__restrict__ flag) {
@@ -879,13 +948,169 @@ __global__ __launch_bounds__(256) void norm2_kernel(int64_t n, const double *__r
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+__device__ __forceinline__ void scale_copy_body(int bid, int nblk, int64_t n, const double *__restrict__ r,
+                                                const double *__restrict__ scale, double *__restrict__ z) {
+  const double s = scale ? *scale : 1.0;
+  for (int64_t e = (int64_t)bid * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256) z[e] = s * r[e];
+}
+
 __global__ __launch_bounds__(256) void scale_copy_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ scale,
                                                          double *__restrict__ z) {
-  const double s = scale ? *scale : 1.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) z[e] = s * r[e];
+  scale_copy_body(blockIdx.x, gridDim.x, n, r, scale, z);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------- batches
+// A batched launch covers several independent systems; each block finds
+// its system by binary search over the segment starts and runs the same
+// body, with the same local block numbering, as a single-system launch.
+struct SegPos {
+  int sys, lb, nb;
+};
+__device__ __forceinline__ SegPos seg_find(const BatchSeg &g) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = g.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return {g.sys[lo], b - g.start[lo], g.start[lo + 1] - g.start[lo]};
+}
+
+// preconditioner input of a system: basis column col (scaled) or t
+__device__ __forceinline__ const double *prec_in(const BatchSys &S, int col, const double *&scale) {
+  if (col >= 0) {
+    scale = S.scale + col;
+    return S.U + (size_t)col * S.ldu;
+  }
+  scale = nullptr;
+  return S.t;
+}
+
+__global__ __launch_bounds__(256) void batch_c1_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int col) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const double *scale;
+  const double *r = prec_in(S, col, scale);
+  gather_sum3_body(p.lb, S.c1lanes, S.c1n, S.c1ptr, S.c1idx, r, scale, S.PA);
+}
+
+__global__ __launch_bounds__(256) void batch_c2_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  gather_sum3_body(p.lb, S.c2lanes, S.c2n, S.c2ptr, S.c2idx, S.PA, nullptr, S.PNF);
+}
+
+__global__ __launch_bounds__(256) void batch_rhs_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int col) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const double *scale;
+  const double *r = prec_in(S, col, scale);
+  gather_rhs_body(p.lb, S.npos, S.ap.fsrc, r, scale, S.ap.cptr3, S.ap.cidx3, S.ap.pnf, S.ap.rs);
+}
+
+__global__ __launch_bounds__(512, 1) void batch_apply_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  __shared__ SweepLds L;
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const ApplyPlan ap = S.ap;
+  ilu_apply_body(ap, p.lb, S.z, L);
+}
+
+__global__ __launch_bounds__(256) void batch_combine_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  additive_combine_body(p.lb, S.N, S.cptr, S.cidx, S.ap.yx, S.z);
+}
+
+__global__ __launch_bounds__(256) void batch_copy_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int col) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const double *scale;
+  const double *r = prec_in(S, col, scale);
+  scale_copy_body(p.lb, p.nb, S.n, r, scale, S.z);
+}
+
+template <bool RESID>
+__global__ __launch_bounds__(256) void batch_spmv_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  __shared__ double red[4];
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  if (RESID) spmv_body<true>(p.lb, S.N, S.nlog, S.sptr, S.cols, S.vals, S.x, S.b, S.U, S.partial, red);
+  else spmv_body<false>(p.lb, S.N, S.nlog, S.sptr, S.cols, S.vals, S.z, nullptr, S.w, nullptr, red);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void batch_multidot_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  __shared__ double red[4 * (NV + 1)];
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  multidot_body<NV>(p.lb, p.nb, S.n, S.U, S.ldu, S.w, S.partial, red);
+}
+
+// One block per system reduces its ncols columns in turn (the same sums, in
+// the same order, as one block per column) from the partial sums of the
+// system's reduction blocks (src 0: CGS kernels, 1: residual SpMV); dots:
+// into dvec, else into misc[2].
+__device__ __forceinline__ int red_blocks(const BatchSys &S, int src) {
+  if (src == 1) return (((int)((S.N + 255) / 256) + 7) >> 3) << 3;
+  const int64_t b = (S.n / 2 + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > kReduceBlocks ? kReduceBlocks : b));
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int ncols,
+                                                           int dots, int src) {
+  __shared__ double sh[4];
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const int nb = red_blocks(S, src);
+  for (int c = 0; c < ncols; ++c) reduce_cols_body(c, nb, ncols, S.partial, dots ? S.dvec : S.misc + 2, sh);
+}
+
+__global__ void batch_finalize_dots_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int j, int ldh) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  finalize_dots_body(j + 1, S.dvec, S.scale, S.H + (size_t)j * ldh, S.coef, S.misc);
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void batch_update_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int ldh) {
+  __shared__ double red[4];
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  update_body<NV>(p.lb, p.nb, S.n, S.U, S.ldu, S.coef, S.w, S.U + (size_t)NV * S.ldu, S.partial, red);
+}
+
+__global__ void batch_finalize_norm_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int j, int ldh,
+                                           int pub_stride) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  if (j >= 0)
+    finalize_norm_body(j + 1, S.misc + 2, S.H + (size_t)j * ldh, S.scale + j + 1, S.misc,
+                       S.pub + (size_t)j * pub_stride);
+  else if (threadIdx.x == 0) {  // true residual norm: beta, 1/beta, and beta to the host
+    const double h = sqrt(S.misc[2]);
+    S.misc[1] = h;
+    S.scale[0] = (h > 0.0) ? 1.0 / h : 0.0;
+    S.pub[-1] = h;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_lincomb_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  __shared__ double cs[kMaxRestart + 1];
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  const int k = (int)S.coefh[0];
+  lincomb_body(p.lb, p.nb, S.n, k, S.U, S.ldu, S.coefh + 1, S.t, cs);
+}
+
+__global__ __launch_bounds__(256) void batch_axpy_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+  const SegPos p = seg_find(g);
+  const BatchSys &S = tab[p.sys];
+  axpy_body(p.lb, p.nb, S.n, S.z, S.x);
+}
 
 }  // namespace
 
@@ -922,16 +1147,9 @@ hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx, 
 hipError_t launch_gather_sum3(int ndst, int lanes, const int32_t *ptr, const int32_t *idx, const double *src,
                               const double *scale, double *dst, hipStream_t s) {
   if (ndst == 0) return hipSuccess;
+  if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const int64_t threads = (int64_t)ndst * lanes;
-  const int grid = (int)((threads + 255) / 256);
-  switch (lanes) {
-    case 1: gather_sum3_kernel<1><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
-    case 2: gather_sum3_kernel<2><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
-    case 4: gather_sum3_kernel<4><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
-    case 8: gather_sum3_kernel<8><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
-    case 16: gather_sum3_kernel<16><<<grid, 256, 0, s>>>(ndst, ptr, idx, src, scale, dst); break;
-    default: return hipErrorInvalidValue;
-  }
+  gather_sum3_kernel<<<(int)((threads + 255) / 256), 256, 0, s>>>(lanes, ndst, ptr, idx, src, scale, dst);
   return hipGetLastError();
 }
 
@@ -1053,6 +1271,104 @@ hipError_t launch_norm2(int64_t n, const double *v, double *partial, int *nblock
   const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
   norm2_kernel<<<grid, 256, 0, s>>>(n, v, partial);
   *nblocks_out = grid;
+  return hipGetLastError();
+}
+
+int batch_blocks(BatchKernel k, const BatchSys &s) {
+  const int64_t n = s.n;
+  switch (k) {
+    case kBkC1: return s.c1n > 0 ? blocks_for((int64_t)s.c1n * s.c1lanes, 256) : 0;
+    case kBkC2: return s.c2n > 0 ? blocks_for((int64_t)s.c2n * s.c2lanes, 256) : 0;
+    case kBkRhs: return blocks_for(s.npos, 256);
+    case kBkApply: return s.nsub;
+    case kBkCombine: return blocks_for(s.N, 256);
+    case kBkCopy: return (int)std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    case kBkSpmv: return xcd_grid(blocks_for(s.N, 256));
+    case kBkRed: return (int)std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
+    case kBkVec: return (int)std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    case kBkOne: return 1;
+    default: return 0;
+  }
+}
+
+hipError_t launch_batch_precond(const BatchSys *tab, const BatchSeg *seg, int col, hipStream_t s) {
+  // seg[k] for every BatchKernel k (empty segments launch nothing)
+  if (seg[kBkCopy].total > 0) batch_copy_kernel<<<seg[kBkCopy].total, 256, 0, s>>>(tab, seg[kBkCopy], col);
+  if (seg[kBkC1].total > 0) batch_c1_kernel<<<seg[kBkC1].total, 256, 0, s>>>(tab, seg[kBkC1], col);
+  if (seg[kBkC2].total > 0) batch_c2_kernel<<<seg[kBkC2].total, 256, 0, s>>>(tab, seg[kBkC2]);
+  if (seg[kBkRhs].total > 0) batch_rhs_kernel<<<seg[kBkRhs].total, 256, 0, s>>>(tab, seg[kBkRhs], col);
+  if (seg[kBkApply].total > 0) batch_apply_kernel<<<seg[kBkApply].total, 512, 0, s>>>(tab, seg[kBkApply]);
+  if (seg[kBkCombine].total > 0) batch_combine_kernel<<<seg[kBkCombine].total, 256, 0, s>>>(tab, seg[kBkCombine]);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_spmv(const BatchSys *tab, const BatchSeg &seg, bool residual, hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  if (residual) batch_spmv_kernel<true><<<seg.total, 256, 0, s>>>(tab, seg);
+  else batch_spmv_kernel<false><<<seg.total, 256, 0, s>>>(tab, seg);
+  return hipGetLastError();
+}
+
+template <int NV>
+static void batch_multidot_launch(const BatchSys *tab, const BatchSeg &seg, hipStream_t s) {
+  batch_multidot_kernel<NV><<<seg.total, 256, 0, s>>>(tab, seg);
+}
+template <int... Is>
+static void batch_multidot_dispatch(int nv, const BatchSys *tab, const BatchSeg &seg, hipStream_t s,
+                                    std::integer_sequence<int, Is...>) {
+  ((nv == Is + 1 ? (batch_multidot_launch<Is + 1>(tab, seg, s), 0) : 0), ...);
+}
+hipError_t launch_batch_multidot(const BatchSys *tab, const BatchSeg &seg, int nv, hipStream_t s) {
+  if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  if (seg.total == 0) return hipSuccess;
+  batch_multidot_dispatch(nv, tab, seg, s, std::make_integer_sequence<int, kMaxRestart>{});
+  return hipGetLastError();
+}
+
+template <int NV>
+static void batch_update_launch(const BatchSys *tab, const BatchSeg &seg, int ldh, hipStream_t s) {
+  batch_update_kernel<NV><<<seg.total, 256, 0, s>>>(tab, seg, ldh);
+}
+template <int... Is>
+static void batch_update_dispatch(int nv, const BatchSys *tab, const BatchSeg &seg, int ldh, hipStream_t s,
+                                  std::integer_sequence<int, Is...>) {
+  ((nv == Is + 1 ? (batch_update_launch<Is + 1>(tab, seg, ldh, s), 0) : 0), ...);
+}
+hipError_t launch_batch_update(const BatchSys *tab, const BatchSeg &seg, int nv, int ldh, hipStream_t s) {
+  if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
+  if (seg.total == 0) return hipSuccess;
+  batch_update_dispatch(nv, tab, seg, ldh, s, std::make_integer_sequence<int, kMaxRestart>{});
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const BatchSys *tab, const BatchSeg &seg, int ncols, bool dots, int src, hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  batch_reduce_kernel<<<seg.total, 256, 0, s>>>(tab, seg, ncols, dots ? 1 : 0, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize_dots(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  batch_finalize_dots_kernel<<<seg.total, 64, 0, s>>>(tab, seg, j, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize_norm(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
+                                      hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  batch_finalize_norm_kernel<<<seg.total, 64, 0, s>>>(tab, seg, j, ldh, pub_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_lincomb(const BatchSys *tab, const BatchSeg &seg, hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  batch_lincomb_kernel<<<seg.total, 256, 0, s>>>(tab, seg);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_axpy(const BatchSys *tab, const BatchSeg &seg, hipStream_t s) {
+  if (seg.total == 0) return hipSuccess;
+  batch_axpy_kernel<<<seg.total, 256, 0, s>>>(tab, seg);
   return hipGetLastError();
 }
 

@@ -77,4 +77,55 @@ hipError_t launch_check_finite(int64_t n, const double *v, int *flag, hipStream_
 hipError_t launch_norm2(int64_t n, const double *v, double *partial, int *nblocks_out, hipStream_t s);
 hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+// One system of a batched solve: what the batched kernels read (device
+// table, one entry per system).  Vectors are the system's own workspace.
+struct BatchSys {
+  int64_t n, ldu;
+  double *U, *w, *z, *t, *partial, *dvec, *H, *scale, *coef, *misc;
+  double *pub;          // pinned (device view): published Hessenberg columns
+  const double *coefh;  // pinned (device view): [0] = k, [1..k] = solution coefficients
+  const double *b;
+  double *x;
+  int32_t N, nlog;
+  const int32_t *sptr, *cols;
+  const double *vals;
+  int32_t kind, restricted, npos, nsub;
+  ApplyPlan ap;
+  int32_t c1n, c1lanes, c2n, c2lanes;
+  const int32_t *c1ptr, *c1idx, *c2ptr, *c2idx;
+  double *PA, *PNF;
+  const int32_t *cptr, *cidx;
+};
+
+// Blocks of one batched launch: block b works for system sys[k] when
+// start[k] <= b < start[k+1] (local block b - start[k]); n segments.
+struct BatchSeg {
+  const int32_t *start, *sys;
+  int32_t n, total;
+};
+
+// Blocks each kernel gives one system (the same as a single-system launch,
+// so batched and single results are identical).
+enum BatchKernel {
+  kBkC1, kBkC2, kBkRhs, kBkApply, kBkCombine, kBkCopy, kBkSpmv, kBkRed, kBkVec, kBkOne, kBkCount
+};
+int batch_blocks(BatchKernel k, const BatchSys &s);
+
+// In every batched launcher, `col` selects the input of the preconditioner
+// (basis column col with its scale, or t unscaled when col < 0).
+hipError_t launch_batch_precond(const BatchSys *tab, const BatchSeg *seg, int col, hipStream_t s);
+hipError_t launch_batch_spmv(const BatchSys *tab, const BatchSeg &seg, bool residual, hipStream_t s);
+hipError_t launch_batch_multidot(const BatchSys *tab, const BatchSeg &seg, int nv, hipStream_t s);
+// src 0: partial sums of the CGS kernels, 1: of the residual SpMV.
+hipError_t launch_batch_reduce(const BatchSys *tab, const BatchSeg &seg, int ncols, bool dots, int src, hipStream_t s);
+hipError_t launch_batch_finalize_dots(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, hipStream_t s);
+hipError_t launch_batch_update(const BatchSys *tab, const BatchSeg &seg, int nv, int ldh, hipStream_t s);
+// j >= 0: step j (norm of the new basis vector, column published at
+// pub + j*pub_stride); j < 0: true residual norm (beta published at pub[-1]).
+hipError_t launch_batch_finalize_norm(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
+                                      hipStream_t s);
+hipError_t launch_batch_lincomb(const BatchSys *tab, const BatchSeg &seg, hipStream_t s);
+hipError_t launch_batch_axpy(const BatchSys *tab, const BatchSeg &seg, hipStream_t s);
+
 }  // namespace asmx

@@ -311,3 +311,67 @@ def test_config2_solve_matches_oracle(P, variant):
     xs = to_np(xf)[np.array(gd["sample"])]
     ref = np.array(g["x_sample"])
     assert np.linalg.norm(xs - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- batched solves
+BATCH_CASES = [
+    ((10, 10, 5), 1, dict(kind=2, combine=1, sx=4, sy=1, overlap=1, near=(2, 2, 2), far=(5, 5, 5)), 0),
+    ((13, 11, 7), 5, dict(kind=1, combine=0, sx=3, sy=3, overlap=2), 0),
+    ((16, 12, 8), 7, dict(kind=2, combine=1, sx=2, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4)), 1),
+    ((9, 9, 6), 8, dict(kind=0, combine=1, sx=1, sy=1, overlap=0), 0),
+    ((20, 18, 10), 9, dict(kind=1, combine=1, sx=3, sy=2, overlap=1), 0),
+]
+
+
+def _batch_setup(P):
+    import torch
+    systems, preconds, bs = [], [], []
+    for grid, seed, o, prec in BATCH_CASES:
+        s = gen.generate(*grid, seed=seed)
+        G = P.System.from_generated(s)
+        systems.append(G)
+        preconds.append(gpu_precond(P, G, o, precision=prec))
+        bs.append(torch.from_numpy(s.b).cuda())
+    return systems, preconds, bs
+
+
+@pytest.mark.parametrize("mode", ["rtol", "fixed", "limit"])
+def test_solve_batch_equals_single_solves(P, mode):
+    """Each system of a batch gets exactly the result of solving it alone
+    (same kernels, same reduction order), whatever the others do."""
+    systems, preconds, bs = _batch_setup(P)
+    kw = dict(restart=30, rtol=1e-6, max_iters=2000)
+    if mode == "fixed":
+        kw.update(fixed_iters=37)
+    if mode == "limit":
+        kw.update(restart=8, max_iters=19)
+    single = [P.solve(G, B, b, **kw) for G, B, b in zip(systems, preconds, bs)]
+    xs, infos = P.solve_batch(systems, preconds, bs, **kw)
+    for (x1, i1), x2, i2 in zip(single, xs, infos):
+        assert (i1.status, i1.iters, i1.cycles) == (i2.status, i2.iters, i2.cycles)
+        assert i1.rel_res_true == i2.rel_res_true
+        assert np.array_equal(to_np(x1), to_np(x2))
+    if mode == "rtol":  # the preconditioned ones converge (GMRES(30) alone may stagnate)
+        assert all(i.status == P.OK for i, c in zip(infos, BATCH_CASES) if c[2]["kind"] != 0)
+    if mode == "fixed":
+        assert all(i.iters == 37 for i in infos)
+    if mode == "limit":
+        assert any(i.status == P.NOT_CONVERGED for i in infos)
+
+
+def test_solve_batch_with_x0_and_errors(P):
+    import torch
+    systems, preconds, bs = _batch_setup(P)
+    x0s = [torch.full_like(b, 0.25) for b in bs]
+    single = [P.solve(G, B, b, x0=x0) for G, B, b, x0 in zip(systems, preconds, bs, x0s)]
+    xs, infos = P.solve_batch(systems, preconds, bs, x0s)
+    for (x1, i1), x2, i2 in zip(single, xs, infos):
+        assert i1.iters == i2.iters and np.array_equal(to_np(x1), to_np(x2))
+    with pytest.raises(P.AsmError):
+        P.solve_batch([systems[0], systems[0]], [preconds[0], preconds[0]], [bs[0], bs[0]])
+    with pytest.raises(P.AsmError):
+        P.solve_batch([systems[0]], [preconds[1]], [bs[0]])
+    bad = bs[1].clone()
+    bad[5] = float("nan")
+    with pytest.raises(P.AsmError):
+        P.solve_batch(systems[:2], preconds[:2], [bs[0], bad])
