@@ -125,6 +125,67 @@ def cpu_baseline(s, gpu_iters, budget_steps):
             "setup_s": round(t1 - t0, 2), "s_per_step": round(per_step, 3)}
 
 
+def batch_systems(gen, np, count=256):
+    """256 systems: nx, ny uniform in 16..96, nz uniform in 8..32 (seed 1000+s
+    for system s), subdomains clamp(round(cells/4096), 16, 64) split in
+    proportion to nx:ny; two-level RAS, overlap 1, near 4^3, far 16^3."""
+    rng = np.random.default_rng(77)
+    out = []
+    for k in range(count):
+        nx, ny = int(rng.integers(16, 97)), int(rng.integers(16, 97))
+        nz = int(rng.integers(8, 33))
+        cells = nx * ny * nz
+        nsub = int(min(64, max(16, round(cells / 4096))))
+        sx = max(1, min(nx, int(round((nsub * nx / ny) ** 0.5))))
+        sy = max(1, min(ny, int(round(nsub / sx))))
+        out.append(((nx, ny, nz), 1000 + k, dict(sx=sx, sy=sy, overlap=1)))
+    return out
+
+
+def bench_batch(P, gen, torch, np, args):
+    specs = batch_systems(gen, np)
+    systems, preconds, bs = [], [], []
+    t0 = time.perf_counter()
+    cells = 0
+    for grid, seed, split in specs:
+        s = gen.generate(*grid, seed=seed)
+        cells += s.N
+        G = P.System.from_generated(s)
+        systems.append(G)
+        preconds.append(P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, near=NEAR, far=FAR,
+                                  precision=P.FP32, **split))
+        bs.append(torch.from_numpy(s.b).cuda())
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    kw = dict(restart=RESTART, rtol=1e-6, max_iters=5000)
+    # warm-up, then one timed batched solve and one timed sequential pass
+    P.solve_batch(systems, preconds, bs, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = P.solve_batch(systems, preconds, bs, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    seq = [P.solve(G, B, b, **kw) for G, B, b in zip(systems, preconds, bs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    identical = all(bool(torch.equal(x, x1)) and i.iters == i1.iters for x, i, (x1, i1) in zip(xs, infos, seq))
+    iters = [i.iters for i in infos]
+    return {
+        "metric": "batch of 256 independent solves to rtol 1e-6 (FP32 preconditioner, FP64 GMRES(30))",
+        "value": round(t_batch * 1e3, 1), "unit": "ms/batch", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f64 (FP32 factors)", "data": "synthetic (seeded generator, no external dataset)",
+        "config": {"workload": "256 systems, nx, ny in 16..96, nz in 8..32 (seeds 1000+s), 16-64 subdomains "
+                               "each, two-level RAS, overlap 1, near 4^3, far 16^3, FP32 factors",
+                   "cells": cells, "systems": len(specs)},
+        "systems_per_s": round(len(specs) / t_batch, 1),
+        "sequential_ms": round(t_seq * 1e3, 1), "speedup_vs_sequential": round(t_seq / t_batch, 2),
+        "identical_to_sequential": identical, "converged": sum(i.status == P.OK for i in infos),
+        "iters": {"min": min(iters), "median": int(np.median(iters)), "max": max(iters)},
+        "setup_s": round(t_setup, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +194,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--workload", choices=["solve1m", "batch256"], default="solve1m",
+                    help="solve1m: the 1M-cell solve (default); batch256: 256 independent systems of "
+                         "2k-295k cells solved as one batch, against solving them one after another")
     ap.add_argument("--counter-workload", choices=["apply", "copy"], default=None,
                     help="run only a short workload for hardware-counter collection: five preconditioner "
                          "applications of the benchmark configuration, or a plain 1 GiB device copy")
@@ -150,6 +214,9 @@ def main():
     import paper_1401_7227_amd as P
 
     torch.cuda.set_device(0)
+    if args.workload == "batch256":
+        print(json.dumps(bench_batch(P, gen, torch, np, args)))
+        return
     if args.counter_workload == "copy":
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
         c = torch.empty_like(a)
