@@ -30,13 +30,19 @@ NEAR, FAR = (4, 4, 4), (16, 16, 16)
 HBM_PEAK_GBS = 8000.0
 RESTART = 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ilu_apply_two_level_1M_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_7227_amd", "csrc", "kernels.hip")
+# Sources that decide what the sweep kernel reads and writes: the kernel
+# itself and the host code that lays out its records.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_7227_amd", "csrc", f)
+                  for f in ("kernels.hip", "kernels.hpp", "plan.hpp", "setup.hpp", "setup.cpp")]
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
 def kernel_source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():

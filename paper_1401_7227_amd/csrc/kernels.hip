@@ -371,7 +371,14 @@ static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threa
 static_assert(kMaxStepRows * 3 <= 3 * 256, "row inputs: three doubles per streaming thread");
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kConsumerThreads = 256;  // one thread per row of a step
+#ifndef ASM_SWEEP_COMPUTE_WAVES
+#define ASM_SWEEP_COMPUTE_WAVES 8
+#endif
+#ifndef ASM_SWEEP_AHEAD
+#define ASM_SWEEP_AHEAD 3
+#endif
+constexpr int kConsumerThreads = 64 * ASM_SWEEP_COMPUTE_WAVES;  // computing waves of the sweep
+constexpr int kSweepThreads = kConsumerThreads + 256;           // plus four streaming waves
 
 // Explicit address spaces: LDS reads must never become generic (flat)
 // accesses, whose completion is tracked together with global memory.
@@ -572,13 +579,15 @@ __device__ __forceinline__ void fill_values(const RecHead &h, const char *recp, 
   }
 }
 
-// The sweep runs with wave-specialised roles.  Waves 0-3 (one thread per
-// row) compute the steps; waves 4-7 only stream: each streaming thread
+// The sweep runs with wave-specialised roles.  The first
+// ASM_SWEEP_COMPUTE_WAVES waves compute the steps; the last four waves
+// only stream: each streaming thread
 // keeps kAhead future records (and their row inputs) in registers and
 // moves the next one into LDS every step, so several steps are in flight
 // while the computing waves work.  Both roles execute the same sequence of
 // barriers.
-constexpr int kAhead = 4;
+constexpr int kAhead = ASM_SWEEP_AHEAD;
+static_assert(kAhead == 3 || kAhead == 4, "three or four records in flight per streaming thread");
 
 struct Producer {
   Stage st[kAhead];
@@ -639,19 +648,28 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   prod_load(steps[min(kAhead, S - 1)], rec, src, P.st[0], P.len[0], P.xlast[0], t);
   RecStep dn = steps[min(1 + kAhead, S - 1)];
   __syncthreads();
-  static_assert(kAhead == 4, "the unrolled streaming loop assumes four stages");
   // full groups of kAhead steps without conditions (exact wait counts),
   // then the remaining steps in straight-line code
   int s = 0;
-  for (; s + kAhead <= S; s += kAhead) {
-    prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-    prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
-    prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
-    prod_iter<0>(s + 3, S, steps, rec, src, L, P, dn, t);
+  if constexpr (kAhead == 4) {
+    for (; s + 4 <= S; s += 4) {
+      prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+      prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+      prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
+      prod_iter<0>(s + 3, S, steps, rec, src, L, P, dn, t);
+    }
+    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+    if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
+  } else {
+    for (; s + 3 <= S; s += 3) {
+      prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+      prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+      prod_iter<0>(s + 2, S, steps, rec, src, L, P, dn, t);
+    }
+    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
+    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
   }
-  if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-  if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
-  if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
   __syncthreads();  // matches the computing waves' final epilogue barrier
 }
 
@@ -696,7 +714,7 @@ __device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, doub
   }
 }
 
-__global__ __launch_bounds__(512, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
+__global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
   __shared__ SweepLds L;
   ilu_apply_body(p, blockIdx.x, z, L);
 }
@@ -1011,7 +1029,7 @@ __global__ __launch_bounds__(256) void batch_rhs_kernel(const BatchSys *__restri
   gather_rhs_body(p.lb, S.npos, S.ap.fsrc, r, scale, S.ap.cptr3, S.ap.cidx3, S.ap.pnf, S.ap.rs);
 }
 
-__global__ __launch_bounds__(512, 1) void batch_apply_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
+__global__ __launch_bounds__(kSweepThreads, 1) void batch_apply_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
   __shared__ SweepLds L;
   const SegPos p = seg_find(g);
   const BatchSys &S = tab[p.sys];
@@ -1174,7 +1192,7 @@ hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, cons
 
 hipError_t launch_ilu_apply(const ApplyPlan &p, double *z, hipStream_t s) {
   if (p.nsub == 0) return hipSuccess;
-  ilu_apply_kernel<<<p.nsub, 512, 0, s>>>(p, z);
+  ilu_apply_kernel<<<p.nsub, kSweepThreads, 0, s>>>(p, z);
   return hipGetLastError();
 }
 
@@ -1297,7 +1315,7 @@ hipError_t launch_batch_precond(const BatchSys *tab, const BatchSeg *seg, int co
   if (seg[kBkC1].total > 0) batch_c1_kernel<<<seg[kBkC1].total, 256, 0, s>>>(tab, seg[kBkC1], col);
   if (seg[kBkC2].total > 0) batch_c2_kernel<<<seg[kBkC2].total, 256, 0, s>>>(tab, seg[kBkC2]);
   if (seg[kBkRhs].total > 0) batch_rhs_kernel<<<seg[kBkRhs].total, 256, 0, s>>>(tab, seg[kBkRhs], col);
-  if (seg[kBkApply].total > 0) batch_apply_kernel<<<seg[kBkApply].total, 512, 0, s>>>(tab, seg[kBkApply]);
+  if (seg[kBkApply].total > 0) batch_apply_kernel<<<seg[kBkApply].total, kSweepThreads, 0, s>>>(tab, seg[kBkApply]);
   if (seg[kBkCombine].total > 0) batch_combine_kernel<<<seg[kBkCombine].total, 256, 0, s>>>(tab, seg[kBkCombine]);
   return hipGetLastError();
 }

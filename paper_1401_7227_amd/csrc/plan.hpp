@@ -19,7 +19,7 @@ struct Step {
 // Apply-sweep layout: every level step of a sweep is one contiguous record
 // in a global buffer, streamed into LDS ahead of its use.
 #ifndef ASM_REC_BYTES
-#define ASM_REC_BYTES 49152
+#define ASM_REC_BYTES 36864
 #endif
 constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (2 buffers)
 #ifndef ASM_VEC_SLOTS
