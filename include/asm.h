@@ -120,6 +120,20 @@ asm_status asm_setup_precond(asm_system sys, const asm_precond_opts *opts, hipSt
 /* Numeric re-assembly and re-factorisation after asm_update_values. */
 asm_status asm_refactor(asm_precond pc, hipStream_t stream);
 
+/*
+ * asm_precond_clone - the preconditioner of `sys` built on the plan of `src`.
+ * Section 4 re-lumps the coarse matrices once per non-linear iteration on a
+ * fixed decomposition: everything that depends only on the grid, the block
+ * pattern and the options (partition, overlap, coarse maps, level schedules,
+ * sweep layout) is computed once.  sys must have the same grid and block
+ * pattern as src's system (INVALID otherwise).  The clone shares that
+ * pattern-only state with src (it stays alive until every handle sharing it
+ * is destroyed; src may be destroyed first) and gets its own assembled
+ * matrices and factors, computed on the device from sys's values, exactly
+ * as asm_setup_precond would compute them.  out: host; receives the handle.
+ */
+asm_status asm_precond_clone(asm_precond src, asm_system sys, hipStream_t stream, asm_precond *out);
+
 /* z = B^-1 r (device vectors of 3*nb doubles). */
 asm_status asm_precond_apply(asm_precond pc, const double *r_dev, double *z_dev, hipStream_t stream);
 
@@ -186,6 +200,88 @@ asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double
 asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
                            const double *const *b_dev, double *const *x_dev, const asm_solve_opts *opts,
                            hipStream_t stream, asm_solve_info *infos, int32_t *status);
+
+/*
+ * Request server.  A request is the sequence of linear solves of one
+ * simulation on one grid: Section 2's Newton iteration (eq. (1.1)) solves
+ * A x = b once per non-linear iteration, with new values on the same block
+ * pattern, and Section 4 re-lumps the coarse matrices for each of them on
+ * the same decomposition.  The server keeps many requests in flight on one
+ * device:
+ *  - admission: queued requests are admitted in submission order while the
+ *    device memory they are expected to hold fits hbm_budget_bytes (0 = no
+ *    limit) and fewer than max_active solves are in flight; the first
+ *    request that does not fit stops admission (no overtaking), except that
+ *    a request is always admitted when no other request is running;
+ *  - plans: the pattern-only part of the preconditioner (asm_setup_precond's
+ *    host planning) is built once per grid, pattern and options and cached;
+ *    every request gets a clone of it (asm_precond_clone) with its own
+ *    factors.  Cached plans no request uses are dropped, least recently used
+ *    first, when the budget needs their memory;
+ *  - execution: the solves of all admitted requests iterate together, as
+ *    asm_solve_batch runs them (one launch per kernel serves all), and a new
+ *    solve joins between restart cycles.  After solve k of a request its
+ *    system takes the values vals_dev[k+1] and its preconditioner is
+ *    refactored (asm_update_values, asm_refactor) before solve k+1 joins.
+ *    Every solve's arithmetic is that of asm_solve on the same system and
+ *    preconditioner options, whatever else is in flight.
+ * One server drives one stream from one host thread.
+ */
+#define ASM_SERVER_MAX_SOLVES 8
+#define ASM_SERVER_MAX_ACTIVE 1024
+typedef struct asm_server_s *asm_server;
+typedef struct {
+  asm_solve_opts solve;      /* for every solve; see asm_solve                    */
+  int64_t hbm_budget_bytes;  /* device bytes for requests and cached plans, 0 = no limit */
+  int32_t max_active;        /* solves in flight at once, 1..ASM_SERVER_MAX_ACTIVE */
+} asm_server_opts;
+
+/* A request; the server copies this descriptor.  Every device buffer it
+ * names belongs to the caller and must stay valid until the request's
+ * completion is returned. */
+typedef struct {
+  int64_t tag;                      /* caller's id, returned on completion          */
+  asm_grid grid;                    /* as asm_create_system                          */
+  int32_t nb;
+  int64_t nnzb;
+  const int32_t *row_ptr_dev;       /* BSR pattern (device)                          */
+  const int32_t *col_idx_dev;
+  asm_precond_opts precond;         /* kind CLASSICAL or TWO_LEVEL                   */
+  int32_t nsolves;                  /* 1..ASM_SERVER_MAX_SOLVES                       */
+  const double *vals_dev[ASM_SERVER_MAX_SOLVES];  /* values of solve k (device)   */
+  const double *b_dev[ASM_SERVER_MAX_SOLVES];     /* right-hand side of solve k     */
+  double *x_dev[ASM_SERVER_MAX_SOLVES];           /* in: x0, out: solution k        */
+} asm_request;
+
+typedef struct {
+  int64_t tag;
+  int32_t status;        /* ASM_OK; ASM_NOT_CONVERGED if any solve stopped at
+                            max_iters; or the error of a setup, refactor or
+                            input check (later solves are not run)            */
+  int32_t solves;        /* solves finished                                    */
+  int32_t iters;         /* Arnoldi steps over all solves                      */
+  int32_t plan_cached;   /* 1 if the plan was in the cache at admission        */
+  double rel_res_true;   /* of the last solve                                  */
+} asm_completion;
+
+typedef struct {
+  int32_t queued, running, iterating, completed_unread, cached_plans;
+  int64_t bytes_in_use;  /* device bytes of running requests and cached plans */
+  int64_t plan_builds, plan_hits;
+} asm_server_state;
+
+asm_status asm_server_create(const asm_server_opts *opts, hipStream_t stream, asm_server *out);
+/* Queues a request (no device work). */
+asm_status asm_server_submit(asm_server srv, const asm_request *req);
+/* One scheduling round: admission, one restart cycle of every solve in
+ * flight, then up to `max` completions (oldest first) into done_host;
+ * *ndone receives their number.  Synchronises the stream.  An error return
+ * (device failure) leaves the server unusable except for destroy. */
+asm_status asm_server_poll(asm_server srv, int32_t max, asm_completion *done_host, int32_t *ndone);
+asm_status asm_server_get_state(asm_server srv, asm_server_state *state_host);
+/* Frees every request still queued or running (their results are lost)
+ * and every cached plan. */
+void asm_server_destroy(asm_server srv);
 
 /* Kernel-phase timing of asm_solve (HIP events on the solve stream).
  * asm_profile_enable(sys, phase_mask): bit k of phase_mask times phase k

@@ -12,4 +12,4 @@ declared in ``include/asm.h``); this package only marshals arguments.
 from ._binding import (  # noqa: F401
     ADDITIVE, ERR_HIP, ERR_INVALID, ERR_NONFINITE, ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FP32,
     FP64, KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, NOT_CONVERGED, OK, RESTRICTED,
-    PHASES, AsmError, Info, Precond, System, load, solve, solve_batch)
+    PHASES, AsmError, Info, Precond, Server, System, load, precond_opts, solve, solve_batch)

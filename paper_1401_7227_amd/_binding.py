@@ -28,7 +28,12 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
 EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_precond",
             "asm_refactor", "asm_precond_apply", "asm_precond_get_stats",
             "asm_precond_export_sub", "asm_solve", "asm_solve_batch", "asm_destroy_precond",
-            "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read"]
+            "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
+            "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
+            "asm_server_get_state", "asm_server_destroy"]
+
+SERVER_MAX_SOLVES = 8
+SERVER_MAX_ACTIVE = 1024
 
 PHASES = ["ilu_apply", "lump", "combine", "spmv", "dots", "update", "residual", "other"]
 
@@ -64,6 +69,28 @@ class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("solve", SolveOpts), ("hbm_budget_bytes", C.c_int64), ("max_active", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("grid", Grid), ("nb", C.c_int32), ("nnzb", C.c_int64),
+                ("row_ptr_dev", C.c_void_p), ("col_idx_dev", C.c_void_p), ("precond", PrecondOpts),
+                ("nsolves", C.c_int32), ("vals_dev", C.c_void_p * SERVER_MAX_SOLVES),
+                ("b_dev", C.c_void_p * SERVER_MAX_SOLVES), ("x_dev", C.c_void_p * SERVER_MAX_SOLVES)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("solves", C.c_int32),
+                ("iters", C.c_int32), ("plan_cached", C.c_int32), ("rel_res_true", C.c_double)]
+
+
+class ServerState(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("running", C.c_int32), ("iterating", C.c_int32),
+                ("completed_unread", C.c_int32), ("cached_plans", C.c_int32),
+                ("bytes_in_use", C.c_int64), ("plan_builds", C.c_int64), ("plan_hits", C.c_int64)]
+
+
 _lib = None
 
 
@@ -92,6 +119,12 @@ def load() -> C.CDLL:
                                   C.POINTER(SolveOpts), V, C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
     L.asm_profile_enable.argtypes = [V, C.c_int32]
     L.asm_profile_read.argtypes = [V, C.POINTER(Profile), C.c_int32]
+    L.asm_precond_clone.argtypes = [V, V, V, C.POINTER(V)]
+    L.asm_server_create.argtypes = [C.POINTER(ServerOpts), V, C.POINTER(V)]
+    L.asm_server_submit.argtypes = [V, C.POINTER(Request)]
+    L.asm_server_poll.argtypes = [V, C.c_int32, C.POINTER(Completion), C.POINTER(C.c_int32)]
+    L.asm_server_get_state.argtypes = [V, C.POINTER(ServerState)]
+    L.asm_server_destroy.argtypes = [V]
     L.asm_destroy_precond.argtypes = [V]
     L.asm_destroy_system.argtypes = [V]
     for name in EXPORTED:
@@ -99,6 +132,7 @@ def load() -> C.CDLL:
             getattr(L, name).restype = C.c_int
     L.asm_destroy_precond.restype = None
     L.asm_destroy_system.restype = None
+    L.asm_server_destroy.restype = None
     _lib = L
     return L
 
@@ -205,15 +239,25 @@ class Precond:
     """Schwarz preconditioner B (classical or two-level) on a System."""
 
     def __init__(self, system: System, kind=KIND_CLASSICAL, combine=RESTRICTED, sx=1, sy=1,
-                 overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64):
+                 overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64, *, _clone_of=None):
         L = load()
         self.system = system
+        h = C.c_void_p()
+        if _clone_of is not None:
+            _check(L.asm_precond_clone(_clone_of.handle, system.handle, _stream(), C.byref(h)))
+            self._h = h
+            self.kind = _clone_of.kind
+            return
         o = PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near),
                         (C.c_int32 * 3)(*far), precision)
-        h = C.c_void_p()
         _check(L.asm_setup_precond(system.handle, C.byref(o), _stream(), C.byref(h)))
         self._h = h
         self.kind = kind
+
+    def clone(self, system: System) -> "Precond":
+        """The preconditioner of `system` (same grid and pattern) on this
+        one's plan: shared pattern-only state, own factors."""
+        return Precond(system, _clone_of=self)
 
     @property
     def handle(self):
@@ -311,3 +355,76 @@ def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_i
     _check(load().asm_solve_batch(n, hs, ps, bp, xp, C.byref(o), _stream(), infos, stat))
     return xs, [Info(int(stat[i]), infos[i].iters, infos[i].cycles, infos[i].rel_res_true,
                      infos[i].rel_res_est) for i in range(n)]
+
+
+def precond_opts(kind=KIND_TWO_LEVEL, combine=RESTRICTED, sx=1, sy=1, overlap=1, near=(2, 2, 2),
+                 far=(4, 4, 4), precision=FP64) -> PrecondOpts:
+    return PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near), (C.c_int32 * 3)(*far),
+                       precision)
+
+
+class Server:
+    """Request server of the library (asm_server_*): requests queue, are
+    admitted within a device-memory budget, and their solves iterate together.
+    Tensors handed to submit() are kept alive here until their completion."""
+
+    def __init__(self, *, restart=30, rtol=1e-6, max_iters=10000, budget_bytes=0, max_active=256):
+        L = load()
+        o = ServerOpts(SolveOpts(restart, rtol, max_iters, 0), budget_bytes, max_active)
+        h = C.c_void_p()
+        _check(L.asm_server_create(C.byref(o), _stream(), C.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, tag: int, grid, row_ptr, col_idx, popts: PrecondOpts, vals, bs, xs):
+        """grid (nx, ny, nz); row_ptr, col_idx: int32 device tensors; vals, bs,
+        xs: lists of float64 device tensors, one per solve (xs hold x0 and
+        receive the solutions)."""
+        k = len(vals)
+        if not (1 <= k <= SERVER_MAX_SOLVES and len(bs) == k and len(xs) == k):
+            raise ValueError("one values, b and x tensor per solve, 1..8 solves")
+        r = Request()
+        r.tag = tag
+        r.grid = Grid(*grid)
+        r.nb = row_ptr.numel() - 1
+        r.nnzb = col_idx.numel()
+        r.row_ptr_dev = row_ptr.data_ptr()
+        r.col_idx_dev = col_idx.data_ptr()
+        r.precond = popts
+        r.nsolves = k
+        for i in range(k):
+            r.vals_dev[i] = vals[i].data_ptr()
+            r.b_dev[i] = bs[i].data_ptr()
+            r.x_dev[i] = xs[i].data_ptr()
+        _check(load().asm_server_submit(self._h, C.byref(r)))
+        self._live[tag] = (row_ptr, col_idx, vals, bs, xs)
+
+    def poll(self, max_done: int = 1024) -> list:
+        """One scheduling round; returns the completions as dicts."""
+        out = (Completion * max_done)()
+        n = C.c_int32()
+        _check(load().asm_server_poll(self._h, max_done, out, C.byref(n)))
+        res = []
+        for i in range(n.value):
+            c = out[i]
+            res.append({"tag": c.tag, "status": c.status, "solves": c.solves, "iters": c.iters,
+                        "plan_cached": c.plan_cached, "rel_res_true": c.rel_res_true})
+            self._live.pop(c.tag, None)
+        return res
+
+    def state(self) -> dict:
+        st = ServerState()
+        _check(load().asm_server_get_state(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerState._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().asm_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,202 +1,12 @@
 // C ABI: system and preconditioner handles, numeric setup on the device, and
 // the restarted right-preconditioned GMRES driver.
-#include <hip/hip_runtime_api.h>
-
-#include <algorithm>
-#include <climits>
 #include <cmath>
-#include <cstring>
-#include <string>
-#include <vector>
 
-#include "../../include/asm.h"
-#include "kernels.hpp"
-#include "setup.hpp"
+#include "handles.hpp"
 
 namespace asmx {
-namespace {
 
 thread_local std::string g_err;
-
-asm_status fail(asm_status st, const std::string &msg) {
-  g_err = msg;
-  return st;
-}
-
-#define ASM_HIP(call)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (call);                                                                  \
-    if (e_ != hipSuccess)                                                                    \
-      return fail(e_ == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP,                     \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                        \
-  } while (0)
-
-// Owner of device allocations; frees everything on destruction.
-struct DevMem {
-  std::vector<void *> ptrs;
-  size_t bytes = 0;
-  ~DevMem() { release(); }
-  void release() {
-    for (void *p : ptrs) (void)hipFree(p);
-    ptrs.clear();
-    bytes = 0;
-  }
-  template <typename T>
-  hipError_t alloc(T **out, size_t n) {
-    *out = nullptr;
-    if (n == 0) n = 1;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) return e;
-    ptrs.push_back(p);
-    bytes += n * sizeof(T);
-    *out = static_cast<T *>(p);
-    return hipSuccess;
-  }
-  template <typename T>
-  hipError_t upload(T **out, const std::vector<T> &v, hipStream_t s) {
-    hipError_t e = alloc(out, v.size());
-    if (e != hipSuccess || v.empty()) return e;
-    return hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-  }
-};
-
-struct GatherDev {
-  int32_t n = 0;
-  int32_t lanes = 1;  // threads per destination (about the mean fan-in)
-  int32_t *ptr = nullptr, *idx = nullptr;
-};
-
-hipError_t upload_gather(DevMem &m, GatherDev &g, const GatherList &h, hipStream_t s) {
-  g.n = h.size();
-  const double mean = g.n > 0 ? (double)h.idx.size() / g.n : 0.0;
-  g.lanes = 1;
-  while (g.lanes < 16 && g.lanes < mean) g.lanes *= 2;
-  hipError_t e = m.upload(&g.ptr, h.ptr, s);
-  if (e == hipSuccess) e = m.upload(&g.idx, h.idx, s);
-  return e;
-}
-
-// HIP-event timing of solve phases (enabled per system).
-struct Profiler {
-  bool on = false;
-  uint32_t mask = 0;  // phases timed (bit k = phase k)
-  std::vector<hipEvent_t> pool;
-  size_t next = 0;
-  struct Span {
-    int phase;
-    size_t a, b;
-  };
-  std::vector<Span> pend;
-  int64_t launches[ASM_NPHASE] = {};
-  double ms[ASM_NPHASE] = {};
-  ~Profiler() {
-    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-  }
-  // Records an event if the phase is timed; returns its pool index, or
-  // SIZE_MAX when not timed.
-  size_t mark(int phase, hipStream_t s) {
-    if (!on || !(mask >> phase & 1u)) return SIZE_MAX;
-    return record(s);
-  }
-  size_t record(hipStream_t s) {
-    if (next == pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
-      pool.push_back(e);
-    }
-    const size_t i = next++;
-    if (hipEventRecord(pool[i], s) != hipSuccess) return SIZE_MAX;
-    return i;
-  }
-  void span(int phase, size_t a, hipStream_t s) {
-    if (!on || a == SIZE_MAX) return;
-    const size_t b = record(s);
-    if (b != SIZE_MAX) pend.push_back({phase, a, b});
-  }
-  // Only after the stream has been synchronised.
-  void flush() {
-    for (const Span &p : pend) {
-      float t = 0.0f;
-      if (hipEventElapsedTime(&t, pool[p.a], pool[p.b]) == hipSuccess) {
-        ms[p.phase] += t;
-        launches[p.phase]++;
-      }
-    }
-    pend.clear();
-    next = 0;
-  }
-  void reset() {
-    std::fill(launches, launches + ASM_NPHASE, 0);
-    std::fill(ms, ms + ASM_NPHASE, 0.0);
-  }
-};
-
-// Krylov workspace of a system, sized for one restart length.
-struct Workspace {
-  DevMem mem;
-  int m = 0;
-  double *U = nullptr;        // (m+1) columns of n (stride ldu) basis (unnormalised)
-  int64_t ldu = 0;
-  double *w = nullptr, *z = nullptr, *t = nullptr;
-  double *partial = nullptr;  // kReduceBlocks x (kMaxRestart+2)
-  double *dvec = nullptr;     // reduced dot products
-  double *H = nullptr;        // (m+1) x m Hessenberg, column-major, ld m+1
-  double *scale = nullptr;    // 1/||U_i||
-  double *coef = nullptr;
-  double *misc = nullptr;     // [0] wnorm, [1] beta, [2] scratch norm
-  int *flag = nullptr;
-  double *pinned = nullptr;   // host staging: scalars, then one published column per step
-  double *pinned_dev = nullptr;  // the same memory as seen by kernels
-  hipEvent_t step_done[kMaxRestart] = {};
-  ~Workspace() {
-    if (pinned) (void)hipHostFree(pinned);
-    for (hipEvent_t e : step_done)
-      if (e) (void)hipEventDestroy(e);
-  }
-};
-
-// Pinned layout: [0, 16) scalars; column j of a cycle at kPubBase + j*kPubStride
-// holds H(0..j+1, j) and then ||w|| (the breakdown reference).
-constexpr int kPubBase = 16, kPubStride = kMaxRestart + 4;
-
-}  // namespace
-}  // namespace asmx
-
-using namespace asmx;
-
-struct asm_system_s {
-  int device = 0;
-  HostPattern pat;
-  DevMem mem;
-  int32_t *rp = nullptr, *ci = nullptr;
-  double *vals = nullptr;  // CSR values (sources of the assembly)
-  SellDev sell;
-  Workspace ws;
-  Profiler prof;
-};
-
-struct asm_precond_s {
-  asm_system sys = nullptr;
-  asm_precond_opts opts{};
-  PlanHost plan;  // small host-side parts kept for export and messages
-  DevMem mem;
-  DevPlan dp{};     // factorisation
-  ApplyPlan ap{};   // sweeps
-  GatherDev l1, l2, asrc, c1, c2, c3;
-  double *L1 = nullptr, *L2 = nullptr;  // lumped block values
-  double *aval = nullptr;               // assembled A_i (CSR)
-  double *PA = nullptr, *PNF = nullptr; // lumped residual sums
-  void *recbuf = nullptr;               // sweep records
-  int32_t *rl_src = nullptr, *rl_base = nullptr, *rl_stride = nullptr;
-  uint8_t *rl_to32 = nullptr;
-  int64_t rl_n = 0;
-  int32_t *cptr = nullptr, *cidx = nullptr;
-  unsigned long long *bad = nullptr;
-  asm_precond_stats stats{};
-};
-
-namespace {
 
 asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   Workspace &W = S->ws;
@@ -228,6 +38,8 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   (void)s;
   return ASM_OK;
 }
+
+namespace {
 
 // Non-finite check of a device vector (synchronises the stream).
 asm_status any_nonfinite(asm_system S, const double *v, int64_t n, hipStream_t s, bool *out) {
@@ -279,7 +91,7 @@ asm_status build_sell(asm_system S, hipStream_t s) {
 // Assembly (lumped matrices, A_i values) and factorisation on the device.
 asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   asm_system S = pc->sys;
-  const PlanHost &P = pc->plan;
+  const PlanHost &P = *pc->plan;
   if (pc->l1.n > 0) {
     ASM_HIP(launch_gather_sum9(pc->l1.n, pc->l1.ptr, pc->l1.idx, S->vals, INT32_MAX, nullptr, pc->L1, s));
     ASM_HIP(launch_gather_sum9(pc->l2.n, pc->l2.ptr, pc->l2.idx, pc->L1, INT32_MAX, nullptr, pc->L2, s));
@@ -305,8 +117,10 @@ asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   return ASM_OK;
 }
 
+}  // namespace
+
 asm_status apply_precond(asm_precond pc, const double *r, const double *scale, double *z, hipStream_t s,
-                         Profiler *prof = nullptr) {
+                         Profiler *prof) {
   asm_system S = pc->sys;
   const int64_t n = 3 * (int64_t)S->pat.N;
   Profiler dummy;
@@ -322,7 +136,7 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
     ASM_HIP(launch_gather_sum3(pc->c1.n, pc->c1.lanes, pc->c1.ptr, pc->c1.idx, r, scale, pc->PA, s));
     ASM_HIP(launch_gather_sum3(pc->c2.n, pc->c2.lanes, pc->c2.ptr, pc->c2.idx, pc->PA, nullptr, pc->PNF, s));
   }
-  ASM_HIP(launch_gather_rhs((int)pc->plan.total_pos, pc->ap, r, scale, s));
+  ASM_HIP(launch_gather_rhs((int)pc->plan->total_pos, pc->ap, r, scale, s));
   pf.span(ASM_PHASE_LUMP, t0, s);
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(ASM_PHASE_ILU_APPLY, s);
@@ -336,7 +150,9 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   return ASM_OK;
 }
 
-}  // namespace
+}  // namespace asmx
+
+using namespace asmx;
 
 extern "C" {
 
@@ -445,11 +261,14 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   if (o->kind == ASM_KIND_TWO_LEVEL)
     for (int d = 0; d < 3; ++d)
       if (o->near_box[d] < 1 || o->far_box[d] < 1) return cleanup(fail(ASM_ERR_INVALID, "bad coarsening box"));
-  PlanHost &P = pc->plan;
+  pc->plan = std::make_shared<PlanHost>();
+  pc->smem = std::make_shared<DevMem>();
+  PlanHost &P = *pc->plan;
   std::string err;
   asm_status st = build_plan(A, *o, P, err);
   if (st != ASM_OK) return cleanup(fail(st, err));
-  DevMem &M = pc->mem;
+  DevMem &M = *pc->smem;  // pattern-only arrays
+  DevMem &O = pc->mem;    // records, factors and work vectors of this handle
   DevPlan &d = pc->dp;
   hipStream_t s = stream;
   auto up = [&](auto **dst, const auto &vec) { return M.upload(dst, vec, s); };
@@ -481,7 +300,9 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   UP(&drf, P.rf);
   UP(&drb, P.rb);
   uint8_t *drec;
-  UP(&drec, P.rec);
+  if ((e = O.upload(&drec, P.rec, s)) != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  pc->rec_bytes = P.rec.size();
   UP(&t32, P.fsrc);
   ApplyPlan &ap = pc->ap;
   ap.nsub = P.nsub;
@@ -492,7 +313,7 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   pc->recbuf = drec;
   ap.fsrc = t32;
 #undef UP
-  auto ALLOC = [&](auto **dst, size_t n) { return M.alloc(dst, n); };
+  auto ALLOC = [&](auto **dst, size_t n) { return O.alloc(dst, n); };
   double *yx, *rs, *fact;
   if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
       (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
@@ -536,7 +357,7 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   pc->stats.factor_blocks = P.total_entries;
   pc->stats.fine_row_blocks = P.fine_row_entries;
   pc->stats.max_levels = P.max_levels;
-  pc->stats.device_bytes = (int64_t)M.bytes;
+  pc->stats.device_bytes = (int64_t)(M.bytes + O.bytes);
   pc->stats.sweep_steps = P.sweep_steps;
   pc->stats.reloaded_rows = P.lds_spilled_rows;
   *out = pc;
@@ -548,6 +369,71 @@ asm_status asm_refactor(asm_precond pc, hipStream_t stream) {
   if (!pc) return fail(ASM_ERR_INVALID, "NULL argument");
   if (pc->opts.kind == ASM_KIND_NONE) return ASM_OK;
   return numeric_setup(pc, stream);
+}
+
+asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, asm_precond *out) {
+  g_err.clear();
+  if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!src || !S) return fail(ASM_ERR_INVALID, "NULL argument");
+  const HostPattern &A = S->pat, &B = src->sys->pat;
+  if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.nnzb != B.nnzb || A.rp != B.rp || A.ci != B.ci)
+    return fail(ASM_ERR_INVALID, "the system's grid or block pattern differs from the source preconditioner's");
+  auto pc = new (std::nothrow) asm_precond_s();
+  if (!pc) return fail(ASM_ERR_OOM, "host allocation failed");
+  pc->sys = S;
+  pc->opts = src->opts;
+  pc->stats = src->stats;
+  if (src->opts.kind == ASM_KIND_NONE) {
+    *out = pc;
+    return ASM_OK;
+  }
+  auto cleanup = [&](asm_status st) {
+    delete pc;
+    return st;
+  };
+  // pattern-only state is shared; everything holding values is this handle's
+  pc->plan = src->plan;
+  pc->smem = src->smem;
+  pc->dp = src->dp;
+  pc->ap = src->ap;
+  pc->l1 = src->l1; pc->l2 = src->l2; pc->asrc = src->asrc;
+  pc->c1 = src->c1; pc->c2 = src->c2; pc->c3 = src->c3;
+  pc->rl_src = src->rl_src; pc->rl_base = src->rl_base; pc->rl_stride = src->rl_stride; pc->rl_to32 = src->rl_to32;
+  pc->rl_n = src->rl_n;
+  pc->cptr = src->cptr; pc->cidx = src->cidx;
+  pc->rec_bytes = src->rec_bytes;
+  const PlanHost &P = *pc->plan;
+  DevMem &O = pc->mem;
+  hipError_t e = hipSuccess;
+  uint8_t *rec = nullptr;
+  double *yx = nullptr, *rs = nullptr, *fact = nullptr;
+  if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
+      (e = O.alloc(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
+      (e = O.alloc(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
+      (e = O.alloc(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess || (e = O.alloc(&pc->bad, 1)) != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  if (pc->opts.kind == ASM_KIND_TWO_LEVEL &&
+      ((e = O.alloc(&pc->L1, (size_t)pc->l1.n * 9)) != hipSuccess ||
+       (e = O.alloc(&pc->L2, (size_t)pc->l2.n * 9)) != hipSuccess ||
+       (e = O.alloc(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
+       (e = O.alloc(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess))
+    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  // the records carry the sweep's row headers and slots next to the factor
+  // values; the values are rewritten by the numeric setup below
+  if ((e = hipMemcpyAsync(rec, src->recbuf, pc->rec_bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+    return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+  pc->recbuf = rec;
+  pc->ap.rec = rec;
+  pc->ap.yx = yx;
+  pc->ap.rs = rs;
+  pc->ap.pnf = pc->PNF;
+  pc->dp.fact = fact;
+  pc->stats.device_bytes = (int64_t)(pc->smem->bytes + O.bytes);
+  asm_status st = numeric_setup(pc, stream);
+  if (st != ASM_OK) return cleanup(st);
+  *out = pc;
+  return ASM_OK;
 }
 
 asm_status asm_precond_apply(asm_precond pc, const double *r_dev, double *z_dev, hipStream_t stream) {
@@ -567,7 +453,7 @@ asm_status asm_precond_export_sub(asm_precond pc, int32_t s, int32_t *n_out, int
                                   int32_t *ci_host, double *a_host, double *f_host, int32_t *label_host) {
   g_err.clear();
   if (!pc || pc->opts.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "no subdomains");
-  const PlanHost &P = pc->plan;
+  const PlanHost &P = *pc->plan;
   if (s < 0 || s >= P.nsub) return fail(ASM_ERR_INVALID, "subdomain out of range");
   const SubDesc &d = P.sub[s];
   const int32_t e0 = P.arp[d.ext_off], e1 = P.arp[d.ext_off + d.n];
@@ -759,315 +645,6 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   }
   ASM_HIP(hipStreamSynchronize(s));
   return result;
-}
-
-asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
-                           const double *const *b, double *const *x, const asm_solve_opts *o, hipStream_t s,
-                           asm_solve_info *infos, int32_t *status) {
-  g_err.clear();
-  if (count < 1 || !systems || !preconds || !b || !x || !o || !infos || !status)
-    return fail(ASM_ERR_INVALID, "NULL argument or empty batch");
-  const int m = o->restart;
-  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
-    return fail(ASM_ERR_INVALID, "bad solver option");
-  for (int i = 0; i < count; ++i) {
-    if (!systems[i] || !preconds[i] || !b[i] || !x[i]) return fail(ASM_ERR_INVALID, "NULL system, preconditioner or vector");
-    if (preconds[i]->sys != systems[i]) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-    for (int k = 0; k < i; ++k)
-      if (systems[k] == systems[i]) return fail(ASM_ERR_INVALID, "a system appears twice in the batch");
-  }
-  asm_status st;
-  for (int i = 0; i < count; ++i)
-    if ((st = ensure_workspace(systems[i], m, s)) != ASM_OK) return st;
-  const int ld = m + 1;
-  // pinned area per system: [beta][m published columns][1 + m coefficients]
-  const size_t region = 1 + (size_t)m * kPubStride + 1 + m;
-  double *pin = nullptr, *pin_dev = nullptr;
-  int32_t *segh = nullptr, *segd = nullptr;
-  BatchSys *tabd = nullptr;
-  struct Guard {
-    double *&pin;
-    int32_t *&segh, *&segd;
-    BatchSys *&tabd;
-    ~Guard() {
-      if (pin) (void)hipHostFree(pin);
-      if (segh) (void)hipHostFree(segh);
-      if (segd) (void)hipFree(segd);
-      if (tabd) (void)hipFree(tabd);
-    }
-  } guard{pin, segh, segd, tabd};
-  ASM_HIP(hipHostMalloc((void **)&pin, sizeof(double) * (region * count + 16), hipHostMallocCoherent));
-  ASM_HIP(hipHostGetDevicePointer((void **)&pin_dev, pin, 0));
-  // per-system finiteness of b and x0, and ||b||
-  for (int i = 0; i < count; ++i) {
-    Workspace &W = systems[i]->ws;
-    const int64_t n = 3 * (int64_t)systems[i]->pat.N;
-    ASM_HIP(hipMemsetAsync(W.flag, 0, sizeof(int), s));
-    ASM_HIP(launch_check_finite(n, b[i], W.flag, s));
-    ASM_HIP(launch_check_finite(n, x[i], W.flag, s));
-    int nb = 0;
-    ASM_HIP(launch_norm2(n, b[i], W.partial, &nb, s));
-    ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
-    ASM_HIP(hipMemcpyAsync(pin + region * i, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipMemcpyAsync(pin + region * i + 1, W.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  }
-  ASM_HIP(hipStreamSynchronize(s));
-  std::vector<double> scl(count), tol(count), beta(count, 0.0);
-  for (int i = 0; i < count; ++i) {
-    int flag = 0;
-    std::memcpy(&flag, pin + region * i + 1, sizeof(int));
-    if (flag) return fail(ASM_ERR_NONFINITE, "non-finite b or x0 in batch entry " + std::to_string(i));
-    const double bn = std::sqrt(pin[region * i]);
-    scl[i] = bn > 0.0 ? bn : 1.0;
-    tol[i] = o->rtol * bn;
-    std::memset(&infos[i], 0, sizeof infos[i]);
-    status[i] = ASM_NOT_CONVERGED;
-  }
-  // device table of the systems
-  std::vector<BatchSys> tab(count);
-  for (int i = 0; i < count; ++i) {
-    asm_system S = systems[i];
-    asm_precond pc = preconds[i];
-    Workspace &W = S->ws;
-    BatchSys &T = tab[i];
-    std::memset(&T, 0, sizeof T);
-    T.n = 3 * (int64_t)S->pat.N;
-    T.ldu = W.ldu;
-    T.U = W.U; T.w = W.w; T.z = W.z; T.t = W.t;
-    T.partial = W.partial; T.dvec = W.dvec; T.H = W.H; T.scale = W.scale; T.coef = W.coef; T.misc = W.misc;
-    T.pub = pin_dev + region * i + 1;
-    T.coefh = pin_dev + region * i + 1 + (size_t)m * kPubStride;
-    T.b = b[i];
-    T.x = x[i];
-    T.N = S->pat.N;
-    T.nlog = (S->pat.N + 255) / 256;
-    T.sptr = S->sell.sptr; T.cols = S->sell.cols; T.vals = S->sell.vals;
-    T.kind = pc->opts.kind;
-    T.restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
-    T.npos = (int32_t)pc->plan.total_pos;
-    T.nsub = pc->ap.nsub;
-    T.ap = pc->ap;
-    T.c1n = pc->c1.n; T.c1lanes = pc->c1.lanes; T.c1ptr = pc->c1.ptr; T.c1idx = pc->c1.idx;
-    T.c2n = pc->c2.n; T.c2lanes = pc->c2.lanes; T.c2ptr = pc->c2.ptr; T.c2idx = pc->c2.idx;
-    T.PA = pc->PA; T.PNF = pc->PNF;
-    T.cptr = pc->cptr; T.cidx = pc->cidx;
-  }
-  ASM_HIP(hipMalloc((void **)&tabd, sizeof(BatchSys) * count));
-  ASM_HIP(hipMemcpyAsync(tabd, tab.data(), sizeof(BatchSys) * count, hipMemcpyHostToDevice, s));
-  // Segment tables: one ring slot per launch group (a step, or a cycle
-  // end), each holding the tables of every kernel kind for its systems.
-  const int nslot = kMaxRestart + 4;
-  const size_t slot_ints = (size_t)kBkCount * (2 * (size_t)count + 1);
-  ASM_HIP(hipHostMalloc((void **)&segh, sizeof(int32_t) * slot_ints * nslot, hipHostMallocDefault));
-  ASM_HIP(hipMalloc((void **)&segd, sizeof(int32_t) * slot_ints * nslot));
-  int slot_next = 0;
-  // Uploads the tables for the systems in `act`; fills seg[kBkCount].
-  auto make_segs = [&](const std::vector<int> &act, BatchSeg *seg) -> asm_status {
-    const int sl = slot_next;
-    slot_next = (slot_next + 1) % nslot;
-    int32_t *h = segh + slot_ints * sl, *d = segd + slot_ints * sl;
-    const int na = (int)act.size();
-    for (int k = 0; k < kBkCount; ++k) {
-      int32_t *st0 = h + (size_t)k * (2 * count + 1), *sy = st0 + count + 1;
-      int nseg = 0, tot = 0;
-      for (int a = 0; a < na; ++a) {
-        const BatchSys &T = tab[act[a]];
-        int nb = batch_blocks((BatchKernel)k, T);
-        if (k == kBkCopy && T.kind != ASM_KIND_NONE) nb = 0;
-        if ((k == kBkC1 || k == kBkC2 || k == kBkRhs || k == kBkApply || k == kBkCombine) && T.kind == ASM_KIND_NONE) nb = 0;
-        if (k == kBkCombine && T.restricted) nb = 0;
-        if (nb <= 0) continue;
-        st0[nseg] = tot;
-        sy[nseg] = act[a];
-        ++nseg;
-        tot += nb;
-      }
-      st0[nseg] = tot;
-      seg[k].start = d + (size_t)k * (2 * count + 1);
-      seg[k].sys = seg[k].start + count + 1;
-      seg[k].n = nseg;
-      seg[k].total = tot;
-    }
-    ASM_HIP(hipMemcpyAsync(d, h, sizeof(int32_t) * slot_ints, hipMemcpyHostToDevice, s));
-    return ASM_OK;
-  };
-  // the one-step-late readback needs the previous copy of a slot to have
-  // run before the host rewrites it: ring slots are reused only after the
-  // stream passed an event recorded after their last use
-  std::vector<hipEvent_t> slot_ev(nslot, nullptr);
-  struct EvGuard {
-    std::vector<hipEvent_t> &v;
-    ~EvGuard() {
-      for (hipEvent_t e : v)
-        if (e) (void)hipEventDestroy(e);
-    }
-  } evguard{slot_ev};
-  for (hipEvent_t &e : slot_ev) ASM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  auto segs_for = [&](const std::vector<int> &act, BatchSeg *seg) -> asm_status {
-    ASM_HIP(hipEventSynchronize(slot_ev[slot_next]));
-    const int sl = slot_next;
-    asm_status e2 = make_segs(act, seg);
-    if (e2 != ASM_OK) return e2;
-    (void)sl;
-    return ASM_OK;
-  };
-  auto mark_slot = [&](int sl) -> asm_status {
-    ASM_HIP(hipEventRecord(slot_ev[sl], s));
-    return ASM_OK;
-  };
-  // true residuals of the systems in act (published as beta)
-  auto residuals = [&](const std::vector<int> &act) -> asm_status {
-    BatchSeg seg[kBkCount];
-    const int sl = slot_next;
-    asm_status e2 = segs_for(act, seg);
-    if (e2 != ASM_OK) return e2;
-    ASM_HIP(launch_batch_spmv(tabd, seg[kBkSpmv], true, s));
-    ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], 1, false, 1, s));
-    ASM_HIP(launch_batch_finalize_norm(tabd, seg[kBkOne], -1, ld, kPubStride, s));
-    ASM_HIP(hipStreamSynchronize(s));
-    (void)mark_slot(sl);
-    for (int i : act) beta[i] = pin[region * i];
-    return ASM_OK;
-  };
-  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
-  std::vector<int> active;
-  for (int i = 0; i < count; ++i) active.push_back(i);
-  if ((st = residuals(active)) != ASM_OK) return st;
-  {
-    std::vector<int> keep;
-    for (int i : active) {
-      infos[i].rel_res_true = infos[i].rel_res_est = beta[i] / scl[i];
-      if ((o->fixed_iters == 0 && beta[i] <= tol[i]) || beta[i] == 0.0) status[i] = ASM_OK;
-      else keep.push_back(i);
-    }
-    active.swap(keep);
-  }
-  // host-side Arnoldi state per system
-  std::vector<std::vector<double>> H(count), cs(count), sn(count), g(count), sc(count);
-  std::vector<int> k(count, 0), kmax(count, 0);
-  std::vector<char> in_cycle(count, 0);
-  while (!active.empty()) {
-    int K = 0;
-    for (int i : active) {
-      H[i].assign((size_t)ld * m, 0.0);
-      cs[i].assign(m, 0.0);
-      sn[i].assign(m, 0.0);
-      g[i].assign(m + 1, 0.0);
-      sc[i].assign(m + 1, 0.0);
-      g[i][0] = beta[i];
-      sc[i][0] = 1.0 / beta[i];
-      k[i] = 0;
-      kmax[i] = std::min(m, limit - infos[i].iters);
-      in_cycle[i] = 1;
-      infos[i].cycles++;
-      K = std::max(K, kmax[i]);
-    }
-    std::vector<std::vector<int>> ran(K);  // systems that ran step j
-    std::vector<int> ran_slot(K, 0);
-    auto enqueue_step = [&](int j) -> asm_status {
-      std::vector<int> act;
-      for (int i : active)
-        if (in_cycle[i] && kmax[i] > j) act.push_back(i);
-      ran[j] = act;
-      if (act.empty()) return ASM_OK;
-      BatchSeg seg[kBkCount];
-      const int sl = slot_next;
-      asm_status e2 = segs_for(act, seg);
-      if (e2 != ASM_OK) return e2;
-      ran_slot[j] = sl;
-      ASM_HIP(launch_batch_precond(tabd, seg, j, s));
-      ASM_HIP(launch_batch_spmv(tabd, seg[kBkSpmv], false, s));
-      ASM_HIP(launch_batch_multidot(tabd, seg[kBkRed], j + 1, s));
-      ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], j + 2, true, 0, s));
-      ASM_HIP(launch_batch_finalize_dots(tabd, seg[kBkOne], j, ld, s));
-      ASM_HIP(launch_batch_update(tabd, seg[kBkRed], j + 1, ld, s));
-      ASM_HIP(launch_batch_reduce(tabd, seg[kBkOne], 1, false, 0, s));
-      ASM_HIP(launch_batch_finalize_norm(tabd, seg[kBkOne], j, ld, kPubStride, s));
-      ASM_HIP(hipEventRecord(systems[0]->ws.step_done[j], s));
-      return mark_slot(sl);
-    };
-    (void)ran_slot;
-    if ((st = enqueue_step(0)) != ASM_OK) return st;
-    for (int j = 0; j < K; ++j) {
-      if (j + 1 < K && (st = enqueue_step(j + 1)) != ASM_OK) return st;
-      if (ran[j].empty()) continue;
-      ASM_HIP(hipEventSynchronize(systems[0]->ws.step_done[j]));
-      for (int i : ran[j]) {
-        if (!in_cycle[i]) continue;  // left the cycle at an earlier step; this step is discarded
-        auto Hh = [&](int r, int c) -> double & { return H[i][(size_t)c * ld + r]; };
-        const double *col = pin + region * i + 1 + (size_t)j * kPubStride;
-        for (int r = 0; r <= j + 1; ++r) Hh(r, j) = col[r];
-        const double w0 = col[j + 2];
-        const double hn = Hh(j + 1, j);
-        sc[i][j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-        for (int r = 0; r < j; ++r) {
-          const double a = Hh(r, j), c = Hh(r + 1, j);
-          Hh(r, j) = cs[i][r] * a + sn[i][r] * c;
-          Hh(r + 1, j) = -sn[i][r] * a + cs[i][r] * c;
-        }
-        const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
-        if (rho == 0.0) {
-          cs[i][j] = 1.0;
-          sn[i][j] = 0.0;
-        } else {
-          cs[i][j] = Hh(j, j) / rho;
-          sn[i][j] = Hh(j + 1, j) / rho;
-        }
-        Hh(j, j) = rho;
-        Hh(j + 1, j) = 0.0;
-        g[i][j + 1] = -sn[i][j] * g[i][j];
-        g[i][j] = cs[i][j] * g[i][j];
-        k[i] = j + 1;
-        infos[i].rel_res_est = std::fabs(g[i][j + 1]) / scl[i];
-        if (hn <= 1e-14 * w0 || (o->fixed_iters == 0 && std::fabs(g[i][j + 1]) <= tol[i]) || k[i] >= kmax[i])
-          in_cycle[i] = 0;
-      }
-    }
-    // cycle end: x += B^-1 (V y) for every system of the cycle
-    for (int i : active) {
-      infos[i].iters += k[i];
-      auto Hh = [&](int r, int c) -> double & { return H[i][(size_t)c * ld + r]; };
-      std::vector<double> y(k[i]);
-      for (int r = k[i] - 1; r >= 0; --r) {
-        double acc = g[i][r];
-        for (int c = r + 1; c < k[i]; ++c) acc -= Hh(r, c) * y[c];
-        y[r] = acc / Hh(r, r);
-      }
-      double *coefh = pin + region * i + 1 + (size_t)m * kPubStride;
-      coefh[0] = (double)k[i];
-      for (int r = 0; r < k[i]; ++r) coefh[1 + r] = y[r] * sc[i][r];
-    }
-    {
-      BatchSeg seg[kBkCount];
-      const int sl = slot_next;
-      if ((st = segs_for(active, seg)) != ASM_OK) return st;
-      ASM_HIP(launch_batch_lincomb(tabd, seg[kBkVec], s));
-      ASM_HIP(launch_batch_precond(tabd, seg, -1, s));
-      ASM_HIP(launch_batch_axpy(tabd, seg[kBkVec], s));
-      if ((st = mark_slot(sl)) != ASM_OK) return st;
-    }
-    if ((st = residuals(active)) != ASM_OK) return st;
-    std::vector<int> keep;
-    for (int i : active) {
-      infos[i].rel_res_true = beta[i] / scl[i];
-      if (o->fixed_iters > 0) {
-        if (infos[i].iters >= o->fixed_iters) { status[i] = ASM_OK; continue; }
-      } else if (beta[i] <= tol[i]) {
-        status[i] = ASM_OK;
-        continue;
-      }
-      if (infos[i].iters >= limit || beta[i] == 0.0) {
-        status[i] = beta[i] == 0.0 ? ASM_OK : ASM_NOT_CONVERGED;
-        continue;
-      }
-      keep.push_back(i);
-    }
-    active.swap(keep);
-  }
-  ASM_HIP(hipStreamSynchronize(s));
-  for (int i = 0; i < count; ++i)
-    if (status[i] != ASM_OK) return ASM_NOT_CONVERGED;
-  return ASM_OK;
 }
 
 asm_status asm_profile_enable(asm_system S, int32_t phase_mask) {

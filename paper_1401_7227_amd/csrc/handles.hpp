@@ -1,0 +1,207 @@
+// Internal definitions shared by the C ABI sources: device memory owners,
+// the per-system Krylov workspace and the system / preconditioner handles.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/asm.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+namespace asmx {
+
+// Thread-local message of the last failing call (asm_last_error).
+extern thread_local std::string g_err;
+
+inline asm_status fail(asm_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define ASM_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return ::asmx::fail(e_ == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP,             \
+                          std::string(#call) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+// Owner of device allocations; frees everything on destruction.
+struct DevMem {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  ~DevMem() { release(); }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  template <typename T>
+  hipError_t alloc(T **out, size_t n) {
+    *out = nullptr;
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    *out = static_cast<T *>(p);
+    return hipSuccess;
+  }
+  template <typename T>
+  hipError_t upload(T **out, const std::vector<T> &v, hipStream_t s) {
+    hipError_t e = alloc(out, v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  }
+};
+
+struct GatherDev {
+  int32_t n = 0;
+  int32_t lanes = 1;  // threads per destination (about the mean fan-in)
+  int32_t *ptr = nullptr, *idx = nullptr;
+};
+
+inline hipError_t upload_gather(DevMem &m, GatherDev &g, const GatherList &h, hipStream_t s) {
+  g.n = h.size();
+  const double mean = g.n > 0 ? (double)h.idx.size() / g.n : 0.0;
+  g.lanes = 1;
+  while (g.lanes < 16 && g.lanes < mean) g.lanes *= 2;
+  hipError_t e = m.upload(&g.ptr, h.ptr, s);
+  if (e == hipSuccess) e = m.upload(&g.idx, h.idx, s);
+  return e;
+}
+
+// HIP-event timing of solve phases (enabled per system).
+struct Profiler {
+  bool on = false;
+  uint32_t mask = 0;  // phases timed (bit k = phase k)
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  struct Span {
+    int phase;
+    size_t a, b;
+  };
+  std::vector<Span> pend;
+  int64_t launches[ASM_NPHASE] = {};
+  double ms[ASM_NPHASE] = {};
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  // Records an event if the phase is timed; returns its pool index, or
+  // SIZE_MAX when not timed.
+  size_t mark(int phase, hipStream_t s) {
+    if (!on || !(mask >> phase & 1u)) return SIZE_MAX;
+    return record(s);
+  }
+  size_t record(hipStream_t s) {
+    if (next == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return SIZE_MAX;
+      pool.push_back(e);
+    }
+    const size_t i = next++;
+    if (hipEventRecord(pool[i], s) != hipSuccess) return SIZE_MAX;
+    return i;
+  }
+  void span(int phase, size_t a, hipStream_t s) {
+    if (!on || a == SIZE_MAX) return;
+    const size_t b = record(s);
+    if (b != SIZE_MAX) pend.push_back({phase, a, b});
+  }
+  // Only after the stream has been synchronised.
+  void flush() {
+    for (const Span &p : pend) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, pool[p.a], pool[p.b]) == hipSuccess) {
+        ms[p.phase] += t;
+        launches[p.phase]++;
+      }
+    }
+    pend.clear();
+    next = 0;
+  }
+  void reset() {
+    std::fill(launches, launches + ASM_NPHASE, 0);
+    std::fill(ms, ms + ASM_NPHASE, 0.0);
+  }
+};
+
+// Krylov workspace of a system, sized for one restart length.
+struct Workspace {
+  DevMem mem;
+  int m = 0;
+  double *U = nullptr;        // (m+1) columns of n (stride ldu) basis (unnormalised)
+  int64_t ldu = 0;
+  double *w = nullptr, *z = nullptr, *t = nullptr;
+  double *partial = nullptr;  // kReduceBlocks x (kMaxRestart+2)
+  double *dvec = nullptr;     // reduced dot products
+  double *H = nullptr;        // (m+1) x m Hessenberg, column-major, ld m+1
+  double *scale = nullptr;    // 1/||U_i||
+  double *coef = nullptr;
+  double *misc = nullptr;     // [0] wnorm, [1] beta, [2] scratch norm
+  int *flag = nullptr;
+  double *pinned = nullptr;   // host staging: scalars, then one published column per step
+  double *pinned_dev = nullptr;  // the same memory as seen by kernels
+  hipEvent_t step_done[kMaxRestart] = {};
+  ~Workspace() {
+    if (pinned) (void)hipHostFree(pinned);
+    for (hipEvent_t e : step_done)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Pinned layout: [0, 16) scalars; column j of a cycle at kPubBase + j*kPubStride
+// holds H(0..j+1, j) and then ||w|| (the breakdown reference).
+constexpr int kPubBase = 16, kPubStride = kMaxRestart + 4;
+
+// Krylov workspace of a system (allocated on first use), the batched-solve
+// helpers and the preconditioner application shared by the solvers.
+asm_status ensure_workspace(asm_system S, int m, hipStream_t s);
+asm_status apply_precond(asm_precond pc, const double *r, const double *scale, double *z, hipStream_t s,
+                         Profiler *prof = nullptr);
+
+}  // namespace asmx
+
+struct asm_system_s {
+  int device = 0;
+  asmx::HostPattern pat;
+  asmx::DevMem mem;
+  int32_t *rp = nullptr, *ci = nullptr;
+  double *vals = nullptr;  // CSR values (sources of the assembly)
+  asmx::SellDev sell;
+  asmx::Workspace ws;
+  asmx::Profiler prof;
+};
+
+struct asm_precond_s {
+  asm_system sys = nullptr;
+  asm_precond_opts opts{};
+  // Pattern-only state, shared by the preconditioners cloned from one
+  // setup: host-side parts kept for export and messages, and the device
+  // arrays that never change after setup (maps, schedules, gather lists).
+  std::shared_ptr<asmx::PlanHost> plan;
+  std::shared_ptr<asmx::DevMem> smem;
+  asmx::DevMem mem;       // this handle's own arrays: records, factors, work vectors
+  size_t rec_bytes = 0;
+  asmx::DevPlan dp{};     // factorisation
+  asmx::ApplyPlan ap{};   // sweeps
+  asmx::GatherDev l1, l2, asrc, c1, c2, c3;
+  double *L1 = nullptr, *L2 = nullptr;  // lumped block values
+  double *aval = nullptr;               // assembled A_i (CSR)
+  double *PA = nullptr, *PNF = nullptr; // lumped residual sums
+  void *recbuf = nullptr;               // sweep records
+  int32_t *rl_src = nullptr, *rl_base = nullptr, *rl_stride = nullptr;
+  uint8_t *rl_to32 = nullptr;
+  int64_t rl_n = 0;
+  int32_t *cptr = nullptr, *cidx = nullptr;
+  unsigned long long *bad = nullptr;
+  asm_precond_stats stats{};
+};
+

@@ -1,0 +1,197 @@
+"""Preconditioner clones and the request server, through the C-ABI library.
+
+A clone must give exactly (bit for bit) the factors and applications of a
+fresh setup on the same system; every solve the server runs must give exactly
+the result of asm_solve on a freshly set-up system and preconditioner with
+the same values, whatever else is in flight.  The single-solve path itself is
+held to the CPU oracle by the parity tests.
+"""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_7227_amd as lib
+    lib.load()
+    assert lib.LIB_PATH in open("/proc/self/maps").read()
+    return lib
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+CLONE_CASES = [
+    ((13, 11, 7), dict(kind=2, combine=1, sx=3, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=0)),
+    ((13, 11, 7), dict(kind=2, combine=1, sx=3, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=1)),
+    ((16, 12, 8), dict(kind=1, combine=0, sx=2, sy=3, overlap=2, precision=0)),
+    ((9, 9, 6), dict(kind=0, combine=1, sx=1, sy=1, overlap=0, precision=0)),
+]
+
+
+@pytest.mark.parametrize("grid,opts", CLONE_CASES)
+def test_clone_equals_fresh_setup(P, grid, opts):
+    import torch
+    s1 = gen.generate(*grid, seed=21)
+    s2 = gen.redraw_values(s1, seed=22)
+    G1, G2 = P.System.from_generated(s1), P.System.from_generated(s2)
+    o = dict(opts)
+    B1 = P.Precond(G1, **o)
+    fresh = P.Precond(G2, **o)
+    clone = B1.clone(G2)
+    assert clone.stats() == fresh.stats()
+    r = torch.from_numpy(np.random.default_rng(3).standard_normal(s1.n)).cuda()
+    z_fresh = to_np(fresh.apply(r))
+    z_clone = to_np(clone.apply(r))
+    assert np.array_equal(z_fresh, z_clone)
+    if opts["kind"] != 0:
+        for sub in range(fresh.stats()["nsub"]):
+            a, b = fresh.export_sub(sub), clone.export_sub(sub)
+            assert np.array_equal(a.f, b.f) and np.array_equal(a.a, b.a) and np.array_equal(a.label, b.label)
+    # the clone outlives its source; refactor keeps it equal to a fresh setup
+    B1.close()
+    G1.close()
+    assert np.array_equal(to_np(clone.apply(r)), z_fresh)
+    s3 = gen.redraw_values(s1, seed=23)
+    G2.update_values(s3.vals)
+    clone.refactor()
+    G3 = P.System.from_generated(s3)
+    fresh3 = P.Precond(G3, **o)
+    assert np.array_equal(to_np(clone.apply(r)), to_np(fresh3.apply(r)))
+
+
+def test_clone_rejects_other_pattern(P):
+    s1 = gen.generate(8, 8, 4, seed=1)
+    s2 = gen.generate(8, 4, 8, seed=1)  # same cell count, other grid
+    G1, G2 = P.System.from_generated(s1), P.System.from_generated(s2)
+    B1 = P.Precond(G1, kind=1, combine=1, sx=2, sy=2, overlap=1)
+    with pytest.raises(P.AsmError) as e:
+        B1.clone(G2)
+    assert e.value.status == P.ERR_INVALID
+
+
+def _opts(nx, ny, nz, kind=2, precision=1):
+    cells = nx * ny * nz
+    nsub = int(min(max(round(cells / 512), 2), 16))
+    sx = max(1, min(nx, int(round((nsub * nx / ny) ** 0.5))))
+    sy = max(1, min(ny, nsub // sx))
+    d = dict(kind=kind, combine=1, sx=sx, sy=sy, overlap=1, near=(2, 2, 2), far=(4, 4, 4),
+             precision=precision)
+    return d
+
+
+def _requests(P, specs, device="cuda"):
+    """specs: (grid, seed, nsolves, kind, precision).  Device-side inputs."""
+    import torch
+    from gen import device as gd
+    reqs = []
+    for tag, (grid, seed, ns, kind, prec) in enumerate(specs):
+        rp, ci = gd.pattern(*grid, device)
+        perm = gd.draw_perm(*grid, seed, device)
+        vals, bs, xs = [], [], []
+        for k in range(ns):
+            v, b, _ = gd.draw_values(*grid, perm, seed * 10 + k)
+            vals.append(v.reshape(-1).contiguous())
+            bs.append(b)
+            xs.append(torch.zeros_like(b))
+        reqs.append(dict(tag=tag, grid=grid, rp=rp, ci=ci, opts=_opts(*grid, kind, prec), vals=vals, bs=bs, xs=xs))
+    return reqs
+
+
+def _reference(P, req, **solve_kw):
+    """Each solve of a request alone: fresh system, fresh setup, asm_solve."""
+    out = []
+    for v, b in zip(req["vals"], req["bs"]):
+        G = P.System(*req["grid"], req["rp"], req["ci"], v)
+        B = P.Precond(G, **req["opts"])
+        x, info = P.solve(G, B, b, **solve_kw)
+        out.append((to_np(x), info))
+    return out
+
+
+SPECS = [
+    ((12, 10, 6), 1, 2, 2, 1),
+    ((16, 16, 8), 2, 3, 2, 1),
+    ((12, 10, 6), 3, 1, 2, 1),   # same grid and options as the first: plan reuse
+    ((20, 14, 10), 4, 2, 1, 0),
+    ((8, 8, 8), 5, 1, 2, 0),
+    ((12, 10, 6), 6, 3, 2, 1),
+    ((24, 20, 12), 7, 1, 2, 1),
+]
+
+
+@pytest.mark.parametrize("max_active,budget", [(64, 0), (2, 0), (64, 1)])
+def test_server_results_equal_single_solves(P, max_active, budget):
+    """Solutions, iteration counts and residuals of every solve served equal
+    those of the solve run alone; admission respects max_active and the
+    budget (budget 1 byte: one request at a time)."""
+    reqs = _requests(P, SPECS)
+    srv = P.Server(restart=30, rtol=1e-6, max_iters=3000, budget_bytes=budget, max_active=max_active)
+    done = {}
+    # requests arrive in two waves
+    for r in reqs[:4]:
+        srv.submit(r["tag"], r["grid"], r["rp"], r["ci"], P.precond_opts(**r["opts"]), r["vals"], r["bs"], r["xs"])
+    polls = 0
+    max_running = 0
+    while len(done) < len(reqs):
+        if polls == 3:
+            for r in reqs[4:]:
+                srv.submit(r["tag"], r["grid"], r["rp"], r["ci"], P.precond_opts(**r["opts"]), r["vals"], r["bs"],
+                           r["xs"])
+        for c in srv.poll():
+            done[c["tag"]] = c
+        st = srv.state()
+        max_running = max(max_running, st["running"])
+        assert st["iterating"] <= max_active
+        polls += 1
+        assert polls < 5000
+    if budget == 1:
+        assert max_running <= 1
+    st = srv.state()
+    assert st["queued"] == 0 and st["running"] == 0 and st["iterating"] == 0
+    assert st["plan_hits"] >= 2 if budget == 0 else True
+    for r in reqs:
+        c = done[r["tag"]]
+        ref = _reference(P, r, restart=30, rtol=1e-6, max_iters=3000)
+        assert c["status"] == P.OK and c["solves"] == len(ref)
+        assert c["iters"] == sum(i.iters for _, i in ref)
+        assert c["rel_res_true"] == ref[-1][1].rel_res_true
+        for (x_ref, _), x in zip(ref, r["xs"]):
+            assert np.array_equal(x_ref, to_np(x))
+    srv.close()
+
+
+def test_server_error_statuses(P):
+    """A request whose input is bad completes with the error; the others are
+    served normally."""
+    import torch
+    reqs = _requests(P, [((10, 8, 6), 11, 2, 2, 1), ((10, 8, 6), 12, 2, 2, 1), ((10, 8, 6), 13, 3, 2, 1)])
+    reqs[0]["bs"][0][7] = float("nan")           # non-finite b: first solve rejected
+    v = reqs[2]["vals"][1].reshape(-1, 9)        # second values: zero row 0 -> singular pivot
+    rp = reqs[2]["rp"].cpu().numpy()
+    v[int(rp[0]):int(rp[1])] = 0.0
+    srv = P.Server(max_active=8)
+    for r in reqs:
+        srv.submit(r["tag"], r["grid"], r["rp"], r["ci"], P.precond_opts(**r["opts"]), r["vals"], r["bs"], r["xs"])
+    done = {}
+    while len(done) < 3:
+        for c in srv.poll():
+            done[c["tag"]] = c
+    assert done[0]["status"] == P.ERR_NONFINITE and done[0]["solves"] == 0
+    assert done[1]["status"] == P.OK and done[1]["solves"] == 2
+    assert done[2]["status"] == P.ERR_SINGULAR_PIVOT and done[2]["solves"] == 1
+    ref = _reference(P, reqs[1])
+    for (x_ref, _), x in zip(ref, reqs[1]["xs"]):
+        assert np.array_equal(x_ref, to_np(x))
+    with pytest.raises(P.AsmError):
+        srv.submit(9, (10, 8, 6), reqs[1]["rp"], reqs[1]["ci"], P.precond_opts(kind=0), reqs[1]["vals"][:1],
+                   reqs[1]["bs"][:1], [torch.zeros_like(reqs[1]["bs"][0])])
+    srv.close()
