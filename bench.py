@@ -192,6 +192,202 @@ def bench_batch(P, gen, torch, np, args):
     }
 
 
+def serve_trace(np, count=1000, rate=200.0, seed=5):
+    """Requests of the serving workload: Poisson arrivals at `rate` per
+    second; cells log-uniform in [1e4, 1e6], nz = round((cells/4)^(1/3)),
+    nx = ny = 2 nz; 1-3 solves each (the Newton iterations of one time step:
+    new values on the same pattern); seed 5 for the trace, request r draws
+    its system from seed 50000 + r."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    cells = np.exp(rng.uniform(np.log(1e4), np.log(1e6), count))
+    nsolves = rng.integers(1, 4, count)
+    out = []
+    for r in range(count):
+        nz = int(round((cells[r] / 4.0) ** (1.0 / 3.0)))
+        out.append({"t": float(t[r]), "grid": (2 * nz, 2 * nz, nz), "nsolves": int(nsolves[r]),
+                    "seed": 50000 + r})
+    return out
+
+
+def serve_split(nx, ny, nz):
+    """Subdomains: clamp(round(cells/4096), 16, 64), split in proportion to nx:ny."""
+    cells = nx * ny * nz
+    nsub = int(min(64, max(16, round(cells / 4096))))
+    sx = max(1, min(nx, int(round((nsub * nx / ny) ** 0.5))))
+    sy = max(1, min(ny, int(round(nsub / sx))))
+    return sx, sy
+
+
+class ServeInputs:
+    """Draws a request's systems on the device when it arrives (the
+    Jacobian assembly of the simulator that sends it).  Patterns are shared
+    per grid."""
+
+    def __init__(self, torch):
+        from gen import device as gd
+        self.gd, self.torch, self.patterns = gd, torch, {}
+
+    def pattern(self, grid):
+        if grid not in self.patterns:
+            self.patterns[grid] = self.gd.pattern(*grid, "cuda")
+        return self.patterns[grid]
+
+    def draw(self, req):
+        grid = req["grid"]
+        rp, ci = self.pattern(grid)
+        perm = self.gd.draw_perm(*grid, req["seed"], "cuda")
+        vals, bs, xs = [], [], []
+        for k in range(req["nsolves"]):
+            v, b, _ = self.gd.draw_values(*grid, perm, req["seed"] * 10 + k)
+            vals.append(v.reshape(-1))
+            bs.append(b)
+            xs.append(self.torch.zeros_like(b))
+        return rp, ci, vals, bs, xs
+
+
+def serve_popts(P, grid, precision):
+    sx, sy = serve_split(*grid)
+    return dict(kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, sx=sx, sy=sy, overlap=1, near=NEAR, far=FAR,
+                precision=precision)
+
+
+def percentiles(np, lat):
+    a = np.asarray(lat) * 1e3
+    return {"p50_ms": round(float(np.percentile(a, 50)), 1), "p99_ms": round(float(np.percentile(a, 99)), 1),
+            "mean_ms": round(float(a.mean()), 1), "max_ms": round(float(a.max()), 1)}
+
+
+def run_server(P, torch, np, trace, precision, budget, max_active, label):
+    """Replays the trace in real time against the library's request server.
+    Arrived requests wait in a front queue and are drawn and submitted while
+    the server's own queue is short (inputs of queued requests are not held
+    on the device for long); latency counts from the arrival time."""
+    from collections import deque
+    inputs = ServeInputs(torch)
+    srv = P.Server(restart=RESTART, rtol=1e-6, max_iters=5000, budget_bytes=budget, max_active=max_active)
+    n = len(trace)
+    front, done, arrived = deque(), {}, 0
+    running_sum, polls, status = 0, 0, {}
+    t0 = time.perf_counter()
+    last = t0
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while arrived < n and trace[arrived]["t"] <= now:
+            front.append(arrived)
+            arrived += 1
+        st = srv.state()
+        while front and st["queued"] < 4:
+            r = front.popleft()
+            rp, ci, vals, bs, xs = inputs.draw(trace[r])
+            srv.submit(r, trace[r]["grid"], rp, ci, P.precond_opts(**serve_popts(P, trace[r]["grid"], precision)),
+                       vals, bs, xs)
+            st["queued"] += 1
+        if st["running"] == 0 and st["queued"] == 0 and not front and arrived < n:
+            time.sleep(max(0.0, trace[arrived]["t"] - (time.perf_counter() - t0)))
+            continue
+        for c in srv.poll():
+            done[c["tag"]] = (time.perf_counter() - t0, c)
+            status[c["status"]] = status.get(c["status"], 0) + 1
+        running_sum += srv.state()["running"]
+        polls += 1
+        if time.perf_counter() - last > 15.0:
+            last = time.perf_counter()
+            print(f"[serve {label}] t={last - t0:.1f}s done {len(done)}/{n} arrived {arrived} "
+                  f"state {srv.state()}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+    wall = time.perf_counter() - t0
+    st = srv.state()
+    srv.close()
+    lat = [done[r][0] - trace[r]["t"] for r in range(n)]
+    cells = sum(trace[r]["grid"][0] * trace[r]["grid"][1] * trace[r]["grid"][2] * trace[r]["nsolves"]
+                for r in range(n))
+    out = percentiles(np, lat)
+    out.update({"requests": n, "wall_s": round(wall, 2), "requests_per_s": round(n / wall, 2),
+                "solves_per_s": round(sum(t["nsolves"] for t in trace) / wall, 2),
+                "cell_solves_per_s": round(cells / wall, 0),
+                "mean_running": round(running_sum / max(polls, 1), 1), "polls": polls,
+                "plan_builds": st["plan_builds"], "plan_hits": st["plan_hits"],
+                "statuses": {str(k): v for k, v in status.items()},
+                "iters_total": sum(done[r][1]["iters"] for r in range(n))})
+    return out
+
+
+def run_fifo(P, torch, np, trace, label):
+    """The same trace served one request at a time, in arrival order, with
+    the plain calls and an FP64 preconditioner set up for each request."""
+    inputs = ServeInputs(torch)
+    n = len(trace)
+    lat, status, iters = [], {}, 0
+    t0 = time.perf_counter()
+    last = t0
+    for r in range(n):
+        now = time.perf_counter() - t0
+        if trace[r]["t"] > now:
+            time.sleep(trace[r]["t"] - now)
+        rp, ci, vals, bs, xs = inputs.draw(trace[r])
+        grid = trace[r]["grid"]
+        st = P.OK
+        try:
+            G = P.System(*grid, rp, ci, vals[0])
+            B = P.Precond(G, **serve_popts(P, grid, P.FP64))
+            for k in range(trace[r]["nsolves"]):
+                if k > 0:
+                    G.update_values(vals[k])
+                    B.refactor()
+                _, info = P.solve(G, B, bs[k], restart=RESTART, rtol=1e-6, max_iters=5000, out=xs[k])
+                iters += info.iters
+                st = min(st, info.status) if info.status < 0 else max(st, info.status)
+            B.close()
+            G.close()
+        except P.AsmError as e:
+            st = e.status
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - trace[r]["t"])
+        status[st] = status.get(st, 0) + 1
+        if time.perf_counter() - last > 15.0:
+            last = time.perf_counter()
+            print(f"[fifo {label}] t={last - t0:.1f}s done {r + 1}/{n}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    out = percentiles(np, lat)
+    out.update({"requests": n, "wall_s": round(wall, 2), "requests_per_s": round(n / wall, 2),
+                "statuses": {str(k): v for k, v in status.items()}, "iters_total": iters})
+    return out
+
+
+def bench_serve(P, gen, torch, np, args):
+    trace = serve_trace(np, count=args.serve_requests)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    prefix = trace[:args.serve_compare]
+    # warm-up: one small request through both paths (library load, kernels)
+    warm = [{"t": 0.0, "grid": (28, 28, 14), "nsolves": 1, "seed": 1}]
+    run_server(P, torch, np, warm, P.FP32, budget, args.serve_max_active, "warm-up")
+    run_fifo(P, torch, np, warm, "warm-up")
+    full = run_server(P, torch, np, trace, P.FP32, budget, args.serve_max_active, "full")
+    torch.cuda.empty_cache()
+    srv_prefix = run_server(P, torch, np, prefix, P.FP32, budget, args.serve_max_active, "prefix")
+    torch.cuda.empty_cache()
+    fifo_prefix = run_fifo(P, torch, np, prefix, "prefix")
+    cells = np.array([t["grid"][0] * t["grid"][1] * t["grid"][2] for t in trace])
+    offered = float(np.sum(cells * np.array([t["nsolves"] for t in trace]))) / trace[-1]["t"]
+    return {
+        "metric": "served latency p50/p99 ms (Poisson arrivals 200/s, 1e4-1e6 cells, 1-3 solves per request)",
+        "value": full["p99_ms"], "unit": "ms (p99)", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f64 (FP32 factors)", "data": "synthetic (seeded generator drawn on the device at arrival)",
+        "config": {"workload": f"{len(trace)} requests, Poisson arrivals at 200/s (trace seed 5), cells "
+                               "log-uniform in [1e4, 1e6], grid 2nz x 2nz x nz, 1-3 solves each with new values "
+                               "on the same pattern; two-level RAS, overlap 1, near 4^3, far 16^3, 16-64 "
+                               "subdomains, FP32 factors, GMRES(30) to rtol 1e-6",
+                   "hbm_budget_gib": args.serve_budget_gib, "max_active": args.serve_max_active},
+        "p50_ms": full["p50_ms"], "p99_ms": full["p99_ms"],
+        "offered_cell_solves_per_s": round(offered, 0),
+        "server_full_trace": full,
+        "prefix_comparison": {"requests": len(prefix), "server_fp32": srv_prefix, "fifo_fp64": fifo_prefix,
+                              "p50_speedup": round(fifo_prefix["p50_ms"] / srv_prefix["p50_ms"], 2),
+                              "p99_speedup": round(fifo_prefix["p99_ms"] / srv_prefix["p99_ms"], 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,9 +396,15 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--workload", choices=["solve1m", "batch256"], default="solve1m",
+    ap.add_argument("--workload", choices=["solve1m", "batch256", "serve"], default="solve1m",
                     help="solve1m: the 1M-cell solve (default); batch256: 256 independent systems of "
-                         "2k-295k cells solved as one batch, against solving them one after another")
+                         "2k-295k cells solved as one batch, against solving them one after another; "
+                         "serve: a Poisson request trace against the request server, and a prefix of it "
+                         "against one-at-a-time FP64 solves")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-compare", type=int, default=100, help="trace prefix for the FIFO comparison")
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0)
+    ap.add_argument("--serve-max-active", type=int, default=256)
     ap.add_argument("--counter-workload", choices=["apply", "copy"], default=None,
                     help="run only a short workload for hardware-counter collection: five preconditioner "
                          "applications of the benchmark configuration, or a plain 1 GiB device copy")
@@ -222,6 +424,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch256":
         print(json.dumps(bench_batch(P, gen, torch, np, args)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(P, gen, torch, np, args)))
         return
     if args.counter_workload == "copy":
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")

@@ -2,8 +2,10 @@
 // every kernel launch serves all of them.  The engine below runs restart
 // cycles over a changing set of solves (solves may join between cycles);
 // asm_solve_batch and the request server are built on it.
+#include <chrono>
 #include <cmath>
 #include <deque>
+#include <future>
 
 #include "handles.hpp"
 
@@ -435,11 +437,18 @@ struct Plan {  // a cached preconditioner whose pattern-only state is cloned
   int32_t nb = 0;
   int64_t nnzb = 0;
   asm_precond_opts popts{};
+  // host planning, run on a worker thread while the device keeps iterating
+  bool building = false;
+  std::shared_ptr<PlanHost> host;
+  std::future<std::pair<asm_status, std::string>> job;
+  asm_status failed = ASM_OK;  // planning error, reported to the requests of this plan
+  std::string err;
   asm_system S = nullptr;
   asm_precond pc = nullptr;
   int64_t bytes = 0;      // device bytes held by the cached system and preconditioner
   int64_t req_bytes = 0;  // device bytes of one request on this plan (0 until known)
-  int users = 0;
+  int users = 0;   // running requests on this plan
+  int served = 0;  // requests that used it so far
   uint64_t last_use = 0;
 };
 
@@ -504,7 +513,7 @@ void evict_for(asm_server srv, int64_t need, int keep) {
   while (srv->bytes_in_use + need > srv->o.hbm_budget_bytes) {
     int best = -1;
     for (int i = 0; i < (int)srv->plans.size(); ++i)
-      if (i != keep && srv->plans[i].users == 0 &&
+      if (i != keep && srv->plans[i].users == 0 && srv->plans[i].pc &&
           (best < 0 || srv->plans[i].last_use < srv->plans[best].last_use))
         best = i;
     if (best < 0) return;
@@ -554,6 +563,88 @@ void complete(asm_server srv, Request *r) {
   delete r;
 }
 
+constexpr int kPlanLookahead = 8;  // queued requests whose plans are built ahead
+constexpr int kMaxBuilds = 3;      // host plannings in flight at once
+
+// Starts the host planning of the first queued requests whose grid, pattern
+// size and options have no plan yet (on worker threads; the pattern is
+// copied to the host and checked here).
+void start_builds(asm_server srv) {
+  int k = 0, inflight = 0;
+  for (const Plan &p : srv->plans) inflight += p.building;
+  for (Request *r : srv->queue) {
+    if (k++ >= kPlanLookahead || inflight >= kMaxBuilds) break;
+    const asm_request &d = r->d;
+    if (find_plan(srv, d) >= 0) continue;
+    ++inflight;
+    Plan np{};
+    np.grid = d.grid;
+    np.nb = d.nb;
+    np.nnzb = d.nnzb;
+    np.popts = d.precond;
+    np.last_use = ++srv->clock;
+    auto pat = std::make_shared<HostPattern>();
+    pat->nx = d.grid.nx; pat->ny = d.grid.ny; pat->nz = d.grid.nz; pat->N = d.nb; pat->nnzb = d.nnzb;
+    if (d.grid.nx < 1 || d.grid.ny < 1 || d.grid.nz < 1 || (int64_t)d.grid.nx * d.grid.ny * d.grid.nz != d.nb ||
+        d.nnzb < d.nb || d.nnzb >= ((int64_t)1 << 31) / 9) {
+      np.failed = ASM_ERR_INVALID;
+      np.err = "grid or nnzb out of range";
+    } else {
+      pat->rp.resize(d.nb + 1);
+      pat->ci.resize(d.nnzb);
+      hipError_t e = hipMemcpy(pat->rp.data(), d.row_ptr_dev, (d.nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(pat->ci.data(), d.col_idx_dev, d.nnzb * sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        np.failed = ASM_ERR_HIP;
+        np.err = std::string("pattern copy: ") + hipGetErrorString(e);
+      } else if ((np.failed = validate_pattern(*pat)) != ASM_OK ||
+                 (np.failed = check_precond_opts(*pat, &d.precond)) != ASM_OK) {
+        np.err = g_err;
+      }
+    }
+    if (np.failed == ASM_OK) {
+      np.building = true;
+      np.host = std::make_shared<PlanHost>();
+      auto host = np.host;
+      const asm_precond_opts o = d.precond;
+      np.job = std::async(std::launch::async, [pat, host, o]() {
+        std::string err;
+        const asm_status st = build_plan(*pat, o, *host, err);
+        return std::make_pair(st, err);
+      });
+    }
+    srv->plans.push_back(std::move(np));
+  }
+}
+
+// Device part of a plan whose host planning finished: the cached system
+// (values of the request that first needed it) and the preconditioner.
+asm_status finish_plan(asm_server srv, int p, const asm_request &d) {
+  Plan &pl = srv->plans[p];
+  auto res = pl.job.get();
+  pl.building = false;
+  if (res.first != ASM_OK) {
+    pl.failed = res.first;
+    pl.err = res.second;
+    pl.host.reset();
+    return ASM_OK;
+  }
+  asm_status st = asm_create_system(&d.grid, d.nb, d.nnzb, d.row_ptr_dev, d.col_idx_dev, d.vals_dev[0], srv->s, &pl.S);
+  if (st == ASM_OK) st = setup_from_plan(pl.S, &d.precond, pl.host, srv->s, &pl.pc);
+  pl.host.reset();
+  if (st != ASM_OK) {
+    if (pl.S) asm_destroy_system(pl.S);
+    pl.S = nullptr;
+    pl.failed = st;
+    pl.err = g_err;
+    return ASM_OK;
+  }
+  pl.bytes = plan_bytes(pl.S, pl.pc);
+  srv->bytes_in_use += pl.bytes;
+  srv->plan_builds++;
+  return ASM_OK;
+}
+
 // Creates the request's system and its preconditioner: a clone of the cached
 // plan for its grid, options and pattern, the plan being built first if
 // there is none.
@@ -565,8 +656,8 @@ asm_status materialise(asm_server srv, Request *r) {
   if (p >= 0) {
     st = asm_precond_clone(srv->plans[p].pc, r->S, srv->s, &r->pc);
     if (st == ASM_OK) {
-      r->hit = 1;
-      srv->plan_hits++;
+      r->hit = srv->plans[p].served > 0;  // the plan's first request built it
+      srv->plan_hits += r->hit;
     } else if (st == ASM_ERR_INVALID) {
       p = -1;  // same grid and options but another pattern: no plan to share
     } else {
@@ -588,8 +679,8 @@ asm_status materialise(asm_server srv, Request *r) {
     }
     np.bytes = plan_bytes(np.S, np.pc);
     np.last_use = ++srv->clock;
-    srv->plans.push_back(np);
-    srv->bytes_in_use += np.bytes;
+    srv->plans.push_back(std::move(np));
+    srv->bytes_in_use += srv->plans.back().bytes;
     srv->plan_builds++;
     p = (int)srv->plans.size() - 1;
     st = asm_precond_clone(srv->plans[p].pc, r->S, srv->s, &r->pc);
@@ -597,6 +688,7 @@ asm_status materialise(asm_server srv, Request *r) {
   }
   r->plan = p;
   srv->plans[p].users++;
+  srv->plans[p].served++;
   srv->plans[p].last_use = ++srv->clock;
   return ASM_OK;
 }
@@ -716,8 +808,28 @@ asm_status asm_server_poll(asm_server srv, int32_t max, asm_completion *out, int
   std::vector<Request *> join;
   join.swap(srv->ready);
   int slots = srv->eng.free_slots() - (int)join.size();
+  start_builds(srv);
   while (!srv->queue.empty() && slots > 0) {
     Request *r = srv->queue.front();
+    const int p = find_plan(srv, r->d);
+    if (p >= 0 && srv->plans[p].building) {
+      // the head waits for its plan (no overtaking); with nothing else to
+      // run, wait here rather than return empty-handed
+      const bool idle = srv->eng.iterating() == 0 && join.empty();
+      if (!idle && srv->plans[p].job.wait_for(std::chrono::seconds(0)) != std::future_status::ready) break;
+      if ((st = finish_plan(srv, p, r->d)) != ASM_OK) return st;
+    }
+    if (p >= 0 && srv->plans[p].failed != ASM_OK) {
+      srv->queue.pop_front();
+      srv->running.push_back(r);
+      r->status = srv->plans[p].failed;
+      g_err = srv->plans[p].err;
+      complete(srv, r);
+      srv->plans.erase(srv->plans.begin() + p);
+      for (Request *q : srv->running)
+        if (q->plan > p) --q->plan;
+      continue;
+    }
     const int64_t need = admission_estimate(srv, r->d);
     if (srv->o.hbm_budget_bytes > 0 && srv->bytes_in_use + need > srv->o.hbm_budget_bytes) {
       evict_for(srv, need, find_plan(srv, r->d));

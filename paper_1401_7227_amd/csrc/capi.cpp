@@ -150,99 +150,42 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   return ASM_OK;
 }
 
-}  // namespace asmx
-
-using namespace asmx;
-
-extern "C" {
-
-const char *asm_last_error(void) { return g_err.c_str(); }
-
-asm_status asm_create_system(const asm_grid *grid, int32_t nb, int64_t nnzb, const int32_t *row_ptr_dev,
-                             const int32_t *col_idx_dev, const double *vals_dev, hipStream_t stream,
-                             asm_system *out) {
-  g_err.clear();
-  if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  if (!grid || !row_ptr_dev || !col_idx_dev || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || (int64_t)grid->nx * grid->ny * grid->nz != nb)
-    return fail(ASM_ERR_INVALID, "grid nx*ny*nz does not equal nb");
-  if (nnzb < nb || nnzb >= ((int64_t)1 << 31) / 9) return fail(ASM_ERR_INVALID, "nnzb out of range");
-  auto S = new (std::nothrow) asm_system_s();
-  if (!S) return fail(ASM_ERR_OOM, "host allocation failed");
-  auto cleanup = [&](asm_status st) {
-    delete S;
-    return st;
-  };
-  (void)hipGetDevice(&S->device);
-  HostPattern &P = S->pat;
-  P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.N = nb; P.nnzb = nnzb;
-  P.rp.resize(nb + 1);
-  P.ci.resize(nnzb);
-  hipError_t e = hipMemcpyAsync(P.rp.data(), row_ptr_dev, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(P.ci.data(), col_idx_dev, nnzb * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return cleanup(fail(ASM_ERR_HIP, std::string("pattern copy: ") + hipGetErrorString(e)));
-  if (P.rp[0] != 0 || P.rp[nb] != nnzb) return cleanup(fail(ASM_ERR_INVALID, "row_ptr must start at 0 and end at nnzb"));
+asm_status validate_pattern(const HostPattern &P) {
+  const int nb = P.N;
+  const int64_t nnzb = P.nnzb;
+  if (P.rp[0] != 0 || P.rp[nb] != nnzb) return fail(ASM_ERR_INVALID, "row_ptr must start at 0 and end at nnzb");
   for (int r = 0; r < nb; ++r) {
-    if (P.rp[r + 1] < P.rp[r]) return cleanup(fail(ASM_ERR_INVALID, "row_ptr not monotone at row " + std::to_string(r)));
+    if (P.rp[r + 1] < P.rp[r]) return fail(ASM_ERR_INVALID, "row_ptr not monotone at row " + std::to_string(r));
     bool diag = false;
     for (int q = P.rp[r]; q < P.rp[r + 1]; ++q) {
       const int c = P.ci[q];
-      if (c < 0 || c >= nb) return cleanup(fail(ASM_ERR_INVALID, "column out of range in row " + std::to_string(r)));
+      if (c < 0 || c >= nb) return fail(ASM_ERR_INVALID, "column out of range in row " + std::to_string(r));
       if (q > P.rp[r] && P.ci[q - 1] >= c)
-        return cleanup(fail(ASM_ERR_INVALID, "columns not strictly increasing in row " + std::to_string(r)));
+        return fail(ASM_ERR_INVALID, "columns not strictly increasing in row " + std::to_string(r));
       diag |= (c == r);
     }
-    if (!diag) return cleanup(fail(ASM_ERR_INVALID, "missing diagonal block in row " + std::to_string(r)));
+    if (!diag) return fail(ASM_ERR_INVALID, "missing diagonal block in row " + std::to_string(r));
   }
-  if ((e = S->mem.upload(&S->rp, P.rp, stream)) != hipSuccess ||
-      (e = S->mem.upload(&S->ci, P.ci, stream)) != hipSuccess ||
-      (e = S->mem.alloc(&S->vals, (size_t)nnzb * 9)) != hipSuccess)
-    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  if ((e = hipMemcpyAsync(S->vals, vals_dev, (size_t)nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice, stream)) !=
-      hipSuccess)
-    return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
-  asm_status st = ensure_workspace(S, 1, stream);
-  if (st != ASM_OK) return cleanup(st);
-  bool bad = false;
-  if ((st = any_nonfinite(S, S->vals, (int64_t)nnzb * 9, stream, &bad)) != ASM_OK) return cleanup(st);
-  if (bad) return cleanup(fail(ASM_ERR_NONFINITE, "non-finite matrix value"));
-  if ((st = build_sell(S, stream)) != ASM_OK) return cleanup(st);
-  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
-  *out = S;
   return ASM_OK;
 }
 
-asm_status asm_update_values(asm_system S, const double *vals_dev, hipStream_t stream) {
-  g_err.clear();
-  if (!S || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  ASM_HIP(hipMemcpyAsync(S->vals, vals_dev, (size_t)S->pat.nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream));
-  bool bad = false;
-  asm_status st = any_nonfinite(S, S->vals, S->pat.nnzb * 9, stream, &bad);
-  if (st != ASM_OK) return st;
-  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite matrix value");
-  ASM_HIP(launch_sell_fill(S->sell, S->vals, stream));
-  return ASM_OK;
-}
-
-asm_status asm_spmv(asm_system S, const double *x_dev, double *y_dev, hipStream_t stream) {
-  g_err.clear();
-  if (!S || !x_dev || !y_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream));
-  return ASM_OK;
-}
-
-asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_t stream, asm_precond *out) {
-  g_err.clear();
-  if (!S || !o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
-  *out = nullptr;
+asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o) {
   if (o->kind < ASM_KIND_NONE || o->kind > ASM_KIND_TWO_LEVEL) return fail(ASM_ERR_INVALID, "bad kind");
   if (o->combine != ASM_COMBINE_ADDITIVE && o->combine != ASM_COMBINE_RESTRICTED)
     return fail(ASM_ERR_INVALID, "bad combine");
   if (o->precision != ASM_PREC_FP64 && o->precision != ASM_PREC_FP32) return fail(ASM_ERR_INVALID, "bad precision");
+  if (o->kind == ASM_KIND_NONE) return ASM_OK;
+  if (o->sx < 1 || o->sy < 1 || o->sx > A.nx || o->sy > A.ny || o->overlap < 0)
+    return fail(ASM_ERR_INVALID, "bad subdomain split or overlap");
+  if (o->kind == ASM_KIND_TWO_LEVEL)
+    for (int d = 0; d < 3; ++d)
+      if (o->near_box[d] < 1 || o->far_box[d] < 1) return fail(ASM_ERR_INVALID, "bad coarsening box");
+  return ASM_OK;
+}
+
+asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_ptr<PlanHost> plan,
+                           hipStream_t stream, asm_precond *out) {
+  *out = nullptr;
   auto pc = new (std::nothrow) asm_precond_s();
   if (!pc) return fail(ASM_ERR_OOM, "host allocation failed");
   pc->sys = S;
@@ -255,18 +198,10 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
     delete pc;
     return st;
   };
-  const HostPattern &A = S->pat;
-  if (o->sx < 1 || o->sy < 1 || o->sx > A.nx || o->sy > A.ny || o->overlap < 0)
-    return cleanup(fail(ASM_ERR_INVALID, "bad subdomain split or overlap"));
-  if (o->kind == ASM_KIND_TWO_LEVEL)
-    for (int d = 0; d < 3; ++d)
-      if (o->near_box[d] < 1 || o->far_box[d] < 1) return cleanup(fail(ASM_ERR_INVALID, "bad coarsening box"));
-  pc->plan = std::make_shared<PlanHost>();
+  pc->plan = std::move(plan);
   pc->smem = std::make_shared<DevMem>();
   PlanHost &P = *pc->plan;
-  std::string err;
-  asm_status st = build_plan(A, *o, P, err);
-  if (st != ASM_OK) return cleanup(fail(st, err));
+  asm_status st = ASM_OK;
   DevMem &M = *pc->smem;  // pattern-only arrays
   DevMem &O = pc->mem;    // records, factors and work vectors of this handle
   DevPlan &d = pc->dp;
@@ -362,6 +297,96 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
   pc->stats.reloaded_rows = P.lds_spilled_rows;
   *out = pc;
   return ASM_OK;
+}
+
+}  // namespace asmx
+
+using namespace asmx;
+
+extern "C" {
+
+const char *asm_last_error(void) { return g_err.c_str(); }
+
+asm_status asm_create_system(const asm_grid *grid, int32_t nb, int64_t nnzb, const int32_t *row_ptr_dev,
+                             const int32_t *col_idx_dev, const double *vals_dev, hipStream_t stream,
+                             asm_system *out) {
+  g_err.clear();
+  if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!grid || !row_ptr_dev || !col_idx_dev || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || (int64_t)grid->nx * grid->ny * grid->nz != nb)
+    return fail(ASM_ERR_INVALID, "grid nx*ny*nz does not equal nb");
+  if (nnzb < nb || nnzb >= ((int64_t)1 << 31) / 9) return fail(ASM_ERR_INVALID, "nnzb out of range");
+  auto S = new (std::nothrow) asm_system_s();
+  if (!S) return fail(ASM_ERR_OOM, "host allocation failed");
+  auto cleanup = [&](asm_status st) {
+    delete S;
+    return st;
+  };
+  (void)hipGetDevice(&S->device);
+  HostPattern &P = S->pat;
+  P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.N = nb; P.nnzb = nnzb;
+  P.rp.resize(nb + 1);
+  P.ci.resize(nnzb);
+  hipError_t e = hipMemcpyAsync(P.rp.data(), row_ptr_dev, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P.ci.data(), col_idx_dev, nnzb * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return cleanup(fail(ASM_ERR_HIP, std::string("pattern copy: ") + hipGetErrorString(e)));
+  asm_status vst = validate_pattern(P);
+  if (vst != ASM_OK) return cleanup(vst);
+  if ((e = S->mem.upload(&S->rp, P.rp, stream)) != hipSuccess ||
+      (e = S->mem.upload(&S->ci, P.ci, stream)) != hipSuccess ||
+      (e = S->mem.alloc(&S->vals, (size_t)nnzb * 9)) != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  if ((e = hipMemcpyAsync(S->vals, vals_dev, (size_t)nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice, stream)) !=
+      hipSuccess)
+    return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+  asm_status st = ensure_workspace(S, 1, stream);
+  if (st != ASM_OK) return cleanup(st);
+  bool bad = false;
+  if ((st = any_nonfinite(S, S->vals, (int64_t)nnzb * 9, stream, &bad)) != ASM_OK) return cleanup(st);
+  if (bad) return cleanup(fail(ASM_ERR_NONFINITE, "non-finite matrix value"));
+  if ((st = build_sell(S, stream)) != ASM_OK) return cleanup(st);
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+  *out = S;
+  return ASM_OK;
+}
+
+asm_status asm_update_values(asm_system S, const double *vals_dev, hipStream_t stream) {
+  g_err.clear();
+  if (!S || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+  ASM_HIP(hipMemcpyAsync(S->vals, vals_dev, (size_t)S->pat.nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
+                         stream));
+  bool bad = false;
+  asm_status st = any_nonfinite(S, S->vals, S->pat.nnzb * 9, stream, &bad);
+  if (st != ASM_OK) return st;
+  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite matrix value");
+  ASM_HIP(launch_sell_fill(S->sell, S->vals, stream));
+  return ASM_OK;
+}
+
+asm_status asm_spmv(asm_system S, const double *x_dev, double *y_dev, hipStream_t stream) {
+  g_err.clear();
+  if (!S || !x_dev || !y_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+  ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream));
+  return ASM_OK;
+}
+
+asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_t stream, asm_precond *out) {
+  g_err.clear();
+  if (!S || !o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  asm_status st = check_precond_opts(S->pat, o);
+  if (st != ASM_OK) return st;
+  std::shared_ptr<PlanHost> plan;
+  if (o->kind != ASM_KIND_NONE) {
+    plan = std::make_shared<PlanHost>();
+    std::string err;
+    st = build_plan(S->pat, *o, *plan, err);
+    if (st != ASM_OK) return fail(st, err);
+  }
+  return setup_from_plan(S, o, std::move(plan), stream, out);
 }
 
 asm_status asm_refactor(asm_precond pc, hipStream_t stream) {

@@ -164,6 +164,13 @@ constexpr int kPubBase = 16, kPubStride = kMaxRestart + 4;
 // Krylov workspace of a system (allocated on first use), the batched-solve
 // helpers and the preconditioner application shared by the solvers.
 asm_status ensure_workspace(asm_system S, int m, hipStream_t s);
+// Structure checks of asm_create_system (host copy of the pattern).
+asm_status validate_pattern(const HostPattern &P);
+// Option checks of asm_setup_precond against a pattern, and its device part:
+// uploads a host plan built by build_plan, then assembles and factorises.
+asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o);
+asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_ptr<PlanHost> plan,
+                           hipStream_t stream, asm_precond *out);
 asm_status apply_precond(asm_precond pc, const double *r, const double *scale, double *z, hipStream_t s,
                          Profiler *prof = nullptr);
 

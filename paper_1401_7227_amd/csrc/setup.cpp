@@ -151,16 +151,35 @@ inline bool contains(const Csr &c, int row, int v) {
   return false;
 }
 
-// Assigns compact ids to keys (in sorted key order).  keys: (k1, k2) pairs.
+// Assigns compact ids to keys (in sorted key order).  keys: (k1, k2) pairs
+// with non-negative components.  The pairs are packed into one 64-bit key
+// when the range allows, and sorted directly (with their index) rather than
+// through an index permutation.
 std::vector<int32_t> compact_ids(const std::vector<std::pair<int64_t, int64_t>> &keys, int32_t &nids) {
-  std::vector<int32_t> order(keys.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
-  std::vector<int32_t> id(keys.size());
+  const size_t n = keys.size();
+  std::vector<int32_t> id(n);
+  int64_t max1 = 0, max2 = 0;
+  for (const auto &k : keys) {
+    max1 = std::max(max1, k.first);
+    max2 = std::max(max2, k.second);
+  }
   int32_t next = -1;
-  for (size_t i = 0; i < order.size(); ++i) {
-    if (i == 0 || keys[order[i]] != keys[order[i - 1]]) ++next;
-    id[order[i]] = next;
+  if (max2 < INT64_MAX / 2 && max1 < INT64_MAX / (max2 + 1) - 1) {
+    std::vector<std::pair<int64_t, int32_t>> s(n);
+    for (size_t i = 0; i < n; ++i) s[i] = {keys[i].first * (max2 + 1) + keys[i].second, (int32_t)i};
+    std::sort(s.begin(), s.end());
+    for (size_t i = 0; i < n; ++i) {
+      if (i == 0 || s[i].first != s[i - 1].first) ++next;
+      id[s[i].second] = next;
+    }
+  } else {
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+    for (size_t i = 0; i < n; ++i) {
+      if (i == 0 || keys[order[i]] != keys[order[i - 1]]) ++next;
+      id[order[i]] = next;
+    }
   }
   nids = next + 1;
   return id;
@@ -170,20 +189,41 @@ std::vector<int32_t> compact_ids(const std::vector<std::pair<int64_t, int64_t>> 
 // triples; returns pattern and gather list (sources in ascending order).
 void triples_to_csr(std::vector<std::array<int32_t, 3>> &t, int32_t nrows, std::vector<int32_t> &ptr,
                     std::vector<int32_t> &col, GatherList &g) {
-  std::sort(t.begin(), t.end());
-  ptr.assign(nrows + 1, 0);
-  col.clear();
-  for (size_t i = 0; i < t.size(); ++i) {
-    const bool first = (i == 0 || t[i][0] != t[i - 1][0] || t[i][1] != t[i - 1][1]);
-    if (first) {
-      col.push_back(t[i][1]);
-      ptr[t[i][0] + 1]++;
-      g.ptr.push_back(g.ptr.back());
-    }
-    g.idx.push_back(t[i][2]);
-    g.ptr.back()++;
+  // bucket by row (counting sort), then sort each row's (col, src) pairs:
+  // the same order as sorting the triples, without one large sort
+  const size_t n = t.size();
+  std::vector<int64_t> rs(nrows + 1, 0);
+  for (const auto &x : t) rs[x[0] + 1]++;
+  for (int r = 0; r < nrows; ++r) rs[r + 1] += rs[r];
+  std::vector<std::pair<int32_t, int32_t>> cs(n);
+  {
+    std::vector<int64_t> cur(rs.begin(), rs.end() - 1);
+    for (const auto &x : t) cs[cur[x[0]]++] = {x[1], x[2]};
   }
-  for (int r = 0; r < nrows; ++r) ptr[r + 1] += ptr[r];
+  std::vector<int32_t> ndist(nrows, 0);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int r = 0; r < nrows; ++r) {
+    std::sort(cs.begin() + rs[r], cs.begin() + rs[r + 1]);
+    int d = 0;
+    for (int64_t i = rs[r]; i < rs[r + 1]; ++i) d += (i == rs[r] || cs[i].first != cs[i - 1].first);
+    ndist[r] = d;
+  }
+  ptr.assign(nrows + 1, 0);
+  for (int r = 0; r < nrows; ++r) ptr[r + 1] = ptr[r] + ndist[r];
+  col.assign(ptr[nrows], 0);
+  const size_t g0 = g.ptr.size() - 1;          // groups already in g
+  const int64_t i0 = (int64_t)g.idx.size();   // sources already in g
+  g.ptr.resize(g0 + 1 + ptr[nrows]);
+  g.idx.resize(i0 + n);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int r = 0; r < nrows; ++r) {
+    int k = ptr[r] - 1;
+    for (int64_t i = rs[r]; i < rs[r + 1]; ++i) {
+      if (i == rs[r] || cs[i].first != cs[i - 1].first) col[++k] = cs[i].first;
+      g.idx[i0 + i] = cs[i].second;
+      g.ptr[g0 + 1 + k] = (int32_t)(i0 + i + 1);
+    }
+  }
 }
 
 inline int32_t align16(int64_t b) { return (int32_t)((b + 15) & ~int64_t(15)); }
@@ -759,9 +799,16 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
       kN[c] = {(int64_t)at.nbox[c] * ns + owner[c], snear[c]};
       kF[c] = {(int64_t)at.fbox[c] * ns + owner[c], sfar[c]};
     }
-    at.cell_atom = compact_ids(kA, at.nA);
-    const std::vector<int32_t> cN = compact_ids(kN, at.nNa);
-    const std::vector<int32_t> cF = compact_ids(kF, at.nFa);
+    std::vector<int32_t> cN, cF;
+#pragma omp parallel sections
+    {
+#pragma omp section
+      at.cell_atom = compact_ids(kA, at.nA);
+#pragma omp section
+      cN = compact_ids(kN, at.nNa);
+#pragma omp section
+      cF = compact_ids(kF, at.nFa);
+    }
     at.a_near.assign(at.nA, -1);
     at.a_far.assign(at.nA, -1);
     at.na_box.assign(at.nNa, 0);
@@ -832,15 +879,14 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     }
     // right-hand side lumping: fine-atom sums of cells, then N/F atoms
     {
-      std::vector<std::array<int32_t, 3>> tc;
-      tc.reserve(N);
-      for (int c = 0; c < N; ++c) tc.push_back({at.cell_atom[c], c, c});
-      std::sort(tc.begin(), tc.end());
-      P.c1.ptr.assign(1, 0);
-      int cur = 0;
-      for (int a = 0; a < at.nA; ++a) {
-        while (cur < (int)tc.size() && tc[cur][0] == a) P.c1.idx.push_back(tc[cur++][2]);
-        P.c1.ptr.push_back((int32_t)P.c1.idx.size());
+      // cells of each fine atom, ascending
+      P.c1.ptr.assign(at.nA + 1, 0);
+      for (int c = 0; c < N; ++c) P.c1.ptr[at.cell_atom[c] + 1]++;
+      for (int a = 0; a < at.nA; ++a) P.c1.ptr[a + 1] += P.c1.ptr[a];
+      P.c1.idx.resize(N);
+      {
+        std::vector<int32_t> cur(P.c1.ptr.begin(), P.c1.ptr.end() - 1);
+        for (int c = 0; c < N; ++c) P.c1.idx[cur[at.cell_atom[c]]++] = c;
       }
       // c2 destinations: [N-atoms | F-atoms]
       std::vector<std::vector<int32_t>> nsrc(at.nNa), fsrc(at.nFa);

@@ -181,10 +181,16 @@ def test_server_error_statuses(P):
     srv = P.Server(max_active=8)
     for r in reqs:
         srv.submit(r["tag"], r["grid"], r["rp"], r["ci"], P.precond_opts(**r["opts"]), r["vals"], r["bs"], r["xs"])
+    # a pattern without the diagonal block of row 0 (another grid: no cached plan)
+    bad = _requests(P, [((6, 6, 4), 14, 1, 2, 1)])[0]
+    ci = bad["ci"].clone()
+    ci[0] = 1
+    srv.submit(3, bad["grid"], bad["rp"], ci, P.precond_opts(**bad["opts"]), bad["vals"], bad["bs"], bad["xs"])
     done = {}
-    while len(done) < 3:
+    while len(done) < 4:
         for c in srv.poll():
             done[c["tag"]] = c
+    assert done[3]["status"] == P.ERR_INVALID and done[3]["solves"] == 0
     assert done[0]["status"] == P.ERR_NONFINITE and done[0]["solves"] == 0
     assert done[1]["status"] == P.OK and done[1]["solves"] == 2
     assert done[2]["status"] == P.ERR_SINGULAR_PIVOT and done[2]["solves"] == 1
