@@ -24,6 +24,8 @@ OK, NOT_CONVERGED, INVALID, OOM, SINGULAR, NONFINITE = 0, 1, -1, -2, -3, -4
 KIND_NONE, KIND_CLASSICAL, KIND_TWO_LEVEL = 0, 1, 2
 ADDITIVE, RESTRICTED = 0, 1
 LOCAL_ILU0, LOCAL_EXACT = 0, 1
+FIELD_NEAR_FAR, FIELD_NEAR, FIELD_FAR = 0, 1, 2
+COARSE_NONE, COARSE_ADDITIVE, COARSE_TWO_STAGE = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -39,7 +41,8 @@ def build(force: bool = True) -> str:
 class _Opts(C.Structure):
     _fields_ = [("kind", C.c_int), ("combine", C.c_int), ("sx", C.c_int),
                 ("sy", C.c_int), ("overlap", C.c_int),
-                ("near", C.c_int * 3), ("far", C.c_int * 3), ("local", C.c_int)]
+                ("near", C.c_int * 3), ("far", C.c_int * 3), ("local", C.c_int),
+                ("field", C.c_int), ("coarse", C.c_int), ("cbox", C.c_int * 3)]
 
 
 class _Info(C.Structure):
@@ -139,10 +142,10 @@ class Precond:
 
     def __init__(self, A: Matrix, kind=KIND_CLASSICAL, combine=RESTRICTED,
                  sx=1, sy=1, overlap=1, near=(2, 2, 2), far=(4, 4, 4),
-                 local=LOCAL_ILU0):
+                 local=LOCAL_ILU0, field=FIELD_NEAR_FAR, coarse=COARSE_NONE, cbox=(4, 4, 4)):
         self.A = A
         o = _Opts(kind, combine, sx, sy, overlap, (C.c_int * 3)(*near),
-                  (C.c_int * 3)(*far), local)
+                  (C.c_int * 3)(*far), local, field, coarse, (C.c_int * 3)(*cbox))
         h = C.c_void_p()
         st = lib().or_precond_setup(A.nx, A.ny, A.nz, _p(A.row_ptr), _p(A.col_idx),
                                     _p(A.vals), C.byref(o), C.byref(h))

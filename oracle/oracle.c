@@ -59,6 +59,21 @@
 #define LOCAL_ILU0 0
 #define LOCAL_EXACT 1
 
+/* Outside cells in the two-level form (Section 5 compares the three):
+ * near and far fields, the near field only (far cells dropped, in effect
+ * additive Schwarz with coarsened overlap) or the far field only (every
+ * outside cell lumped into far boxes). */
+#define FIELD_NEAR_FAR 0
+#define FIELD_NEAR 1
+#define FIELD_FAR 2
+
+/* Global coarse-grid correction added to the Schwarz preconditioner:
+ * eq. (3.5)-(3.6) (added to the local solves) or eq. (3.7)-(3.8) (applied
+ * after them to the remaining residual). */
+#define COARSE_NONE 0
+#define COARSE_ADDITIVE 1
+#define COARSE_TWO_STAGE 2
+
 static char g_err[512];
 
 const char *or_last_error(void) { return g_err; }
@@ -190,9 +205,18 @@ typedef struct {
   int kind, combine, local;
   int sx, sy, overlap;
   int near[3], far[3];
+  int field;
   int N, nsub;
   Sub *sub;
   int *owner;     /* [N] subdomain owning each cell */
+  /* global coarse-grid correction */
+  int coarse;
+  int cbox[3];    /* coarse box size */
+  int nC;         /* coarse variables (boxes of the global box grid) */
+  int *cvar;      /* [N] coarse variable of each cell */
+  double *clu;    /* dense LU of A_C = R_C A R_C^T, (3 nC)^2 */
+  int *cpiv;
+  Mat A;          /* the matrix (the caller keeps its arrays alive) */
 } Precond;
 
 void or_precond_free(Precond *P);
@@ -303,10 +327,10 @@ static int make_labels(const Mat *A, const Precond *P, const Graph *G, int s, Su
       if (S->label[c] >= 0) continue;
       int o = P->owner[c];
       int ox = o / P->sy, oy = o % P->sy;
-      int is_near = (abs(ox - px) + abs(oy - py)) == 1;
+      int is_near = (abs(ox - px) + abs(oy - py)) == 1 && P->field != FIELD_FAR;
       int ix = c / (nny * nnz), iy = (c / nnz) % nny, iz = c % nnz;
       if (is_near) near_id[box_index(ix, iy, iz, P->near, nny, nnz)] = 0;
-      else far_id[box_index(ix, iy, iz, P->far, nny, nnz)] = 0;
+      else if (P->field != FIELD_NEAR) far_id[box_index(ix, iy, iz, P->far, nny, nnz)] = 0;
     }
     int next = nfine;
     for (int k = 0; k < nbn; k++) if (near_id[k] == 0) near_id[k] = next++;
@@ -316,10 +340,11 @@ static int make_labels(const Mat *A, const Precond *P, const Graph *G, int s, Su
       if (S->label[c] >= 0) continue;
       int o = P->owner[c];
       int ox = o / P->sy, oy = o % P->sy;
-      int is_near = (abs(ox - px) + abs(oy - py)) == 1;
+      int is_near = (abs(ox - px) + abs(oy - py)) == 1 && P->field != FIELD_FAR;
       int ix = c / (nny * nnz), iy = (c / nnz) % nny, iz = c % nnz;
       if (is_near) S->label[c] = near_id[box_index(ix, iy, iz, P->near, nny, nnz)];
-      else S->label[c] = far_id[box_index(ix, iy, iz, P->far, nny, nnz)];
+      else if (P->field != FIELD_NEAR) S->label[c] = far_id[box_index(ix, iy, iz, P->far, nny, nnz)];
+      /* near field only: far cells stay unlabelled (dropped) */
     }
     free(near_id);
     free(far_id);
@@ -458,6 +483,43 @@ static int ilu0(Sub *S, int *bad_row) {
 
 /* Exact local solver (Section 5): dense LU with partial pivoting of the
  * scalar 3n x 3n matrix A_i. */
+/* Dense LU with partial pivoting of the m x m row-major matrix M, in
+ * place (P M = L U, unit L below the diagonal); piv[c] is the row swapped
+ * with row c at step c.  bad receives the failing column on a zero pivot. */
+static int lu_factor(double *M, int *piv, int m, int *bad) {
+  for (int c = 0; c < m; c++) {
+    int p = c;
+    for (int r = c + 1; r < m; r++) if (fabs(M[(size_t)r * m + c]) > fabs(M[(size_t)p * m + c])) p = r;
+    piv[c] = p;
+    if (!(fabs(M[(size_t)p * m + c]) > 0.0)) { *bad = c; return OR_SINGULAR; }
+    if (p != c)
+      for (int j = 0; j < m; j++) { double t = M[(size_t)c * m + j]; M[(size_t)c * m + j] = M[(size_t)p * m + j]; M[(size_t)p * m + j] = t; }
+    for (int r = c + 1; r < m; r++) {
+      double f = M[(size_t)r * m + c] / M[(size_t)c * m + c];
+      M[(size_t)r * m + c] = f;
+      if (f != 0.0)
+        for (int j = c + 1; j < m; j++) M[(size_t)r * m + j] -= f * M[(size_t)c * m + j];
+    }
+  }
+  return OR_OK;
+}
+
+/* x <- M^-1 x with the factors of lu_factor. */
+static void lu_solve(const double *M, const int *piv, int m, double *x) {
+  /* the factorisation swapped whole rows, so P A = L U: permute first */
+  for (int c = 0; c < m; c++) {
+    int p = piv[c];
+    if (p != c) { double t = x[c]; x[c] = x[p]; x[p] = t; }
+  }
+  for (int c = 0; c < m; c++)
+    for (int r = c + 1; r < m; r++) x[r] -= M[(size_t)r * m + c] * x[c];
+  for (int r = m - 1; r >= 0; r--) {
+    double s = x[r];
+    for (int j = r + 1; j < m; j++) s -= M[(size_t)r * m + j] * x[j];
+    x[r] = s / M[(size_t)r * m + r];
+  }
+}
+
 static int dense_lu(Sub *S, int *bad_row) {
   int m = 3 * S->n;
   size_t mm = (size_t)m * (size_t)m;
@@ -471,43 +533,18 @@ static int dense_lu(Sub *S, int *bad_row) {
         for (int j = 0; j < 3; j++)
           S->lu[(size_t)(3 * u + i) * m + 3 * v + j] = S->a[9 * (size_t)e + 3 * i + j];
     }
-  double *M = S->lu;
-  for (int c = 0; c < m; c++) {
-    int p = c;
-    for (int r = c + 1; r < m; r++) if (fabs(M[(size_t)r * m + c]) > fabs(M[(size_t)p * m + c])) p = r;
-    S->piv[c] = p;
-    if (!(fabs(M[(size_t)p * m + c]) > 0.0)) { *bad_row = c / 3; return OR_SINGULAR; }
-    if (p != c)
-      for (int j = 0; j < m; j++) { double t = M[(size_t)c * m + j]; M[(size_t)c * m + j] = M[(size_t)p * m + j]; M[(size_t)p * m + j] = t; }
-    for (int r = c + 1; r < m; r++) {
-      double f = M[(size_t)r * m + c] / M[(size_t)c * m + c];
-      M[(size_t)r * m + c] = f;
-      if (f != 0.0)
-        for (int j = c + 1; j < m; j++) M[(size_t)r * m + j] -= f * M[(size_t)c * m + j];
-    }
-  }
-  return OR_OK;
+  int bad = 0;
+  int st = lu_factor(S->lu, S->piv, m, &bad);
+  if (st != OR_OK) *bad_row = bad / 3;
+  return st;
 }
 
 /* Solve A_i xh = rh with the subdomain's local solver. */
 static void local_solve(const Precond *P, const Sub *S, const double *rh, double *xh) {
   int n = S->n;
   if (P->local == LOCAL_EXACT) {
-    int m = 3 * n;
-    const double *M = S->lu;
-    memcpy(xh, rh, (size_t)m * sizeof(double));
-    /* the factorisation swapped whole rows, so P A = L U: permute first */
-    for (int c = 0; c < m; c++) {
-      int p = S->piv[c];
-      if (p != c) { double t = xh[c]; xh[c] = xh[p]; xh[p] = t; }
-    }
-    for (int c = 0; c < m; c++)
-      for (int r = c + 1; r < m; r++) xh[r] -= M[(size_t)r * m + c] * xh[c];
-    for (int r = m - 1; r >= 0; r--) {
-      double s = xh[r];
-      for (int j = r + 1; j < m; j++) s -= M[(size_t)r * m + j] * xh[j];
-      xh[r] = s / M[(size_t)r * m + r];
-    }
+    memcpy(xh, rh, (size_t)3 * n * sizeof(double));
+    lu_solve(S->lu, S->piv, 3 * n, xh);
     return;
   }
   /* forward: y_i = rh_i - sum_{k<i} L_ik y_k (unit lower) */
@@ -559,7 +596,56 @@ typedef struct {
   int kind, combine, sx, sy, overlap;
   int near[3], far[3];
   int local;
+  int field;
+  int coarse;
+  int cbox[3];
 } or_opts;
+
+/* The global coarse operator of eq. (3.5)-(3.6): R_C sums the cells of each
+ * box of a global box grid (per unknown component, as the lumping of
+ * Appendix B), A_C = R_C A R_C^T is the 3x3-block matrix of the box sums of
+ * A's blocks, factorised densely (the coarse problem is solved exactly). */
+static int coarse_setup(Precond *P) {
+  const Mat *A = &P->A;
+  int N = A->N, ny = A->ny, nz = A->nz;
+  int nbx = (A->nx + P->cbox[0] - 1) / P->cbox[0], nby = (ny + P->cbox[1] - 1) / P->cbox[1],
+      nbz = (nz + P->cbox[2] - 1) / P->cbox[2];
+  P->nC = nbx * nby * nbz;  /* boxes clipped at the boundary are never empty */
+  P->cvar = malloc((size_t)N * sizeof(int));
+  int m = 3 * P->nC;
+  P->clu = calloc((size_t)m * m, sizeof(double));
+  P->cpiv = malloc((size_t)m * sizeof(int));
+  if (!P->cvar || !P->clu || !P->cpiv) return OR_OOM;
+  for (int c = 0; c < N; c++) {
+    int ix = c / (ny * nz), iy = (c / nz) % ny, iz = c % nz;
+    P->cvar[c] = box_index(ix, iy, iz, P->cbox, ny, nz);
+  }
+  for (int a = 0; a < N; a++)
+    for (int e = A->rp[a]; e < A->rp[a + 1]; e++) {
+      int U = P->cvar[a], V = P->cvar[A->ci[e]];
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) P->clu[(size_t)(3 * U + i) * m + 3 * V + j] += A->v[9 * (size_t)e + 3 * i + j];
+    }
+  int bad = 0;
+  int st = lu_factor(P->clu, P->cpiv, m, &bad);
+  if (st == OR_SINGULAR) snprintf(g_err, sizeof g_err, "singular coarse operator at coarse row %d", bad / 3);
+  return st;
+}
+
+/* z += R_C^T A_C^-1 R_C r: box sums of r, the coarse solve, and the coarse
+ * value given back to every cell of its box. */
+static int coarse_correct(const Precond *P, const double *r, double *z) {
+  int N = P->N, m = 3 * P->nC;
+  double *xc = calloc((size_t)m, sizeof(double));
+  if (!xc) return OR_OOM;
+  for (int c = 0; c < N; c++)
+    for (int q = 0; q < 3; q++) xc[3 * P->cvar[c] + q] += r[3 * (size_t)c + q];
+  lu_solve(P->clu, P->cpiv, m, xc);
+  for (int c = 0; c < N; c++)
+    for (int q = 0; q < 3; q++) z[3 * (size_t)c + q] += xc[3 * P->cvar[c] + q];
+  free(xc);
+  return OR_OK;
+}
 
 int or_precond_setup(int nx, int ny, int nz, const int *rp, const int *ci, const double *v,
                      const or_opts *o, Precond **out) {
@@ -569,7 +655,9 @@ int or_precond_setup(int nx, int ny, int nz, const int *rp, const int *ci, const
   int st = check_matrix(&A);
   if (st != OR_OK) return st;
   if (o->kind < KIND_NONE || o->kind > KIND_TWO_LEVEL || o->combine < 0 || o->combine > 1 ||
-      o->local < 0 || o->local > 1) {
+      o->local < 0 || o->local > 1 || o->field < FIELD_NEAR_FAR || o->field > FIELD_FAR ||
+      o->coarse < COARSE_NONE || o->coarse > COARSE_TWO_STAGE ||
+      (o->coarse != COARSE_NONE && (o->kind == KIND_NONE || o->cbox[0] < 1 || o->cbox[1] < 1 || o->cbox[2] < 1))) {
     set_err("bad preconditioner option", o->kind);
     return OR_INVALID;
   }
@@ -579,6 +667,10 @@ int or_precond_setup(int nx, int ny, int nz, const int *rp, const int *ci, const
   P->sx = o->sx; P->sy = o->sy; P->overlap = o->overlap;
   memcpy(P->near, o->near, sizeof P->near);
   memcpy(P->far, o->far, sizeof P->far);
+  P->field = o->field;
+  P->coarse = o->coarse;
+  memcpy(P->cbox, o->cbox, sizeof P->cbox);
+  P->A = A;
   P->N = A.N;
   if (P->kind == KIND_NONE) { *out = P; return OR_OK; }
   if (o->sx < 1 || o->sy < 1 || o->sx > nx || o->sy > ny || o->overlap < 0) {
@@ -616,6 +708,7 @@ int or_precond_setup(int nx, int ny, int nz, const int *rp, const int *ci, const
   }
   free(G.ptr);
   free(G.idx);
+  if (st == OR_OK && P->coarse != COARSE_NONE) st = coarse_setup(P);
   if (st != OR_OK) { or_precond_free(P); return st; }
   *out = P;
   return OR_OK;
@@ -631,6 +724,9 @@ void or_precond_free(Precond *P) {
     }
   free(P->sub);
   free(P->owner);
+  free(P->cvar);
+  free(P->clu);
+  free(P->cpiv);
   free(P);
 }
 
@@ -639,7 +735,9 @@ void or_precond_free(Precond *P) {
  *              each subdomain, contributions summed in subdomain order;
  *   restricted (4.2): z = sum_i P_i (A_i^-1 R_i r), each cell taking the
  *              value from its owning subdomain; the coarse part of the
- *              local solution is discarded. */
+ *              local solution is discarded;
+ * then, with a global coarse grid, z += B_C^-1 r (eq. (3.5)) or
+ * z += B_C^-1 (r - A z) (eq. (3.8)), B_C^-1 = R_C^T A_C^-1 R_C (eq. (3.6)). */
 int or_precond_apply(const Precond *P, const double *r, double *z) {
   int N = P->N;
   if (P->kind == KIND_NONE) { memcpy(z, r, (size_t)3 * N * sizeof(double)); return OR_OK; }
@@ -660,6 +758,17 @@ int or_precond_apply(const Precond *P, const double *r, double *z) {
     }
     free(rh);
     free(xh);
+  }
+  if (P->coarse == COARSE_ADDITIVE) return coarse_correct(P, r, z);  /* eq. (3.5) */
+  if (P->coarse == COARSE_TWO_STAGE) {                               /* eq. (3.8) */
+    size_t n = (size_t)3 * N;
+    double *az = malloc(n * sizeof(double));
+    if (!az) return OR_OOM;
+    or_spmv(N, P->A.rp, P->A.ci, P->A.v, z, az);
+    for (size_t k = 0; k < n; k++) az[k] = r[k] - az[k];  /* (I - A B_AS^-1) r */
+    int st = coarse_correct(P, az, z);
+    free(az);
+    return st;
   }
   return OR_OK;
 }
