@@ -55,6 +55,11 @@ typedef struct {
 enum { ASM_KIND_NONE = 0, ASM_KIND_CLASSICAL = 1, ASM_KIND_TWO_LEVEL = 2 };
 enum { ASM_COMBINE_ADDITIVE = 0, ASM_COMBINE_RESTRICTED = 1 };
 enum { ASM_PREC_FP64 = 0, ASM_PREC_FP32 = 1 };
+/* Outside cells of the two-level form (the variants of Section 5). */
+enum { ASM_FIELD_NEAR_FAR = 0, ASM_FIELD_NEAR = 1, ASM_FIELD_FAR = 2 };
+/* Global coarse-grid correction (Section 3). */
+enum { ASM_COARSE_NONE = 0, ASM_COARSE_ADDITIVE = 1, ASM_COARSE_TWO_STAGE = 2 };
+#define ASM_COARSE_MAX_UNKNOWNS 8192
 
 /*
  * asm_create_system - take a device copy of A (Section 2's A = -J).
@@ -97,6 +102,19 @@ asm_status asm_spmv(asm_system sys, const double *x_dev, double *y_dev, hipStrea
  *   precision FP64, or FP32: factors of fine rows stored and applied in
  *             single precision, coarse rows kept in double; the outer GMRES
  *             stays double.
+ *   field     two-level only (Section 5 compares the three): NEAR_FAR
+ *             (default), NEAR (near field only: outside cells of
+ *             non-neighbouring subdomains are dropped) or FAR (far field only:
+ *             every outside cell is lumped into far boxes).
+ *   coarse    global coarse-grid correction with boxes of coarse_box cells:
+ *             R_C sums the cells of each box of a global box grid (per
+ *             unknown), A_C = R_C A R_C^T (eq. (3.6)) is inverted exactly
+ *             (dense, on the device; at most ASM_COARSE_MAX_UNKNOWNS = 3 x
+ *             boxes, INVALID beyond) and B_C^-1 = R_C^T A_C^-1 R_C is
+ *             ADDITIVE: added to the Schwarz part (eq. (3.5)), or
+ *             TWO_STAGE: applied to the residual the Schwarz part leaves,
+ *             B^-1 = B_AS^-1 + B_C^-1 (I - A B_AS^-1) (eq. (3.8)).  Not
+ *             available in asm_solve_batch or the server (INVALID).
  * Local solver: block ILU(0) with 3x3 pivots inverted directly (Section 2;
  * Section 6 names ILU as the approximate local solve).
  */
@@ -108,6 +126,9 @@ typedef struct {
   int32_t near_box[3];
   int32_t far_box[3];
   int32_t precision;
+  int32_t field;
+  int32_t coarse;
+  int32_t coarse_box[3];
 } asm_precond_opts;
 
 /* Builds the partition, overlap, coarse maps, extended patterns and level

@@ -10,6 +10,7 @@ The compute path is the C-ABI library ``libasm_mi355x.so`` (HIP for gfx950,
 declared in ``include/asm.h``); this package only marshals arguments.
 """
 from ._binding import (  # noqa: F401
-    ADDITIVE, ERR_HIP, ERR_INVALID, ERR_NONFINITE, ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FP32,
-    FP64, KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, NOT_CONVERGED, OK, RESTRICTED,
-    PHASES, AsmError, Info, Precond, Server, System, load, precond_opts, solve, solve_batch)
+    ADDITIVE, COARSE_ADDITIVE, COARSE_NONE, COARSE_TWO_STAGE, ERR_HIP, ERR_INVALID, ERR_NONFINITE,
+    ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FIELD_FAR, FIELD_NEAR, FIELD_NEAR_FAR, FP32, FP64,
+    KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, NOT_CONVERGED, OK, PHASES, RESTRICTED,
+    AsmError, Info, Precond, Server, System, load, precond_opts, solve, solve_batch)

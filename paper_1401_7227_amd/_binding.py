@@ -21,6 +21,8 @@ ERR_INVALID, ERR_OOM, ERR_SINGULAR_PIVOT, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -
 KIND_NONE, KIND_CLASSICAL, KIND_TWO_LEVEL = 0, 1, 2
 ADDITIVE, RESTRICTED = 0, 1
 FP64, FP32 = 0, 1
+FIELD_NEAR_FAR, FIELD_NEAR, FIELD_FAR = 0, 1, 2
+COARSE_NONE, COARSE_ADDITIVE, COARSE_TWO_STAGE = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
                 -3: "ERR_SINGULAR_PIVOT", -4: "ERR_NONFINITE", -5: "ERR_HIP"}
@@ -45,7 +47,8 @@ class Grid(C.Structure):
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("combine", C.c_int32), ("sx", C.c_int32),
                 ("sy", C.c_int32), ("overlap", C.c_int32), ("near_box", C.c_int32 * 3),
-                ("far_box", C.c_int32 * 3), ("precision", C.c_int32)]
+                ("far_box", C.c_int32 * 3), ("precision", C.c_int32), ("field", C.c_int32),
+                ("coarse", C.c_int32), ("coarse_box", C.c_int32 * 3)]
 
 
 class PrecondStats(C.Structure):
@@ -239,7 +242,8 @@ class Precond:
     """Schwarz preconditioner B (classical or two-level) on a System."""
 
     def __init__(self, system: System, kind=KIND_CLASSICAL, combine=RESTRICTED, sx=1, sy=1,
-                 overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64, *, _clone_of=None):
+                 overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64, field=FIELD_NEAR_FAR,
+                 coarse=COARSE_NONE, cbox=(4, 4, 4), *, _clone_of=None):
         L = load()
         self.system = system
         h = C.c_void_p()
@@ -249,7 +253,7 @@ class Precond:
             self.kind = _clone_of.kind
             return
         o = PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near),
-                        (C.c_int32 * 3)(*far), precision)
+                        (C.c_int32 * 3)(*far), precision, field, coarse, (C.c_int32 * 3)(*cbox))
         _check(L.asm_setup_precond(system.handle, C.byref(o), _stream(), C.byref(h)))
         self._h = h
         self.kind = kind
@@ -358,9 +362,10 @@ def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_i
 
 
 def precond_opts(kind=KIND_TWO_LEVEL, combine=RESTRICTED, sx=1, sy=1, overlap=1, near=(2, 2, 2),
-                 far=(4, 4, 4), precision=FP64) -> PrecondOpts:
+                 far=(4, 4, 4), precision=FP64, field=FIELD_NEAR_FAR, coarse=COARSE_NONE,
+                 cbox=(4, 4, 4)) -> PrecondOpts:
     return PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near), (C.c_int32 * 3)(*far),
-                       precision)
+                       precision, field, coarse, (C.c_int32 * 3)(*cbox))
 
 
 class Server:

@@ -88,6 +88,23 @@ asm_status build_sell(asm_system S, hipStream_t s) {
   return ASM_OK;
 }
 
+// This handle's arrays of the global coarse correction.
+hipError_t alloc_coarse_own(asm_precond pc) {
+  DevMem &O = pc->mem;
+  const size_t n = 3 * (size_t)pc->ncv, N3 = 3 * (size_t)pc->sys->pat.N;
+  hipError_t e;
+  if ((e = O.alloc(&pc->acv, (size_t)pc->casrc.n * 9)) != hipSuccess || (e = O.alloc(&pc->cM, n * n)) != hipSuccess ||
+      (e = O.alloc(&pc->cMinv, n * n)) != hipSuccess || (e = O.alloc(&pc->cfcol, n)) != hipSuccess ||
+      (e = O.alloc(&pc->crc, n)) != hipSuccess || (e = O.alloc(&pc->cxc, n)) != hipSuccess ||
+      (e = O.alloc(&pc->cbad, 1)) != hipSuccess)
+    return e;
+  if (pc->opts.coarse == ASM_COARSE_TWO_STAGE &&
+      ((e = O.alloc(&pc->crtmp, N3)) != hipSuccess || (e = O.alloc(&pc->cr2, N3)) != hipSuccess ||
+       (e = O.alloc(&pc->cpart, (size_t)kReduceBlocks * 8)) != hipSuccess))
+    return e;
+  return hipSuccess;
+}
+
 // Assembly (lumped matrices, A_i values) and factorisation on the device.
 asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   asm_system S = pc->sys;
@@ -104,6 +121,19 @@ asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   ASM_HIP(launch_ilu_factor(pc->dp, pc->bad, s));
   ASM_HIP(launch_relayout((int)pc->rl_n, pc->rl_src, pc->rl_base, pc->rl_stride, pc->rl_to32, pc->dp.fact,
                           static_cast<double *>(pc->recbuf), static_cast<float *>(pc->recbuf), s));
+  if (pc->opts.coarse != ASM_COARSE_NONE) {
+    // A_C = R_C A R_C^T (box sums of A's blocks), inverted densely
+    ASM_HIP(launch_gather_sum9(pc->casrc.n, pc->casrc.ptr, pc->casrc.idx, S->vals, (int32_t)S->pat.nnzb, nullptr,
+                               pc->acv, s));
+    ASM_HIP(launch_dense_init(pc->ncv, pc->acp, pc->acc, pc->acv, pc->cM, pc->cMinv, s));
+    ASM_HIP(hipMemsetAsync(pc->cbad, 0xff, sizeof(int), s));
+    ASM_HIP(launch_gauss_jordan(3 * pc->ncv, pc->cM, pc->cMinv, pc->cfcol, pc->cbad, s));
+    int cbad = -1;
+    ASM_HIP(hipMemcpyAsync(&cbad, pc->cbad, sizeof cbad, hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    if (cbad >= 0)
+      return fail(ASM_ERR_SINGULAR_PIVOT, "singular coarse operator A_C at coarse row " + std::to_string(cbad / 3));
+  }
   unsigned long long bad = 0;
   ASM_HIP(hipMemcpyAsync(&bad, pc->bad, sizeof bad, hipMemcpyDeviceToHost, s));
   ASM_HIP(hipStreamSynchronize(s));
@@ -147,6 +177,26 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
     ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->ap.yx, z, s));
     pf.span(ASM_PHASE_COMBINE, t2, s);
   }
+  if (pc->opts.coarse != ASM_COARSE_NONE) {
+    // z += R_C^T A_C^-1 R_C r (eq. (3.5)), or of the residual r - A z left
+    // by the Schwarz part (eq. (3.8))
+    const size_t t3 = pf.mark(ASM_PHASE_OTHER, s);
+    const double *rr = r, *sc = scale;
+    if (pc->opts.coarse == ASM_COARSE_TWO_STAGE) {
+      if (scale) {
+        ASM_HIP(launch_scale_copy(n, r, scale, pc->crtmp, s));
+        rr = pc->crtmp;
+      }
+      int nb = 0;
+      ASM_HIP(launch_residual(S->sell, z, rr, pc->cr2, pc->cpart, &nb, s));
+      rr = pc->cr2;
+      sc = nullptr;
+    }
+    ASM_HIP(launch_gather_sum3(pc->ncv, pc->cbox.lanes, pc->cbox.ptr, pc->cbox.idx, rr, sc, pc->crc, s));
+    ASM_HIP(launch_dense_gemv(3 * pc->ncv, pc->cMinv, pc->crc, pc->cxc, s));
+    ASM_HIP(launch_prolong_add(S->pat.N, pc->cvar, pc->cxc, z, s));
+    pf.span(ASM_PHASE_OTHER, t3, s);
+  }
   return ASM_OK;
 }
 
@@ -174,6 +224,13 @@ asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o) {
   if (o->combine != ASM_COMBINE_ADDITIVE && o->combine != ASM_COMBINE_RESTRICTED)
     return fail(ASM_ERR_INVALID, "bad combine");
   if (o->precision != ASM_PREC_FP64 && o->precision != ASM_PREC_FP32) return fail(ASM_ERR_INVALID, "bad precision");
+  if (o->field < ASM_FIELD_NEAR_FAR || o->field > ASM_FIELD_FAR) return fail(ASM_ERR_INVALID, "bad field");
+  if (o->coarse < ASM_COARSE_NONE || o->coarse > ASM_COARSE_TWO_STAGE) return fail(ASM_ERR_INVALID, "bad coarse");
+  if (o->coarse != ASM_COARSE_NONE) {
+    if (o->kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "a coarse correction needs a Schwarz preconditioner");
+    for (int d = 0; d < 3; ++d)
+      if (o->coarse_box[d] < 1) return fail(ASM_ERR_INVALID, "bad coarse box");
+  }
   if (o->kind == ASM_KIND_NONE) return ASM_OK;
   if (o->sx < 1 || o->sy < 1 || o->sx > A.nx || o->sy > A.ny || o->overlap < 0)
     return fail(ASM_ERR_INVALID, "bad subdomain split or overlap");
@@ -273,6 +330,15 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
     ap.cidx3 = pc->c3.idx;
     ap.pnf = pc->PNF;
   }
+  if (o->coarse != ASM_COARSE_NONE) {
+    pc->ncv = P.ncv;
+    if ((e = M.upload(&pc->cvar, P.cvar, s)) != hipSuccess || (e = upload_gather(M, pc->cbox, P.cbox_cells, s)) != hipSuccess ||
+        (e = M.upload(&pc->acp, P.acp, s)) != hipSuccess || (e = M.upload(&pc->acc, P.acc, s)) != hipSuccess ||
+        (e = upload_gather(M, pc->casrc, P.ac_src, s)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    if ((e = alloc_coarse_own(pc)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
   // keep only what export and error messages need on the host
   P.rl = RelayoutMap{};
@@ -284,6 +350,9 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   P.asm_src = GatherList{};
   P.l1 = GatherList{};
   P.l2 = GatherList{};
+  P.cvar = std::vector<int32_t>();
+  P.cbox_cells = GatherList{};
+  P.ac_src = GatherList{};
   st = numeric_setup(pc, s);
   if (st != ASM_OK) return cleanup(st);
   pc->stats.nsub = P.nsub;
@@ -454,6 +523,16 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
   pc->ap.rs = rs;
   pc->ap.pnf = pc->PNF;
   pc->dp.fact = fact;
+  if (pc->opts.coarse != ASM_COARSE_NONE) {
+    pc->ncv = src->ncv;
+    pc->cvar = src->cvar;
+    pc->cbox = src->cbox;
+    pc->casrc = src->casrc;
+    pc->acp = src->acp;
+    pc->acc = src->acc;
+    if ((e = alloc_coarse_own(pc)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  }
   pc->stats.device_bytes = (int64_t)(pc->smem->bytes + O.bytes);
   asm_status st = numeric_setup(pc, stream);
   if (st != ASM_OK) return cleanup(st);

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/asm.h"
+#include "coarse.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -209,6 +210,15 @@ struct asm_precond_s {
   int64_t rl_n = 0;
   int32_t *cptr = nullptr, *cidx = nullptr;
   unsigned long long *bad = nullptr;
+  // global coarse grid: pattern-only maps (shared), then this handle's A_C
+  // values, dense matrix and inverse, and work vectors
+  int32_t ncv = 0;
+  int32_t *cvar = nullptr;
+  asmx::GatherDev cbox, casrc;
+  int32_t *acp = nullptr, *acc = nullptr;
+  double *acv = nullptr, *cM = nullptr, *cMinv = nullptr, *cfcol = nullptr, *crc = nullptr, *cxc = nullptr;
+  double *crtmp = nullptr, *cr2 = nullptr, *cpart = nullptr;
+  int *cbad = nullptr;
   asm_precond_stats stats{};
 };
 

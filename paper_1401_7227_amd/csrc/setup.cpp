@@ -698,6 +698,11 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     const int ax = a / sy, ay = a % sy, bx = b / sy, by = b % sy;
     return std::abs(ax - bx) + std::abs(ay - by) == 1;
   };
+  // Outside cells owned by a face neighbour form the near region, the rest
+  // the far region; the far-field-only variant treats all as far, the
+  // near-field-only variant drops the far region (Section 5).
+  auto near_rel = [&](int a, int b) { return o.field != ASM_FIELD_FAR && face_nbr(a, b); };
+  const bool keep_far = (o.field != ASM_FIELD_NEAR);
 
   const Csr G = undirected(A);
 
@@ -787,7 +792,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
       tmp.assign(sig.idx.begin() + sig.ptr[c], sig.idx.begin() + sig.ptr[c + 1]);
       tn.clear();
       tf.clear();
-      for (int s : tmp) (face_nbr(s, owner[c]) ? tn : tf).push_back(s);
+      for (int s : tmp) (near_rel(s, owner[c]) ? tn : tf).push_back(s);
       sfull[c] = sig_id(tmp);
       snear[c] = sig_id(tn);
       sfar[c] = sig_id(tf);
@@ -931,12 +936,12 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         // elsewhere, each restricted to atoms not fine for s
         for (int o2 = 0; o2 < nsub; ++o2) {
           if (o2 == s) continue;
-          if (face_nbr(o2, s)) {
+          if (near_rel(o2, s)) {
             for (int t = at.owner_na.ptr[o2]; t < at.owner_na.ptr[o2 + 1]; ++t) {
               const int a = at.owner_na.idx[t];
               if (!contains(at.na_sig, a, s)) near_boxes.push_back(at.na_box[a]);
             }
-          } else {
+          } else if (keep_far) {
             for (int t = at.owner_fa.ptr[o2]; t < at.owner_fa.ptr[o2 + 1]; ++t) {
               const int a = at.owner_fa.idx[t];
               if (!contains(at.fa_sig, a, s)) far_boxes.push_back(at.fa_box[a]);
@@ -960,7 +965,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         if (loc[c] >= 0) return loc[c];
         if (!two) return -1;
         const int o2 = owner[c];
-        return face_nbr(o2, s) ? nvar[at.nbox[c]] : fvar[at.fbox[c]];
+        return near_rel(o2, s) ? nvar[at.nbox[c]] : keep_far ? fvar[at.fbox[c]] : -1;
       };
       trip.clear();
       // (a) fine rows: every block of the cell's row
@@ -978,18 +983,19 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
           for (int t = T.ptr[d]; t < T.ptr[d + 1]; ++t) {
             const int a = T.row[t];
             if (is_fine(a)) continue;
-            trip.push_back({label(a), u, T.ent[t]});
+            const int32_t la = label(a);
+            if (la >= 0) trip.push_back({la, u, T.ent[t]});
           }
         }
         // (c) coarse against coarse, from the shared lumped atom matrices
-        auto near_ok = [&](int na) { return face_nbr(at.na_owner[na], s) && !contains(at.na_sig, na, s); };
+        auto near_ok = [&](int na) { return near_rel(at.na_owner[na], s) && !contains(at.na_sig, na, s); };
         auto far_ok = [&](int fa) {
           const int o2 = at.fa_owner[fa];
-          return o2 != s && !face_nbr(o2, s) && !contains(at.fa_sig, fa, s);
+          return keep_far && o2 != s && !near_rel(o2, s) && !contains(at.fa_sig, fa, s);
         };
         for (int o2 = 0; o2 < nsub; ++o2) {
           if (o2 == s) continue;
-          if (face_nbr(o2, s)) {
+          if (near_rel(o2, s)) {
             for (int t = at.owner_na.ptr[o2]; t < at.owner_na.ptr[o2 + 1]; ++t) {
               const int a = at.owner_na.idx[t];
               if (!near_ok(a)) continue;
@@ -1235,6 +1241,36 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
       for (int u = 0; u < L[s].nfine; ++u) P.cidx[fill[L[s].cells[u]]++] = (int32_t)(o_ext[s] + L[s].bpos[u]);
   }
   P.any_fp32 = fp32;
+  // ---------------------------------------------------------------- global coarse grid
+  if (o.coarse != ASM_COARSE_NONE) {
+    const int *cb = o.coarse_box;
+    const int cby = (ny + cb[1] - 1) / cb[1], cbz = (nz + cb[2] - 1) / cb[2];
+    const int64_t ncv = (int64_t)((nx + cb[0] - 1) / cb[0]) * cby * cbz;  // clipped boxes are never empty
+    if (3 * ncv > ASM_COARSE_MAX_UNKNOWNS) {
+      err = "global coarse grid has " + std::to_string(3 * ncv) + " unknowns, more than " +
+            std::to_string(ASM_COARSE_MAX_UNKNOWNS);
+      return ASM_ERR_INVALID;
+    }
+    P.ncv = (int32_t)ncv;
+    P.cvar.resize(N);
+    for (int c = 0; c < N; ++c) {
+      const int ix = c / (ny * nz), iy = (c / nz) % ny, iz = c % nz;
+      P.cvar[c] = ((ix / cb[0]) * cby + iy / cb[1]) * cbz + iz / cb[2];
+    }
+    P.cbox_cells.ptr.assign(ncv + 1, 0);
+    for (int c = 0; c < N; ++c) P.cbox_cells.ptr[P.cvar[c] + 1]++;
+    for (int64_t k = 0; k < ncv; ++k) P.cbox_cells.ptr[k + 1] += P.cbox_cells.ptr[k];
+    P.cbox_cells.idx.resize(N);
+    {
+      std::vector<int32_t> cur(P.cbox_cells.ptr.begin(), P.cbox_cells.ptr.end() - 1);
+      for (int c = 0; c < N; ++c) P.cbox_cells.idx[cur[P.cvar[c]]++] = c;
+    }
+    std::vector<std::array<int32_t, 3>> t;
+    t.reserve(A.nnzb);
+    for (int a = 0; a < N; ++a)
+      for (int e = A.rp[a]; e < A.rp[a + 1]; ++e) t.push_back({P.cvar[a], P.cvar[A.ci[e]], e});
+    triples_to_csr(t, P.ncv, P.acp, P.acc, P.ac_src);
+  }
   return ASM_OK;
 }
 

@@ -58,6 +58,14 @@ struct PlanHost {
   GatherList c1, c2, c3;
   // Additive combine: per cell the backward positions holding its value.
   std::vector<int32_t> cptr, cidx;
+  // Global coarse grid (when a coarse correction is asked for): coarse
+  // variable (box) of each cell, the cells of each box, and the block CSR
+  // of A_C = R_C A R_C^T with the A blocks summed into each entry.
+  int32_t ncv = 0;
+  std::vector<int32_t> cvar;
+  GatherList cbox_cells;
+  std::vector<int32_t> acp, acc;
+  GatherList ac_src;
   bool any_fp32 = false;
 };
 
