@@ -60,6 +60,10 @@ enum { ASM_FIELD_NEAR_FAR = 0, ASM_FIELD_NEAR = 1, ASM_FIELD_FAR = 2 };
 /* Global coarse-grid correction (Section 3). */
 enum { ASM_COARSE_NONE = 0, ASM_COARSE_ADDITIVE = 1, ASM_COARSE_TWO_STAGE = 2 };
 #define ASM_COARSE_MAX_UNKNOWNS 8192
+/* Local solver: block ILU(0) (Section 2, Section 6) or exact (Section 5:
+ * Gaussian elimination; here a dense inverse of each A_i). */
+enum { ASM_LOCAL_ILU0 = 0, ASM_LOCAL_EXACT = 1 };
+#define ASM_EXACT_MAX_UNKNOWNS 6144
 
 /*
  * asm_create_system - take a device copy of A (Section 2's A = -J).
@@ -115,8 +119,15 @@ asm_status asm_spmv(asm_system sys, const double *x_dev, double *y_dev, hipStrea
  *             TWO_STAGE: applied to the residual the Schwarz part leaves,
  *             B^-1 = B_AS^-1 + B_C^-1 (I - A B_AS^-1) (eq. (3.8)).  Not
  *             available in asm_solve_batch or the server (INVALID).
- * Local solver: block ILU(0) with 3x3 pivots inverted directly (Section 2;
- * Section 6 names ILU as the approximate local solve).
+ *   local     ILU0 (default), or EXACT: every A_i is inverted densely on
+ *             the device (Gauss-Jordan with partial pivoting, FP64 whatever
+ *             the precision option) and applied as a dense product; for
+ *             small subdomains only: 3 x rows of A_i at most
+ *             ASM_EXACT_MAX_UNKNOWNS and all inverses together at most
+ *             8 GiB (INVALID beyond).  Not available in asm_solve_batch or
+ *             the server (INVALID).
+ * Default local solver: block ILU(0) with 3x3 pivots inverted directly
+ * (Section 2; Section 6 names ILU as the approximate local solve).
  */
 typedef struct {
   int32_t kind;
@@ -129,6 +140,7 @@ typedef struct {
   int32_t field;
   int32_t coarse;
   int32_t coarse_box[3];
+  int32_t local;
 } asm_precond_opts;
 
 /* Builds the partition, overlap, coarse maps, extended patterns and level

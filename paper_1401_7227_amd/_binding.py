@@ -23,6 +23,7 @@ ADDITIVE, RESTRICTED = 0, 1
 FP64, FP32 = 0, 1
 FIELD_NEAR_FAR, FIELD_NEAR, FIELD_FAR = 0, 1, 2
 COARSE_NONE, COARSE_ADDITIVE, COARSE_TWO_STAGE = 0, 1, 2
+LOCAL_ILU0, LOCAL_EXACT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
                 -3: "ERR_SINGULAR_PIVOT", -4: "ERR_NONFINITE", -5: "ERR_HIP"}
@@ -48,7 +49,7 @@ class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("combine", C.c_int32), ("sx", C.c_int32),
                 ("sy", C.c_int32), ("overlap", C.c_int32), ("near_box", C.c_int32 * 3),
                 ("far_box", C.c_int32 * 3), ("precision", C.c_int32), ("field", C.c_int32),
-                ("coarse", C.c_int32), ("coarse_box", C.c_int32 * 3)]
+                ("coarse", C.c_int32), ("coarse_box", C.c_int32 * 3), ("local", C.c_int32)]
 
 
 class PrecondStats(C.Structure):
@@ -243,7 +244,7 @@ class Precond:
 
     def __init__(self, system: System, kind=KIND_CLASSICAL, combine=RESTRICTED, sx=1, sy=1,
                  overlap=1, near=(2, 2, 2), far=(4, 4, 4), precision=FP64, field=FIELD_NEAR_FAR,
-                 coarse=COARSE_NONE, cbox=(4, 4, 4), *, _clone_of=None):
+                 coarse=COARSE_NONE, cbox=(4, 4, 4), local=LOCAL_ILU0, *, _clone_of=None):
         L = load()
         self.system = system
         h = C.c_void_p()
@@ -253,7 +254,7 @@ class Precond:
             self.kind = _clone_of.kind
             return
         o = PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near),
-                        (C.c_int32 * 3)(*far), precision, field, coarse, (C.c_int32 * 3)(*cbox))
+                        (C.c_int32 * 3)(*far), precision, field, coarse, (C.c_int32 * 3)(*cbox), local)
         _check(L.asm_setup_precond(system.handle, C.byref(o), _stream(), C.byref(h)))
         self._h = h
         self.kind = kind
@@ -363,9 +364,9 @@ def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_i
 
 def precond_opts(kind=KIND_TWO_LEVEL, combine=RESTRICTED, sx=1, sy=1, overlap=1, near=(2, 2, 2),
                  far=(4, 4, 4), precision=FP64, field=FIELD_NEAR_FAR, coarse=COARSE_NONE,
-                 cbox=(4, 4, 4)) -> PrecondOpts:
+                 cbox=(4, 4, 4), local=LOCAL_ILU0) -> PrecondOpts:
     return PrecondOpts(kind, combine, sx, sy, overlap, (C.c_int32 * 3)(*near), (C.c_int32 * 3)(*far),
-                       precision, field, coarse, (C.c_int32 * 3)(*cbox))
+                       precision, field, coarse, (C.c_int32 * 3)(*cbox), local)
 
 
 class Server:

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libasm_mi355x.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "coarse.hip", "setup.cpp", "capi.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "dense.hip", "setup.cpp", "capi.cpp", "batch.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}"]
 # Device code: gfx950 only; packed-FP32 instructions disabled (the compiler

@@ -738,8 +738,8 @@ asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_p
   for (int i = 0; i < count; ++i) {
     if (!systems[i] || !preconds[i] || !b[i] || !x[i]) return fail(ASM_ERR_INVALID, "NULL system, preconditioner or vector");
     if (preconds[i]->sys != systems[i]) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-    if (preconds[i]->opts.coarse != ASM_COARSE_NONE)
-      return fail(ASM_ERR_INVALID, "a global coarse correction is not available in batched solves");
+    if (preconds[i]->opts.coarse != ASM_COARSE_NONE || preconds[i]->opts.local != ASM_LOCAL_ILU0)
+      return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in batched solves");
     for (int k = 0; k < i; ++k)
       if (systems[k] == systems[i]) return fail(ASM_ERR_INVALID, "a system appears twice in the batch");
   }
@@ -793,8 +793,8 @@ asm_status asm_server_submit(asm_server srv, const asm_request *req) {
   for (int k = 0; k < req->nsolves; ++k)
     if (!req->vals_dev[k] || !req->b_dev[k] || !req->x_dev[k]) return fail(ASM_ERR_INVALID, "NULL values or vector");
   if (req->precond.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "requests need a Schwarz preconditioner");
-  if (req->precond.coarse != ASM_COARSE_NONE)
-    return fail(ASM_ERR_INVALID, "a global coarse correction is not available in served solves");
+  if (req->precond.coarse != ASM_COARSE_NONE || req->precond.local != ASM_LOCAL_ILU0)
+    return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in served solves");
   auto r = new (std::nothrow) Request();
   if (!r) return fail(ASM_ERR_OOM, "host allocation failed");
   r->d = *req;

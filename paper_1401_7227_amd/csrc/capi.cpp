@@ -105,6 +105,18 @@ hipError_t alloc_coarse_own(asm_precond pc) {
   return hipSuccess;
 }
 
+// This handle's dense inverses of the exact local solves.
+hipError_t alloc_exact_own(asm_precond pc, int64_t dense_elems, int64_t total_ext) {
+  DevMem &O = pc->mem;
+  hipError_t e;
+  if ((e = O.alloc(&pc->xd.M, (size_t)dense_elems)) != hipSuccess ||
+      (e = O.alloc(&pc->xd.Minv, (size_t)dense_elems)) != hipSuccess ||
+      (e = O.alloc(&pc->xd.fcol, 3 * (size_t)total_ext)) != hipSuccess ||
+      (e = O.alloc(&pc->xd.bad, (size_t)pc->xd.nsub)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
 // Assembly (lumped matrices, A_i values) and factorisation on the device.
 asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   asm_system S = pc->sys;
@@ -118,9 +130,22 @@ asm_status numeric_setup(asm_precond pc, hipStream_t s) {
   ASM_HIP(hipMemcpyAsync(pc->dp.fact, pc->aval, (size_t)P.total_entries * 9 * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
   ASM_HIP(hipMemsetAsync(pc->bad, 0xff, sizeof(unsigned long long), s));
-  ASM_HIP(launch_ilu_factor(pc->dp, pc->bad, s));
-  ASM_HIP(launch_relayout((int)pc->rl_n, pc->rl_src, pc->rl_base, pc->rl_stride, pc->rl_to32, pc->dp.fact,
-                          static_cast<double *>(pc->recbuf), static_cast<float *>(pc->recbuf), s));
+  if (pc->opts.local == ASM_LOCAL_EXACT) {
+    // dense inverse of every A_i (no incomplete factors are computed)
+    ASM_HIP(launch_local_dense_init(pc->xd, pc->dp.arp, pc->dp.aci, pc->aval, pc->xmaxn3, s));
+    ASM_HIP(launch_local_gauss_jordan(pc->xd, pc->xmaxn3, s));
+    std::vector<int> xb(pc->xd.nsub);
+    ASM_HIP(hipMemcpyAsync(xb.data(), pc->xd.bad, xb.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    for (int sd = 0; sd < pc->xd.nsub; ++sd)
+      if (xb[sd] >= 0)
+        return fail(ASM_ERR_SINGULAR_PIVOT, "singular local matrix A_i of subdomain " + std::to_string(sd) +
+                                                " (dense elimination, column " + std::to_string(xb[sd]) + ")");
+  } else {
+    ASM_HIP(launch_ilu_factor(pc->dp, pc->bad, s));
+    ASM_HIP(launch_relayout((int)pc->rl_n, pc->rl_src, pc->rl_base, pc->rl_stride, pc->rl_to32, pc->dp.fact,
+                            static_cast<double *>(pc->recbuf), static_cast<float *>(pc->recbuf), s));
+  }
   if (pc->opts.coarse != ASM_COARSE_NONE) {
     // A_C = R_C A R_C^T (box sums of A's blocks), inverted densely
     ASM_HIP(launch_gather_sum9(pc->casrc.n, pc->casrc.ptr, pc->casrc.idx, S->vals, (int32_t)S->pat.nnzb, nullptr,
@@ -170,7 +195,10 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   pf.span(ASM_PHASE_LUMP, t0, s);
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(ASM_PHASE_ILU_APPLY, s);
-  ASM_HIP(launch_ilu_apply(pc->ap, z, s));
+  if (pc->opts.local == ASM_LOCAL_EXACT)
+    ASM_HIP(launch_local_dense_apply(pc->xd, (int64_t)pc->plan->total_pos, pc->ap.rs, restricted, z, pc->ap.yx, s));
+  else
+    ASM_HIP(launch_ilu_apply(pc->ap, z, s));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
     const size_t t2 = pf.mark(ASM_PHASE_COMBINE, s);
@@ -226,6 +254,7 @@ asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o) {
   if (o->precision != ASM_PREC_FP64 && o->precision != ASM_PREC_FP32) return fail(ASM_ERR_INVALID, "bad precision");
   if (o->field < ASM_FIELD_NEAR_FAR || o->field > ASM_FIELD_FAR) return fail(ASM_ERR_INVALID, "bad field");
   if (o->coarse < ASM_COARSE_NONE || o->coarse > ASM_COARSE_TWO_STAGE) return fail(ASM_ERR_INVALID, "bad coarse");
+  if (o->local != ASM_LOCAL_ILU0 && o->local != ASM_LOCAL_EXACT) return fail(ASM_ERR_INVALID, "bad local solver");
   if (o->coarse != ASM_COARSE_NONE) {
     if (o->kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "a coarse correction needs a Schwarz preconditioner");
     for (int d = 0; d < 3; ++d)
@@ -339,6 +368,21 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
     if ((e = alloc_coarse_own(pc)) != hipSuccess)
       return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   }
+  if (o->local == ASM_LOCAL_EXACT) {
+    DenseLocal &x = pc->xd;
+    x.nsub = P.nsub;
+    x.sub = dsub;
+    int64_t *doff;
+    int32_t *lpos, *psub, *pout, *pbpos;
+    if ((e = M.upload(&doff, P.xdoff, s)) != hipSuccess || (e = M.upload(&lpos, P.xlpos, s)) != hipSuccess ||
+        (e = M.upload(&psub, P.xpsub, s)) != hipSuccess || (e = M.upload(&pout, P.xout, s)) != hipSuccess ||
+        (e = M.upload(&pbpos, P.xbpos, s)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    x.doff = doff; x.lpos = lpos; x.psub = psub; x.pout = pout; x.pbpos = pbpos;
+    pc->xmaxn3 = P.xmaxn3;
+    if ((e = alloc_exact_own(pc, P.xdoff[P.nsub], P.total_ext)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
   // keep only what export and error messages need on the host
   P.rl = RelayoutMap{};
@@ -353,6 +397,10 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   P.cvar = std::vector<int32_t>();
   P.cbox_cells = GatherList{};
   P.ac_src = GatherList{};
+  P.xlpos = std::vector<int32_t>();
+  P.xpsub = std::vector<int32_t>();
+  P.xout = std::vector<int32_t>();
+  P.xbpos = std::vector<int32_t>();
   st = numeric_setup(pc, s);
   if (st != ASM_OK) return cleanup(st);
   pc->stats.nsub = P.nsub;
@@ -531,6 +579,12 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
     pc->acp = src->acp;
     pc->acc = src->acc;
     if ((e = alloc_coarse_own(pc)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+  }
+  if (pc->opts.local == ASM_LOCAL_EXACT) {
+    pc->xd = src->xd;
+    pc->xmaxn3 = src->xmaxn3;
+    if ((e = alloc_exact_own(pc, P.xdoff.back(), P.total_ext)) != hipSuccess)
       return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   }
   pc->stats.device_bytes = (int64_t)(pc->smem->bytes + O.bytes);

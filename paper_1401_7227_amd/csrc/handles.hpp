@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/asm.h"
-#include "coarse.hpp"
+#include "dense.hpp"
 #include "kernels.hpp"
 #include "setup.hpp"
 
@@ -219,6 +219,9 @@ struct asm_precond_s {
   double *acv = nullptr, *cM = nullptr, *cMinv = nullptr, *cfcol = nullptr, *crc = nullptr, *cxc = nullptr;
   double *crtmp = nullptr, *cr2 = nullptr, *cpart = nullptr;
   int *cbad = nullptr;
+  // exact local solves: dense inverses of every A_i
+  asmx::DenseLocal xd{};
+  int32_t xmaxn3 = 0;
   asm_precond_stats stats{};
 };
 

@@ -1225,6 +1225,38 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     // free the local copies early
     std::vector<uint8_t>().swap(S.rec);
   }
+  if (o.local == ASM_LOCAL_EXACT) {
+    P.xdoff.assign(nsub + 1, 0);
+    for (int s = 0; s < nsub; ++s) {
+      const int64_t n3 = 3 * (int64_t)L[s].n;
+      if (n3 > ASM_EXACT_MAX_UNKNOWNS) {
+        err = "exact local solve of subdomain " + std::to_string(s) + " has " + std::to_string(n3) +
+              " unknowns, more than " + std::to_string(ASM_EXACT_MAX_UNKNOWNS);
+        return ASM_ERR_INVALID;
+      }
+      P.xmaxn3 = std::max<int32_t>(P.xmaxn3, (int32_t)n3);
+      P.xdoff[s + 1] = P.xdoff[s] + n3 * n3;
+    }
+    if (P.xdoff[nsub] * 8 > ((int64_t)8 << 30)) {
+      err = "exact local solves need more than 8 GiB of dense inverses";
+      return ASM_ERR_INVALID;
+    }
+    P.xlpos.resize(ext);
+    P.xpsub.resize(ext);
+    P.xout.resize(ext);
+    P.xbpos.resize(ext);
+    for (int s = 0; s < nsub; ++s) {
+      const SubLocal &S = L[s];
+      for (int q = 0; q < S.n; ++q) {
+        const int u = S.frow[q];
+        const int64_t g = o_ext[s];
+        P.xlpos[g + u] = q;
+        P.xpsub[g + q] = s;
+        P.xout[g + q] = (u < S.nfine && S.owned[u]) ? S.cells[u] : -1;
+        P.xbpos[g + q] = (int32_t)(g + S.bpos[u]);
+      }
+    }
+  }
   P.arp[ext] = (int32_t)ent;
   P.tptr[ent] = (int32_t)tcount;
   P.asm_src.ptr[ent] = (int32_t)asrc;

@@ -66,6 +66,12 @@ struct PlanHost {
   GatherList cbox_cells;
   std::vector<int32_t> acp, acc;
   GatherList ac_src;
+  // Exact local solves: per extended row its position in the subdomain's
+  // forward order; per position its subdomain, owned output cell (or -1)
+  // and backward position; per subdomain the offset of its dense matrix.
+  std::vector<int32_t> xlpos, xpsub, xout, xbpos;
+  std::vector<int64_t> xdoff;
+  int32_t xmaxn3 = 0;
   bool any_fp32 = false;
 };
 

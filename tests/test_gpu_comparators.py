@@ -139,3 +139,66 @@ def test_coarse_refactor_clone_and_errors(P):
         P.Precond(G2, kind=2, sx=2, field=5)
     with pytest.raises(P.AsmError):  # not in batched solves
         P.solve_batch([G2], [P.Precond(G2, **o)], [s2.b])
+
+
+EXACT_CASES = [
+    ("classical_ras", (13, 11, 7), 5, dict(kind=1, combine=1, sx=3, sy=2, overlap=1)),
+    ("classical_additive_d2", (13, 11, 7), 5, dict(kind=1, combine=0, sx=3, sy=3, overlap=2)),
+    ("two_level", (13, 11, 7), 5, dict(kind=2, combine=1, sx=3, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4))),
+    ("far_only_d0_x_split", (21, 21, 5), 3, dict(kind=2, combine=1, sx=6, sy=1, overlap=0, near=(3, 3, 3),
+                                                  far=(3, 3, 3), field=2)),
+    ("near_only_d0_x_split", (21, 21, 5), 3, dict(kind=2, combine=1, sx=6, sy=1, overlap=0, near=(3, 3, 3),
+                                                   far=(3, 3, 3), field=1)),
+    ("two_stage_exact", (21, 21, 5), 3, dict(kind=1, combine=1, sx=6, sy=1, overlap=0, coarse=2, cbox=(3, 3, 5))),
+]
+
+
+@pytest.mark.parametrize("name,grid,seed,o", EXACT_CASES, ids=[c[0] for c in EXACT_CASES])
+def test_exact_local_solves_match_oracle(P, name, grid, seed, o):
+    """Exact local solves (Section 5): dense inverses of every A_i on the
+    device against the oracle's dense LU; one application and GMRES."""
+    import torch
+    s = gen.generate(*grid, seed=seed)
+    G = P.System.from_generated(s)
+    B = P.Precond(G, local=P.LOCAL_EXACT, **o)
+    Bo = O.Precond(O.Matrix.from_system(s), local=O.LOCAL_EXACT, **o)
+    r = np.random.default_rng(6).standard_normal(s.n)
+    assert rel(to_np(B.apply(torch.from_numpy(r).cuda())), Bo.apply(r)) <= 1e-9
+    ref = O.gmres(O.Matrix.from_system(s), Bo, s.b, restart=30, rtol=1e-6)
+    assert ref.status == O.OK
+    x, info = P.solve(G, B, s.b, restart=30, rtol=1e-6)
+    assert info.status == P.OK and abs(info.iters - ref.iters) <= 1
+    xf, _ = P.solve(G, B, s.b, restart=30, fixed_iters=ref.iters)
+    assert np.linalg.norm(to_np(xf) - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+
+
+def test_exact_unit_boxes_give_the_inverse(P):
+    """Two-level with 1x1x1 boxes and exact local solves: every A_i is a
+    permutation of A, so B^-1 = A^-1 and GMRES takes one step."""
+    s = gen.generate(6, 5, 4, seed=17)
+    G = P.System.from_generated(s)
+    B = P.Precond(G, kind=2, combine=1, sx=2, sy=2, overlap=1, near=(1, 1, 1), far=(1, 1, 1), local=P.LOCAL_EXACT)
+    x, info = P.solve(G, B, s.b, rtol=1e-10)
+    assert info.status == P.OK and info.iters == 1
+    ref = np.linalg.solve(s.dense(), s.b)
+    assert np.linalg.norm(to_np(x) - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_exact_refactor_clone_and_limits(P):
+    import torch
+    s1 = gen.generate(13, 11, 7, seed=5)
+    s2 = gen.redraw_values(s1, seed=6)
+    o = dict(kind=2, combine=1, sx=3, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4), local=P.LOCAL_EXACT)
+    G1, G2 = P.System.from_generated(s1), P.System.from_generated(s2)
+    B1 = P.Precond(G1, **o)
+    r = torch.from_numpy(np.random.default_rng(7).standard_normal(s1.n)).cuda()
+    fresh = to_np(P.Precond(G2, **o).apply(r))
+    assert np.array_equal(to_np(B1.clone(G2).apply(r)), fresh)
+    G1.update_values(s2.vals)
+    B1.refactor()
+    assert np.array_equal(to_np(B1.apply(r)), fresh)
+    with pytest.raises(P.AsmError):  # one subdomain of 2,400 cells: 7,200 unknowns
+        P.Precond(P.System.from_generated(gen.generate(20, 20, 6, seed=1)), kind=1, sx=1, sy=1, overlap=0,
+                  local=P.LOCAL_EXACT)
+    with pytest.raises(P.AsmError):
+        P.solve_batch([G2], [P.Precond(G2, **o)], [s2.b])
