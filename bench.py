@@ -388,6 +388,76 @@ def bench_serve(P, gen, torch, np, args):
     }
 
 
+def bench_comparators(P, gen, torch, np, args):
+    """The comparisons of Section 5 on synthetic stand-ins: iteration counts
+    against the number of subdomains K and the coarsening size C for the
+    near field only, the far field only and both (near boxes C, far boxes
+    2C), the far field against the classical two-level Schwarz method
+    (eq. (3.5)) and the two-stage method (eq. (3.8)) with coarse boxes C,
+    and the far field with one- and two-dimensional splits.  No overlap,
+    exact (dense) or ILU(0) local solves, GMRES(30) to rtol 1e-6."""
+    def run(s, G, b, **o):
+        try:
+            B = P.Precond(G, **o)
+        except P.AsmError as e:
+            return {"error": str(e).split(":")[0]}
+        st = B.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = P.solve(G, B, b, restart=RESTART, rtol=1e-6, max_iters=3000)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        return {"iters": info.iters if info.status == P.OK else None, "ms": round(ms, 2),
+                "rows_per_sub": round(st["ext_rows"] / st["nsub"], 1),
+                "blocks_per_sub": round(st["factor_blocks"] / st["nsub"], 1)}
+
+    out = {"metric": "GMRES iterations to rtol 1e-6 for the preconditioners compared in Section 5",
+           "unit": "iterations", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded generator, no external dataset)"}
+    # Figs. 5 and 6: 21x21x5 (the grid size of the ORSREG1 benchmark), x split
+    s = gen.generate(21, 21, 5, seed=1)
+    G = P.System.from_generated(s)
+    b = torch.from_numpy(s.b).cuda()
+    fields = {"near": P.FIELD_NEAR, "far": P.FIELD_FAR, "near_far": P.FIELD_NEAR_FAR}
+    fig5, fig6 = [], []
+    for local_name, local in [("exact", P.LOCAL_EXACT), ("ilu0", P.LOCAL_ILU0)]:
+        for K in (2, 3, 5, 7):
+            for C in (2, 3, 4, 5):
+                row = {"local": local_name, "K": K, "C": C}
+                for name, f in fields.items():
+                    row[name] = run(s, G, b, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, sx=K, sy=1, overlap=0,
+                                    near=(C, C, C), far=(2 * C, 2 * C, 2 * C) if f == P.FIELD_NEAR_FAR else (C, C, C),
+                                    field=f, local=local)
+                fig5.append(row)
+                row6 = {"local": local_name, "K": K, "C": C, "far": row["far"]}
+                row6["two_level_3_5"] = run(s, G, b, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, sx=K, sy=1,
+                                            overlap=0, coarse=P.COARSE_ADDITIVE, cbox=(C, C, C), local=local)
+                row6["two_stage_3_8"] = run(s, G, b, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, sx=K, sy=1,
+                                            overlap=0, coarse=P.COARSE_TWO_STAGE, cbox=(C, C, C), local=local)
+                fig6.append(row6)
+            row0 = run(s, G, b, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, sx=K, sy=1, overlap=0, local=local)
+            fig5.append({"local": local_name, "K": K, "C": None, "classical_ras": row0})
+            print(f"[comparators] 21x21x5 {local_name} K={K} done", file=sys.stderr, flush=True)
+    out["fig5_near_far_21x21x5"] = fig5
+    out["fig6_coarse_21x21x5"] = fig6
+    # Fig. 9: 30x30x9, far field, 1-D (K x 1) against 2-D splits
+    s = gen.generate(30, 30, 9, seed=2)
+    G = P.System.from_generated(s)
+    b = torch.from_numpy(s.b).cuda()
+    fig9 = []
+    for K, split2 in ((4, (2, 2)), (9, (3, 3)), (16, (4, 4))):
+        for C in (2, 3, 5):
+            for local_name, local in [("exact", P.LOCAL_EXACT), ("ilu0", P.LOCAL_ILU0)]:
+                common = dict(kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, overlap=0, near=(C, C, C), far=(C, C, C),
+                              field=P.FIELD_FAR, local=local)
+                fig9.append({"local": local_name, "K": K, "C": C,
+                             "split_1d": run(s, G, b, sx=K, sy=1, **common),
+                             "split_2d": run(s, G, b, sx=split2[0], sy=split2[1], **common)})
+        print(f"[comparators] 30x30x9 K={K} done", file=sys.stderr, flush=True)
+    out["fig9_splits_30x30x9"] = fig9
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,11 +466,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--workload", choices=["solve1m", "batch256", "serve"], default="solve1m",
+    ap.add_argument("--workload", choices=["solve1m", "batch256", "serve", "comparators"], default="solve1m",
                     help="solve1m: the 1M-cell solve (default); batch256: 256 independent systems of "
                          "2k-295k cells solved as one batch, against solving them one after another; "
                          "serve: a Poisson request trace against the request server, and a prefix of it "
-                         "against one-at-a-time FP64 solves")
+                         "against one-at-a-time FP64 solves; comparators: the iteration-count studies of "
+                         "the paper's Section 5 on synthetic systems")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-compare", type=int, default=100, help="trace prefix for the FIFO comparison")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -427,6 +498,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(P, gen, torch, np, args)))
+        return
+    if args.workload == "comparators":
+        print(json.dumps(bench_comparators(P, gen, torch, np, args)))
         return
     if args.counter_workload == "copy":
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
