@@ -597,6 +597,13 @@ def main():
         variants["classical_ras_fp64"] = {"ms_per_solve": round(msc, 3), "iters": infoc.iters,
                                           "rel_res_true": infoc.rel_res_true}
         del Bc
+        # the two-stage global coarse-grid comparator (eq. (3.8)), coarse boxes 16^3
+        Bt = P.Precond(G, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, coarse=P.COARSE_TWO_STAGE,
+                       cbox=(16, 16, 16), **SPLIT)
+        mst, infot, _, _ = timed_solves(P, torch, G, Bt, b, max(1, args.steps // 2), 1, profile=None)
+        variants["classical_ras_two_stage_coarse16_fp64"] = {"ms_per_solve": round(mst, 3), "iters": infot.iters,
+                                                             "rel_res_true": infot.rel_res_true}
+        del Bt
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, info.iters, args.cpu_steps)
