@@ -704,13 +704,17 @@ __device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__res
 __device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, double *__restrict__ z, SweepLds &L) {
   const SubDesc sd = p.sub[sub];
   const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
-  const int nf = sd.rf1 - sd.rf0, nb = sd.rb1 - sd.rb0;
+  // the step counts bound loops of barriers: wave-uniform values, held in
+  // scalar registers whatever address space the plan was read through, so
+  // that the compiler treats the loops as uniform control flow
+  const int rf0 = __builtin_amdgcn_readfirstlane(sd.rf0), rb0 = __builtin_amdgcn_readfirstlane(sd.rb0);
+  const int nf = __builtin_amdgcn_readfirstlane(sd.rf1) - rf0, nb = __builtin_amdgcn_readfirstlane(sd.rb1) - rb0;
   if (threadIdx.x < kConsumerThreads) {
     consumer_sweep<true>(nf, L, p.yx, z);
     consumer_sweep<false>(nb, L, p.yx, z);
   } else {
-    producer_sweep(p.fstep + sd.rf0, nf, rec, p.rs, L);
-    producer_sweep(p.bstep + sd.rb0, nb, rec, p.yx, L);
+    producer_sweep(p.fstep + rf0, nf, rec, p.rs, L);
+    producer_sweep(p.bstep + rb0, nb, rec, p.yx, L);
   }
 }
 
