@@ -204,10 +204,8 @@ class BatchEngine {
       ASM_HIP(launch_batch_spmv(tabd_, seg[kBkSpmv], false, s_));
       ASM_HIP(launch_batch_multidot(tabd_, seg[kBkRed], j + 1, s_));
       ASM_HIP(launch_batch_reduce(tabd_, seg[kBkOne], j + 2, true, 0, s_));
-      ASM_HIP(launch_batch_finalize_dots(tabd_, seg[kBkOne], j, ld_, s_));
       ASM_HIP(launch_batch_update(tabd_, seg[kBkRed], j + 1, ld_, s_));
-      ASM_HIP(launch_batch_reduce(tabd_, seg[kBkOne], 1, false, 0, s_));
-      ASM_HIP(launch_batch_finalize_norm(tabd_, seg[kBkOne], j, ld_, kPubStride, s_));
+      ASM_HIP(launch_batch_norm_finalize(tabd_, seg[kBkOne], j, ld_, kPubStride, 0, s_));
       ASM_HIP(hipEventRecord(step_ev_[j], s_));
       ASM_HIP(hipEventRecord(ring_ev_[sl], s_));
       return ASM_OK;
@@ -307,7 +305,7 @@ class BatchEngine {
     T.n = 3 * (int64_t)S->pat.N;
     T.ldu = W.ldu;
     T.U = W.U; T.w = W.w; T.z = W.z; T.t = W.t;
-    T.partial = W.partial; T.dvec = W.dvec; T.H = W.H; T.scale = W.scale; T.coef = W.coef; T.misc = W.misc;
+    T.partial = W.partial; T.dvec = W.dvec; T.H = W.H; T.scale = W.scale; T.misc = W.misc;
     T.pub = pin_dev_ + region_ * i + 1;
     T.coefh = pin_dev_ + region_ * i + 1 + (size_t)m_ * kPubStride;
     T.b = E.b;
@@ -321,8 +319,10 @@ class BatchEngine {
       T.npos = (int32_t)pc->plan->total_pos;
       T.nsub = pc->ap.nsub;
       T.ap = pc->ap;
-      T.c1n = pc->c1.n; T.c1lanes = pc->c1.lanes; T.c1ptr = pc->c1.ptr; T.c1idx = pc->c1.idx;
-      T.c2n = pc->c2.n; T.c2lanes = pc->c2.lanes; T.c2ptr = pc->c2.ptr; T.c2idx = pc->c2.idx;
+      T.c1n = pc->c1.n; T.c1n1 = pc->c1.n1; T.c1lanes = pc->c1.lanes; T.c1lanes2 = pc->c1.lanes2;
+      T.c1ptr = pc->c1.ptr; T.c1idx = pc->c1.idx;
+      T.c2n = pc->c2.n; T.c2n1 = pc->c2.n1; T.c2lanes = pc->c2.lanes; T.c2lanes2 = pc->c2.lanes2;
+      T.c2ptr = pc->c2.ptr; T.c2idx = pc->c2.idx;
       T.PA = pc->PA; T.PNF = pc->PNF;
       T.cptr = pc->cptr; T.cidx = pc->cidx;
     }
@@ -371,8 +371,7 @@ class BatchEngine {
     asm_status st = segs_for(act, seg, &sl);
     if (st != ASM_OK) return st;
     ASM_HIP(launch_batch_spmv(tabd_, seg[kBkSpmv], true, s_));
-    ASM_HIP(launch_batch_reduce(tabd_, seg[kBkOne], 1, false, 1, s_));
-    ASM_HIP(launch_batch_finalize_norm(tabd_, seg[kBkOne], -1, ld_, kPubStride, s_));
+    ASM_HIP(launch_batch_norm_finalize(tabd_, seg[kBkOne], -1, ld_, kPubStride, 1, s_));
     ASM_HIP(hipEventRecord(ring_ev_[sl], s_));
     ASM_HIP(hipStreamSynchronize(s_));
     for (int i : act) ent_[i].beta = pin_[region_ * i];

@@ -188,8 +188,10 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
   }
   const size_t t0 = pf.mark(ASM_PHASE_LUMP, s);
   if (pc->c1.n > 0) {
-    ASM_HIP(launch_gather_sum3(pc->c1.n, pc->c1.lanes, pc->c1.ptr, pc->c1.idx, r, scale, pc->PA, s));
-    ASM_HIP(launch_gather_sum3(pc->c2.n, pc->c2.lanes, pc->c2.ptr, pc->c2.idx, pc->PA, nullptr, pc->PNF, s));
+    ASM_HIP(launch_gather_sum3(pc->c1.n1, pc->c1.lanes, pc->c1.n, pc->c1.lanes2, pc->c1.ptr, pc->c1.idx, r, scale,
+                               pc->PA, s));
+    ASM_HIP(launch_gather_sum3(pc->c2.n1, pc->c2.lanes, pc->c2.n, pc->c2.lanes2, pc->c2.ptr, pc->c2.idx, pc->PA,
+                               nullptr, pc->PNF, s));
   }
   ASM_HIP(launch_gather_rhs((int)pc->plan->total_pos, pc->ap, r, scale, s));
   pf.span(ASM_PHASE_LUMP, t0, s);
@@ -220,7 +222,8 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
       rr = pc->cr2;
       sc = nullptr;
     }
-    ASM_HIP(launch_gather_sum3(pc->ncv, pc->cbox.lanes, pc->cbox.ptr, pc->cbox.idx, rr, sc, pc->crc, s));
+    ASM_HIP(launch_gather_sum3(pc->cbox.n1, pc->cbox.lanes, pc->cbox.n, pc->cbox.lanes2, pc->cbox.ptr, pc->cbox.idx,
+                               rr, sc, pc->crc, s));
     ASM_HIP(launch_dense_gemv(3 * pc->ncv, pc->cMinv, pc->crc, pc->cxc, s));
     ASM_HIP(launch_prolong_add(S->pat.N, pc->cvar, pc->cxc, z, s));
     pf.span(ASM_PHASE_OTHER, t3, s);
@@ -683,8 +686,7 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
     ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
     pf.span(ASM_PHASE_RESIDUAL, t0, s);
     const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_reduce_cols(nbr, 1, W.partial, W.misc + 2, s));
-    ASM_HIP(launch_finalize_norm(0, W.misc + 2, W.misc + 1, W.scale, nullptr, nullptr, s));
+    ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
     pf.span(ASM_PHASE_OTHER, t1, s);
     ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
@@ -716,15 +718,14 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
     pf.span(ASM_PHASE_DOTS, t0, s);
     t0 = pf.mark(ASM_PHASE_OTHER, s);
     ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
-    ASM_HIP(launch_finalize_dots(j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.coef, W.misc, s));
     pf.span(ASM_PHASE_OTHER, t0, s);
     int nbu = 0;
     t0 = pf.mark(ASM_PHASE_UPDATE, s);
-    ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.coef, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial, &nbu, s));
+    ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
+                          &nbu, s));
     pf.span(ASM_PHASE_UPDATE, t0, s);
     t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_reduce_cols(nbu, 1, W.partial, W.misc + 2, s));
-    ASM_HIP(launch_finalize_norm(j + 1, W.misc + 2, W.H + (size_t)j * ld, W.scale + j + 1, W.misc,
+    ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
                                  W.pinned_dev + kPubBase + (size_t)j * kPubStride, s));
     pf.span(ASM_PHASE_OTHER, t0, s);
     ASM_HIP(hipEventRecord(W.step_done[j], s));

@@ -65,15 +65,27 @@ struct DevMem {
 
 struct GatherDev {
   int32_t n = 0;
-  int32_t lanes = 1;  // threads per destination (about the mean fan-in)
+  int32_t n1 = 0;      // destinations of the first segment
+  int32_t lanes = 1;   // threads per destination in [0, n1) (about the mean fan-in)
+  int32_t lanes2 = 1;  // threads per destination in [n1, n)
   int32_t *ptr = nullptr, *idx = nullptr;
 };
 
+// Largest power of two (at most 64) not above the mean fan-in of
+// destinations [d0, d1).
+inline int32_t gather_lanes(const GatherList &h, int32_t d0, int32_t d1) {
+  if (d1 <= d0) return 1;
+  const double mean = (double)(h.ptr[d1] - h.ptr[d0]) / (d1 - d0);
+  int32_t g = 1;
+  while (g < 64 && 2 * g <= mean) g *= 2;
+  return g;
+}
+
 inline hipError_t upload_gather(DevMem &m, GatherDev &g, const GatherList &h, hipStream_t s) {
   g.n = h.size();
-  const double mean = g.n > 0 ? (double)h.idx.size() / g.n : 0.0;
-  g.lanes = 1;
-  while (g.lanes < 16 && g.lanes < mean) g.lanes *= 2;
+  g.n1 = (h.split >= 0 && h.split <= g.n) ? h.split : g.n;
+  g.lanes = gather_lanes(h, 0, g.n1);
+  g.lanes2 = gather_lanes(h, g.n1, g.n);
   hipError_t e = m.upload(&g.ptr, h.ptr, s);
   if (e == hipSuccess) e = m.upload(&g.idx, h.idx, s);
   return e;
@@ -146,7 +158,7 @@ struct Workspace {
   double *H = nullptr;        // (m+1) x m Hessenberg, column-major, ld m+1
   double *scale = nullptr;    // 1/||U_i||
   double *coef = nullptr;
-  double *misc = nullptr;     // [0] wnorm, [1] beta, [2] scratch norm
+  double *misc = nullptr;     // [1] beta, [2] scratch norm
   int *flag = nullptr;
   double *pinned = nullptr;   // host staging: scalars, then one published column per step
   double *pinned_dev = nullptr;  // the same memory as seen by kernels

@@ -188,13 +188,27 @@ __global__ __launch_bounds__(256) void gather_sum9_kernel(int ndst, const int32_
 }
 
 // dst[d] = scale * sum of src over idx[ptr[d] .. ptr[d+1]), 3 doubles per
-// entry; G lanes (1, 2, 4, 8 or 16) share a destination and combine their
-// partial sums in a fixed butterfly order (deterministic).
-__device__ __forceinline__ void gather_sum3_body(int bid, int G, int ndst, const int32_t *__restrict__ ptr,
-                                                 const int32_t *__restrict__ idx, const double *__restrict__ src,
-                                                 const double *__restrict__ scale, double *__restrict__ dst) {
-  const int gid = bid * 256 + (int)threadIdx.x;
-  const int d = gid / G, lane = gid % G;
+// entry.  Destinations [0, n1) take G1 lanes each and [n1, ndst) G2 lanes
+// (powers of two up to 64), so that a segment of a few wide sums does not
+// wait on lanes sized for many narrow ones.  The lanes of a destination
+// combine their partial sums in a fixed butterfly order (deterministic).
+// The first segment's blocks come first, so each block serves one segment.
+__device__ __forceinline__ void gather_sum3_body(int bid, int n1, int G1, int ndst, int G2,
+                                                 const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                 const double *__restrict__ src, const double *__restrict__ scale,
+                                                 double *__restrict__ dst) {
+  const int b1 = (int)(((int64_t)n1 * G1 + 255) / 256);
+  const bool first = bid < b1;
+  const int G = first ? G1 : G2;
+  const int gid = (first ? bid : bid - b1) * 256 + (int)threadIdx.x;
+  const int lg = 31 - __clz(G);
+  int d = gid >> lg;
+  const int lane = gid & (G - 1);
+  if (first) {
+    if (d >= n1) d = ndst;  // idle tail of the first segment
+  } else {
+    d += n1;
+  }
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (d < ndst) {
     for (int t = ptr[d] + lane; t < ptr[d + 1]; t += G) {
@@ -217,12 +231,13 @@ __device__ __forceinline__ void gather_sum3_body(int bid, int G, int ndst, const
   }
 }
 
-__global__ __launch_bounds__(256) void gather_sum3_kernel(int G, int ndst, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void gather_sum3_kernel(int n1, int G1, int ndst, int G2,
+                                                          const int32_t *__restrict__ ptr,
                                                           const int32_t *__restrict__ idx,
                                                           const double *__restrict__ src,
                                                           const double *__restrict__ scale,
                                                           double *__restrict__ dst) {
-  gather_sum3_body(blockIdx.x, G, ndst, ptr, idx, src, scale, dst);
+  gather_sum3_body(blockIdx.x, n1, G1, ndst, G2, ptr, idx, src, scale, dst);
 }
 
 // ---------------------------------------------------------------- 3x3 block math
@@ -604,7 +619,25 @@ struct Producer {
   Stage st[kAhead];
   int len[kAhead];
   int xlast[kAhead];
+  int dq[kAhead];  // descriptors of later steps, one word per lane (desc_load)
 };
+
+// Descriptor of step k by a vector load, lane l holding word l % 4.  The
+// wait for the LDS stores before each barrier also waits for every scalar
+// load in flight, so a descriptor fetched by a scalar load would put its
+// full latency on every step; a vector load issued kAhead steps before use
+// completes together with the record loads issued after it.
+__device__ __forceinline__ int desc_load(const RecStep *__restrict__ steps, int k, int t) {
+  return reinterpret_cast<const int32_t *>(steps + k)[t & 3];
+}
+__device__ __forceinline__ RecStep desc_get(int v) {
+  RecStep d;
+  d.rec = __builtin_amdgcn_readlane(v, 0);
+  d.len = __builtin_amdgcn_readlane(v, 1);
+  d.pos = __builtin_amdgcn_readlane(v, 2);
+  d.nrows = __builtin_amdgcn_readlane(v, 3);
+  return d;
+}
 
 // Streamer: load record k of the sweep and its row inputs (3 doubles per
 // row from src at the step's positions) into a stage.  Loads are clamped
@@ -637,13 +670,14 @@ __device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len,
 template <int K>
 __device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restrict__ steps,
                                           const u32x4 *__restrict__ rec, const double *__restrict__ src,
-                                          SweepLds &L, Producer &P, RecStep &dn, int t) {
+                                          SweepLds &L, Producer &P, int t) {
   // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
-  // the stage for record s+1+kAhead (descriptor loaded last iteration)
+  // the stage for record s+1+kAhead, whose descriptor dq[K] was loaded
+  // kAhead steps ago; dq[K] then fetches the descriptor of s+1+2*kAhead
   prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.xlast[K], t);
-  const RecStep d = dn;
+  const RecStep d = desc_get(P.dq[K]);
+  P.dq[K] = desc_load(steps, min(s + 1 + 2 * kAhead, S - 1), t);
   prod_load(d, rec, src, P.st[K], P.len[K], P.xlast[K], t);
-  dn = steps[min(s + 2 + kAhead, S - 1)];
   __syncthreads();
 }
 
@@ -653,33 +687,36 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   if (S == 0) return;
   const int t = threadIdx.x - kConsumerThreads;
   Producer P;
+  // dq[k] starts with the descriptor of the step s+1+kAhead that iteration
+  // s with (s+1) % kAhead == k loads; issued before the first records
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) P.dq[k] = desc_load(steps, min(kAhead + (k == 0 ? kAhead : k), S - 1), t);
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) prod_load(steps[min(k, S - 1)], rec, src, P.st[k], P.len[k], P.xlast[k], t);
   prod_store(L.buf[0], P.st[0], P.len[0], P.xlast[0], t);
   prod_load(steps[min(kAhead, S - 1)], rec, src, P.st[0], P.len[0], P.xlast[0], t);
-  RecStep dn = steps[min(1 + kAhead, S - 1)];
   __syncthreads();
   // full groups of kAhead steps without conditions (exact wait counts),
   // then the remaining steps in straight-line code
   int s = 0;
   if constexpr (kAhead == 4) {
     for (; s + 4 <= S; s += 4) {
-      prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-      prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
-      prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
-      prod_iter<0>(s + 3, S, steps, rec, src, L, P, dn, t);
+      prod_iter<1>(s, S, steps, rec, src, L, P, t);
+      prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
+      prod_iter<3>(s + 2, S, steps, rec, src, L, P, t);
+      prod_iter<0>(s + 3, S, steps, rec, src, L, P, t);
     }
-    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
-    if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, dn, t);
+    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, t);
+    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
+    if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, t);
   } else {
     for (; s + 3 <= S; s += 3) {
-      prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-      prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
-      prod_iter<0>(s + 2, S, steps, rec, src, L, P, dn, t);
+      prod_iter<1>(s, S, steps, rec, src, L, P, t);
+      prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
+      prod_iter<0>(s + 2, S, steps, rec, src, L, P, t);
     }
-    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, dn, t);
-    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, dn, t);
+    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, t);
+    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
   }
   __syncthreads();  // matches the computing waves' final epilogue barrier
 }
@@ -736,7 +773,10 @@ __global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p
 
 // Forward right-hand sides in sweep order: the restriction R_i r of every
 // subdomain.  Fine rows gather r (times the basis scale); a coarse row sums
-// its near/far atoms' lumped residuals (App. B, eq. (B.2)).
+// its near/far atoms' lumped residuals (App. B, eq. (B.2)).  Sweep order
+// walks a subdomain's level planes, so consecutive positions touch cells far
+// apart in r while a few consecutive blocks share cache lines: the launches
+// give each XCD a contiguous range of blocks, so those lines stay in one L2.
 __device__ __forceinline__ void gather_rhs_body(int bid, int npos, const int32_t *__restrict__ fsrc,
                                                 const double *__restrict__ r, const double *__restrict__ scale,
                                                 const int32_t *__restrict__ cptr3, const int32_t *__restrict__ cidx3,
@@ -764,7 +804,7 @@ __global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t
                                                          const int32_t *__restrict__ cptr3,
                                                          const int32_t *__restrict__ cidx3,
                                                          const double *__restrict__ pnf, double *__restrict__ rs) {
-  gather_rhs_body(blockIdx.x, npos, fsrc, r, scale, cptr3, cidx3, pnf, rs);
+  gather_rhs_body(xcd_logical_block((npos + 255) / 256, blockIdx.x), npos, fsrc, r, scale, cptr3, cidx3, pnf, rs);
 }
 
 __device__ __forceinline__ void additive_combine_body(int bid, int N, const int32_t *__restrict__ cptr,
@@ -853,32 +893,17 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(int nblocks, int ncols
   reduce_cols_body(blockIdx.x, nblocks, ncols, partial, out, red);
 }
 
-__device__ __forceinline__ void finalize_dots_body(int nv, const double *__restrict__ d,
-                                                   const double *__restrict__ scale, double *__restrict__ Hcol,
-                                                   double *__restrict__ coef, double *__restrict__ wnorm) {
-  const int i = threadIdx.x;
-  if (i < nv) {
-    const double h = scale[i] * d[i];
-    Hcol[i] = h;
-    coef[i] = h * scale[i];
-  }
-  if (i == 0) *wnorm = sqrt(d[nv]);
-}
-
-__global__ void finalize_dots_kernel(int nv, const double *__restrict__ d, const double *__restrict__ scale,
-                                     double *__restrict__ Hcol, double *__restrict__ coef,
-                                     double *__restrict__ wnorm) {
-  finalize_dots_body(nv, d, scale, Hcol, coef, wnorm);
-}
-
-// unew = w - sum_i coef[i] U_i and per-block partial sums of ||unew||^2.
+// unew = w - sum_i c_i U_i and per-block partial sums of ||unew||^2.  The
+// basis is stored unnormalised (v_i = scale_i U_i) and d[i] = U_i . w, so
+// the Hessenberg entry is h_i = scale_i d_i and c_i = h_i scale_i.
 template <int NV>
 __device__ __forceinline__ void update_body(int bid, int nblk, int64_t n, const double *__restrict__ U, int64_t ldu,
-                                            const double *__restrict__ coef, const double *__restrict__ w,
-                                            double *__restrict__ unew, double *__restrict__ partial, double *red) {
+                                            const double *__restrict__ d, const double *__restrict__ scale,
+                                            const double *__restrict__ w, double *__restrict__ unew,
+                                            double *__restrict__ partial, double *red) {
   double cs[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) cs[i] = coef[i];
+  for (int i = 0; i < NV; ++i) cs[i] = (scale[i] * d[i]) * scale[i];
   double nrm = 0.0;
   const int64_t n2 = n / 2;
   const double2 *w2 = reinterpret_cast<const double2 *>(w);
@@ -907,37 +932,48 @@ __device__ __forceinline__ void update_body(int bid, int nblk, int64_t n, const 
 
 template <int NV>
 __global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
-                                                     const double *__restrict__ coef,
+                                                     const double *__restrict__ d, const double *__restrict__ scale,
                                                      const double *__restrict__ w, double *__restrict__ unew,
                                                      double *__restrict__ partial) {
   __shared__ double red[4];
-  update_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, coef, w, unew, partial, red);
+  update_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, d, scale, w, unew, partial, red);
 }
 
-// h = ||u_new|| into hcol[nv] and its inverse into scale_out; optionally
-// publishes hcol[0..nv] and *wnorm to pinned host memory (pub).
-__device__ __forceinline__ void finalize_norm_body(int nv, const double *__restrict__ nrm2,
+// One block of 256 threads: h = sqrt(sum of partial[0 .. nblocks)) (the
+// partial sums in the order of reduce_cols_body) into hcol[nv] and 1/h
+// into scale_out; for i < nv, hcol[i] = scale[i] * d[i] (the projections
+// of the step).  If pub is not NULL, hcol[0..nv] and sqrt(d[nv]) (the norm
+// of w before the projections) are also written to pub[0..nv+1].
+__device__ __forceinline__ void norm_finalize_body(int nblocks, const double *__restrict__ partial, int nv,
+                                                   const double *__restrict__ d, const double *__restrict__ scale,
                                                    double *__restrict__ hcol, double *__restrict__ scale_out,
-                                                   const double *__restrict__ wnorm, double *__restrict__ pub) {
-  const int i = threadIdx.x;
-  const double h = sqrt(nrm2[0]);
-  if (i == 0) {
+                                                   double *__restrict__ pub, double *red) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[b];
+  s = block_sum<256>(s, red);
+  for (int q = threadIdx.x; q < nv; q += 256) {
+    const double h = scale[q] * d[q];
+    hcol[q] = h;
+    if (pub) pub[q] = h;
+  }
+  if (threadIdx.x == 0) {
+    const double h = sqrt(s);
     hcol[nv] = h;
     *scale_out = (h > 0.0) ? 1.0 / h : 0.0;
-  }
-  if (pub) {
-    for (int q = i; q < nv; q += blockDim.x) pub[q] = hcol[q];
-    if (i == 0) {
+    if (pub) {
       pub[nv] = h;
-      pub[nv + 1] = *wnorm;
+      pub[nv + 1] = sqrt(d[nv]);
     }
   }
 }
 
-__global__ void finalize_norm_kernel(int nv, const double *__restrict__ nrm2, double *__restrict__ hcol,
-                                     double *__restrict__ scale_out, const double *__restrict__ wnorm,
-                                     double *__restrict__ pub) {
-  finalize_norm_body(nv, nrm2, hcol, scale_out, wnorm, pub);
+__global__ __launch_bounds__(256) void norm_finalize_kernel(int nblocks, const double *__restrict__ partial, int nv,
+                                                            const double *__restrict__ d,
+                                                            const double *__restrict__ scale,
+                                                            double *__restrict__ hcol, double *__restrict__ scale_out,
+                                                            double *__restrict__ pub) {
+  __shared__ double red[4];
+  norm_finalize_body(nblocks, partial, nv, d, scale, hcol, scale_out, pub, red);
 }
 
 __device__ __forceinline__ void lincomb_body(int bid, int nblk, int64_t n, int nv, const double *__restrict__ U,
@@ -1001,8 +1037,7 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 struct SegPos {
   int sys, lb, nb;
 };
-__device__ __forceinline__ SegPos seg_find(const BatchSeg &g) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ SegPos seg_find(const BatchSeg &g, int b = blockIdx.x) {
   int lo = 0, hi = g.n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1027,17 +1062,19 @@ __global__ __launch_bounds__(256) void batch_c1_kernel(const BatchSys *__restric
   const BatchSys &S = tab[p.sys];
   const double *scale;
   const double *r = prec_in(S, col, scale);
-  gather_sum3_body(p.lb, S.c1lanes, S.c1n, S.c1ptr, S.c1idx, r, scale, S.PA);
+  gather_sum3_body(p.lb, S.c1n1, S.c1lanes, S.c1n, S.c1lanes2, S.c1ptr, S.c1idx, r, scale, S.PA);
 }
 
 __global__ __launch_bounds__(256) void batch_c2_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
   const SegPos p = seg_find(g);
   const BatchSys &S = tab[p.sys];
-  gather_sum3_body(p.lb, S.c2lanes, S.c2n, S.c2ptr, S.c2idx, S.PA, nullptr, S.PNF);
+  gather_sum3_body(p.lb, S.c2n1, S.c2lanes, S.c2n, S.c2lanes2, S.c2ptr, S.c2idx, S.PA, nullptr, S.PNF);
 }
 
 __global__ __launch_bounds__(256) void batch_rhs_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int col) {
-  const SegPos p = seg_find(g);
+  const int b = xcd_logical_block(g.total, blockIdx.x);
+  if (b >= g.total) return;
+  const SegPos p = seg_find(g, b);
   const BatchSys &S = tab[p.sys];
   const double *scale;
   const double *r = prec_in(S, col, scale);
@@ -1102,32 +1139,30 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchSys *__res
   for (int c = 0; c < ncols; ++c) reduce_cols_body(c, nb, ncols, S.partial, dots ? S.dvec : S.misc + 2, sh);
 }
 
-__global__ void batch_finalize_dots_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int j, int ldh) {
-  const SegPos p = seg_find(g);
-  const BatchSys &S = tab[p.sys];
-  finalize_dots_body(j + 1, S.dvec, S.scale, S.H + (size_t)j * ldh, S.coef, S.misc);
-}
-
 template <int NV>
 __global__ __launch_bounds__(256) void batch_update_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int ldh) {
   __shared__ double red[4];
   const SegPos p = seg_find(g);
   const BatchSys &S = tab[p.sys];
-  update_body<NV>(p.lb, p.nb, S.n, S.U, S.ldu, S.coef, S.w, S.U + (size_t)NV * S.ldu, S.partial, red);
+  update_body<NV>(p.lb, p.nb, S.n, S.U, S.ldu, S.dvec, S.scale, S.w, S.U + (size_t)NV * S.ldu, S.partial, red);
 }
 
-__global__ void batch_finalize_norm_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int j, int ldh,
-                                           int pub_stride) {
+// One block per system: the norm of the new basis vector of step j from the
+// partial sums of the update kernel (src 0), or for j < 0 the true residual
+// norm from those of the residual SpMV (src 1): beta into misc[1], 1/beta
+// into scale[0], beta to the host at pub[-1].
+__global__ __launch_bounds__(256) void batch_norm_finalize_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int j,
+                                                                  int ldh, int pub_stride, int src) {
+  __shared__ double red[4];
   const SegPos p = seg_find(g);
   const BatchSys &S = tab[p.sys];
-  if (j >= 0)
-    finalize_norm_body(j + 1, S.misc + 2, S.H + (size_t)j * ldh, S.scale + j + 1, S.misc,
-                       S.pub + (size_t)j * pub_stride);
-  else if (threadIdx.x == 0) {  // true residual norm: beta, 1/beta, and beta to the host
-    const double h = sqrt(S.misc[2]);
-    S.misc[1] = h;
-    S.scale[0] = (h > 0.0) ? 1.0 / h : 0.0;
-    S.pub[-1] = h;
+  const int nb = red_blocks(S, src);
+  if (j >= 0) {
+    norm_finalize_body(nb, S.partial, j + 1, S.dvec, S.scale, S.H + (size_t)j * ldh, S.scale + j + 1,
+                       S.pub + (size_t)j * pub_stride, red);
+  } else {
+    norm_finalize_body(nb, S.partial, 0, nullptr, nullptr, S.misc + 1, S.scale, nullptr, red);
+    if (threadIdx.x == 0) S.pub[-1] = S.misc[1];
   }
 }
 
@@ -1177,12 +1212,14 @@ hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx, 
   return hipGetLastError();
 }
 
-hipError_t launch_gather_sum3(int ndst, int lanes, const int32_t *ptr, const int32_t *idx, const double *src,
-                              const double *scale, double *dst, hipStream_t s) {
-  if (ndst == 0) return hipSuccess;
-  if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
-  const int64_t threads = (int64_t)ndst * lanes;
-  gather_sum3_kernel<<<(int)((threads + 255) / 256), 256, 0, s>>>(lanes, ndst, ptr, idx, src, scale, dst);
+static bool lanes_ok(int g) { return g >= 1 && g <= 64 && (g & (g - 1)) == 0; }
+
+hipError_t launch_gather_sum3(int n1, int lanes1, int n, int lanes2, const int32_t *ptr, const int32_t *idx,
+                              const double *src, const double *scale, double *dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (n1 < 0 || n1 > n || !lanes_ok(lanes1) || !lanes_ok(lanes2)) return hipErrorInvalidValue;
+  gather_sum3_kernel<<<gather_sum3_blocks(n1, lanes1, n, lanes2), 256, 0, s>>>(n1, lanes1, n, lanes2, ptr, idx,
+                                                                                src, scale, dst);
   return hipGetLastError();
 }
 
@@ -1201,7 +1238,7 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base, 
 
 hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s) {
   if (npos == 0) return hipSuccess;
-  gather_rhs_kernel<<<blocks_for(npos, 256), 256, 0, s>>>(npos, p.fsrc, r, scale, p.cptr3, p.cidx3, p.pnf, p.rs);
+  gather_rhs_kernel<<<xcd_grid(blocks_for(npos, 256)), 256, 0, s>>>(npos, p.fsrc, r, scale, p.cptr3, p.cidx3, p.pnf, p.rs);
   return hipGetLastError();
 }
 
@@ -1245,38 +1282,35 @@ hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, dou
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_dots(int nv, const double *d, const double *scale, double *Hcol, double *coef,
-                                double *wnorm, hipStream_t s) {
-  finalize_dots_kernel<<<1, 64, 0, s>>>(nv, d, scale, Hcol, coef, wnorm);
-  return hipGetLastError();
-}
-
 template <int NV>
-static void update_launch(int64_t n, const double *U, int64_t ldu, const double *coef, const double *w, double *unew,
-                          double *partial, int grid, hipStream_t s) {
-  update_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, coef, w, unew, partial);
+static void update_launch(int64_t n, const double *U, int64_t ldu, const double *d, const double *scale,
+                          const double *w, double *unew, double *partial, int grid, hipStream_t s) {
+  update_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, d, scale, w, unew, partial);
 }
 
 template <int... Is>
-static bool update_dispatch(int nv, int64_t n, const double *U, int64_t ldu, const double *coef, const double *w,
-                            double *unew, double *partial, int grid, hipStream_t s, std::integer_sequence<int, Is...>) {
+static bool update_dispatch(int nv, int64_t n, const double *U, int64_t ldu, const double *d, const double *scale,
+                            const double *w, double *unew, double *partial, int grid, hipStream_t s,
+                            std::integer_sequence<int, Is...>) {
   bool done = false;
-  ((nv == Is + 1 ? (update_launch<Is + 1>(n, U, ldu, coef, w, unew, partial, grid, s), done = true) : false), ...);
+  ((nv == Is + 1 ? (update_launch<Is + 1>(n, U, ldu, d, scale, w, unew, partial, grid, s), done = true) : false),
+   ...);
   return done;
 }
 
-hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *coef, const double *w,
-                         double *unew, double *partial, int *nblocks_out, hipStream_t s) {
+hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d, const double *scale,
+                         const double *w, double *unew, double *partial, int *nblocks_out, hipStream_t s) {
   const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
-  update_dispatch(nv, n, U, ldu, coef, w, unew, partial, grid, s, std::make_integer_sequence<int, kMaxRestart>{});
+  update_dispatch(nv, n, U, ldu, d, scale, w, unew, partial, grid, s,
+                  std::make_integer_sequence<int, kMaxRestart>{});
   *nblocks_out = grid;
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_norm(int nv, const double *nrm2, double *hcol, double *scale_out, const double *wnorm,
-                                double *pub, hipStream_t s) {
-  finalize_norm_kernel<<<1, 64, 0, s>>>(nv, nrm2, hcol, scale_out, wnorm, pub);
+hipError_t launch_norm_finalize(int nblocks, const double *partial, int nv, const double *d, const double *scale,
+                                double *hcol, double *scale_out, double *pub, hipStream_t s) {
+  norm_finalize_kernel<<<1, 256, 0, s>>>(nblocks, partial, nv, d, scale, hcol, scale_out, pub);
   return hipGetLastError();
 }
 
@@ -1310,8 +1344,8 @@ hipError_t launch_norm2(int64_t n, const double *v, double *partial, int *nblock
 int batch_blocks(BatchKernel k, const BatchSys &s) {
   const int64_t n = s.n;
   switch (k) {
-    case kBkC1: return s.c1n > 0 ? blocks_for((int64_t)s.c1n * s.c1lanes, 256) : 0;
-    case kBkC2: return s.c2n > 0 ? blocks_for((int64_t)s.c2n * s.c2lanes, 256) : 0;
+    case kBkC1: return s.c1n > 0 ? gather_sum3_blocks(s.c1n1, s.c1lanes, s.c1n, s.c1lanes2) : 0;
+    case kBkC2: return s.c2n > 0 ? gather_sum3_blocks(s.c2n1, s.c2lanes, s.c2n, s.c2lanes2) : 0;
     case kBkRhs: return blocks_for(s.npos, 256);
     case kBkApply: return s.nsub;
     case kBkCombine: return blocks_for(s.N, 256);
@@ -1329,7 +1363,8 @@ hipError_t launch_batch_precond(const BatchSys *tab, const BatchSeg *seg, int co
   if (seg[kBkCopy].total > 0) batch_copy_kernel<<<seg[kBkCopy].total, 256, 0, s>>>(tab, seg[kBkCopy], col);
   if (seg[kBkC1].total > 0) batch_c1_kernel<<<seg[kBkC1].total, 256, 0, s>>>(tab, seg[kBkC1], col);
   if (seg[kBkC2].total > 0) batch_c2_kernel<<<seg[kBkC2].total, 256, 0, s>>>(tab, seg[kBkC2]);
-  if (seg[kBkRhs].total > 0) batch_rhs_kernel<<<seg[kBkRhs].total, 256, 0, s>>>(tab, seg[kBkRhs], col);
+  if (seg[kBkRhs].total > 0)
+    batch_rhs_kernel<<<xcd_grid(seg[kBkRhs].total), 256, 0, s>>>(tab, seg[kBkRhs], col);
   if (seg[kBkApply].total > 0) batch_apply_kernel<<<seg[kBkApply].total, kSweepThreads, 0, s>>>(tab, seg[kBkApply]);
   if (seg[kBkCombine].total > 0) batch_combine_kernel<<<seg[kBkCombine].total, 256, 0, s>>>(tab, seg[kBkCombine]);
   return hipGetLastError();
@@ -1380,16 +1415,10 @@ hipError_t launch_batch_reduce(const BatchSys *tab, const BatchSeg &seg, int nco
   return hipGetLastError();
 }
 
-hipError_t launch_batch_finalize_dots(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, hipStream_t s) {
+hipError_t launch_batch_norm_finalize(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
+                                      int src, hipStream_t s) {
   if (seg.total == 0) return hipSuccess;
-  batch_finalize_dots_kernel<<<seg.total, 64, 0, s>>>(tab, seg, j, ldh);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_finalize_norm(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
-                                      hipStream_t s) {
-  if (seg.total == 0) return hipSuccess;
-  batch_finalize_norm_kernel<<<seg.total, 64, 0, s>>>(tab, seg, j, ldh, pub_stride);
+  batch_norm_finalize_kernel<<<seg.total, 256, 0, s>>>(tab, seg, j, ldh, pub_stride, src);
   return hipGetLastError();
 }
 

@@ -31,9 +31,15 @@ hipError_t launch_residual(const SellDev &A, const double *x, const double *b, d
 hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx,
                               const double *srcA, int32_t nA, const double *srcB, double *dst,
                               hipStream_t s);
-// lanes (1, 2, 4, 8 or 16) threads share each destination.
-hipError_t launch_gather_sum3(int ndst, int lanes, const int32_t *ptr, const int32_t *idx, const double *src,
-                              const double *scale, double *dst, hipStream_t s);
+// dst[d] = scale * sum of src over idx[ptr[d] .. ptr[d+1]) (3 doubles per
+// entry).  Destinations [0, n1) take lanes1 threads each, [n1, n) lanes2
+// (powers of two, 1 .. 64).
+hipError_t launch_gather_sum3(int n1, int lanes1, int n, int lanes2, const int32_t *ptr, const int32_t *idx,
+                              const double *src, const double *scale, double *dst, hipStream_t s);
+// Blocks of 256 threads of that launch.
+inline int gather_sum3_blocks(int n1, int lanes1, int n, int lanes2) {
+  return (int)(((int64_t)n1 * lanes1 + 255) / 256 + ((int64_t)(n - n1) * lanes2 + 255) / 256);
+}
 
 // Level-scheduled block ILU(0) of every subdomain; singular pivots reported
 // through *bad as (subdomain << 32 | local row), minimum over all.
@@ -57,18 +63,16 @@ hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, cons
                            double *partial, int *nblocks_out, hipStream_t s);
 hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out,
                               hipStream_t s);
-// After multidot of column j: H[j*ldh + i] = scale[i]*d[i] (i<=j), coef[i] =
-// H[j*ldh+i]*scale[i], wnorm = sqrt(d[nv]).
-hipError_t launch_finalize_dots(int nv, const double *d, const double *scale, double *Hcol,
-                                double *coef, double *wnorm, hipStream_t s);
-hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
-                         const double *w, double *unew, double *partial, int *nblocks_out,
-                         hipStream_t s);
-// hn = sqrt(nrm2[0]); *hout = hn; *scale_out = hn > 0 ? 1/hn : 0.
-// h = sqrt(*nrm2) into hcol[nv], 1/h into *scale_out; if pub is not NULL,
-// hcol[0..nv] and *wnorm are also written to pub[0..nv+1] (pinned host).
-hipError_t launch_finalize_norm(int nv, const double *nrm2, double *hcol, double *scale_out, const double *wnorm,
-                                double *pub, hipStream_t s);
+// unew = w - sum_{i<nv} (scale[i] d[i]) scale[i] U_i, d the reduced
+// projections of the step; per-block partial sums of ||unew||^2.
+hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d,
+                         const double *scale, const double *w, double *unew, double *partial,
+                         int *nblocks_out, hipStream_t s);
+// One block: h = sqrt(sum of partial[0..nblocks)) into hcol[nv], 1/h (0 if
+// h = 0) into *scale_out, hcol[i] = scale[i]*d[i] for i < nv; if pub is not
+// NULL, hcol[0..nv] and sqrt(d[nv]) are also written to pub[0..nv+1].
+hipError_t launch_norm_finalize(int nblocks, const double *partial, int nv, const double *d, const double *scale,
+                                double *hcol, double *scale_out, double *pub, hipStream_t s);
 hipError_t launch_lincomb(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
                           double *out, hipStream_t s);
 hipError_t launch_axpy(int64_t n, const double *z, double *x, hipStream_t s);
@@ -82,7 +86,7 @@ hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, do
 // table, one entry per system).  Vectors are the system's own workspace.
 struct BatchSys {
   int64_t n, ldu;
-  double *U, *w, *z, *t, *partial, *dvec, *H, *scale, *coef, *misc;
+  double *U, *w, *z, *t, *partial, *dvec, *H, *scale, *misc;
   double *pub;          // pinned (device view): published Hessenberg columns
   const double *coefh;  // pinned (device view): [0] = k, [1..k] = solution coefficients
   const double *b;
@@ -92,7 +96,7 @@ struct BatchSys {
   const double *vals;
   int32_t kind, restricted, npos, nsub;
   ApplyPlan ap;
-  int32_t c1n, c1lanes, c2n, c2lanes;
+  int32_t c1n, c1n1, c1lanes, c1lanes2, c2n, c2n1, c2lanes, c2lanes2;
   const int32_t *c1ptr, *c1idx, *c2ptr, *c2idx;
   double *PA, *PNF;
   const int32_t *cptr, *cidx;
@@ -119,12 +123,12 @@ hipError_t launch_batch_spmv(const BatchSys *tab, const BatchSeg &seg, bool resi
 hipError_t launch_batch_multidot(const BatchSys *tab, const BatchSeg &seg, int nv, hipStream_t s);
 // src 0: partial sums of the CGS kernels, 1: of the residual SpMV.
 hipError_t launch_batch_reduce(const BatchSys *tab, const BatchSeg &seg, int ncols, bool dots, int src, hipStream_t s);
-hipError_t launch_batch_finalize_dots(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, hipStream_t s);
 hipError_t launch_batch_update(const BatchSys *tab, const BatchSeg &seg, int nv, int ldh, hipStream_t s);
+// Reduces the partial sums (src as for launch_batch_reduce) and finalises:
 // j >= 0: step j (norm of the new basis vector, column published at
 // pub + j*pub_stride); j < 0: true residual norm (beta published at pub[-1]).
-hipError_t launch_batch_finalize_norm(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
-                                      hipStream_t s);
+hipError_t launch_batch_norm_finalize(const BatchSys *tab, const BatchSeg &seg, int j, int ldh, int pub_stride,
+                                      int src, hipStream_t s);
 hipError_t launch_batch_lincomb(const BatchSys *tab, const BatchSeg &seg, hipStream_t s);
 hipError_t launch_batch_axpy(const BatchSys *tab, const BatchSeg &seg, hipStream_t s);
 

@@ -903,6 +903,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         P.c2.idx.insert(P.c2.idx.end(), v.begin(), v.end());
         P.c2.ptr.push_back((int32_t)P.c2.idx.size());
       }
+      P.c2.split = at.nNa;
       for (auto &v : fsrc) {
         P.c2.idx.insert(P.c2.idx.end(), v.begin(), v.end());
         P.c2.ptr.push_back((int32_t)P.c2.idx.size());

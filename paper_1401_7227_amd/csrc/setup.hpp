@@ -27,6 +27,9 @@ struct RelayoutMap {
 // Gather-sum description: dst entry d sums sources idx[ptr[d] .. ptr[d+1]).
 struct GatherList {
   std::vector<int32_t> ptr{0}, idx;
+  // destinations [0, split) and [split, size) have different fan-ins and
+  // are gathered with their own lane counts (-1: one segment)
+  int32_t split = -1;
   int32_t size() const { return (int32_t)ptr.size() - 1; }
 };
 
