@@ -344,7 +344,7 @@ class BatchEngine {
         const BatchSys &T = tabh_[act[a]];
         int nb = batch_blocks((BatchKernel)k, T);
         if (k == kBkCopy && T.kind != ASM_KIND_NONE) nb = 0;
-        if ((k == kBkC1 || k == kBkC2 || k == kBkRhs || k == kBkApply || k == kBkCombine) && T.kind == ASM_KIND_NONE)
+        if ((k == kBkC1 || k == kBkC2 || k == kBkCrs || k == kBkApply || k == kBkCombine) && T.kind == ASM_KIND_NONE)
           nb = 0;
         if (k == kBkCombine && T.restricted) nb = 0;
         if (nb <= 0) continue;

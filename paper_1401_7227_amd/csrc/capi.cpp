@@ -193,14 +193,19 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
     ASM_HIP(launch_gather_sum3(pc->c2.n1, pc->c2.lanes, pc->c2.n, pc->c2.lanes2, pc->c2.ptr, pc->c2.idx, pc->PA,
                                nullptr, pc->PNF, s));
   }
-  ASM_HIP(launch_gather_rhs((int)pc->plan->total_pos, pc->ap, r, scale, s));
+  // the ILU sweeps gather their fine inputs from r themselves; the dense
+  // local solves take every subdomain's inputs gathered in sweep order
+  if (pc->opts.local == ASM_LOCAL_EXACT)
+    ASM_HIP(launch_gather_rhs((int)pc->plan->total_pos, pc->ap, r, scale, s));
+  else
+    ASM_HIP(launch_coarse_rhs(pc->ap, s));
   pf.span(ASM_PHASE_LUMP, t0, s);
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(ASM_PHASE_ILU_APPLY, s);
   if (pc->opts.local == ASM_LOCAL_EXACT)
     ASM_HIP(launch_local_dense_apply(pc->xd, (int64_t)pc->plan->total_pos, pc->ap.rs, restricted, z, pc->ap.yx, s));
   else
-    ASM_HIP(launch_ilu_apply(pc->ap, z, s));
+    ASM_HIP(launch_ilu_apply(pc->ap, r, scale, z, s));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
     const size_t t2 = pf.mark(ASM_PHASE_COMBINE, s);
@@ -356,11 +361,13 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
         (e = upload_gather(M, pc->c3, P.c3, s)) != hipSuccess || (e = ALLOC(&pc->L1, (size_t)pc->l1.n * 9)) != hipSuccess ||
         (e = ALLOC(&pc->L2, (size_t)pc->l2.n * 9)) != hipSuccess ||
         (e = ALLOC(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
-        (e = ALLOC(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess)
+        (e = ALLOC(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess ||
+        (e = ALLOC(&ap.crs, (size_t)pc->c3.n * 3)) != hipSuccess)
       return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
     ap.cptr3 = pc->c3.ptr;
     ap.cidx3 = pc->c3.idx;
     ap.pnf = pc->PNF;
+    ap.ncoarse = pc->c3.n;
   }
   if (o->coarse != ASM_COARSE_NONE) {
     pc->ncv = P.ncv;
@@ -562,7 +569,8 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
       ((e = O.alloc(&pc->L1, (size_t)pc->l1.n * 9)) != hipSuccess ||
        (e = O.alloc(&pc->L2, (size_t)pc->l2.n * 9)) != hipSuccess ||
        (e = O.alloc(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
-       (e = O.alloc(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess))
+       (e = O.alloc(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess ||
+       (e = O.alloc(&pc->ap.crs, (size_t)pc->c3.n * 3)) != hipSuccess))
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
   // the records carry the sweep's row headers and slots next to the factor
   // values; the values are rewritten by the numeric setup below

@@ -413,6 +413,32 @@ constexpr int kSweepThreads = kConsumerThreads + 256;           // plus four str
 typedef ASMX_LDS double lds_double;
 typedef const ASMX_LDS double lds_cdouble;
 typedef const ASMX_GLB double glb_cdouble;
+typedef ASMX_GLB double glb_double;
+
+// Global memory by its own address space.  A pointer the kernel reads from
+// memory (the batched launches take their plans from a table) is generic
+// to the compiler, and a generic (flat) access is counted with the LDS
+// accesses too: every wait for the LDS stores before a barrier would then
+// also wait for the record loads in flight.
+template <typename T>
+__device__ __forceinline__ const ASMX_GLB T *glb(const T *p) {
+  return (const ASMX_GLB T *)p;
+}
+template <typename T>
+__device__ __forceinline__ ASMX_GLB T *glb(T *p) {
+  return (ASMX_GLB T *)p;
+}
+// A small plan struct read word by word through a global pointer.
+template <typename T>
+__device__ __forceinline__ T ld_glb(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  T v;
+  const ASMX_GLB int32_t *q = (const ASMX_GLB int32_t *)p;
+  int32_t *o = reinterpret_cast<int32_t *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
+  return v;
+}
 
 struct Stage {
   u32x4 v[kStageU4];
@@ -462,11 +488,13 @@ struct SweepLds {
 // component r of the result.  Sections with more than 64 rows take
 // several passes.  j0: first step row of the section; n: its rows;
 // koff: its diagonal starts (LDS); dinv rows of the section start at
-// index doff of a plane of dstride rows.
+// index doff of a plane of dstride rows; sc: the basis scale of the
+// forward inputs flagged as cell values.
 template <bool FWD, typename T>
 __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
                                            double *__restrict__ z, int j0, int n, const int32_t *koff, int nslots,
-                                           int vals_off, int dinv_off, int dstride, int doff, int in_off) {
+                                           int vals_off, int dinv_off, int dstride, int doff, int in_off,
+                                           double sc) {
   constexpr int kRowsPerPass = kConsumerThreads / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int r = threadIdx.x & 3;
@@ -483,7 +511,8 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     const int rc = r < 3 ? r : 2;
     T a0, a1, a2, e0 = 0, e1 = 0, e2 = 0;
     if (FWD) {
-      a0 = (T)inb[3 * j + rc];
+      const double x = inb[3 * j + rc];
+      a0 = (T)((m.w & 2) ? sc * x : x);  // a cell value of r times the basis scale
       a1 = a2 = 0;
     } else {
       a0 = (T)inb[3 * j]; a1 = (T)inb[3 * j + 1]; a2 = (T)inb[3 * j + 2];
@@ -523,8 +552,8 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
       }
       const double od = (double)o;
       if (m.x >= 0) ((lds_double *)L.vec)[3 * m.x + r] = od;
-      if (m.w & 1) yx[3 * (size_t)m.y + r] = od;
-      if (m.z >= 0) z[3 * (size_t)m.z + r] = od;
+      if (m.w & 1) glb(yx)[3 * (size_t)m.y + r] = od;
+      if (m.z >= 0) glb(z)[3 * (size_t)m.z + r] = od;
     }
   }
 }
@@ -535,7 +564,7 @@ template <bool FWD>
 __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
                                           double *__restrict__ z, int j0, int n, int piece, int deps_off,
                                           int rptr_off, int vals_off, int dinv_off, int dstride, int doff,
-                                          int in_off) {
+                                          int in_off, double sc) {
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = kConsumerThreads / kWave;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int32_t *deps = reinterpret_cast<const int32_t *>(recp + deps_off);
@@ -556,12 +585,16 @@ __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double 
     s2 = wave_sum_dpp(s2);
     if (lane == 0) {
       const int j = j0 + i;
+      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
       double a0, a1, a2;
       if (piece == kPieceMiddle || piece == kPieceLast) {
         a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
       } else {
         const double *inp = reinterpret_cast<const double *>(recp + in_off) + 3 * j;
         a0 = inp[0]; a1 = inp[1]; a2 = inp[2];
+        if (FWD && (m.w & 2)) {
+          a0 = sc * a0; a1 = sc * a1; a2 = sc * a2;
+        }
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
       if (piece == kPieceFirst || piece == kPieceMiddle) {
@@ -575,15 +608,14 @@ __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double 
           const double x2 = dv[6 * S] * a0 + dv[7 * S] * a1 + dv[8 * S] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
-        const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
         lds_double *w = (lds_double *)L.vec;
         if (m.x >= 0) { w[3 * m.x] = a0; w[3 * m.x + 1] = a1; w[3 * m.x + 2] = a2; }
         if (m.w & 1) {
-          double *g = yx + 3 * (size_t)m.y;
+          glb_double *g = glb(yx) + 3 * (size_t)m.y;
           g[0] = a0; g[1] = a1; g[2] = a2;
         }
         if (m.z >= 0) {
-          double *g = z + 3 * (size_t)m.z;
+          glb_double *g = glb(z) + 3 * (size_t)m.z;
           g[0] = a0; g[1] = a1; g[2] = a2;
         }
       }
@@ -615,11 +647,27 @@ __device__ __forceinline__ void fill_values(const RecHead &h, const char *recp, 
 constexpr int kAhead = ASM_SWEEP_AHEAD;
 static_assert(kAhead == 3 || kAhead == 4, "three or four records in flight per streaming thread");
 
+// Where the streaming waves take a sweep's row inputs from.  Backward: the
+// forward results, contiguous at the step's positions (src).  Forward
+// (gather): the input of forward position q is sc * r[3c + k] for a fine
+// row of cell c (fsrc[q] = c) or the lumped input crs[3j + k] of coarse row
+// j (fsrc[q] = -(1 + j)): the restriction R_i r of Section 4 read straight
+// from r, with no gathered copy in between.  The computing waves apply sc
+// to the rows flagged as cell values.
+struct SweepIn {
+  const double *src;
+  const int32_t *fsrc;
+  const double *r, *crs;
+};
+
+template <bool G>
 struct Producer {
   Stage st[kAhead];
   int len[kAhead];
   int xlast[kAhead];
-  int dq[kAhead];  // descriptors of later steps, one word per lane (desc_load)
+  int dq[kAhead];            // descriptor of the record stage k loads next (one word per lane)
+  int dq2[G ? kAhead : 1];   // gathering: the descriptor kAhead records after that
+  int ix[G ? kAhead : 1][3]; // gathering: sources of this thread's inputs of record dq[k]
 };
 
 // Descriptor of step k by a vector load, lane l holding word l % 4.  The
@@ -628,7 +676,7 @@ struct Producer {
 // full latency on every step; a vector load issued kAhead steps before use
 // completes together with the record loads issued after it.
 __device__ __forceinline__ int desc_load(const RecStep *__restrict__ steps, int k, int t) {
-  return reinterpret_cast<const int32_t *>(steps + k)[t & 3];
+  return glb(reinterpret_cast<const int32_t *>(steps + k))[t & 3];
 }
 __device__ __forceinline__ RecStep desc_get(int v) {
   RecStep d;
@@ -639,18 +687,40 @@ __device__ __forceinline__ RecStep desc_get(int v) {
   return d;
 }
 
-// Streamer: load record k of the sweep and its row inputs (3 doubles per
-// row from src at the step's positions) into a stage.  Loads are clamped
-// to the record / the input segment, never conditional; records are read
-// once per application, so they are loaded non-temporally.
-__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec,
-                                          const double *__restrict__ src, Stage &st, int &len, int &xlast, int t) {
-#pragma unroll
-  for (int i = 0; i < kStageU4; ++i) st.v[i] = __builtin_nontemporal_load(rec + d.rec + min(i * 256 + t, d.len - 1));
+// Sources of this thread's three inputs (elements t, t+256, t+512 of the
+// step's 3 * nrows, clamped) of the step described by d.
+__device__ __forceinline__ void ix_load(const RecStep &d, const int32_t *__restrict__ fsrc, int (&ix)[3], int t) {
   const int last = 3 * max(d.nrows, 1) - 1;
-  const double *xs = src + 3 * (size_t)d.pos;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) st.x[i] = xs[min(i * 256 + t, last)];
+  for (int i = 0; i < 3; ++i) ix[i] = __builtin_nontemporal_load(glb(fsrc) + d.pos + min(i * 256 + t, last) / 3);
+}
+
+// Streamer: load record k of the sweep and its row inputs into a stage.
+// Loads are clamped to the record / the input segment, never conditional;
+// records are read once per application, so they are loaded
+// non-temporally.  A gathered cell value is scaled by the computing waves
+// (row flag bit 1), so that nothing here waits on the loads it issues.
+template <bool G>
+__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec, const SweepIn &in,
+                                          const int (&ix)[3], Stage &st, int &len, int &xlast, int t) {
+#pragma unroll
+  for (int i = 0; i < kStageU4; ++i)
+    st.v[i] = __builtin_nontemporal_load(glb(rec) + d.rec + min(i * 256 + t, d.len - 1));
+  const int last = 3 * max(d.nrows, 1) - 1;
+  if constexpr (G) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int e = min(i * 256 + t, last);
+      const int k = e - 3 * (e / 3);
+      const int c = ix[i];
+      glb_cdouble *p = c >= 0 ? glb(in.r) + 3 * (size_t)c + k : glb(in.crs) + 3 * (size_t)(-c - 1) + k;
+      st.x[i] = *p;
+    }
+  } else {
+    glb_cdouble *xs = glb(in.src) + 3 * (size_t)d.pos;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) st.x[i] = xs[min(i * 256 + t, last)];
+  }
   len = d.len;
   xlast = last;
 }
@@ -667,56 +737,84 @@ __device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len,
     if (i * 256 + t <= xlast) xd[i * 256 + t] = st.x[i];
 }
 
-template <int K>
+template <bool G, int K>
 __device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restrict__ steps,
-                                          const u32x4 *__restrict__ rec, const double *__restrict__ src,
-                                          SweepLds &L, Producer &P, int t) {
+                                          const u32x4 *__restrict__ rec, const SweepIn &in, SweepLds &L,
+                                          Producer<G> &P, int t) {
   // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
   // the stage for record s+1+kAhead, whose descriptor dq[K] was loaded
-  // kAhead steps ago; dq[K] then fetches the descriptor of s+1+2*kAhead
+  // kAhead steps ago.  Gathering, the sources of that record's inputs
+  // (ix[K]) were loaded kAhead steps ago too; once the gathers are issued,
+  // ix[K] takes the sources of record s+1+2*kAhead (descriptor dq2[K], also
+  // kAhead steps old) and dq2[K] the descriptor of s+1+3*kAhead.  Each ring
+  // register is overwritten in place, after its last use: a copy of a value
+  // still in flight would wait for it.
   prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.xlast[K], t);
   const RecStep d = desc_get(P.dq[K]);
-  P.dq[K] = desc_load(steps, min(s + 1 + 2 * kAhead, S - 1), t);
-  prod_load(d, rec, src, P.st[K], P.len[K], P.xlast[K], t);
+  if constexpr (G) {
+    const RecStep d2 = desc_get(P.dq2[K]);
+    P.dq[K] = P.dq2[K];
+    P.dq2[K] = desc_load(steps, min(s + 1 + 3 * kAhead, S - 1), t);
+    prod_load<G>(d, rec, in, P.ix[K], P.st[K], P.len[K], P.xlast[K], t);
+    ix_load(d2, in.fsrc, P.ix[K], t);
+  } else {
+    P.dq[K] = desc_load(steps, min(s + 1 + 2 * kAhead, S - 1), t);
+    prod_load<G>(d, rec, in, P.ix[0], P.st[K], P.len[K], P.xlast[K], t);
+  }
   __syncthreads();
 }
 
+template <bool G>
 __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
-                                               const u32x4 *__restrict__ rec, const double *__restrict__ src,
-                                               SweepLds &L) {
+                                               const u32x4 *__restrict__ rec, const SweepIn &in, SweepLds &L) {
   if (S == 0) return;
   const int t = threadIdx.x - kConsumerThreads;
-  Producer P;
-  // dq[k] starts with the descriptor of the step s+1+kAhead that iteration
-  // s with (s+1) % kAhead == k loads; issued before the first records
+  Producer<G> P;
+  // iteration s with (s+1) % kAhead == k reloads stage k with record
+  // s+1+kAhead: dq[k] starts with its descriptor (and, gathering, ix[k] with
+  // its input sources, dq2[k] with the descriptor kAhead records later)
+  auto first = [&](int k) { return min(kAhead + (k == 0 ? kAhead : k), S - 1); };
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) P.dq[k] = desc_load(steps, min(kAhead + (k == 0 ? kAhead : k), S - 1), t);
+  for (int k = 0; k < kAhead; ++k) P.dq[k] = desc_load(steps, first(k), t);
+  // gathering: the sources of the first kAhead+1 records' inputs and of
+  // those the first iterations load, ahead of the first records, so that
+  // the loop finds them as old as in its steady state
+  int ix0[kAhead + 1][3];
+  if constexpr (G) {
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) prod_load(steps[min(k, S - 1)], rec, src, P.st[k], P.len[k], P.xlast[k], t);
+    for (int k = 0; k < kAhead; ++k) P.dq2[k] = desc_load(steps, min(first(k) + kAhead, S - 1), t);
+#pragma unroll
+    for (int k = 0; k <= kAhead; ++k) ix_load(ld_glb(steps + min(k, S - 1)), in.fsrc, ix0[k], t);
+#pragma unroll
+    for (int k = 0; k < kAhead; ++k) ix_load(desc_get(P.dq[k]), in.fsrc, P.ix[k], t);
+  }
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k)
+    prod_load<G>(ld_glb(steps + min(k, S - 1)), rec, in, ix0[k], P.st[k], P.len[k], P.xlast[k], t);
   prod_store(L.buf[0], P.st[0], P.len[0], P.xlast[0], t);
-  prod_load(steps[min(kAhead, S - 1)], rec, src, P.st[0], P.len[0], P.xlast[0], t);
+  prod_load<G>(ld_glb(steps + min(kAhead, S - 1)), rec, in, ix0[kAhead], P.st[0], P.len[0], P.xlast[0], t);
   __syncthreads();
   // full groups of kAhead steps without conditions (exact wait counts),
   // then the remaining steps in straight-line code
   int s = 0;
   if constexpr (kAhead == 4) {
     for (; s + 4 <= S; s += 4) {
-      prod_iter<1>(s, S, steps, rec, src, L, P, t);
-      prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
-      prod_iter<3>(s + 2, S, steps, rec, src, L, P, t);
-      prod_iter<0>(s + 3, S, steps, rec, src, L, P, t);
+      prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
+      prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
+      prod_iter<G, 3>(s + 2, S, steps, rec, in, L, P, t);
+      prod_iter<G, 0>(s + 3, S, steps, rec, in, L, P, t);
     }
-    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, t);
-    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
-    if (s + 2 < S) prod_iter<3>(s + 2, S, steps, rec, src, L, P, t);
+    if (s < S) prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
+    if (s + 1 < S) prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
+    if (s + 2 < S) prod_iter<G, 3>(s + 2, S, steps, rec, in, L, P, t);
   } else {
     for (; s + 3 <= S; s += 3) {
-      prod_iter<1>(s, S, steps, rec, src, L, P, t);
-      prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
-      prod_iter<0>(s + 2, S, steps, rec, src, L, P, t);
+      prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
+      prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
+      prod_iter<G, 0>(s + 2, S, steps, rec, in, L, P, t);
     }
-    if (s < S) prod_iter<1>(s, S, steps, rec, src, L, P, t);
-    if (s + 1 < S) prod_iter<2>(s + 1, S, steps, rec, src, L, P, t);
+    if (s < S) prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
+    if (s + 1 < S) prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
   }
   __syncthreads();  // matches the computing waves' final epilogue barrier
 }
@@ -724,33 +822,38 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
 // Computing iteration for step s: step s from LDS (or the reloads of a
 // fill step), results stored at once.
 template <bool FWD>
-__device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
+__device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z,
+                                          double sc) {
   const char *recp = reinterpret_cast<const char *>(L.buf[s & 1]);
   const RecHead *hp = reinterpret_cast<const RecHead *>(recp);
   const RecHead h = *hp;
   const int nlong = h.nrows - h.n32 - h.n64;
   if (h.n32 > 0)
-    short_rows<FWD, float>(recp, L, yx, z, 0, h.n32, hp->koff32, h.nslots32, h.vals32, h.dinv32, h.n32, 0, h.in);
+    short_rows<FWD, float>(recp, L, yx, z, 0, h.n32, hp->koff32, h.nslots32, h.vals32, h.dinv32, h.n32, 0, h.in,
+                           sc);
   if (h.n64 > 0)
     short_rows<FWD, double>(recp, L, yx, z, h.n32, h.n64, hp->koff64, h.nslots64, h.vals64, h.dinv64,
-                            h.n64 + nlong, 0, h.in);
+                            h.n64 + nlong, 0, h.in, sc);
   if (nlong > 0)
     long_rows<FWD>(recp, L, yx, z, h.n32 + h.n64, nlong, h.piece, h.ldeps, h.lrptr, h.lvals, h.dinv64,
-                   h.n64 + nlong, h.n64, h.in);
+                   h.n64 + nlong, h.n64, h.in, sc);
   if (h.nfill > 0) fill_values(h, recp, L, yx);
   __syncthreads();
 }
 
 template <bool FWD>
-__device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__restrict__ yx, double *__restrict__ z) {
+__device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__restrict__ yx, double *__restrict__ z,
+                                               double sc) {
   if (S == 0) return;
   __syncthreads();
-  for (int s = 0; s < S; ++s) cons_iter<FWD>(s, L, yx, z);
+  for (int s = 0; s < S; ++s) cons_iter<FWD>(s, L, yx, z, sc);
   __syncthreads();  // matches the streaming waves' final barrier
 }
 
-__device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, double *__restrict__ z, SweepLds &L) {
-  const SubDesc sd = p.sub[sub];
+__device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, const double *__restrict__ r,
+                                               const double *__restrict__ scale, double *__restrict__ z,
+                                               SweepLds &L) {
+  const SubDesc sd = ld_glb(p.sub + sub);
   const u32x4 *rec = reinterpret_cast<const u32x4 *>(p.rec);
   // the step counts bound loops of barriers: wave-uniform values, held in
   // scalar registers whatever address space the plan was read through, so
@@ -758,17 +861,21 @@ __device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, doub
   const int rf0 = __builtin_amdgcn_readfirstlane(sd.rf0), rb0 = __builtin_amdgcn_readfirstlane(sd.rb0);
   const int nf = __builtin_amdgcn_readfirstlane(sd.rf1) - rf0, nb = __builtin_amdgcn_readfirstlane(sd.rb1) - rb0;
   if (threadIdx.x < kConsumerThreads) {
-    consumer_sweep<true>(nf, L, p.yx, z);
-    consumer_sweep<false>(nb, L, p.yx, z);
+    consumer_sweep<true>(nf, L, p.yx, z, scale ? *glb(scale) : 1.0);
+    consumer_sweep<false>(nb, L, p.yx, z, 1.0);
   } else {
-    producer_sweep(p.fstep + rf0, nf, rec, p.rs, L);
-    producer_sweep(p.bstep + rb0, nb, rec, p.yx, L);
+    const SweepIn fin{nullptr, p.fsrc, r, p.crs};
+    const SweepIn bin{p.yx, nullptr, nullptr, nullptr};
+    producer_sweep<true>(p.fstep + rf0, nf, rec, fin, L);
+    producer_sweep<false>(p.bstep + rb0, nb, rec, bin, L);
   }
 }
 
-__global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p, double *__restrict__ z) {
+__global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p, const double *__restrict__ r,
+                                                                     const double *__restrict__ scale,
+                                                                     double *__restrict__ z) {
   __shared__ SweepLds L;
-  ilu_apply_body(p, blockIdx.x, z, L);
+  ilu_apply_body(p, blockIdx.x, r, scale, z, L);
 }
 
 // Forward right-hand sides in sweep order: the restriction R_i r of every
@@ -805,6 +912,27 @@ __global__ __launch_bounds__(256) void gather_rhs_kernel(int npos, const int32_t
                                                          const int32_t *__restrict__ cidx3,
                                                          const double *__restrict__ pnf, double *__restrict__ rs) {
   gather_rhs_body(xcd_logical_block((npos + 255) / 256, blockIdx.x), npos, fsrc, r, scale, cptr3, cidx3, pnf, rs);
+}
+
+// Lumped input of each coarse row: the sum of its near/far atoms' lumped
+// residuals (App. B, eq. (B.2)), in the order the gather above sums them.
+__device__ __forceinline__ void coarse_rhs_body(int bid, int ncoarse, const int32_t *__restrict__ cptr3,
+                                                const int32_t *__restrict__ cidx3, const double *__restrict__ pnf,
+                                                double *__restrict__ crs) {
+  const int c = bid * 256 + (int)threadIdx.x;
+  if (c >= ncoarse) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int t = cptr3[c]; t < cptr3[c + 1]; ++t) {
+    const double *p = pnf + 3 * (size_t)cidx3[t];
+    a0 += p[0]; a1 += p[1]; a2 += p[2];
+  }
+  crs[3 * (size_t)c] = a0; crs[3 * (size_t)c + 1] = a1; crs[3 * (size_t)c + 2] = a2;
+}
+
+__global__ __launch_bounds__(256) void coarse_rhs_kernel(int ncoarse, const int32_t *__restrict__ cptr3,
+                                                         const int32_t *__restrict__ cidx3,
+                                                         const double *__restrict__ pnf, double *__restrict__ crs) {
+  coarse_rhs_body(blockIdx.x, ncoarse, cptr3, cidx3, pnf, crs);
 }
 
 __device__ __forceinline__ void additive_combine_body(int bid, int N, const int32_t *__restrict__ cptr,
@@ -1071,22 +1199,24 @@ __global__ __launch_bounds__(256) void batch_c2_kernel(const BatchSys *__restric
   gather_sum3_body(p.lb, S.c2n1, S.c2lanes, S.c2n, S.c2lanes2, S.c2ptr, S.c2idx, S.PA, nullptr, S.PNF);
 }
 
-__global__ __launch_bounds__(256) void batch_rhs_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int col) {
-  const int b = xcd_logical_block(g.total, blockIdx.x);
-  if (b >= g.total) return;
-  const SegPos p = seg_find(g, b);
-  const BatchSys &S = tab[p.sys];
-  const double *scale;
-  const double *r = prec_in(S, col, scale);
-  gather_rhs_body(p.lb, S.npos, S.ap.fsrc, r, scale, S.ap.cptr3, S.ap.cidx3, S.ap.pnf, S.ap.rs);
-}
-
-__global__ __launch_bounds__(kSweepThreads, 1) void batch_apply_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
-  __shared__ SweepLds L;
+__global__ __launch_bounds__(256) void batch_crs_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
   const SegPos p = seg_find(g);
   const BatchSys &S = tab[p.sys];
+  coarse_rhs_body(p.lb, S.ap.ncoarse, S.ap.cptr3, S.ap.cidx3, S.ap.pnf, S.ap.crs);
+}
+
+__global__ __launch_bounds__(kSweepThreads, 1) void batch_apply_kernel(const BatchSys *__restrict__ tab, BatchSeg g,
+                                                                       int col) {
+  __shared__ SweepLds L;
+  // the system and its subdomain are the same for the whole workgroup:
+  // scalar registers keep the plan's fields out of the vector budget
+  const SegPos p = seg_find(g);
+  const int sys = __builtin_amdgcn_readfirstlane(p.sys), lb = __builtin_amdgcn_readfirstlane(p.lb);
+  const BatchSys &S = tab[sys];
   const ApplyPlan ap = S.ap;
-  ilu_apply_body(ap, p.lb, S.z, L);
+  const double *scale;
+  const double *r = prec_in(S, col, scale);
+  ilu_apply_body(ap, lb, r, scale, S.z, L);
 }
 
 __global__ __launch_bounds__(256) void batch_combine_kernel(const BatchSys *__restrict__ tab, BatchSeg g) {
@@ -1242,9 +1372,15 @@ hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, cons
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(const ApplyPlan &p, double *z, hipStream_t s) {
+hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s) {
+  if (p.ncoarse == 0) return hipSuccess;
+  coarse_rhs_kernel<<<blocks_for(p.ncoarse, 256), 256, 0, s>>>(p.ncoarse, p.cptr3, p.cidx3, p.pnf, p.crs);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s) {
   if (p.nsub == 0) return hipSuccess;
-  ilu_apply_kernel<<<p.nsub, kSweepThreads, 0, s>>>(p, z);
+  ilu_apply_kernel<<<p.nsub, kSweepThreads, 0, s>>>(p, r, scale, z);
   return hipGetLastError();
 }
 
@@ -1346,7 +1482,7 @@ int batch_blocks(BatchKernel k, const BatchSys &s) {
   switch (k) {
     case kBkC1: return s.c1n > 0 ? gather_sum3_blocks(s.c1n1, s.c1lanes, s.c1n, s.c1lanes2) : 0;
     case kBkC2: return s.c2n > 0 ? gather_sum3_blocks(s.c2n1, s.c2lanes, s.c2n, s.c2lanes2) : 0;
-    case kBkRhs: return blocks_for(s.npos, 256);
+    case kBkCrs: return blocks_for(s.ap.ncoarse, 256);
     case kBkApply: return s.nsub;
     case kBkCombine: return blocks_for(s.N, 256);
     case kBkCopy: return (int)std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
@@ -1363,9 +1499,9 @@ hipError_t launch_batch_precond(const BatchSys *tab, const BatchSeg *seg, int co
   if (seg[kBkCopy].total > 0) batch_copy_kernel<<<seg[kBkCopy].total, 256, 0, s>>>(tab, seg[kBkCopy], col);
   if (seg[kBkC1].total > 0) batch_c1_kernel<<<seg[kBkC1].total, 256, 0, s>>>(tab, seg[kBkC1], col);
   if (seg[kBkC2].total > 0) batch_c2_kernel<<<seg[kBkC2].total, 256, 0, s>>>(tab, seg[kBkC2]);
-  if (seg[kBkRhs].total > 0)
-    batch_rhs_kernel<<<xcd_grid(seg[kBkRhs].total), 256, 0, s>>>(tab, seg[kBkRhs], col);
-  if (seg[kBkApply].total > 0) batch_apply_kernel<<<seg[kBkApply].total, kSweepThreads, 0, s>>>(tab, seg[kBkApply]);
+  if (seg[kBkCrs].total > 0) batch_crs_kernel<<<seg[kBkCrs].total, 256, 0, s>>>(tab, seg[kBkCrs]);
+  if (seg[kBkApply].total > 0)
+    batch_apply_kernel<<<seg[kBkApply].total, kSweepThreads, 0, s>>>(tab, seg[kBkApply], col);
   if (seg[kBkCombine].total > 0) batch_combine_kernel<<<seg[kBkCombine].total, 256, 0, s>>>(tab, seg[kBkCombine]);
   return hipGetLastError();
 }

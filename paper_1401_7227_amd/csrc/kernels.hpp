@@ -51,9 +51,14 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base,
 // z = B^-1 (scale * r) over all subdomains: owned rows of a restricted
 // combine go straight into z; values needed by the additive combine are in
 // the plan's global work vector.
-// Forward right-hand sides of all subdomains in sweep order (p.rs).
+// Forward right-hand sides of all subdomains in sweep order (p.rs), for
+// the dense local solves.
 hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s);
-hipError_t launch_ilu_apply(const ApplyPlan &p, double *z, hipStream_t s);
+// Lumped inputs of the coarse rows (p.crs) from the near/far atom sums.
+hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s);
+// Both sweeps; the forward sweep gathers its inputs from r (times *scale,
+// if scale is not NULL) and p.crs.
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s);
 hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx,
                                    const double *yext, double *z, hipStream_t s);
 
@@ -112,7 +117,7 @@ struct BatchSeg {
 // Blocks each kernel gives one system (the same as a single-system launch,
 // so batched and single results are identical).
 enum BatchKernel {
-  kBkC1, kBkC2, kBkRhs, kBkApply, kBkCombine, kBkCopy, kBkSpmv, kBkRed, kBkVec, kBkOne, kBkCount
+  kBkC1, kBkC2, kBkCrs, kBkApply, kBkCombine, kBkCopy, kBkSpmv, kBkRed, kBkVec, kBkOne, kBkCount
 };
 int batch_blocks(BatchKernel k, const BatchSys &s);
 

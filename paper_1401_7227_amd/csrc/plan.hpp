@@ -49,9 +49,11 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 //   head    RecHead (kRecHead bytes).
 //   rows    32 bytes per row: int4 {LDS slot or -1, own position, output
 //           cell or -1, flags}, flags bit 0 = store the value to the global
-//           vector at the own position (always in the forward sweep), bits
-//           8.. = the row's entry count; then (short rows) the LDS slots of
-//           the row's dependencies, 8 x uint16.
+//           vector at the own position (always in the forward sweep), bit 1
+//           = the row's input is a cell value of r, to be multiplied by the
+//           basis scale (forward fine rows), bits 8.. = the row's entry
+//           count; then (short rows) the LDS slots of the row's
+//           dependencies, 8 x uint16.
 //   ldeps   long rows: int per entry, the LDS slot of the dependency.
 //   lrptr   long rows: relative entry offsets (nlong+1).
 //   vals32, vals64  short rows: jagged diagonals; entry q = koff[k] + i for
@@ -69,9 +71,9 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 //           vector into the fill slots (only in empty "fill" steps).
 // The stored record ends there (len 16-byte units); in LDS it is followed
 // by the "in" section, 3 doubles per row (at least one row): the rows'
-// inputs (forward: gathered right-hand side; backward: forward result),
-// which the streaming waves copy from the global vectors at the step's
-// positions.
+// inputs, which the streaming waves fetch (forward: gathered from r and
+// the coarse rows' lumped inputs through the position's source; backward:
+// the forward results at the step's positions).
 // A long row whose record would not fit one LDS buffer is split into
 // pieces in consecutive one-row steps that carry the partial sum in LDS.
 // A value reloaded by a fill step is produced at least two steps before
@@ -108,6 +110,8 @@ struct ApplyPlan {
   const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
   const int32_t *cptr3, *cidx3;  // coarse row -> its near/far atom sums (two-level only)
   const double *pnf;             // 3 doubles per near/far atom: lumped residual sums
+  double *crs;                   // 3 doubles per coarse row: its lumped input (two-level only)
+  int32_t ncoarse;               // coarse rows
 };
 
 struct SubDesc {

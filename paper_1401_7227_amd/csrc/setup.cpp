@@ -617,10 +617,12 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         int32_t *m = meta + 8 * j;
         m[0] = slot[i];
         m[1] = bpos[i];
-        // flags: bit 0 = store to the global vector, bits 8.. = entry count
+        // flags: bit 0 = store to the global vector, bit 1 = the input is a
+        // cell value of r (forward fine rows: scaled by the basis scale),
+        // bits 8.. = entry count
         if (fwd) {
           m[2] = -1;
-          m[3] = 1;
+          m[3] = 1 | (i < S.nfine ? 2 : 0);
         } else {
           const bool fine = i < S.nfine;
           m[2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
