@@ -343,9 +343,10 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   ap.fsrc = t32;
 #undef UP
   auto ALLOC = [&](auto **dst, size_t n) { return O.alloc(dst, n); };
+  // gathered inputs in sweep order: only the dense local solves read them
+  const size_t nrs = o->local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0;
   double *yx, *rs, *fact;
-  if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
-      (e = ALLOC(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
+  if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess || (e = ALLOC(&rs, nrs)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->bad, 1)) != hipSuccess)
@@ -561,7 +562,7 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
   uint8_t *rec = nullptr;
   double *yx = nullptr, *rs = nullptr, *fact = nullptr;
   if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
-      (e = O.alloc(&rs, (size_t)P.total_pos * 3)) != hipSuccess ||
+      (e = O.alloc(&rs, pc->opts.local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0)) != hipSuccess ||
       (e = O.alloc(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = O.alloc(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess || (e = O.alloc(&pc->bad, 1)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
