@@ -91,14 +91,15 @@ def krylov_vector_bytes(n, iters, cycles, restart):
     return dots, update, len(js)
 
 
-def timed_solves(P, torch, G, B, b, steps, warmup, profile):
+def timed_solves(P, torch, G, B, b, steps, warmup, profile, graph=False):
     """Times `steps` solves; `profile` names the phases timed by HIP events
-    inside the timed region (None: none)."""
+    inside the timed region (None: none); graph: restart cycles run as
+    captured graphs (asm_solve_graph)."""
     x = torch.zeros_like(b)
     info = None
     for _ in range(warmup):
         x.zero_()
-        _, info = P.solve(G, B, b, out=x, restart=RESTART, rtol=1e-6, max_iters=5000)
+        _, info = P.solve(G, B, b, out=x, restart=RESTART, rtol=1e-6, max_iters=5000, graph=graph)
     G.profile(profile is not None, phases=profile)
     G.profile_read(reset=True)
     torch.cuda.synchronize()
@@ -107,7 +108,7 @@ def timed_solves(P, torch, G, B, b, steps, warmup, profile):
     for _ in range(steps):
         ts = time.perf_counter()
         x.zero_()
-        _, info = P.solve(G, B, b, out=x, restart=RESTART, rtol=1e-6, max_iters=5000)  # synchronises
+        _, info = P.solve(G, B, b, out=x, restart=RESTART, rtol=1e-6, max_iters=5000, graph=graph)  # synchronises
         per.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -591,6 +592,11 @@ def main():
     if not args.no_variants:
         variants = {}
         x64 = x.cpu().numpy()
+        # the same solve with every restart cycle one captured graph
+        msg, infog, _, xg = timed_solves(P, torch, G, B, b, max(1, args.steps // 2), 1, profile=None, graph=True)
+        variants["two_level_fp64_graph_cycles"] = {
+            "ms_per_solve": round(msg, 3), "iters": infog.iters, "rel_res_true": infog.rel_res_true,
+            "rel_diff_vs_host_loop_solution": float(np.linalg.norm(xg.cpu().numpy() - x64) / np.linalg.norm(x64))}
         B32 = P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, near=NEAR, far=FAR, precision=P.FP32,
                         **SPLIT)
         ms32, info32, prof32, x32 = timed_solves(P, torch, G, B32, b, args.steps, args.warmup, profile=None)

@@ -218,6 +218,25 @@ typedef struct {
 asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
                      const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
 
+/* The same solve as asm_solve, with every restart cycle run as one HIP
+ * graph: the m Arnoldi steps, the Givens rotations (computed on the device),
+ * the triangular solve, the correction x += B^-1 V_k y and the true residual.
+ * A cycle's end (residual estimate at the tolerance, breakdown, or the step
+ * limit the host writes before each cycle) sets a device flag on which the
+ * later steps' kernels return at once, so the host synchronises once per
+ * cycle instead of reading every step.  The graph is captured on the first
+ * cycle and kept by the system for later calls with the same preconditioner,
+ * b, x and restart length (capturing again otherwise); it runs on a stream of
+ * the library's own, after the work already queued on `stream`.  Results
+ * equal asm_solve's up to rounding (the rotations are computed on the
+ * device).  Preconditioners with ILU(0) local solves and no global coarse
+ * grid (or none) only: others give ASM_ERR_INVALID.  The host thread does no
+ * per-step work; on one MI355X this is not faster than asm_solve, whose host
+ * loop keeps one step queued ahead of the device (the steps after a cycle's
+ * end still launch, then return). */
+asm_status asm_solve_graph(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
+                           const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
+
 /* Solves `count` independent systems together: systems[i] x[i] = b[i] with
  * preconds[i] (built on systems[i]), all with the same options.  Every
  * kernel launch serves all systems still iterating (one sweep launch covers
@@ -341,6 +360,8 @@ typedef struct {
 asm_status asm_profile_enable(asm_system sys, int32_t phase_mask);
 asm_status asm_profile_read(asm_system sys, asm_profile *out_host, int32_t reset);
 
+/* Frees a handle and its device memory.  A system's preconditioners are
+ * destroyed before the system. */
 void asm_destroy_precond(asm_precond pc);
 void asm_destroy_system(asm_system sys);
 

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
 
 EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_precond",
             "asm_refactor", "asm_precond_apply", "asm_precond_get_stats",
-            "asm_precond_export_sub", "asm_solve", "asm_solve_batch", "asm_destroy_precond",
+            "asm_precond_export_sub", "asm_solve", "asm_solve_graph", "asm_solve_batch", "asm_destroy_precond",
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
             "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
             "asm_server_get_state", "asm_server_destroy"]
@@ -119,6 +119,7 @@ def load() -> C.CDLL:
     L.asm_precond_export_sub.argtypes = [V, C.c_int32, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32), V, V, V, V, V]
     L.asm_solve.argtypes = [V, V, V, V, C.POINTER(SolveOpts), V, C.POINTER(SolveInfo)]
+    L.asm_solve_graph.argtypes = [V, V, V, V, C.POINTER(SolveOpts), V, C.POINTER(SolveInfo)]
     L.asm_solve_batch.argtypes = [C.c_int32, C.POINTER(V), C.POINTER(V), C.POINTER(V), C.POINTER(V),
                                   C.POINTER(SolveOpts), V, C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
     L.asm_profile_enable.argtypes = [V, C.c_int32]
@@ -320,8 +321,10 @@ class Info:
 
 
 def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6,
-          max_iters=10000, fixed_iters=0, out: torch.Tensor | None = None):
-    """Solves A x = b; returns (x, Info).  b, x0: device tensors or arrays."""
+          max_iters=10000, fixed_iters=0, out: torch.Tensor | None = None, graph=False):
+    """Solves A x = b; returns (x, Info).  b, x0: device tensors or arrays.
+    graph: every restart cycle runs as one captured HIP graph with the
+    convergence test on the device (asm_solve_graph)."""
     b = _dev(b, torch.float64)
     if out is not None:
         x = out
@@ -331,8 +334,8 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
         x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64).clone()
     o = SolveOpts(restart, rtol, max_iters, fixed_iters)
     info = SolveInfo()
-    st = _check(load().asm_solve(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o),
-                                 _stream(), C.byref(info)))
+    fn = load().asm_solve_graph if graph else load().asm_solve
+    st = _check(fn(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o), _stream(), C.byref(info)))
     return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)
 
 

@@ -11,6 +11,7 @@ thread_local std::string g_err;
 asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   Workspace &W = S->ws;
   if (W.m >= m && W.U) return ASM_OK;
+  W.drop_graph();
   W.mem.release();
   if (W.pinned) {
     (void)hipHostFree(W.pinned);
@@ -29,6 +30,10 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   ASM_HIP(W.mem.alloc(&W.coef, m + 1));
   ASM_HIP(W.mem.alloc(&W.misc, 8));
   ASM_HIP(W.mem.alloc(&W.flag, 4));
+  ASM_HIP(W.mem.alloc(&W.cst, 1));
+  ASM_HIP(W.mem.alloc(&W.gcs, m + 1));
+  ASM_HIP(W.mem.alloc(&W.gsn, m + 1));
+  ASM_HIP(W.mem.alloc(&W.gg, m + 1));
   ASM_HIP(hipHostMalloc((void **)&W.pinned, sizeof(double) * (kPubBase + (size_t)kMaxRestart * kPubStride),
                         hipHostMallocCoherent));
   ASM_HIP(hipHostGetDevicePointer((void **)&W.pinned_dev, W.pinned, 0));
@@ -175,41 +180,41 @@ asm_status numeric_setup(asm_precond pc, hipStream_t s) {
 }  // namespace
 
 asm_status apply_precond(asm_precond pc, const double *r, const double *scale, double *z, hipStream_t s,
-                         Profiler *prof) {
+                         Profiler *prof, const int *skip) {
   asm_system S = pc->sys;
   const int64_t n = 3 * (int64_t)S->pat.N;
   Profiler dummy;
   Profiler &pf = prof ? *prof : dummy;
   if (pc->opts.kind == ASM_KIND_NONE) {
     const size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_scale_copy(n, r, scale, z, s));
+    ASM_HIP(launch_scale_copy(n, r, scale, z, s, skip));
     pf.span(ASM_PHASE_OTHER, t0, s);
     return ASM_OK;
   }
   const size_t t0 = pf.mark(ASM_PHASE_LUMP, s);
   if (pc->c1.n > 0) {
     ASM_HIP(launch_gather_sum3(pc->c1.n1, pc->c1.lanes, pc->c1.n, pc->c1.lanes2, pc->c1.ptr, pc->c1.idx, r, scale,
-                               pc->PA, s));
+                               pc->PA, s, skip));
     ASM_HIP(launch_gather_sum3(pc->c2.n1, pc->c2.lanes, pc->c2.n, pc->c2.lanes2, pc->c2.ptr, pc->c2.idx, pc->PA,
-                               nullptr, pc->PNF, s));
+                               nullptr, pc->PNF, s, skip));
   }
   // the ILU sweeps gather their fine inputs from r themselves; the dense
   // local solves take every subdomain's inputs gathered in sweep order
   if (pc->opts.local == ASM_LOCAL_EXACT)
     ASM_HIP(launch_gather_rhs((int)pc->plan->total_pos, pc->ap, r, scale, s));
   else
-    ASM_HIP(launch_coarse_rhs(pc->ap, s));
+    ASM_HIP(launch_coarse_rhs(pc->ap, s, skip));
   pf.span(ASM_PHASE_LUMP, t0, s);
   const bool restricted = pc->opts.combine == ASM_COMBINE_RESTRICTED;
   const size_t t1 = pf.mark(ASM_PHASE_ILU_APPLY, s);
   if (pc->opts.local == ASM_LOCAL_EXACT)
     ASM_HIP(launch_local_dense_apply(pc->xd, (int64_t)pc->plan->total_pos, pc->ap.rs, restricted, z, pc->ap.yx, s));
   else
-    ASM_HIP(launch_ilu_apply(pc->ap, r, scale, z, s));
+    ASM_HIP(launch_ilu_apply(pc->ap, r, scale, z, s, skip));
   pf.span(ASM_PHASE_ILU_APPLY, t1, s);
   if (!restricted) {
     const size_t t2 = pf.mark(ASM_PHASE_COMBINE, s);
-    ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->ap.yx, z, s));
+    ASM_HIP(launch_additive_combine(S->pat.N, pc->cptr, pc->cidx, pc->ap.yx, z, s, skip));
     pf.span(ASM_PHASE_COMBINE, t2, s);
   }
   if (pc->opts.coarse != ASM_COARSE_NONE) {
@@ -815,6 +820,149 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
   return result;
 }
 
+// Restarted GMRES with every cycle run as one captured graph (see asm.h).
+// The arithmetic is that of asm_solve; the Givens rotations and the small
+// triangular solve run on the device, the host reads k, beta and the
+// residual estimate once per cycle.
+asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
+                           hipStream_t user_stream, asm_solve_info *info) {
+  g_err.clear();
+  if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
+  if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+  std::memset(info, 0, sizeof *info);
+  const int m = o->restart;
+  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
+    return fail(ASM_ERR_INVALID, "bad solver option");
+  if (pc->opts.kind != ASM_KIND_NONE &&
+      (pc->opts.local != ASM_LOCAL_ILU0 || pc->opts.coarse != ASM_COARSE_NONE))
+    return fail(ASM_ERR_INVALID, "graph cycles support ILU(0) local solves without a global coarse grid");
+  const int64_t n = 3 * (int64_t)S->pat.N;
+  asm_status st = ensure_workspace(S, m, user_stream);
+  if (st != ASM_OK) return st;
+  Workspace &W = S->ws;
+  // the graphs run on a stream of the library's own (a capture needs a
+  // stream that is not the legacy default one), after the caller's work
+  if (!W.gstream) ASM_HIP(hipStreamCreateWithFlags(&W.gstream, hipStreamNonBlocking));
+  if (!W.gready) ASM_HIP(hipEventCreateWithFlags(&W.gready, hipEventDisableTiming));
+  hipStream_t s = W.gstream;
+  ASM_HIP(hipEventRecord(W.gready, user_stream));
+  ASM_HIP(hipStreamWaitEvent(s, W.gready, 0));
+  bool bad = false;
+  if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
+  if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
+  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
+  const int ld = m + 1;
+  double *hp = W.pinned;
+  int nb = 0;
+  ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
+  ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
+  ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  ASM_HIP(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(hp[0]);
+  if (bnorm == 0.0 && o->fixed_iters == 0) {
+    ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    ASM_HIP(hipStreamSynchronize(s));
+    return ASM_OK;
+  }
+  const double scl = bnorm > 0.0 ? bnorm : 1.0;
+  const double tol = o->rtol * bnorm;
+  // initial residual: beta into misc[1], 1/beta into scale[0], r into U_0
+  int nbr = 0;
+  ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
+  ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+  ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  ASM_HIP(hipStreamSynchronize(s));
+  double beta = hp[0];
+  info->rel_res_true = info->rel_res_est = beta / scl;
+  if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
+  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+  // stopping test of the cycles (host-written, read by the Givens kernel).
+  // Pinned scalars: [4, 7) this state, [8, 11) what a cycle publishes,
+  // [12] the step limit of the next cycle.
+  static_assert(sizeof(CycleState) <= 3 * sizeof(double), "cycle state fits its pinned slot");
+  CycleState cs0{};
+  cs0.use_tol = o->fixed_iters == 0 ? 1 : 0;
+  cs0.tol = tol;
+  std::memcpy(hp + 4, &cs0, sizeof cs0);
+  ASM_HIP(hipMemcpyAsync(W.cst, hp + 4, sizeof cs0, hipMemcpyHostToDevice, s));
+  ASM_HIP(hipStreamSynchronize(s));
+  double *pub = W.pinned_dev + 8;
+  const void *key[4] = {pc, b, x, reinterpret_cast<const void *>((intptr_t)m)};
+  if (!W.gexec || std::memcmp(W.gkey, key, sizeof key) != 0) {
+    W.drop_graph();
+    // one cycle: m steps whose kernels return at once after the cycle's
+    // end, then the correction x += B^-1 V_k y and the true residual
+    const int *skip = &W.cst->done;
+    ASM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    auto record = [&]() -> asm_status {
+      Profiler none;
+      ASM_HIP(launch_cycle_start(W.cst, W.gg, W.misc + 1, s));
+      for (int j = 0; j < m; ++j) {
+        const double *Uj = W.U + (size_t)j * W.ldu;
+        asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &none, skip);
+        if (e2 != ASM_OK) return e2;
+        ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, skip));
+        int nbd = 0, nbu = 0;
+        ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, skip));
+        ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s, skip));
+        ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
+                              &nbu, s, skip));
+        ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
+                                     nullptr, s, skip));
+        ASM_HIP(launch_givens(j, ld, W.H, W.gcs, W.gsn, W.gg, W.dvec, W.cst, s));
+      }
+      ASM_HIP(launch_cycle_end(ld, W.H, W.gg, W.scale, W.coef, W.cst, s));
+      ASM_HIP(launch_lincomb_dev(n, W.cst, W.U, W.ldu, W.coef, W.t, s));
+      asm_status e2 = apply_precond(pc, W.t, nullptr, W.z, s, &none);
+      if (e2 != ASM_OK) return e2;
+      ASM_HIP(launch_axpy(n, W.z, x, s));
+      int nbe = 0;
+      ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbe, s));
+      ASM_HIP(launch_norm_finalize(nbe, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+      ASM_HIP(launch_cycle_publish(W.cst, W.gg, W.misc + 1, pub, s));
+      return ASM_OK;
+    };
+    const asm_status rec = record();
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rec != ASM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rec;
+    }
+    if (ec != hipSuccess) return fail(ASM_ERR_HIP, hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&W.gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      W.gexec = nullptr;
+      return fail(ASM_ERR_HIP, hipGetErrorString(ei));
+    }
+    std::memcpy(W.gkey, key, sizeof key);
+  }
+  asm_status result = ASM_NOT_CONVERGED;
+  int *kmax_host = reinterpret_cast<int *>(hp + 12);
+  while (true) {
+    if (beta == 0.0) { result = ASM_OK; break; }
+    info->cycles++;
+    *kmax_host = std::min(m, limit - info->iters);
+    ASM_HIP(hipMemcpyAsync(&W.cst->kmax, kmax_host, sizeof(int), hipMemcpyHostToDevice, s));
+    ASM_HIP(hipGraphLaunch(W.gexec, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    const double *pr = hp + 8;
+    info->iters += (int)pr[0];
+    beta = pr[1];
+    info->rel_res_est = pr[2] / scl;
+    info->rel_res_true = beta / scl;
+    if (o->fixed_iters > 0) {
+      if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
+    } else if (beta <= tol) {
+      result = ASM_OK;
+      break;
+    }
+    if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
+  }
+  return result;
+}
+
 asm_status asm_profile_enable(asm_system S, int32_t phase_mask) {
   g_err.clear();
   if (!S) return fail(ASM_ERR_INVALID, "NULL argument");
@@ -834,7 +982,12 @@ asm_status asm_profile_read(asm_system S, asm_profile *out, int32_t reset) {
   return ASM_OK;
 }
 
-void asm_destroy_precond(asm_precond pc) { delete pc; }
+void asm_destroy_precond(asm_precond pc) {
+  // a cycle graph captured for this preconditioner holds its device
+  // pointers: it goes with it (a later handle may reuse the address)
+  if (pc && pc->sys && pc->sys->ws.gkey[0] == pc) pc->sys->ws.drop_graph();
+  delete pc;
+}
 void asm_destroy_system(asm_system S) { delete S; }
 
 }  // extern "C"

@@ -163,7 +163,24 @@ struct Workspace {
   double *pinned = nullptr;   // host staging: scalars, then one published column per step
   double *pinned_dev = nullptr;  // the same memory as seen by kernels
   hipEvent_t step_done[kMaxRestart] = {};
+  // restart cycles run as graphs (asm_solve_graph): device cycle state and
+  // Givens arrays, the stream the graphs run on, and the executable graph
+  // with what it was captured for (preconditioner, b, x, restart length)
+  asmx::CycleState *cst = nullptr;
+  double *gcs = nullptr, *gsn = nullptr, *gg = nullptr;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gready = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void *gkey[4] = {};
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    gkey[0] = gkey[1] = gkey[2] = gkey[3] = nullptr;
+  }
   ~Workspace() {
+    drop_graph();
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (gready) (void)hipEventDestroy(gready);
     if (pinned) (void)hipHostFree(pinned);
     for (hipEvent_t e : step_done)
       if (e) (void)hipEventDestroy(e);
@@ -184,8 +201,10 @@ asm_status validate_pattern(const HostPattern &P);
 asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o);
 asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_ptr<PlanHost> plan,
                            hipStream_t stream, asm_precond *out);
+// skip: optional device flag of a graph-mode cycle (the ILU(0) and
+// unpreconditioned paths only).
 asm_status apply_precond(asm_precond pc, const double *r, const double *scale, double *z, hipStream_t s,
-                         Profiler *prof = nullptr);
+                         Profiler *prof = nullptr, const int *skip = nullptr);
 
 }  // namespace asmx
 

@@ -161,7 +161,9 @@ __global__ __launch_bounds__(256) void spmv_kernel(int N, int nlogical, const in
                                                    const double *__restrict__ vals,
                                                    const double *__restrict__ x,
                                                    const double *__restrict__ b, double *__restrict__ y,
-                                                   double *__restrict__ partial) {
+                                                   double *__restrict__ partial,
+                                                   const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ double red[4];
   spmv_body<RESID>(blockIdx.x, N, nlogical, sptr, cols, vals, x, b, y, partial, red);
 }
@@ -236,7 +238,9 @@ __global__ __launch_bounds__(256) void gather_sum3_kernel(int n1, int G1, int nd
                                                           const int32_t *__restrict__ idx,
                                                           const double *__restrict__ src,
                                                           const double *__restrict__ scale,
-                                                          double *__restrict__ dst) {
+                                                          double *__restrict__ dst,
+                                                          const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   gather_sum3_body(blockIdx.x, n1, G1, ndst, G2, ptr, idx, src, scale, dst);
 }
 
@@ -873,7 +877,9 @@ __device__ __forceinline__ void ilu_apply_body(const ApplyPlan &p, int sub, cons
 
 __global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p, const double *__restrict__ r,
                                                                      const double *__restrict__ scale,
-                                                                     double *__restrict__ z) {
+                                                                     double *__restrict__ z,
+                                                                     const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ SweepLds L;
   ilu_apply_body(p, blockIdx.x, r, scale, z, L);
 }
@@ -931,7 +937,9 @@ __device__ __forceinline__ void coarse_rhs_body(int bid, int ncoarse, const int3
 
 __global__ __launch_bounds__(256) void coarse_rhs_kernel(int ncoarse, const int32_t *__restrict__ cptr3,
                                                          const int32_t *__restrict__ cidx3,
-                                                         const double *__restrict__ pnf, double *__restrict__ crs) {
+                                                         const double *__restrict__ pnf, double *__restrict__ crs,
+                                                         const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   coarse_rhs_body(blockIdx.x, ncoarse, cptr3, cidx3, pnf, crs);
 }
 
@@ -951,7 +959,9 @@ __device__ __forceinline__ void additive_combine_body(int bid, int N, const int3
 __global__ __launch_bounds__(256) void additive_combine_kernel(int N, const int32_t *__restrict__ cptr,
                                                                const int32_t *__restrict__ cidx,
                                                                const double *__restrict__ yext,
-                                                               double *__restrict__ z) {
+                                                               double *__restrict__ z,
+                                                               const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   additive_combine_body(blockIdx.x, N, cptr, cidx, yext, z);
 }
 
@@ -1001,7 +1011,9 @@ __device__ __forceinline__ void multidot_body(int bid, int nblk, int64_t n, cons
 template <int NV>
 __global__ __launch_bounds__(256) void multidot_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
                                                        const double *__restrict__ w,
-                                                       double *__restrict__ partial) {
+                                                       double *__restrict__ partial,
+                                                       const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ double red[4 * (NV + 1)];
   multidot_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, w, partial, red);
 }
@@ -1016,7 +1028,9 @@ __device__ __forceinline__ void reduce_cols_body(int c, int nblocks, int ncols, 
 }
 
 __global__ __launch_bounds__(256) void reduce_cols_kernel(int nblocks, int ncols, const double *__restrict__ partial,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out,
+                                                          const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ double red[4];
   reduce_cols_body(blockIdx.x, nblocks, ncols, partial, out, red);
 }
@@ -1062,7 +1076,9 @@ template <int NV>
 __global__ __launch_bounds__(256) void update_kernel(int64_t n, const double *__restrict__ U, int64_t ldu,
                                                      const double *__restrict__ d, const double *__restrict__ scale,
                                                      const double *__restrict__ w, double *__restrict__ unew,
-                                                     double *__restrict__ partial) {
+                                                     double *__restrict__ partial,
+                                                     const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ double red[4];
   update_body<NV>(blockIdx.x, gridDim.x, n, U, ldu, d, scale, w, unew, partial, red);
 }
@@ -1099,7 +1115,9 @@ __global__ __launch_bounds__(256) void norm_finalize_kernel(int nblocks, const d
                                                             const double *__restrict__ d,
                                                             const double *__restrict__ scale,
                                                             double *__restrict__ hcol, double *__restrict__ scale_out,
-                                                            double *__restrict__ pub) {
+                                                            double *__restrict__ pub,
+                                                            const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   __shared__ double red[4];
   norm_finalize_body(nblocks, partial, nv, d, scale, hcol, scale_out, pub, red);
 }
@@ -1152,7 +1170,9 @@ __device__ __forceinline__ void scale_copy_body(int bid, int nblk, int64_t n, co
 }
 
 __global__ __launch_bounds__(256) void scale_copy_kernel(int64_t n, const double *__restrict__ r, const double *__restrict__ scale,
-                                                         double *__restrict__ z) {
+                                                         double *__restrict__ z,
+                                                         const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
   scale_copy_body(blockIdx.x, gridDim.x, n, r, scale, z);
 }
 
@@ -1310,9 +1330,103 @@ __global__ __launch_bounds__(256) void batch_axpy_kernel(const BatchSys *__restr
   axpy_body(p.lb, p.nb, S.n, S.z, S.x);
 }
 
+// ---------------------------------------------------------------- device-side restart cycles
+// The host loop's Givens and triangular-solve arithmetic, one thread, for a
+// cycle that runs without the host.
+__global__ void cycle_start_kernel(CycleState *st, double *g, const double *beta) {
+  if (threadIdx.x != 0) return;
+  st->done = 0;
+  st->k = 0;
+  g[0] = *beta;
+}
+
+__global__ void givens_kernel(int j, int ld, double *H, double *cs, double *sn, double *g, const double *d,
+                              CycleState *st) {
+  if (threadIdx.x != 0 || st->done) return;
+  double *col = H + (size_t)j * ld;
+  const double hn = col[j + 1];
+  const double w0 = sqrt(d[j + 1]);
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * c;
+    col[i + 1] = -sn[i] * a + cs[i] * c;
+  }
+  const double rho = hypot(col[j], col[j + 1]);
+  if (rho == 0.0) {
+    cs[j] = 1.0;
+    sn[j] = 0.0;
+  } else {
+    cs[j] = col[j] / rho;
+    sn[j] = col[j + 1] / rho;
+  }
+  col[j] = rho;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  st->k = j + 1;
+  if (hn <= 1e-14 * w0 || (st->use_tol && fabs(g[j + 1]) <= st->tol) || j + 1 >= st->kmax) st->done = 1;
+}
+
+__global__ void cycle_end_kernel(int ld, const double *H, const double *g, const double *scale, double *coef,
+                                 const CycleState *st) {
+  if (threadIdx.x != 0) return;
+  const int k = st->k;
+  double y[kMaxRestart];
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int c = i + 1; c < k; ++c) acc -= H[(size_t)c * ld + i] * y[c];
+    y[i] = acc / H[(size_t)i * ld + i];
+  }
+  for (int i = 0; i < k; ++i) coef[i] = y[i] * scale[i];
+}
+
+__global__ __launch_bounds__(256) void lincomb_dev_kernel(int64_t n, const CycleState *__restrict__ st,
+                                                          const double *__restrict__ U, int64_t ldu,
+                                                          const double *__restrict__ coef, double *__restrict__ out) {
+  __shared__ double cs[kMaxRestart + 1];
+  lincomb_body(blockIdx.x, gridDim.x, n, st->k, U, ldu, coef, out, cs);
+}
+
+__global__ void cycle_publish_kernel(const CycleState *st, const double *g, const double *beta, double *pub) {
+  if (threadIdx.x != 0) return;
+  const int k = st->k;
+  pub[0] = (double)k;
+  pub[1] = *beta;
+  pub[2] = fabs(g[k]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+hipError_t launch_cycle_start(CycleState *st, double *g, const double *beta, hipStream_t s) {
+  cycle_start_kernel<<<1, 64, 0, s>>>(st, g, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens(int j, int ld, double *H, double *cs, double *sn, double *g, const double *d,
+                         CycleState *st, hipStream_t s) {
+  givens_kernel<<<1, 64, 0, s>>>(j, ld, H, cs, sn, g, d, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cycle_end(int ld, const double *H, const double *g, const double *scale, double *coef,
+                            const CycleState *st, hipStream_t s) {
+  cycle_end_kernel<<<1, 64, 0, s>>>(ld, H, g, scale, coef, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb_dev(int64_t n, const CycleState *st, const double *U, int64_t ldu, const double *coef,
+                              double *out, hipStream_t s) {
+  const int grid = std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  lincomb_dev_kernel<<<grid, 256, 0, s>>>(n, st, U, ldu, coef, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cycle_publish(const CycleState *st, const double *g, const double *beta, double *pub,
+                                hipStream_t s) {
+  cycle_publish_kernel<<<1, 64, 0, s>>>(st, g, beta, pub);
+  return hipGetLastError();
+}
 hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_t s) {
   const int nslots = A.ngroups * 64;
   if (nslots == 0) return hipSuccess;
@@ -1320,9 +1434,9 @@ hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s) {
+hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip) {
   const int nlog = blocks_for(A.N, 256);
-  spmv_kernel<false><<<xcd_grid(nlog), 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, nullptr, y, nullptr);
+  spmv_kernel<false><<<xcd_grid(nlog), 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, nullptr, y, nullptr, skip);
   return hipGetLastError();
 }
 
@@ -1330,7 +1444,7 @@ hipError_t launch_residual(const SellDev &A, const double *x, const double *b, d
                            int *nblocks_out, hipStream_t s) {
   const int nlog = blocks_for(A.N, 256);
   const int grid = xcd_grid(nlog);
-  spmv_kernel<true><<<grid, 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, b, r, partial);
+  spmv_kernel<true><<<grid, 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, b, r, partial, nullptr);
   *nblocks_out = grid;
   return hipGetLastError();
 }
@@ -1345,11 +1459,11 @@ hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx, 
 static bool lanes_ok(int g) { return g >= 1 && g <= 64 && (g & (g - 1)) == 0; }
 
 hipError_t launch_gather_sum3(int n1, int lanes1, int n, int lanes2, const int32_t *ptr, const int32_t *idx,
-                              const double *src, const double *scale, double *dst, hipStream_t s) {
+                              const double *src, const double *scale, double *dst, hipStream_t s, const int *skip) {
   if (n == 0) return hipSuccess;
   if (n1 < 0 || n1 > n || !lanes_ok(lanes1) || !lanes_ok(lanes2)) return hipErrorInvalidValue;
   gather_sum3_kernel<<<gather_sum3_blocks(n1, lanes1, n, lanes2), 256, 0, s>>>(n1, lanes1, n, lanes2, ptr, idx,
-                                                                                src, scale, dst);
+                                                                                src, scale, dst, skip);
   return hipGetLastError();
 }
 
@@ -1372,81 +1486,86 @@ hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, cons
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s) {
+hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s, const int *skip) {
   if (p.ncoarse == 0) return hipSuccess;
-  coarse_rhs_kernel<<<blocks_for(p.ncoarse, 256), 256, 0, s>>>(p.ncoarse, p.cptr3, p.cidx3, p.pnf, p.crs);
+  coarse_rhs_kernel<<<blocks_for(p.ncoarse, 256), 256, 0, s>>>(p.ncoarse, p.cptr3, p.cidx3, p.pnf, p.crs, skip);
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s) {
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s,
+                            const int *skip) {
   if (p.nsub == 0) return hipSuccess;
-  ilu_apply_kernel<<<p.nsub, kSweepThreads, 0, s>>>(p, r, scale, z);
+  ilu_apply_kernel<<<p.nsub, kSweepThreads, 0, s>>>(p, r, scale, z, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx, const double *yext, double *z,
-                                   hipStream_t s) {
-  additive_combine_kernel<<<blocks_for(N, 256), 256, 0, s>>>(N, cptr, cidx, yext, z);
+                                   hipStream_t s, const int *skip) {
+  additive_combine_kernel<<<blocks_for(N, 256), 256, 0, s>>>(N, cptr, cidx, yext, z, skip);
   return hipGetLastError();
 }
 
 template <int NV>
 static void multidot_launch(int64_t n, const double *U, int64_t ldu, const double *w, double *partial, int grid,
-                            hipStream_t s) {
-  multidot_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, w, partial);
+                            hipStream_t s, const int *skip) {
+  multidot_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, w, partial, skip);
 }
 
 template <int... Is>
 static bool multidot_dispatch(int nv, int64_t n, const double *U, int64_t ldu, const double *w, double *partial,
-                              int grid, hipStream_t s, std::integer_sequence<int, Is...>) {
+                              int grid, hipStream_t s, const int *skip, std::integer_sequence<int, Is...>) {
   bool done = false;
-  ((nv == Is + 1 ? (multidot_launch<Is + 1>(n, U, ldu, w, partial, grid, s), done = true) : false), ...);
+  ((nv == Is + 1 ? (multidot_launch<Is + 1>(n, U, ldu, w, partial, grid, s, skip), done = true) : false), ...);
   return done;
 }
 
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w, double *partial,
-                           int *nblocks_out, hipStream_t s) {
+                           int *nblocks_out, hipStream_t s, const int *skip) {
   const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > 32) return hipErrorInvalidValue;
-  multidot_dispatch(nv, n, U, ldu, w, partial, grid, s, std::make_integer_sequence<int, 32>{});
+  multidot_dispatch(nv, n, U, ldu, w, partial, grid, s, skip, std::make_integer_sequence<int, 32>{});
   *nblocks_out = grid;
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out, hipStream_t s) {
-  reduce_cols_kernel<<<ncols, 256, 0, s>>>(nblocks, ncols, partial, out);
+hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out, hipStream_t s,
+                              const int *skip) {
+  reduce_cols_kernel<<<ncols, 256, 0, s>>>(nblocks, ncols, partial, out, skip);
   return hipGetLastError();
 }
 
 template <int NV>
 static void update_launch(int64_t n, const double *U, int64_t ldu, const double *d, const double *scale,
-                          const double *w, double *unew, double *partial, int grid, hipStream_t s) {
-  update_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, d, scale, w, unew, partial);
+                          const double *w, double *unew, double *partial, int grid, hipStream_t s,
+                          const int *skip) {
+  update_kernel<NV><<<grid, 256, 0, s>>>(n, U, ldu, d, scale, w, unew, partial, skip);
 }
 
 template <int... Is>
 static bool update_dispatch(int nv, int64_t n, const double *U, int64_t ldu, const double *d, const double *scale,
                             const double *w, double *unew, double *partial, int grid, hipStream_t s,
-                            std::integer_sequence<int, Is...>) {
+                            const int *skip, std::integer_sequence<int, Is...>) {
   bool done = false;
-  ((nv == Is + 1 ? (update_launch<Is + 1>(n, U, ldu, d, scale, w, unew, partial, grid, s), done = true) : false),
+  ((nv == Is + 1 ? (update_launch<Is + 1>(n, U, ldu, d, scale, w, unew, partial, grid, s, skip), done = true)
+                 : false),
    ...);
   return done;
 }
 
 hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d, const double *scale,
-                         const double *w, double *unew, double *partial, int *nblocks_out, hipStream_t s) {
+                         const double *w, double *unew, double *partial, int *nblocks_out, hipStream_t s,
+                         const int *skip) {
   const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
-  update_dispatch(nv, n, U, ldu, d, scale, w, unew, partial, grid, s,
+  update_dispatch(nv, n, U, ldu, d, scale, w, unew, partial, grid, s, skip,
                   std::make_integer_sequence<int, kMaxRestart>{});
   *nblocks_out = grid;
   return hipGetLastError();
 }
 
 hipError_t launch_norm_finalize(int nblocks, const double *partial, int nv, const double *d, const double *scale,
-                                double *hcol, double *scale_out, double *pub, hipStream_t s) {
-  norm_finalize_kernel<<<1, 256, 0, s>>>(nblocks, partial, nv, d, scale, hcol, scale_out, pub);
+                                double *hcol, double *scale_out, double *pub, hipStream_t s, const int *skip) {
+  norm_finalize_kernel<<<1, 256, 0, s>>>(nblocks, partial, nv, d, scale, hcol, scale_out, pub, skip);
   return hipGetLastError();
 }
 
@@ -1570,9 +1689,10 @@ hipError_t launch_batch_axpy(const BatchSys *tab, const BatchSeg &seg, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s) {
+hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s,
+                             const int *skip) {
   const int grid = std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
-  scale_copy_kernel<<<grid, 256, 0, s>>>(n, r, scale, z);
+  scale_copy_kernel<<<grid, 256, 0, s>>>(n, r, scale, z, skip);
   return hipGetLastError();
 }
 

@@ -22,8 +22,12 @@ struct SellDev {
 constexpr int kReduceBlocks = 1024;  // partial-sum blocks of the Krylov kernels
 constexpr int kMaxRestart = 32;
 
+// The launchers of the kernels an Arnoldi step runs take an optional skip
+// flag (device): a kernel whose flag is set returns at once.  A restart
+// cycle captured as one graph sets it when the cycle ends on the device.
+
 hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_t s);
-hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s);
+hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip = nullptr);
 // r = b - A x; partial[kReduceBlocks-sized region] receives per-block sums of r.r
 hipError_t launch_residual(const SellDev &A, const double *x, const double *b, double *r,
                            double *partial, int *nblocks_out, hipStream_t s);
@@ -35,7 +39,8 @@ hipError_t launch_gather_sum9(int ndst, const int32_t *ptr, const int32_t *idx,
 // entry).  Destinations [0, n1) take lanes1 threads each, [n1, n) lanes2
 // (powers of two, 1 .. 64).
 hipError_t launch_gather_sum3(int n1, int lanes1, int n, int lanes2, const int32_t *ptr, const int32_t *idx,
-                              const double *src, const double *scale, double *dst, hipStream_t s);
+                              const double *src, const double *scale, double *dst, hipStream_t s,
+                              const int *skip = nullptr);
 // Blocks of 256 threads of that launch.
 inline int gather_sum3_blocks(int n1, int lanes1, int n, int lanes2) {
   return (int)(((int64_t)n1 * lanes1 + 255) / 256 + ((int64_t)(n - n1) * lanes2 + 255) / 256);
@@ -55,36 +60,66 @@ hipError_t launch_relayout(int nslots, const int32_t *src, const int32_t *base,
 // the dense local solves.
 hipError_t launch_gather_rhs(int npos, const ApplyPlan &p, const double *r, const double *scale, hipStream_t s);
 // Lumped inputs of the coarse rows (p.crs) from the near/far atom sums.
-hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s);
+hipError_t launch_coarse_rhs(const ApplyPlan &p, hipStream_t s, const int *skip = nullptr);
 // Both sweeps; the forward sweep gathers its inputs from r (times *scale,
 // if scale is not NULL) and p.crs.
-hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s);
+hipError_t launch_ilu_apply(const ApplyPlan &p, const double *r, const double *scale, double *z, hipStream_t s,
+                            const int *skip = nullptr);
 hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *cidx,
-                                   const double *yext, double *z, hipStream_t s);
+                                   const double *yext, double *z, hipStream_t s, const int *skip = nullptr);
 
 // Krylov kernels (n = scalar length).
 // U columns (stride ldu, even) and w must be 16-byte aligned.
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w,
-                           double *partial, int *nblocks_out, hipStream_t s);
+                           double *partial, int *nblocks_out, hipStream_t s, const int *skip = nullptr);
 hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out,
-                              hipStream_t s);
+                              hipStream_t s, const int *skip = nullptr);
 // unew = w - sum_{i<nv} (scale[i] d[i]) scale[i] U_i, d the reduced
 // projections of the step; per-block partial sums of ||unew||^2.
 hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d,
                          const double *scale, const double *w, double *unew, double *partial,
-                         int *nblocks_out, hipStream_t s);
+                         int *nblocks_out, hipStream_t s, const int *skip = nullptr);
 // One block: h = sqrt(sum of partial[0..nblocks)) into hcol[nv], 1/h (0 if
 // h = 0) into *scale_out, hcol[i] = scale[i]*d[i] for i < nv; if pub is not
 // NULL, hcol[0..nv] and sqrt(d[nv]) are also written to pub[0..nv+1].
 hipError_t launch_norm_finalize(int nblocks, const double *partial, int nv, const double *d, const double *scale,
-                                double *hcol, double *scale_out, double *pub, hipStream_t s);
+                                double *hcol, double *scale_out, double *pub, hipStream_t s,
+                                const int *skip = nullptr);
 hipError_t launch_lincomb(int64_t n, int nv, const double *U, int64_t ldu, const double *coef,
                           double *out, hipStream_t s);
 hipError_t launch_axpy(int64_t n, const double *z, double *x, hipStream_t s);
 
 hipError_t launch_check_finite(int64_t n, const double *v, int *flag, hipStream_t s);
+
+// ---------------------------------------------------------------- device-side restart cycles
+// State of a restart cycle that runs on the device (a captured graph): done
+// is the step kernels' skip flag, k the steps taken, kmax the steps allowed
+// (written by the host before each cycle), use_tol / tol the stopping test
+// on the residual estimate |g_k|.
+struct CycleState {
+  int done, k, kmax, use_tol;
+  double tol;
+};
+// done = 0, k = 0, g[0] = *beta.
+hipError_t launch_cycle_start(CycleState *st, double *g, const double *beta, hipStream_t s);
+// Givens step j: rotates column j of H (leading dimension ld) by the
+// earlier rotations, forms rotation j, updates g, sets k = j+1 and done on a
+// breakdown (h_{j+1,j} <= 1e-14 ||w||, ||w||^2 = d[j+1]), on |g_{j+1}| <= tol
+// or at kmax steps.  Does nothing once done is set.
+hipError_t launch_givens(int j, int ld, double *H, double *cs, double *sn, double *g, const double *d,
+                         CycleState *st, hipStream_t s);
+// y from the rotated H and g (k = st->k rows), coef[i] = y[i] * scale[i].
+hipError_t launch_cycle_end(int ld, const double *H, const double *g, const double *scale, double *coef,
+                            const CycleState *st, hipStream_t s);
+// out = sum_{i < st->k} coef[i] U_i.
+hipError_t launch_lincomb_dev(int64_t n, const CycleState *st, const double *U, int64_t ldu, const double *coef,
+                              double *out, hipStream_t s);
+// pub[0] = k, pub[1] = *beta, pub[2] = |g_k| (pinned host memory).
+hipError_t launch_cycle_publish(const CycleState *st, const double *g, const double *beta, double *pub,
+                                hipStream_t s);
 hipError_t launch_norm2(int64_t n, const double *v, double *partial, int *nblocks_out, hipStream_t s);
-hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s);
+hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s,
+                             const int *skip = nullptr);
 
 // ---------------------------------------------------------------- batches
 // One system of a batched solve: what the batched kernels read (device
