@@ -390,9 +390,10 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 // One workgroup per subdomain runs its forward sweep y = L^-1 R_i r and
 // backward sweep x = U^-1 y (D^-1 applied per row).  Every level step is a
 // contiguous record (see RecStep) that the streaming waves copy from HBM,
-// together with the step's row inputs, into one of two LDS buffers (step s
-// is computed from one while step s+1 is written into the other); the
-// loads run several steps ahead in registers.  The computing waves then touch global
+// together with the step's row inputs (forward: gathered from r and the
+// coarse rows' lumped inputs; backward: the forward results), into one of
+// two LDS buffers (step s is computed from one while step s+1 is written
+// into the other); the loads run several steps ahead in registers.  The computing waves then touch global
 // memory only to store results: vector values live in an LDS slot pool,
 // and values without a slot are reloaded into LDS by "fill" steps.
 constexpr int kRecU4 = kRecBytes / 16;
@@ -884,9 +885,10 @@ __global__ __launch_bounds__(kSweepThreads, 1) void ilu_apply_kernel(ApplyPlan p
   ilu_apply_body(p, blockIdx.x, r, scale, z, L);
 }
 
-// Forward right-hand sides in sweep order: the restriction R_i r of every
-// subdomain.  Fine rows gather r (times the basis scale); a coarse row sums
-// its near/far atoms' lumped residuals (App. B, eq. (B.2)).  Sweep order
+// Forward right-hand sides in sweep order, for the dense local solves (the
+// ILU sweeps gather their own): the restriction R_i r of every subdomain.
+// Fine rows gather r (times the basis scale); a coarse row sums its near/far
+// atoms' lumped residuals (App. B, eq. (B.2)).  Sweep order
 // walks a subdomain's level planes, so consecutive positions touch cells far
 // apart in r while a few consecutive blocks share cache lines: the launches
 // give each XCD a contiguous range of blocks, so those lines stay in one L2.

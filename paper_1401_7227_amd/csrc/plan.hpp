@@ -105,7 +105,7 @@ struct ApplyPlan {
   const struct SubDesc *sub;
   const RecStep *fstep, *bstep;
   const void *rec;              // all records (16-byte aligned)
-  double *rs;                   // 3 doubles per forward position: gathered rhs
+  double *rs;                   // 3 doubles per forward position: gathered rhs (dense local solves)
   double *yx;                   // 3 doubles per backward position
   const int32_t *fsrc;          // forward position -> cell (>= 0) or -(1+coarse row)
   const int32_t *cptr3, *cidx3;  // coarse row -> its near/far atom sums (two-level only)
