@@ -20,7 +20,9 @@
  *  - Work is ordered on the given stream; calls that return host results
  *    synchronise that stream before returning.
  *  - Errors are returned as asm_status, never thrown; asm_last_error()
- *    gives a thread-local message for the last failing call.
+ *    gives a thread-local message for the last failing call.  A host
+ *    allocation failure inside the library returns ASM_ERR_OOM, any other
+ *    internal C++ exception ASM_ERR_INVALID ("internal error: ...").
  *  - A handle must not be used from two threads at once.  Handles hold
  *    device memory until destroyed.
  */

@@ -729,179 +729,192 @@ extern "C" {
 asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
                            const double *const *b, double *const *x, const asm_solve_opts *o, hipStream_t s,
                            asm_solve_info *infos, int32_t *status) {
-  g_err.clear();
-  if (count < 1 || !systems || !preconds || !b || !x || !o || !infos || !status)
-    return fail(ASM_ERR_INVALID, "NULL argument or empty batch");
-  asm_status st = check_solve_opts(o);
-  if (st != ASM_OK) return st;
-  for (int i = 0; i < count; ++i) {
-    if (!systems[i] || !preconds[i] || !b[i] || !x[i]) return fail(ASM_ERR_INVALID, "NULL system, preconditioner or vector");
-    if (preconds[i]->sys != systems[i]) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-    if (preconds[i]->opts.coarse != ASM_COARSE_NONE || preconds[i]->opts.local != ASM_LOCAL_ILU0)
-      return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in batched solves");
-    for (int k = 0; k < i; ++k)
-      if (systems[k] == systems[i]) return fail(ASM_ERR_INVALID, "a system appears twice in the batch");
+  try {
+    g_err.clear();
+    if (count < 1 || !systems || !preconds || !b || !x || !o || !infos || !status)
+      return fail(ASM_ERR_INVALID, "NULL argument or empty batch");
+    asm_status st = check_solve_opts(o);
+    if (st != ASM_OK) return st;
+    for (int i = 0; i < count; ++i) {
+      if (!systems[i] || !preconds[i] || !b[i] || !x[i]) return fail(ASM_ERR_INVALID, "NULL system, preconditioner or vector");
+      if (preconds[i]->sys != systems[i]) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+      if (preconds[i]->opts.coarse != ASM_COARSE_NONE || preconds[i]->opts.local != ASM_LOCAL_ILU0)
+        return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in batched solves");
+      for (int k = 0; k < i; ++k)
+        if (systems[k] == systems[i]) return fail(ASM_ERR_INVALID, "a system appears twice in the batch");
+    }
+    BatchEngine eng;
+    if ((st = eng.init(count, *o, s)) != ASM_OK) return st;
+    std::vector<BatchEngine::NewSolve> add(count);
+    for (int i = 0; i < count; ++i) add[i] = {systems[i], preconds[i], b[i], x[i], i};
+    std::vector<int> slots;
+    if ((st = eng.add(add, slots, true)) != ASM_OK) return st;
+    for (int i = 0; i < count; ++i)
+      if (eng.entry(slots[i]).status == ASM_ERR_NONFINITE)
+        return fail(ASM_ERR_NONFINITE, "non-finite b or x0 in batch entry " + std::to_string(i));
+    while (eng.iterating() > 0)
+      if ((st = eng.cycle()) != ASM_OK) return st;
+    ASM_HIP(hipStreamSynchronize(s));
+    asm_status result = ASM_OK;
+    for (int i = 0; i < count; ++i) {
+      const BatchEntry &E = eng.entry(slots[i]);
+      infos[i] = E.info;
+      status[i] = E.status;
+      if (E.status != ASM_OK) result = ASM_NOT_CONVERGED;
+    }
+    return result;
   }
-  BatchEngine eng;
-  if ((st = eng.init(count, *o, s)) != ASM_OK) return st;
-  std::vector<BatchEngine::NewSolve> add(count);
-  for (int i = 0; i < count; ++i) add[i] = {systems[i], preconds[i], b[i], x[i], i};
-  std::vector<int> slots;
-  if ((st = eng.add(add, slots, true)) != ASM_OK) return st;
-  for (int i = 0; i < count; ++i)
-    if (eng.entry(slots[i]).status == ASM_ERR_NONFINITE)
-      return fail(ASM_ERR_NONFINITE, "non-finite b or x0 in batch entry " + std::to_string(i));
-  while (eng.iterating() > 0)
-    if ((st = eng.cycle()) != ASM_OK) return st;
-  ASM_HIP(hipStreamSynchronize(s));
-  asm_status result = ASM_OK;
-  for (int i = 0; i < count; ++i) {
-    const BatchEntry &E = eng.entry(slots[i]);
-    infos[i] = E.info;
-    status[i] = E.status;
-    if (E.status != ASM_OK) result = ASM_NOT_CONVERGED;
-  }
-  return result;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_server_create(const asm_server_opts *o, hipStream_t stream, asm_server *out) {
-  g_err.clear();
-  if (!o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
-  *out = nullptr;
-  asm_status st = check_solve_opts(&o->solve);
-  if (st != ASM_OK) return st;
-  if (o->max_active < 1 || o->max_active > ASM_SERVER_MAX_ACTIVE || o->hbm_budget_bytes < 0)
-    return fail(ASM_ERR_INVALID, "bad server option");
-  auto srv = new (std::nothrow) asm_server_s();
-  if (!srv) return fail(ASM_ERR_OOM, "host allocation failed");
-  srv->o = *o;
-  srv->s = stream;
-  if ((st = srv->eng.init(o->max_active, o->solve, stream)) != ASM_OK) {
-    delete srv;
-    return st;
+  try {
+    g_err.clear();
+    if (!o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    asm_status st = check_solve_opts(&o->solve);
+    if (st != ASM_OK) return st;
+    if (o->max_active < 1 || o->max_active > ASM_SERVER_MAX_ACTIVE || o->hbm_budget_bytes < 0)
+      return fail(ASM_ERR_INVALID, "bad server option");
+    std::unique_ptr<asm_server_s> srv(new (std::nothrow) asm_server_s());
+    if (!srv) return fail(ASM_ERR_OOM, "host allocation failed");
+    srv->o = *o;
+    srv->s = stream;
+    if ((st = srv->eng.init(o->max_active, o->solve, stream)) != ASM_OK) return st;
+    *out = srv.release();
+    return ASM_OK;
   }
-  *out = srv;
-  return ASM_OK;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_server_submit(asm_server srv, const asm_request *req) {
-  g_err.clear();
-  if (!srv || !req) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (req->nsolves < 1 || req->nsolves > ASM_SERVER_MAX_SOLVES) return fail(ASM_ERR_INVALID, "nsolves out of range");
-  if (!req->row_ptr_dev || !req->col_idx_dev) return fail(ASM_ERR_INVALID, "NULL pattern");
-  for (int k = 0; k < req->nsolves; ++k)
-    if (!req->vals_dev[k] || !req->b_dev[k] || !req->x_dev[k]) return fail(ASM_ERR_INVALID, "NULL values or vector");
-  if (req->precond.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "requests need a Schwarz preconditioner");
-  if (req->precond.coarse != ASM_COARSE_NONE || req->precond.local != ASM_LOCAL_ILU0)
-    return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in served solves");
-  auto r = new (std::nothrow) Request();
-  if (!r) return fail(ASM_ERR_OOM, "host allocation failed");
-  r->d = *req;
-  srv->queue.push_back(r);
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!srv || !req) return fail(ASM_ERR_INVALID, "NULL argument");
+    if (req->nsolves < 1 || req->nsolves > ASM_SERVER_MAX_SOLVES) return fail(ASM_ERR_INVALID, "nsolves out of range");
+    if (!req->row_ptr_dev || !req->col_idx_dev) return fail(ASM_ERR_INVALID, "NULL pattern");
+    for (int k = 0; k < req->nsolves; ++k)
+      if (!req->vals_dev[k] || !req->b_dev[k] || !req->x_dev[k]) return fail(ASM_ERR_INVALID, "NULL values or vector");
+    if (req->precond.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "requests need a Schwarz preconditioner");
+    if (req->precond.coarse != ASM_COARSE_NONE || req->precond.local != ASM_LOCAL_ILU0)
+      return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in served solves");
+    std::unique_ptr<Request> r(new (std::nothrow) Request());
+    if (!r) return fail(ASM_ERR_OOM, "host allocation failed");
+    r->d = *req;
+    srv->queue.push_back(r.get());
+    r.release();  // owned by the queue from here
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_server_poll(asm_server srv, int32_t max, asm_completion *out, int32_t *ndone) {
-  g_err.clear();
-  if (!srv || !ndone || max < 0 || (max > 0 && !out)) return fail(ASM_ERR_INVALID, "NULL argument");
-  *ndone = 0;
-  asm_status st;
-  // 1. admission in arrival order; stop at the first request that does not
-  //    fit the budget (unless nothing else holds memory) or the batch
-  std::vector<Request *> join;
-  join.swap(srv->ready);
-  int slots = srv->eng.free_slots() - (int)join.size();
-  start_builds(srv);
-  while (!srv->queue.empty() && slots > 0) {
-    Request *r = srv->queue.front();
-    const int p = find_plan(srv, r->d);
-    if (p >= 0 && srv->plans[p].building) {
-      // the head waits for its plan (no overtaking); with nothing else to
-      // run, wait here rather than return empty-handed
-      const bool idle = srv->eng.iterating() == 0 && join.empty();
-      if (!idle && srv->plans[p].job.wait_for(std::chrono::seconds(0)) != std::future_status::ready) break;
-      if ((st = finish_plan(srv, p, r->d)) != ASM_OK) return st;
-    }
-    if (p >= 0 && srv->plans[p].failed != ASM_OK) {
+  try {
+    g_err.clear();
+    if (!srv || !ndone || max < 0 || (max > 0 && !out)) return fail(ASM_ERR_INVALID, "NULL argument");
+    *ndone = 0;
+    asm_status st;
+    // 1. admission in arrival order; stop at the first request that does not
+    //    fit the budget (unless nothing else holds memory) or the batch
+    std::vector<Request *> join;
+    join.swap(srv->ready);
+    int slots = srv->eng.free_slots() - (int)join.size();
+    start_builds(srv);
+    while (!srv->queue.empty() && slots > 0) {
+      Request *r = srv->queue.front();
+      const int p = find_plan(srv, r->d);
+      if (p >= 0 && srv->plans[p].building) {
+        // the head waits for its plan (no overtaking); with nothing else to
+        // run, wait here rather than return empty-handed
+        const bool idle = srv->eng.iterating() == 0 && join.empty();
+        if (!idle && srv->plans[p].job.wait_for(std::chrono::seconds(0)) != std::future_status::ready) break;
+        if ((st = finish_plan(srv, p, r->d)) != ASM_OK) return st;
+      }
+      if (p >= 0 && srv->plans[p].failed != ASM_OK) {
+        srv->queue.pop_front();
+        srv->running.push_back(r);
+        r->status = srv->plans[p].failed;
+        g_err = srv->plans[p].err;
+        complete(srv, r);
+        srv->plans.erase(srv->plans.begin() + p);
+        for (Request *q : srv->running)
+          if (q->plan > p) --q->plan;
+        continue;
+      }
+      const int64_t need = admission_estimate(srv, r->d);
+      if (srv->o.hbm_budget_bytes > 0 && srv->bytes_in_use + need > srv->o.hbm_budget_bytes) {
+        evict_for(srv, need, find_plan(srv, r->d));
+        if (srv->bytes_in_use + need > srv->o.hbm_budget_bytes && !srv->running.empty()) break;
+      }
       srv->queue.pop_front();
       srv->running.push_back(r);
-      r->status = srv->plans[p].failed;
-      g_err = srv->plans[p].err;
-      complete(srv, r);
-      srv->plans.erase(srv->plans.begin() + p);
-      for (Request *q : srv->running)
-        if (q->plan > p) --q->plan;
-      continue;
+      st = materialise(srv, r);
+      if (st != ASM_OK) {
+        r->status = st;
+        complete(srv, r);
+        continue;
+      }
+      join.push_back(r);
+      --slots;
     }
-    const int64_t need = admission_estimate(srv, r->d);
-    if (srv->o.hbm_budget_bytes > 0 && srv->bytes_in_use + need > srv->o.hbm_budget_bytes) {
-      evict_for(srv, need, find_plan(srv, r->d));
-      if (srv->bytes_in_use + need > srv->o.hbm_budget_bytes && !srv->running.empty()) break;
-    }
-    srv->queue.pop_front();
-    srv->running.push_back(r);
-    st = materialise(srv, r);
-    if (st != ASM_OK) {
-      r->status = st;
-      complete(srv, r);
-      continue;
-    }
-    join.push_back(r);
-    --slots;
-  }
-  // 2. the new solves join the batch (checks, ||b||, initial residuals)
-  if (!join.empty()) {
-    std::vector<BatchEngine::NewSolve> add;
-    for (Request *r : join) add.push_back({r->S, r->pc, r->d.b_dev[r->next], r->d.x_dev[r->next], r->d.tag});
-    std::vector<int> sl;
-    if ((st = srv->eng.add(add, sl, false)) != ASM_OK) return st;
-    for (size_t a = 0; a < join.size(); ++a) {
-      Request *r = join[a];
-      r->slot = sl[a];
-      if (r->bytes == 0) {  // first solve: the system's workspace now exists
-        r->bytes = system_bytes(r->S) + (int64_t)r->pc->mem.bytes;
-        srv->bytes_in_use += r->bytes;
-        Plan &p = srv->plans[r->plan];
-        if (p.req_bytes == 0) {
-          p.req_bytes = r->bytes;
-          const double bpb = (double)(p.bytes + r->bytes) / (double)std::max<int64_t>(p.nnzb, 1);
-          srv->bytes_per_block = std::max(srv->bytes_per_block, bpb);
+    // 2. the new solves join the batch (checks, ||b||, initial residuals)
+    if (!join.empty()) {
+      std::vector<BatchEngine::NewSolve> add;
+      for (Request *r : join) add.push_back({r->S, r->pc, r->d.b_dev[r->next], r->d.x_dev[r->next], r->d.tag});
+      std::vector<int> sl;
+      if ((st = srv->eng.add(add, sl, false)) != ASM_OK) return st;
+      for (size_t a = 0; a < join.size(); ++a) {
+        Request *r = join[a];
+        r->slot = sl[a];
+        if (r->bytes == 0) {  // first solve: the system's workspace now exists
+          r->bytes = system_bytes(r->S) + (int64_t)r->pc->mem.bytes;
+          srv->bytes_in_use += r->bytes;
+          Plan &p = srv->plans[r->plan];
+          if (p.req_bytes == 0) {
+            p.req_bytes = r->bytes;
+            const double bpb = (double)(p.bytes + r->bytes) / (double)std::max<int64_t>(p.nnzb, 1);
+            srv->bytes_per_block = std::max(srv->bytes_per_block, bpb);
+          }
         }
       }
+      for (Request *r : join)
+        if (!srv->eng.entry(r->slot).iterating) solve_ended(srv, r);
     }
-    for (Request *r : join)
-      if (!srv->eng.entry(r->slot).iterating) solve_ended(srv, r);
+    // 3. one restart cycle of every iterating solve
+    if (srv->eng.iterating() > 0) {
+      if ((st = srv->eng.cycle()) != ASM_OK) return st;
+      std::vector<Request *> ended;
+      for (Request *r : srv->running)
+        if (r->slot >= 0 && !srv->eng.entry(r->slot).iterating) ended.push_back(r);
+      for (Request *r : ended) solve_ended(srv, r);
+    }
+    ASM_HIP(hipStreamSynchronize(srv->s));
+    // 4. completions
+    while (*ndone < max && !srv->done.empty()) {
+      out[(*ndone)++] = srv->done.front();
+      srv->done.pop_front();
+    }
+    return ASM_OK;
   }
-  // 3. one restart cycle of every iterating solve
-  if (srv->eng.iterating() > 0) {
-    if ((st = srv->eng.cycle()) != ASM_OK) return st;
-    std::vector<Request *> ended;
-    for (Request *r : srv->running)
-      if (r->slot >= 0 && !srv->eng.entry(r->slot).iterating) ended.push_back(r);
-    for (Request *r : ended) solve_ended(srv, r);
-  }
-  ASM_HIP(hipStreamSynchronize(srv->s));
-  // 4. completions
-  while (*ndone < max && !srv->done.empty()) {
-    out[(*ndone)++] = srv->done.front();
-    srv->done.pop_front();
-  }
-  return ASM_OK;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_server_get_state(asm_server srv, asm_server_state *st) {
-  g_err.clear();
-  if (!srv || !st) return fail(ASM_ERR_INVALID, "NULL argument");
-  std::memset(st, 0, sizeof *st);
-  st->queued = (int32_t)srv->queue.size();
-  st->running = (int32_t)srv->running.size();
-  st->iterating = srv->eng.iterating();
-  st->completed_unread = (int32_t)srv->done.size();
-  st->cached_plans = (int32_t)srv->plans.size();
-  st->bytes_in_use = srv->bytes_in_use;
-  st->plan_builds = srv->plan_builds;
-  st->plan_hits = srv->plan_hits;
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!srv || !st) return fail(ASM_ERR_INVALID, "NULL argument");
+    std::memset(st, 0, sizeof *st);
+    st->queued = (int32_t)srv->queue.size();
+    st->running = (int32_t)srv->running.size();
+    st->iterating = srv->eng.iterating();
+    st->completed_unread = (int32_t)srv->done.size();
+    st->cached_plans = (int32_t)srv->plans.size();
+    st->bytes_in_use = srv->bytes_in_use;
+    st->plan_builds = srv->plan_builds;
+    st->plan_hits = srv->plan_hits;
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 void asm_server_destroy(asm_server srv) { delete srv; }

@@ -285,18 +285,16 @@ asm_status check_precond_opts(const HostPattern &A, const asm_precond_opts *o) {
 asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_ptr<PlanHost> plan,
                            hipStream_t stream, asm_precond *out) {
   *out = nullptr;
-  auto pc = new (std::nothrow) asm_precond_s();
+  std::unique_ptr<asm_precond_s> hold(new (std::nothrow) asm_precond_s());
+  asm_precond pc = hold.get();
   if (!pc) return fail(ASM_ERR_OOM, "host allocation failed");
   pc->sys = S;
   pc->opts = *o;
   if (o->kind == ASM_KIND_NONE) {
-    *out = pc;
+    *out = hold.release();
     return ASM_OK;
   }
-  auto cleanup = [&](asm_status st) {
-    delete pc;
-    return st;
-  };
+  auto cleanup = [](asm_status st) { return st; };  // hold frees the handle
   pc->plan = std::move(plan);
   pc->smem = std::make_shared<DevMem>();
   PlanHost &P = *pc->plan;
@@ -428,7 +426,7 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   pc->stats.device_bytes = (int64_t)(M.bytes + O.bytes);
   pc->stats.sweep_steps = P.sweep_steps;
   pc->stats.reloaded_rows = P.lds_spilled_rows;
-  *out = pc;
+  *out = hold.release();
   return ASM_OK;
 }
 
@@ -443,381 +441,407 @@ const char *asm_last_error(void) { return g_err.c_str(); }
 asm_status asm_create_system(const asm_grid *grid, int32_t nb, int64_t nnzb, const int32_t *row_ptr_dev,
                              const int32_t *col_idx_dev, const double *vals_dev, hipStream_t stream,
                              asm_system *out) {
-  g_err.clear();
-  if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  if (!grid || !row_ptr_dev || !col_idx_dev || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || (int64_t)grid->nx * grid->ny * grid->nz != nb)
-    return fail(ASM_ERR_INVALID, "grid nx*ny*nz does not equal nb");
-  if (nnzb < nb || nnzb >= ((int64_t)1 << 31) / 9) return fail(ASM_ERR_INVALID, "nnzb out of range");
-  auto S = new (std::nothrow) asm_system_s();
-  if (!S) return fail(ASM_ERR_OOM, "host allocation failed");
-  auto cleanup = [&](asm_status st) {
-    delete S;
-    return st;
-  };
-  (void)hipGetDevice(&S->device);
-  HostPattern &P = S->pat;
-  P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.N = nb; P.nnzb = nnzb;
-  P.rp.resize(nb + 1);
-  P.ci.resize(nnzb);
-  hipError_t e = hipMemcpyAsync(P.rp.data(), row_ptr_dev, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(P.ci.data(), col_idx_dev, nnzb * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return cleanup(fail(ASM_ERR_HIP, std::string("pattern copy: ") + hipGetErrorString(e)));
-  asm_status vst = validate_pattern(P);
-  if (vst != ASM_OK) return cleanup(vst);
-  if ((e = S->mem.upload(&S->rp, P.rp, stream)) != hipSuccess ||
-      (e = S->mem.upload(&S->ci, P.ci, stream)) != hipSuccess ||
-      (e = S->mem.alloc(&S->vals, (size_t)nnzb * 9)) != hipSuccess)
-    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  if ((e = hipMemcpyAsync(S->vals, vals_dev, (size_t)nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice, stream)) !=
-      hipSuccess)
-    return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
-  asm_status st = ensure_workspace(S, 1, stream);
-  if (st != ASM_OK) return cleanup(st);
-  bool bad = false;
-  if ((st = any_nonfinite(S, S->vals, (int64_t)nnzb * 9, stream, &bad)) != ASM_OK) return cleanup(st);
-  if (bad) return cleanup(fail(ASM_ERR_NONFINITE, "non-finite matrix value"));
-  if ((st = build_sell(S, stream)) != ASM_OK) return cleanup(st);
-  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
-  *out = S;
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!grid || !row_ptr_dev || !col_idx_dev || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || (int64_t)grid->nx * grid->ny * grid->nz != nb)
+      return fail(ASM_ERR_INVALID, "grid nx*ny*nz does not equal nb");
+    if (nnzb < nb || nnzb >= ((int64_t)1 << 31) / 9) return fail(ASM_ERR_INVALID, "nnzb out of range");
+    std::unique_ptr<asm_system_s> hold(new (std::nothrow) asm_system_s());
+    asm_system S = hold.get();
+    if (!S) return fail(ASM_ERR_OOM, "host allocation failed");
+    auto cleanup = [](asm_status st) { return st; };  // hold frees the handle
+    (void)hipGetDevice(&S->device);
+    HostPattern &P = S->pat;
+    P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.N = nb; P.nnzb = nnzb;
+    P.rp.resize(nb + 1);
+    P.ci.resize(nnzb);
+    hipError_t e = hipMemcpyAsync(P.rp.data(), row_ptr_dev, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P.ci.data(), col_idx_dev, nnzb * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return cleanup(fail(ASM_ERR_HIP, std::string("pattern copy: ") + hipGetErrorString(e)));
+    asm_status vst = validate_pattern(P);
+    if (vst != ASM_OK) return cleanup(vst);
+    if ((e = S->mem.upload(&S->rp, P.rp, stream)) != hipSuccess ||
+        (e = S->mem.upload(&S->ci, P.ci, stream)) != hipSuccess ||
+        (e = S->mem.alloc(&S->vals, (size_t)nnzb * 9)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    if ((e = hipMemcpyAsync(S->vals, vals_dev, (size_t)nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice, stream)) !=
+        hipSuccess)
+      return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+    asm_status st = ensure_workspace(S, 1, stream);
+    if (st != ASM_OK) return cleanup(st);
+    bool bad = false;
+    if ((st = any_nonfinite(S, S->vals, (int64_t)nnzb * 9, stream, &bad)) != ASM_OK) return cleanup(st);
+    if (bad) return cleanup(fail(ASM_ERR_NONFINITE, "non-finite matrix value"));
+    if ((st = build_sell(S, stream)) != ASM_OK) return cleanup(st);
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+    *out = hold.release();
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_update_values(asm_system S, const double *vals_dev, hipStream_t stream) {
-  g_err.clear();
-  if (!S || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  ASM_HIP(hipMemcpyAsync(S->vals, vals_dev, (size_t)S->pat.nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream));
-  bool bad = false;
-  asm_status st = any_nonfinite(S, S->vals, S->pat.nnzb * 9, stream, &bad);
-  if (st != ASM_OK) return st;
-  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite matrix value");
-  ASM_HIP(launch_sell_fill(S->sell, S->vals, stream));
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!S || !vals_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+    ASM_HIP(hipMemcpyAsync(S->vals, vals_dev, (size_t)S->pat.nnzb * 9 * sizeof(double), hipMemcpyDeviceToDevice,
+                           stream));
+    bool bad = false;
+    asm_status st = any_nonfinite(S, S->vals, S->pat.nnzb * 9, stream, &bad);
+    if (st != ASM_OK) return st;
+    if (bad) return fail(ASM_ERR_NONFINITE, "non-finite matrix value");
+    ASM_HIP(launch_sell_fill(S->sell, S->vals, stream));
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_spmv(asm_system S, const double *x_dev, double *y_dev, hipStream_t stream) {
-  g_err.clear();
-  if (!S || !x_dev || !y_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream));
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!S || !x_dev || !y_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+    ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream));
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_t stream, asm_precond *out) {
-  g_err.clear();
-  if (!S || !o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
-  *out = nullptr;
-  asm_status st = check_precond_opts(S->pat, o);
-  if (st != ASM_OK) return st;
-  std::shared_ptr<PlanHost> plan;
-  if (o->kind != ASM_KIND_NONE) {
-    plan = std::make_shared<PlanHost>();
-    std::string err;
-    st = build_plan(S->pat, *o, *plan, err);
-    if (st != ASM_OK) return fail(st, err);
+  try {
+    g_err.clear();
+    if (!S || !o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    asm_status st = check_precond_opts(S->pat, o);
+    if (st != ASM_OK) return st;
+    std::shared_ptr<PlanHost> plan;
+    if (o->kind != ASM_KIND_NONE) {
+      plan = std::make_shared<PlanHost>();
+      std::string err;
+      st = build_plan(S->pat, *o, *plan, err);
+      if (st != ASM_OK) return fail(st, err);
+    }
+    return setup_from_plan(S, o, std::move(plan), stream, out);
   }
-  return setup_from_plan(S, o, std::move(plan), stream, out);
+  ASM_CATCH_ALL
 }
 
 asm_status asm_refactor(asm_precond pc, hipStream_t stream) {
-  g_err.clear();
-  if (!pc) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (pc->opts.kind == ASM_KIND_NONE) return ASM_OK;
-  return numeric_setup(pc, stream);
+  try {
+    g_err.clear();
+    if (!pc) return fail(ASM_ERR_INVALID, "NULL argument");
+    if (pc->opts.kind == ASM_KIND_NONE) return ASM_OK;
+    return numeric_setup(pc, stream);
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, asm_precond *out) {
-  g_err.clear();
-  if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  if (!src || !S) return fail(ASM_ERR_INVALID, "NULL argument");
-  const HostPattern &A = S->pat, &B = src->sys->pat;
-  if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.nnzb != B.nnzb || A.rp != B.rp || A.ci != B.ci)
-    return fail(ASM_ERR_INVALID, "the system's grid or block pattern differs from the source preconditioner's");
-  auto pc = new (std::nothrow) asm_precond_s();
-  if (!pc) return fail(ASM_ERR_OOM, "host allocation failed");
-  pc->sys = S;
-  pc->opts = src->opts;
-  pc->stats = src->stats;
-  if (src->opts.kind == ASM_KIND_NONE) {
-    *out = pc;
+  try {
+    g_err.clear();
+    if (!out) return fail(ASM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!src || !S) return fail(ASM_ERR_INVALID, "NULL argument");
+    const HostPattern &A = S->pat, &B = src->sys->pat;
+    if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.nnzb != B.nnzb || A.rp != B.rp || A.ci != B.ci)
+      return fail(ASM_ERR_INVALID, "the system's grid or block pattern differs from the source preconditioner's");
+    std::unique_ptr<asm_precond_s> hold(new (std::nothrow) asm_precond_s());
+    asm_precond pc = hold.get();
+    if (!pc) return fail(ASM_ERR_OOM, "host allocation failed");
+    pc->sys = S;
+    pc->opts = src->opts;
+    pc->stats = src->stats;
+    if (src->opts.kind == ASM_KIND_NONE) {
+      *out = hold.release();
+      return ASM_OK;
+    }
+    auto cleanup = [](asm_status st) { return st; };  // hold frees the handle
+    // pattern-only state is shared; everything holding values is this handle's
+    pc->plan = src->plan;
+    pc->smem = src->smem;
+    pc->dp = src->dp;
+    pc->ap = src->ap;
+    pc->l1 = src->l1; pc->l2 = src->l2; pc->asrc = src->asrc;
+    pc->c1 = src->c1; pc->c2 = src->c2; pc->c3 = src->c3;
+    pc->rl_src = src->rl_src; pc->rl_base = src->rl_base; pc->rl_stride = src->rl_stride; pc->rl_to32 = src->rl_to32;
+    pc->rl_n = src->rl_n;
+    pc->cptr = src->cptr; pc->cidx = src->cidx;
+    pc->rec_bytes = src->rec_bytes;
+    const PlanHost &P = *pc->plan;
+    DevMem &O = pc->mem;
+    hipError_t e = hipSuccess;
+    uint8_t *rec = nullptr;
+    double *yx = nullptr, *rs = nullptr, *fact = nullptr;
+    if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
+        (e = O.alloc(&rs, pc->opts.local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0)) != hipSuccess ||
+        (e = O.alloc(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
+        (e = O.alloc(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess || (e = O.alloc(&pc->bad, 1)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    if (pc->opts.kind == ASM_KIND_TWO_LEVEL &&
+        ((e = O.alloc(&pc->L1, (size_t)pc->l1.n * 9)) != hipSuccess ||
+         (e = O.alloc(&pc->L2, (size_t)pc->l2.n * 9)) != hipSuccess ||
+         (e = O.alloc(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
+         (e = O.alloc(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess ||
+         (e = O.alloc(&pc->ap.crs, (size_t)pc->c3.n * 3)) != hipSuccess))
+      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    // the records carry the sweep's row headers and slots next to the factor
+    // values; the values are rewritten by the numeric setup below
+    if ((e = hipMemcpyAsync(rec, src->recbuf, pc->rec_bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+      return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
+    pc->recbuf = rec;
+    pc->ap.rec = rec;
+    pc->ap.yx = yx;
+    pc->ap.rs = rs;
+    pc->ap.pnf = pc->PNF;
+    pc->dp.fact = fact;
+    if (pc->opts.coarse != ASM_COARSE_NONE) {
+      pc->ncv = src->ncv;
+      pc->cvar = src->cvar;
+      pc->cbox = src->cbox;
+      pc->casrc = src->casrc;
+      pc->acp = src->acp;
+      pc->acc = src->acc;
+      if ((e = alloc_coarse_own(pc)) != hipSuccess)
+        return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    }
+    if (pc->opts.local == ASM_LOCAL_EXACT) {
+      pc->xd = src->xd;
+      pc->xmaxn3 = src->xmaxn3;
+      if ((e = alloc_exact_own(pc, P.xdoff.back(), P.total_ext)) != hipSuccess)
+        return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
+    }
+    pc->stats.device_bytes = (int64_t)(pc->smem->bytes + O.bytes);
+    asm_status st = numeric_setup(pc, stream);
+    if (st != ASM_OK) return cleanup(st);
+    *out = hold.release();
     return ASM_OK;
   }
-  auto cleanup = [&](asm_status st) {
-    delete pc;
-    return st;
-  };
-  // pattern-only state is shared; everything holding values is this handle's
-  pc->plan = src->plan;
-  pc->smem = src->smem;
-  pc->dp = src->dp;
-  pc->ap = src->ap;
-  pc->l1 = src->l1; pc->l2 = src->l2; pc->asrc = src->asrc;
-  pc->c1 = src->c1; pc->c2 = src->c2; pc->c3 = src->c3;
-  pc->rl_src = src->rl_src; pc->rl_base = src->rl_base; pc->rl_stride = src->rl_stride; pc->rl_to32 = src->rl_to32;
-  pc->rl_n = src->rl_n;
-  pc->cptr = src->cptr; pc->cidx = src->cidx;
-  pc->rec_bytes = src->rec_bytes;
-  const PlanHost &P = *pc->plan;
-  DevMem &O = pc->mem;
-  hipError_t e = hipSuccess;
-  uint8_t *rec = nullptr;
-  double *yx = nullptr, *rs = nullptr, *fact = nullptr;
-  if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
-      (e = O.alloc(&rs, pc->opts.local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0)) != hipSuccess ||
-      (e = O.alloc(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
-      (e = O.alloc(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess || (e = O.alloc(&pc->bad, 1)) != hipSuccess)
-    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  if (pc->opts.kind == ASM_KIND_TWO_LEVEL &&
-      ((e = O.alloc(&pc->L1, (size_t)pc->l1.n * 9)) != hipSuccess ||
-       (e = O.alloc(&pc->L2, (size_t)pc->l2.n * 9)) != hipSuccess ||
-       (e = O.alloc(&pc->PA, (size_t)pc->c1.n * 3)) != hipSuccess ||
-       (e = O.alloc(&pc->PNF, (size_t)pc->c2.n * 3)) != hipSuccess ||
-       (e = O.alloc(&pc->ap.crs, (size_t)pc->c3.n * 3)) != hipSuccess))
-    return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  // the records carry the sweep's row headers and slots next to the factor
-  // values; the values are rewritten by the numeric setup below
-  if ((e = hipMemcpyAsync(rec, src->recbuf, pc->rec_bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
-    return cleanup(fail(ASM_ERR_HIP, hipGetErrorString(e)));
-  pc->recbuf = rec;
-  pc->ap.rec = rec;
-  pc->ap.yx = yx;
-  pc->ap.rs = rs;
-  pc->ap.pnf = pc->PNF;
-  pc->dp.fact = fact;
-  if (pc->opts.coarse != ASM_COARSE_NONE) {
-    pc->ncv = src->ncv;
-    pc->cvar = src->cvar;
-    pc->cbox = src->cbox;
-    pc->casrc = src->casrc;
-    pc->acp = src->acp;
-    pc->acc = src->acc;
-    if ((e = alloc_coarse_own(pc)) != hipSuccess)
-      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  }
-  if (pc->opts.local == ASM_LOCAL_EXACT) {
-    pc->xd = src->xd;
-    pc->xmaxn3 = src->xmaxn3;
-    if ((e = alloc_exact_own(pc, P.xdoff.back(), P.total_ext)) != hipSuccess)
-      return cleanup(fail(e == hipErrorOutOfMemory ? ASM_ERR_OOM : ASM_ERR_HIP, hipGetErrorString(e)));
-  }
-  pc->stats.device_bytes = (int64_t)(pc->smem->bytes + O.bytes);
-  asm_status st = numeric_setup(pc, stream);
-  if (st != ASM_OK) return cleanup(st);
-  *out = pc;
-  return ASM_OK;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_precond_apply(asm_precond pc, const double *r_dev, double *z_dev, hipStream_t stream) {
-  g_err.clear();
-  if (!pc || !r_dev || !z_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-  return apply_precond(pc, r_dev, nullptr, z_dev, stream);
+  try {
+    g_err.clear();
+    if (!pc || !r_dev || !z_dev) return fail(ASM_ERR_INVALID, "NULL argument");
+    return apply_precond(pc, r_dev, nullptr, z_dev, stream);
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_precond_get_stats(asm_precond pc, asm_precond_stats *st) {
-  g_err.clear();
-  if (!pc || !st) return fail(ASM_ERR_INVALID, "NULL argument");
-  *st = pc->stats;
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!pc || !st) return fail(ASM_ERR_INVALID, "NULL argument");
+    *st = pc->stats;
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_precond_export_sub(asm_precond pc, int32_t s, int32_t *n_out, int32_t *nnz_out, int32_t *rp_host,
                                   int32_t *ci_host, double *a_host, double *f_host, int32_t *label_host) {
-  g_err.clear();
-  if (!pc || pc->opts.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "no subdomains");
-  const PlanHost &P = *pc->plan;
-  if (s < 0 || s >= P.nsub) return fail(ASM_ERR_INVALID, "subdomain out of range");
-  const SubDesc &d = P.sub[s];
-  const int32_t e0 = P.arp[d.ext_off], e1 = P.arp[d.ext_off + d.n];
-  if (n_out) *n_out = d.n;
-  if (nnz_out) *nnz_out = e1 - e0;
-  if (rp_host)
-    for (int u = 0; u <= d.n; ++u) rp_host[u] = P.arp[d.ext_off + u] - e0;
-  if (ci_host) std::copy(P.aci.begin() + e0, P.aci.begin() + e1, ci_host);
-  if (a_host) ASM_HIP(hipMemcpy(a_host, pc->aval + (size_t)e0 * 9, (size_t)(e1 - e0) * 9 * sizeof(double), hipMemcpyDeviceToHost));
-  if (f_host) ASM_HIP(hipMemcpy(f_host, pc->dp.fact + (size_t)e0 * 9, (size_t)(e1 - e0) * 9 * sizeof(double), hipMemcpyDeviceToHost));
-  if (label_host) {
-    const int N = pc->sys->pat.N;
-    std::fill(label_host, label_host + N, -1);
-    for (int u = 0; u < d.nfine; ++u) label_host[P.rhs_src[d.ext_off + u]] = u;
-    // coarse rows: member near/far atoms -> fine atoms -> cells
-    const int nNa_plus = (int)P.c2.size();
-    (void)nNa_plus;
-    for (int u = d.nfine; u < d.n; ++u) {
-      const int q = -P.rhs_src[d.ext_off + u] - 1;
-      for (int t = P.c3.ptr[q]; t < P.c3.ptr[q + 1]; ++t) {
-        const int nf = P.c3.idx[t];
-        for (int t2 = P.c2.ptr[nf]; t2 < P.c2.ptr[nf + 1]; ++t2) {
-          const int a = P.c2.idx[t2];
-          for (int t3 = P.c1.ptr[a]; t3 < P.c1.ptr[a + 1]; ++t3) label_host[P.c1.idx[t3]] = u;
+  try {
+    g_err.clear();
+    if (!pc || pc->opts.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "no subdomains");
+    const PlanHost &P = *pc->plan;
+    if (s < 0 || s >= P.nsub) return fail(ASM_ERR_INVALID, "subdomain out of range");
+    const SubDesc &d = P.sub[s];
+    const int32_t e0 = P.arp[d.ext_off], e1 = P.arp[d.ext_off + d.n];
+    if (n_out) *n_out = d.n;
+    if (nnz_out) *nnz_out = e1 - e0;
+    if (rp_host)
+      for (int u = 0; u <= d.n; ++u) rp_host[u] = P.arp[d.ext_off + u] - e0;
+    if (ci_host) std::copy(P.aci.begin() + e0, P.aci.begin() + e1, ci_host);
+    if (a_host) ASM_HIP(hipMemcpy(a_host, pc->aval + (size_t)e0 * 9, (size_t)(e1 - e0) * 9 * sizeof(double), hipMemcpyDeviceToHost));
+    if (f_host) ASM_HIP(hipMemcpy(f_host, pc->dp.fact + (size_t)e0 * 9, (size_t)(e1 - e0) * 9 * sizeof(double), hipMemcpyDeviceToHost));
+    if (label_host) {
+      const int N = pc->sys->pat.N;
+      std::fill(label_host, label_host + N, -1);
+      for (int u = 0; u < d.nfine; ++u) label_host[P.rhs_src[d.ext_off + u]] = u;
+      // coarse rows: member near/far atoms -> fine atoms -> cells
+      const int nNa_plus = (int)P.c2.size();
+      (void)nNa_plus;
+      for (int u = d.nfine; u < d.n; ++u) {
+        const int q = -P.rhs_src[d.ext_off + u] - 1;
+        for (int t = P.c3.ptr[q]; t < P.c3.ptr[q + 1]; ++t) {
+          const int nf = P.c3.idx[t];
+          for (int t2 = P.c2.ptr[nf]; t2 < P.c2.ptr[nf + 1]; ++t2) {
+            const int a = P.c2.idx[t2];
+            for (int t3 = P.c1.ptr[a]; t3 < P.c1.ptr[a + 1]; ++t3) label_host[P.c1.idx[t3]] = u;
+          }
         }
       }
     }
+    return ASM_OK;
   }
-  return ASM_OK;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                      hipStream_t s, asm_solve_info *info) {
-  g_err.clear();
-  if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-  std::memset(info, 0, sizeof *info);
-  const int m = o->restart;
-  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
-    return fail(ASM_ERR_INVALID, "bad solver option");
-  const int64_t n = 3 * (int64_t)S->pat.N;
-  asm_status st = ensure_workspace(S, m, s);
-  if (st != ASM_OK) return st;
-  Workspace &W = S->ws;
-  Profiler &pf = S->prof;
-  bool bad = false;
-  if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
-  if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
-  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
-  const int ld = m + 1;
-  double *hp = W.pinned;
-  int nb = 0;
-  // ||b||
-  ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
-  ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
-  ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-  ASM_HIP(hipStreamSynchronize(s));
-  const double bnorm = std::sqrt(hp[0]);
-  if (bnorm == 0.0 && o->fixed_iters == 0) {
-    ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  try {
+    g_err.clear();
+    if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
+    if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+    std::memset(info, 0, sizeof *info);
+    const int m = o->restart;
+    if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
+      return fail(ASM_ERR_INVALID, "bad solver option");
+    const int64_t n = 3 * (int64_t)S->pat.N;
+    asm_status st = ensure_workspace(S, m, s);
+    if (st != ASM_OK) return st;
+    Workspace &W = S->ws;
+    Profiler &pf = S->prof;
+    bool bad = false;
+    if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
+    if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
+    if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
+    const int ld = m + 1;
+    double *hp = W.pinned;
+    int nb = 0;
+    // ||b||
+    ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
+    ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
+    ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
-    return ASM_OK;
-  }
-  const double scl = bnorm > 0.0 ? bnorm : 1.0;
-  const double tol = o->rtol * bnorm;
-  auto true_residual = [&](double *beta) -> asm_status {
-    int nbr = 0;
-    const size_t t0 = pf.mark(ASM_PHASE_RESIDUAL, s);
-    ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
-    pf.span(ASM_PHASE_RESIDUAL, t0, s);
-    const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
-    pf.span(ASM_PHASE_OTHER, t1, s);
-    ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipStreamSynchronize(s));
-    pf.flush();
-    *beta = hp[0];
-    return ASM_OK;
-  };
-  double beta = 0.0;
-  if ((st = true_residual(&beta)) != ASM_OK) return st;
-  info->rel_res_true = info->rel_res_est = beta / scl;
-  if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
-  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
-  std::vector<double> H((size_t)ld * m), cs(m), sn(m), g(m + 1), y(m), sc(m + 1), coef(m + 1);
-  auto Hh = [&](int i, int j) -> double & { return H[(size_t)j * ld + i]; };
-  asm_status result = ASM_NOT_CONVERGED;
-  // One Arnoldi step on the stream: z = B^-1 v_j, w = A z, CGS projections,
-  // the new basis vector and its norm; the step's Hessenberg column is then
-  // published to pinned memory and an event marks the step's end.
-  auto enqueue_step = [&](int j) -> asm_status {
-    const double *Uj = W.U + (size_t)j * W.ldu;
-    asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
-    if (e2 != ASM_OK) return e2;
-    size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
-    ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
-    pf.span(ASM_PHASE_SPMV, t0, s);
-    int nbd = 0;
-    t0 = pf.mark(ASM_PHASE_DOTS, s);
-    ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
-    pf.span(ASM_PHASE_DOTS, t0, s);
-    t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
-    pf.span(ASM_PHASE_OTHER, t0, s);
-    int nbu = 0;
-    t0 = pf.mark(ASM_PHASE_UPDATE, s);
-    ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
-                          &nbu, s));
-    pf.span(ASM_PHASE_UPDATE, t0, s);
-    t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
-                                 W.pinned_dev + kPubBase + (size_t)j * kPubStride, s));
-    pf.span(ASM_PHASE_OTHER, t0, s);
-    ASM_HIP(hipEventRecord(W.step_done[j], s));
-    return ASM_OK;
-  };
-  while (true) {
-    if (beta == 0.0) { result = ASM_OK; break; }
-    info->cycles++;
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    sc[0] = 1.0 / beta;
-    // steps of this cycle: at most m, and never past the iteration limit
-    const int kmax = std::min(m, limit - info->iters);
-    int k = 0, queued = 0;
-    if ((st = enqueue_step(0)) != ASM_OK) return st;
-    queued = 1;
-    for (int j = 0; j < kmax; ++j) {
-      // keep the next step queued while step j's column is read back
-      if (queued < kmax) {
-        if ((st = enqueue_step(queued)) != ASM_OK) return st;
-        ++queued;
-      }
-      ASM_HIP(hipEventSynchronize(W.step_done[j]));
-      const double *col = hp + kPubBase + (size_t)j * kPubStride;
-      for (int i = 0; i <= j + 1; ++i) Hh(i, j) = col[i];
-      const double w0 = col[j + 2];
-      const double hn = Hh(j + 1, j);
-      sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-      // previous rotations, then a new one annihilating h_{j+1,j}
-      for (int i = 0; i < j; ++i) {
-        const double a = Hh(i, j), c = Hh(i + 1, j);
-        Hh(i, j) = cs[i] * a + sn[i] * c;
-        Hh(i + 1, j) = -sn[i] * a + cs[i] * c;
-      }
-      const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
-      if (rho == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = Hh(j, j) / rho;
-        sn[j] = Hh(j + 1, j) / rho;
-      }
-      Hh(j, j) = rho;
-      Hh(j + 1, j) = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      info->rel_res_est = std::fabs(g[j + 1]) / scl;
-      if (hn <= 1e-14 * w0) break;
-      if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
+    const double bnorm = std::sqrt(hp[0]);
+    if (bnorm == 0.0 && o->fixed_iters == 0) {
+      ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+      ASM_HIP(hipStreamSynchronize(s));
+      return ASM_OK;
     }
-    info->iters += k;
-    for (int i = k - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int j = i + 1; j < k; ++j) acc -= Hh(i, j) * y[j];
-      y[i] = acc / Hh(i, i);
-    }
-    for (int i = 0; i < k; ++i) coef[i] = y[i] * sc[i];
-    ASM_HIP(hipMemcpyAsync(W.coef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-    size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_lincomb(n, k, W.U, W.ldu, W.coef, W.t, s));
-    pf.span(ASM_PHASE_OTHER, t0, s);
-    if ((st = apply_precond(pc, W.t, nullptr, W.z, s, &pf)) != ASM_OK) return st;
-    t0 = pf.mark(ASM_PHASE_OTHER, s);
-    ASM_HIP(launch_axpy(n, W.z, x, s));
-    pf.span(ASM_PHASE_OTHER, t0, s);
+    const double scl = bnorm > 0.0 ? bnorm : 1.0;
+    const double tol = o->rtol * bnorm;
+    auto true_residual = [&](double *beta) -> asm_status {
+      int nbr = 0;
+      const size_t t0 = pf.mark(ASM_PHASE_RESIDUAL, s);
+      ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
+      pf.span(ASM_PHASE_RESIDUAL, t0, s);
+      const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
+      ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+      pf.span(ASM_PHASE_OTHER, t1, s);
+      ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      ASM_HIP(hipStreamSynchronize(s));
+      pf.flush();
+      *beta = hp[0];
+      return ASM_OK;
+    };
+    double beta = 0.0;
     if ((st = true_residual(&beta)) != ASM_OK) return st;
-    info->rel_res_true = beta / scl;
-    if (o->fixed_iters > 0) {
-      if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
-    } else if (beta <= tol) {
-      result = ASM_OK;
-      break;
+    info->rel_res_true = info->rel_res_est = beta / scl;
+    if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
+    const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+    std::vector<double> H((size_t)ld * m), cs(m), sn(m), g(m + 1), y(m), sc(m + 1), coef(m + 1);
+    auto Hh = [&](int i, int j) -> double & { return H[(size_t)j * ld + i]; };
+    asm_status result = ASM_NOT_CONVERGED;
+    // One Arnoldi step on the stream: z = B^-1 v_j, w = A z, CGS projections,
+    // the new basis vector and its norm; the step's Hessenberg column is then
+    // published to pinned memory and an event marks the step's end.
+    auto enqueue_step = [&](int j) -> asm_status {
+      const double *Uj = W.U + (size_t)j * W.ldu;
+      asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
+      if (e2 != ASM_OK) return e2;
+      size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
+      ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
+      pf.span(ASM_PHASE_SPMV, t0, s);
+      int nbd = 0;
+      t0 = pf.mark(ASM_PHASE_DOTS, s);
+      ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
+      pf.span(ASM_PHASE_DOTS, t0, s);
+      t0 = pf.mark(ASM_PHASE_OTHER, s);
+      ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
+      pf.span(ASM_PHASE_OTHER, t0, s);
+      int nbu = 0;
+      t0 = pf.mark(ASM_PHASE_UPDATE, s);
+      ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
+                            &nbu, s));
+      pf.span(ASM_PHASE_UPDATE, t0, s);
+      t0 = pf.mark(ASM_PHASE_OTHER, s);
+      ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
+                                   W.pinned_dev + kPubBase + (size_t)j * kPubStride, s));
+      pf.span(ASM_PHASE_OTHER, t0, s);
+      ASM_HIP(hipEventRecord(W.step_done[j], s));
+      return ASM_OK;
+    };
+    while (true) {
+      if (beta == 0.0) { result = ASM_OK; break; }
+      info->cycles++;
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      sc[0] = 1.0 / beta;
+      // steps of this cycle: at most m, and never past the iteration limit
+      const int kmax = std::min(m, limit - info->iters);
+      int k = 0, queued = 0;
+      if ((st = enqueue_step(0)) != ASM_OK) return st;
+      queued = 1;
+      for (int j = 0; j < kmax; ++j) {
+        // keep the next step queued while step j's column is read back
+        if (queued < kmax) {
+          if ((st = enqueue_step(queued)) != ASM_OK) return st;
+          ++queued;
+        }
+        ASM_HIP(hipEventSynchronize(W.step_done[j]));
+        const double *col = hp + kPubBase + (size_t)j * kPubStride;
+        for (int i = 0; i <= j + 1; ++i) Hh(i, j) = col[i];
+        const double w0 = col[j + 2];
+        const double hn = Hh(j + 1, j);
+        sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        // previous rotations, then a new one annihilating h_{j+1,j}
+        for (int i = 0; i < j; ++i) {
+          const double a = Hh(i, j), c = Hh(i + 1, j);
+          Hh(i, j) = cs[i] * a + sn[i] * c;
+          Hh(i + 1, j) = -sn[i] * a + cs[i] * c;
+        }
+        const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
+        if (rho == 0.0) {
+          cs[j] = 1.0;
+          sn[j] = 0.0;
+        } else {
+          cs[j] = Hh(j, j) / rho;
+          sn[j] = Hh(j + 1, j) / rho;
+        }
+        Hh(j, j) = rho;
+        Hh(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        info->rel_res_est = std::fabs(g[j + 1]) / scl;
+        if (hn <= 1e-14 * w0) break;
+        if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
+      }
+      info->iters += k;
+      for (int i = k - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int j = i + 1; j < k; ++j) acc -= Hh(i, j) * y[j];
+        y[i] = acc / Hh(i, i);
+      }
+      for (int i = 0; i < k; ++i) coef[i] = y[i] * sc[i];
+      ASM_HIP(hipMemcpyAsync(W.coef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
+      ASM_HIP(launch_lincomb(n, k, W.U, W.ldu, W.coef, W.t, s));
+      pf.span(ASM_PHASE_OTHER, t0, s);
+      if ((st = apply_precond(pc, W.t, nullptr, W.z, s, &pf)) != ASM_OK) return st;
+      t0 = pf.mark(ASM_PHASE_OTHER, s);
+      ASM_HIP(launch_axpy(n, W.z, x, s));
+      pf.span(ASM_PHASE_OTHER, t0, s);
+      if ((st = true_residual(&beta)) != ASM_OK) return st;
+      info->rel_res_true = beta / scl;
+      if (o->fixed_iters > 0) {
+        if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
+      } else if (beta <= tol) {
+        result = ASM_OK;
+        break;
+      }
+      if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
     }
-    if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
+    ASM_HIP(hipStreamSynchronize(s));
+    return result;
   }
-  ASM_HIP(hipStreamSynchronize(s));
-  return result;
+  ASM_CATCH_ALL
 }
 
 // Restarted GMRES with every cycle run as one captured graph (see asm.h).
@@ -826,160 +850,169 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
 // residual estimate once per cycle.
 asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                            hipStream_t user_stream, asm_solve_info *info) {
-  g_err.clear();
-  if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
-  if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-  std::memset(info, 0, sizeof *info);
-  const int m = o->restart;
-  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
-    return fail(ASM_ERR_INVALID, "bad solver option");
-  if (pc->opts.kind != ASM_KIND_NONE &&
-      (pc->opts.local != ASM_LOCAL_ILU0 || pc->opts.coarse != ASM_COARSE_NONE))
-    return fail(ASM_ERR_INVALID, "graph cycles support ILU(0) local solves without a global coarse grid");
-  const int64_t n = 3 * (int64_t)S->pat.N;
-  asm_status st = ensure_workspace(S, m, user_stream);
-  if (st != ASM_OK) return st;
-  Workspace &W = S->ws;
-  // the graphs run on a stream of the library's own (a capture needs a
-  // stream that is not the legacy default one), after the caller's work
-  if (!W.gstream) ASM_HIP(hipStreamCreateWithFlags(&W.gstream, hipStreamNonBlocking));
-  if (!W.gready) ASM_HIP(hipEventCreateWithFlags(&W.gready, hipEventDisableTiming));
-  hipStream_t s = W.gstream;
-  ASM_HIP(hipEventRecord(W.gready, user_stream));
-  ASM_HIP(hipStreamWaitEvent(s, W.gready, 0));
-  bool bad = false;
-  if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
-  if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
-  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
-  const int ld = m + 1;
-  double *hp = W.pinned;
-  int nb = 0;
-  ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
-  ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
-  ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-  ASM_HIP(hipStreamSynchronize(s));
-  const double bnorm = std::sqrt(hp[0]);
-  if (bnorm == 0.0 && o->fixed_iters == 0) {
-    ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  try {
+    g_err.clear();
+    if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
+    if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+    std::memset(info, 0, sizeof *info);
+    const int m = o->restart;
+    if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
+      return fail(ASM_ERR_INVALID, "bad solver option");
+    if (pc->opts.kind != ASM_KIND_NONE &&
+        (pc->opts.local != ASM_LOCAL_ILU0 || pc->opts.coarse != ASM_COARSE_NONE))
+      return fail(ASM_ERR_INVALID, "graph cycles support ILU(0) local solves without a global coarse grid");
+    const int64_t n = 3 * (int64_t)S->pat.N;
+    asm_status st = ensure_workspace(S, m, user_stream);
+    if (st != ASM_OK) return st;
+    Workspace &W = S->ws;
+    // the graphs run on a stream of the library's own (a capture needs a
+    // stream that is not the legacy default one), after the caller's work
+    if (!W.gstream) ASM_HIP(hipStreamCreateWithFlags(&W.gstream, hipStreamNonBlocking));
+    if (!W.gready) ASM_HIP(hipEventCreateWithFlags(&W.gready, hipEventDisableTiming));
+    hipStream_t s = W.gstream;
+    ASM_HIP(hipEventRecord(W.gready, user_stream));
+    ASM_HIP(hipStreamWaitEvent(s, W.gready, 0));
+    bool bad = false;
+    if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
+    if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
+    if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
+    const int ld = m + 1;
+    double *hp = W.pinned;
+    int nb = 0;
+    ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
+    ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
+    ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
-    return ASM_OK;
-  }
-  const double scl = bnorm > 0.0 ? bnorm : 1.0;
-  const double tol = o->rtol * bnorm;
-  // initial residual: beta into misc[1], 1/beta into scale[0], r into U_0
-  int nbr = 0;
-  ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
-  ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
-  ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-  ASM_HIP(hipStreamSynchronize(s));
-  double beta = hp[0];
-  info->rel_res_true = info->rel_res_est = beta / scl;
-  if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
-  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
-  // stopping test of the cycles (host-written, read by the Givens kernel).
-  // Pinned scalars: [4, 7) this state, [8, 11) what a cycle publishes,
-  // [12] the step limit of the next cycle.
-  static_assert(sizeof(CycleState) <= 3 * sizeof(double), "cycle state fits its pinned slot");
-  CycleState cs0{};
-  cs0.use_tol = o->fixed_iters == 0 ? 1 : 0;
-  cs0.tol = tol;
-  std::memcpy(hp + 4, &cs0, sizeof cs0);
-  ASM_HIP(hipMemcpyAsync(W.cst, hp + 4, sizeof cs0, hipMemcpyHostToDevice, s));
-  ASM_HIP(hipStreamSynchronize(s));
-  double *pub = W.pinned_dev + 8;
-  const void *key[4] = {pc, b, x, reinterpret_cast<const void *>((intptr_t)m)};
-  if (!W.gexec || std::memcmp(W.gkey, key, sizeof key) != 0) {
-    W.drop_graph();
-    // one cycle: m steps whose kernels return at once after the cycle's
-    // end, then the correction x += B^-1 V_k y and the true residual
-    const int *skip = &W.cst->done;
-    ASM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    auto record = [&]() -> asm_status {
-      Profiler none;
-      ASM_HIP(launch_cycle_start(W.cst, W.gg, W.misc + 1, s));
-      for (int j = 0; j < m; ++j) {
-        const double *Uj = W.U + (size_t)j * W.ldu;
-        asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &none, skip);
-        if (e2 != ASM_OK) return e2;
-        ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, skip));
-        int nbd = 0, nbu = 0;
-        ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, skip));
-        ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s, skip));
-        ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
-                              &nbu, s, skip));
-        ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
-                                     nullptr, s, skip));
-        ASM_HIP(launch_givens(j, ld, W.H, W.gcs, W.gsn, W.gg, W.dvec, W.cst, s));
-      }
-      ASM_HIP(launch_cycle_end(ld, W.H, W.gg, W.scale, W.coef, W.cst, s));
-      ASM_HIP(launch_lincomb_dev(n, W.cst, W.U, W.ldu, W.coef, W.t, s));
-      asm_status e2 = apply_precond(pc, W.t, nullptr, W.z, s, &none);
-      if (e2 != ASM_OK) return e2;
-      ASM_HIP(launch_axpy(n, W.z, x, s));
-      int nbe = 0;
-      ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbe, s));
-      ASM_HIP(launch_norm_finalize(nbe, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
-      ASM_HIP(launch_cycle_publish(W.cst, W.gg, W.misc + 1, pub, s));
+    const double bnorm = std::sqrt(hp[0]);
+    if (bnorm == 0.0 && o->fixed_iters == 0) {
+      ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+      ASM_HIP(hipStreamSynchronize(s));
       return ASM_OK;
-    };
-    const asm_status rec = record();
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(s, &graph);
-    if (rec != ASM_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rec;
     }
-    if (ec != hipSuccess) return fail(ASM_ERR_HIP, hipGetErrorString(ec));
-    const hipError_t ei = hipGraphInstantiate(&W.gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) {
-      W.gexec = nullptr;
-      return fail(ASM_ERR_HIP, hipGetErrorString(ei));
-    }
-    std::memcpy(W.gkey, key, sizeof key);
-  }
-  asm_status result = ASM_NOT_CONVERGED;
-  int *kmax_host = reinterpret_cast<int *>(hp + 12);
-  while (true) {
-    if (beta == 0.0) { result = ASM_OK; break; }
-    info->cycles++;
-    *kmax_host = std::min(m, limit - info->iters);
-    ASM_HIP(hipMemcpyAsync(&W.cst->kmax, kmax_host, sizeof(int), hipMemcpyHostToDevice, s));
-    ASM_HIP(hipGraphLaunch(W.gexec, s));
+    const double scl = bnorm > 0.0 ? bnorm : 1.0;
+    const double tol = o->rtol * bnorm;
+    // initial residual: beta into misc[1], 1/beta into scale[0], r into U_0
+    int nbr = 0;
+    ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
+    ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+    ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
-    const double *pr = hp + 8;
-    info->iters += (int)pr[0];
-    beta = pr[1];
-    info->rel_res_est = pr[2] / scl;
-    info->rel_res_true = beta / scl;
-    if (o->fixed_iters > 0) {
-      if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
-    } else if (beta <= tol) {
-      result = ASM_OK;
-      break;
+    double beta = hp[0];
+    info->rel_res_true = info->rel_res_est = beta / scl;
+    if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
+    const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+    // stopping test of the cycles (host-written, read by the Givens kernel).
+    // Pinned scalars: [4, 7) this state, [8, 11) what a cycle publishes,
+    // [12] the step limit of the next cycle.
+    static_assert(sizeof(CycleState) <= 3 * sizeof(double), "cycle state fits its pinned slot");
+    CycleState cs0{};
+    cs0.use_tol = o->fixed_iters == 0 ? 1 : 0;
+    cs0.tol = tol;
+    std::memcpy(hp + 4, &cs0, sizeof cs0);
+    ASM_HIP(hipMemcpyAsync(W.cst, hp + 4, sizeof cs0, hipMemcpyHostToDevice, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    double *pub = W.pinned_dev + 8;
+    const void *key[4] = {pc, b, x, reinterpret_cast<const void *>((intptr_t)m)};
+    if (!W.gexec || std::memcmp(W.gkey, key, sizeof key) != 0) {
+      W.drop_graph();
+      // one cycle: m steps whose kernels return at once after the cycle's
+      // end, then the correction x += B^-1 V_k y and the true residual
+      const int *skip = &W.cst->done;
+      ASM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      auto record = [&]() -> asm_status {
+        Profiler none;
+        ASM_HIP(launch_cycle_start(W.cst, W.gg, W.misc + 1, s));
+        for (int j = 0; j < m; ++j) {
+          const double *Uj = W.U + (size_t)j * W.ldu;
+          asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &none, skip);
+          if (e2 != ASM_OK) return e2;
+          ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, skip));
+          int nbd = 0, nbu = 0;
+          ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, skip));
+          ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s, skip));
+          ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
+                                &nbu, s, skip));
+          ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
+                                       nullptr, s, skip));
+          ASM_HIP(launch_givens(j, ld, W.H, W.gcs, W.gsn, W.gg, W.dvec, W.cst, s));
+        }
+        ASM_HIP(launch_cycle_end(ld, W.H, W.gg, W.scale, W.coef, W.cst, s));
+        ASM_HIP(launch_lincomb_dev(n, W.cst, W.U, W.ldu, W.coef, W.t, s));
+        asm_status e2 = apply_precond(pc, W.t, nullptr, W.z, s, &none);
+        if (e2 != ASM_OK) return e2;
+        ASM_HIP(launch_axpy(n, W.z, x, s));
+        int nbe = 0;
+        ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbe, s));
+        ASM_HIP(launch_norm_finalize(nbe, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+        ASM_HIP(launch_cycle_publish(W.cst, W.gg, W.misc + 1, pub, s));
+        return ASM_OK;
+      };
+      const asm_status rec = record();
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s, &graph);
+      if (rec != ASM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rec;
+      }
+      if (ec != hipSuccess) return fail(ASM_ERR_HIP, hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&W.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        W.gexec = nullptr;
+        return fail(ASM_ERR_HIP, hipGetErrorString(ei));
+      }
+      std::memcpy(W.gkey, key, sizeof key);
     }
-    if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
+    asm_status result = ASM_NOT_CONVERGED;
+    int *kmax_host = reinterpret_cast<int *>(hp + 12);
+    while (true) {
+      if (beta == 0.0) { result = ASM_OK; break; }
+      info->cycles++;
+      *kmax_host = std::min(m, limit - info->iters);
+      ASM_HIP(hipMemcpyAsync(&W.cst->kmax, kmax_host, sizeof(int), hipMemcpyHostToDevice, s));
+      ASM_HIP(hipGraphLaunch(W.gexec, s));
+      ASM_HIP(hipStreamSynchronize(s));
+      const double *pr = hp + 8;
+      info->iters += (int)pr[0];
+      beta = pr[1];
+      info->rel_res_est = pr[2] / scl;
+      info->rel_res_true = beta / scl;
+      if (o->fixed_iters > 0) {
+        if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
+      } else if (beta <= tol) {
+        result = ASM_OK;
+        break;
+      }
+      if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
+    }
+    return result;
   }
-  return result;
+  ASM_CATCH_ALL
 }
 
 asm_status asm_profile_enable(asm_system S, int32_t phase_mask) {
-  g_err.clear();
-  if (!S) return fail(ASM_ERR_INVALID, "NULL argument");
-  S->prof.on = (phase_mask != 0);
-  S->prof.mask = (uint32_t)phase_mask;
-  return ASM_OK;
+  try {
+    g_err.clear();
+    if (!S) return fail(ASM_ERR_INVALID, "NULL argument");
+    S->prof.on = (phase_mask != 0);
+    S->prof.mask = (uint32_t)phase_mask;
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
 }
 
 asm_status asm_profile_read(asm_system S, asm_profile *out, int32_t reset) {
-  g_err.clear();
-  if (!S || !out) return fail(ASM_ERR_INVALID, "NULL argument");
-  for (int k = 0; k < ASM_NPHASE; ++k) {
-    out->launches[k] = S->prof.launches[k];
-    out->ms[k] = S->prof.ms[k];
+  try {
+    g_err.clear();
+    if (!S || !out) return fail(ASM_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < ASM_NPHASE; ++k) {
+      out->launches[k] = S->prof.launches[k];
+      out->ms[k] = S->prof.ms[k];
+    }
+    if (reset) S->prof.reset();
+    return ASM_OK;
   }
-  if (reset) S->prof.reset();
-  return ASM_OK;
+  ASM_CATCH_ALL
 }
 
 void asm_destroy_precond(asm_precond pc) {

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,21 @@ inline asm_status fail(asm_status st, const std::string &msg) {
   g_err = msg;
   return st;
 }
+
+// Every C entry point returns its errors: the body runs in a try block and
+// no C++ exception (a host allocation failing inside a container, say)
+// crosses the ABI.  Handles under construction are held by unique_ptr until
+// they are handed out, so nothing leaks on that path either.
+#define ASM_CATCH_ALL                                                                          \
+  catch (const std::bad_alloc &) {                                                             \
+    return fail(ASM_ERR_OOM, "host allocation failed");                                        \
+  }                                                                                            \
+  catch (const std::exception &ex_) {                                                          \
+    return fail(ASM_ERR_INVALID, std::string("internal error: ") + ex_.what());                \
+  }                                                                                            \
+  catch (...) {                                                                                \
+    return fail(ASM_ERR_INVALID, "internal error");                                            \
+  }
 
 #define ASM_HIP(call)                                                                        \
   do {                                                                                       \
