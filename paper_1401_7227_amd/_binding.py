@@ -169,6 +169,34 @@ def _ptr(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+def _checked(t, dtype, n: int, name: str) -> torch.Tensor:
+    """A tensor the library reads or writes through a bare pointer: the C
+    side cannot see its size, so it must be a contiguous tensor of `dtype`
+    on the current GPU with exactly n elements."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.device.type != "cuda" or t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name}: must live on the current GPU (cuda:{torch.cuda.current_device()}), not {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+    return t
+
+
+def _vec(t, n: int, name: str) -> torch.Tensor:
+    """An input vector (array or tensor) as a contiguous float64 tensor on
+    the GPU with n elements."""
+    return _checked(_dev(t, torch.float64), torch.float64, n, name)
+
+
+def _out(t, n: int, name: str) -> torch.Tensor:
+    """An output vector: written in place, so never converted."""
+    return _checked(t, torch.float64, n, name)
+
+
 class System:
     """Device copy of A (= -J) in the library's own layout."""
 
@@ -176,10 +204,10 @@ class System:
         L = load()
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
-        rp = _dev(row_ptr, torch.int32)
+        rp = _dev(row_ptr, torch.int32)  # its length gives nb, which the library checks against the grid
         ci = _dev(col_idx, torch.int32)
-        v = _dev(vals, torch.float64).reshape(-1)
         self.nnzb = int(ci.numel())
+        v = _checked(_dev(vals, torch.float64).reshape(-1), torch.float64, 9 * self.nnzb, "vals")
         h = C.c_void_p()
         g = Grid(nx, ny, nz)
         _check(L.asm_create_system(C.byref(g), int(rp.numel()) - 1, self.nnzb, _ptr(rp),
@@ -195,12 +223,12 @@ class System:
         return self._h
 
     def update_values(self, vals):
-        v = _dev(vals, torch.float64).reshape(-1)
+        v = _checked(_dev(vals, torch.float64).reshape(-1), torch.float64, 9 * self.nnzb, "vals")
         _check(load().asm_update_values(self._h, _ptr(v), _stream()))
 
     def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        x = _dev(x, torch.float64)
-        y = torch.empty_like(x) if out is None else out
+        x = _vec(x, 3 * self.N, "x")
+        y = torch.empty_like(x) if out is None else _out(out, 3 * self.N, "out")
         _check(load().asm_spmv(self._h, _ptr(x), _ptr(y), _stream()))
         return y
 
@@ -273,8 +301,9 @@ class Precond:
         _check(load().asm_refactor(self._h, _stream()))
 
     def apply(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        r = _dev(r, torch.float64)
-        z = torch.empty_like(r) if out is None else out
+        n = 3 * self.system.N
+        r = _vec(r, n, "r")
+        z = torch.empty_like(r) if out is None else _out(out, n, "out")
         _check(load().asm_precond_apply(self._h, _ptr(r), _ptr(z), _stream()))
         return z
 
@@ -325,13 +354,14 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
     """Solves A x = b; returns (x, Info).  b, x0: device tensors or arrays.
     graph: every restart cycle runs as one captured HIP graph with the
     convergence test on the device (asm_solve_graph)."""
-    b = _dev(b, torch.float64)
+    n = 3 * system.N
+    b = _vec(b, n, "b")
     if out is not None:
-        x = out
+        x = _out(out, n, "out")
         if x0 is not None:
-            x.copy_(_dev(x0, torch.float64))
+            x.copy_(_vec(x0, n, "x0"))
     else:
-        x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64).clone()
+        x = torch.zeros_like(b) if x0 is None else _vec(x0, n, "x0").clone()
     o = SolveOpts(restart, rtol, max_iters, fixed_iters)
     info = SolveInfo()
     fn = load().asm_solve_graph if graph else load().asm_solve
@@ -345,13 +375,15 @@ def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_i
     n = len(systems)
     if n == 0:
         return [], []
-    bs = [_dev(b, torch.float64) for b in bs]
+    if len(preconds) != n or len(bs) != n or (x0s is not None and len(x0s) != n):
+        raise ValueError("one preconditioner, b (and x0) per system")
+    bs = [_vec(b, 3 * S.N, f"bs[{i}]") for i, (b, S) in enumerate(zip(bs, systems))]
     xs = []
     for i in range(n):
         if x0s is None or x0s[i] is None:
             xs.append(torch.zeros_like(bs[i]))
         else:
-            xs.append(_dev(x0s[i], torch.float64).clone())
+            xs.append(_vec(x0s[i], 3 * systems[i].N, f"x0s[{i}]").clone())
     V = C.c_void_p
     hs = (V * n)(*[s.handle.value for s in systems])
     ps = (V * n)(*[p.handle.value for p in preconds])
@@ -392,11 +424,19 @@ class Server:
         k = len(vals)
         if not (1 <= k <= SERVER_MAX_SOLVES and len(bs) == k and len(xs) == k):
             raise ValueError("one values, b and x tensor per solve, 1..8 solves")
+        nb = row_ptr.numel() - 1  # the library checks it against the grid
+        _checked(row_ptr, torch.int32, nb + 1, "row_ptr")
+        nnzb = col_idx.numel()
+        _checked(col_idx, torch.int32, nnzb, "col_idx")
+        for i in range(k):
+            _checked(vals[i], torch.float64, 9 * nnzb, f"vals[{i}]")
+            _checked(bs[i], torch.float64, 3 * nb, f"bs[{i}]")
+            _checked(xs[i], torch.float64, 3 * nb, f"xs[{i}]")
         r = Request()
         r.tag = tag
         r.grid = Grid(*grid)
-        r.nb = row_ptr.numel() - 1
-        r.nnzb = col_idx.numel()
+        r.nb = nb
+        r.nnzb = nnzb
         r.row_ptr_dev = row_ptr.data_ptr()
         r.col_idx_dev = col_idx.data_ptr()
         r.precond = popts
