@@ -4,9 +4,12 @@ Calls only the CPU oracle on the seeded generator's input (seed 2, 16x16
 subdomains of 8x8x64, overlap 1, GMRES(30) to rtol 1e-6).  For each
 preconditioner it stores the iteration count, the true relative residual,
 and the solution at a fixed sample of unknowns, so that the GPU tests can
-compare at equal iteration counts without re-running the oracle.
+compare at equal iteration counts without re-running the oracle.  With
+--apply it stores instead, for every variant, one application z = B^-1 b of
+the preconditioner (the same sample of z and its norm): the check of the
+Schwarz apply alone at full size, additive combine included.
 
-Usage: python tests/golden/make_config2_golden.py [variant ...]
+Usage: python tests/golden/make_config2_golden.py [--apply] [variant ...]
 """
 import json
 import os
@@ -55,5 +58,24 @@ def main(names):
         json.dump(data, open(OUT, "w"), indent=1)
 
 
+def main_apply(names):
+    s = gen.generate(*GRID, seed=SEED)
+    A = O.Matrix.from_system(s)
+    data = json.load(open(OUT))
+    sample = np.array(data["sample"])
+    app = data.setdefault("apply", {})
+    for name in names:
+        t0 = time.perf_counter()
+        P = O.Precond(A, near=NEAR, far=FAR, **SPLIT, **VARIANTS[name])
+        z = P.apply(s.b)
+        app[name] = dict(r="b", z_norm=float(np.linalg.norm(z)), z_sample=z[sample].tolist())
+        print(name, "apply", f"{time.perf_counter() - t0:.1f}s", flush=True)
+        json.dump(data, open(OUT, "w"), indent=1)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(VARIANTS))
+    args = sys.argv[1:]
+    if args and args[0] == "--apply":
+        main_apply(args[1:] or list(VARIANTS))
+    else:
+        main(args or list(VARIANTS))

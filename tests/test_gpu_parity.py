@@ -313,6 +313,28 @@ def test_config2_solve_matches_oracle(P, variant):
     assert np.linalg.norm(xs - ref) <= 1e-8 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("variant", ["two_level_ras", "classical_ras", "classical_additive"])
+def test_config2_apply_matches_oracle(P, variant):
+    """One application z = B^-1 b at full size (128x128x64, 256 subdomains,
+    the launch configuration of the benchmark): z on the stored sample of
+    unknowns and the norm of the whole z agree with the oracle's to 1e-12
+    (FP64 arithmetic, only the summation order differs)."""
+    gd = _golden()
+    if variant not in gd.get("apply", {}):
+        pytest.skip(f"{variant} apply not in golden file")
+    g = gd["apply"][variant]
+    kinds = {"two_level_ras": (P.KIND_TWO_LEVEL, P.RESTRICTED), "classical_ras": (P.KIND_CLASSICAL, P.RESTRICTED),
+             "classical_additive": (P.KIND_CLASSICAL, P.ADDITIVE)}
+    kind, combine = kinds[variant]
+    s = gen.generate(*gd["grid"], seed=gd["seed"])
+    G = P.System.from_generated(s)
+    B = P.Precond(G, kind=kind, combine=combine, sx=16, sy=16, overlap=1, near=(4, 4, 4), far=(16, 16, 16))
+    z = to_np(B.apply(s.b))
+    ref = np.array(g["z_sample"])
+    assert np.linalg.norm(z[np.array(gd["sample"])] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert abs(np.linalg.norm(z) - g["z_norm"]) <= 1e-12 * g["z_norm"]
+
+
 # ---------------------------------------------------------------- batched solves
 BATCH_CASES = [
     ((10, 10, 5), 1, dict(kind=2, combine=1, sx=4, sy=1, overlap=1, near=(2, 2, 2), far=(5, 5, 5)), 0),
