@@ -290,7 +290,7 @@ def _golden():
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("variant", ["two_level_ras", "classical_ras"])
+@pytest.mark.parametrize("variant", ["two_level_ras", "classical_ras", "classical_additive"])
 def test_config2_solve_matches_oracle(P, variant):
     """128x128x64, 256 subdomains: iteration count within +-1 of the
     oracle's, true residual <= 1e-6, and at the oracle's iteration count the
@@ -302,7 +302,8 @@ def test_config2_solve_matches_oracle(P, variant):
     s = gen.generate(*gd["grid"], seed=gd["seed"])
     G = P.System.from_generated(s)
     kind = P.KIND_TWO_LEVEL if variant.startswith("two") else P.KIND_CLASSICAL
-    B = P.Precond(G, kind=kind, combine=P.RESTRICTED, sx=g["sx"], sy=g["sy"], overlap=g["overlap"],
+    combine = P.ADDITIVE if variant.endswith("additive") else P.RESTRICTED
+    B = P.Precond(G, kind=kind, combine=combine, sx=g["sx"], sy=g["sy"], overlap=g["overlap"],
                   near=tuple(g["near"]), far=tuple(g["far"]))
     x, info = P.solve(G, B, s.b, restart=30, rtol=1e-6, max_iters=3000)
     assert info.status == P.OK and info.rel_res_true <= 1e-6
