@@ -399,7 +399,7 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 constexpr int kRecU4 = kRecBytes / 16;
 constexpr int kStageU4 = kRecU4 / 256;
 static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
-static_assert(kMaxStepRows * 3 <= 3 * 256, "row inputs: three doubles per streaming thread");
+static_assert(kMaxStepRows <= 256, "row inputs: one row (three doubles) per streaming thread");
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 #ifndef ASM_SWEEP_COMPUTE_WAVES
@@ -669,10 +669,10 @@ template <bool G>
 struct Producer {
   Stage st[kAhead];
   int len[kAhead];
-  int xlast[kAhead];
+  int nrows[kAhead];         // rows of the staged record (at least 1): the threads that store inputs
   int dq[kAhead];            // descriptor of the record stage k loads next (one word per lane)
   int dq2[G ? kAhead : 1];   // gathering: the descriptor kAhead records after that
-  int ix[G ? kAhead : 1][3]; // gathering: sources of this thread's inputs of record dq[k]
+  int ix[G ? kAhead : 1];    // gathering: source of this thread's row of record dq[k]
 };
 
 // Descriptor of step k by a vector load, lane l holding word l % 4.  The
@@ -692,54 +692,50 @@ __device__ __forceinline__ RecStep desc_get(int v) {
   return d;
 }
 
-// Sources of this thread's three inputs (elements t, t+256, t+512 of the
-// step's 3 * nrows, clamped) of the step described by d.
-__device__ __forceinline__ void ix_load(const RecStep &d, const int32_t *__restrict__ fsrc, int (&ix)[3], int t) {
-  const int last = 3 * max(d.nrows, 1) - 1;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) ix[i] = __builtin_nontemporal_load(glb(fsrc) + d.pos + min(i * 256 + t, last) / 3);
+// Source of this thread's row (row t of the step, clamped) of the step
+// described by d.
+__device__ __forceinline__ int ix_load(const RecStep &d, const int32_t *__restrict__ fsrc, int t) {
+  return __builtin_nontemporal_load(glb(fsrc) + d.pos + min(t, max(d.nrows, 1) - 1));
 }
 
 // Streamer: load record k of the sweep and its row inputs into a stage.
 // Loads are clamped to the record / the input segment, never conditional;
 // records are read once per application, so they are loaded
-// non-temporally.  A gathered cell value is scaled by the computing waves
-// (row flag bit 1), so that nothing here waits on the loads it issues.
+// non-temporally.  Each thread loads the three inputs of one row (24
+// contiguous bytes).  A gathered cell value is scaled by the computing
+// waves (row flag bit 1), so that nothing here waits on the loads it issues.
 template <bool G>
 __device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec, const SweepIn &in,
-                                          const int (&ix)[3], Stage &st, int &len, int &xlast, int t) {
+                                          int ix, Stage &st, int &len, int &nrows, int t) {
 #pragma unroll
   for (int i = 0; i < kStageU4; ++i)
     st.v[i] = __builtin_nontemporal_load(glb(rec) + d.rec + min(i * 256 + t, d.len - 1));
-  const int last = 3 * max(d.nrows, 1) - 1;
+  const int nst = max(d.nrows, 1);
+  glb_cdouble *p;
   if constexpr (G) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int e = min(i * 256 + t, last);
-      const int k = e - 3 * (e / 3);
-      const int c = ix[i];
-      glb_cdouble *p = c >= 0 ? glb(in.r) + 3 * (size_t)c + k : glb(in.crs) + 3 * (size_t)(-c - 1) + k;
-      st.x[i] = *p;
-    }
+    p = ix >= 0 ? glb(in.r) + 3 * (size_t)ix : glb(in.crs) + 3 * (size_t)(-ix - 1);
   } else {
-    glb_cdouble *xs = glb(in.src) + 3 * (size_t)d.pos;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) st.x[i] = xs[min(i * 256 + t, last)];
+    p = glb(in.src) + 3 * ((size_t)d.pos + min(t, nst - 1));
   }
+  st.x[0] = p[0];
+  st.x[1] = p[1];
+  st.x[2] = p[2];
   len = d.len;
-  xlast = last;
+  nrows = nst;
 }
 
 // Stores a stage into an LDS buffer: the record words, then the inputs
 // right behind the record.
-__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len, int xlast, int t) {
+__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len, int nrows, int t) {
 #pragma unroll
   for (int i = 0; i < kStageU4; ++i)
     if (i * 256 + t < len) dst[i * 256 + t] = st.v[i];
   double *xd = reinterpret_cast<double *>(dst + len);
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-    if (i * 256 + t <= xlast) xd[i * 256 + t] = st.x[i];
+  if (t < nrows) {
+    xd[3 * t] = st.x[0];
+    xd[3 * t + 1] = st.x[1];
+    xd[3 * t + 2] = st.x[2];
+  }
 }
 
 template <bool G, int K>
@@ -754,17 +750,17 @@ __device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restric
   // kAhead steps old) and dq2[K] the descriptor of s+1+3*kAhead.  Each ring
   // register is overwritten in place, after its last use: a copy of a value
   // still in flight would wait for it.
-  prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.xlast[K], t);
+  prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.nrows[K], t);
   const RecStep d = desc_get(P.dq[K]);
   if constexpr (G) {
     const RecStep d2 = desc_get(P.dq2[K]);
     P.dq[K] = P.dq2[K];
     P.dq2[K] = desc_load(steps, min(s + 1 + 3 * kAhead, S - 1), t);
-    prod_load<G>(d, rec, in, P.ix[K], P.st[K], P.len[K], P.xlast[K], t);
-    ix_load(d2, in.fsrc, P.ix[K], t);
+    prod_load<G>(d, rec, in, P.ix[K], P.st[K], P.len[K], P.nrows[K], t);
+    P.ix[K] = ix_load(d2, in.fsrc, t);
   } else {
     P.dq[K] = desc_load(steps, min(s + 1 + 2 * kAhead, S - 1), t);
-    prod_load<G>(d, rec, in, P.ix[0], P.st[K], P.len[K], P.xlast[K], t);
+    prod_load<G>(d, rec, in, 0, P.st[K], P.len[K], P.nrows[K], t);
   }
   __syncthreads();
 }
@@ -784,20 +780,20 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   // gathering: the sources of the first kAhead+1 records' inputs and of
   // those the first iterations load, ahead of the first records, so that
   // the loop finds them as old as in its steady state
-  int ix0[kAhead + 1][3];
+  int ix0[kAhead + 1] = {};
   if constexpr (G) {
 #pragma unroll
     for (int k = 0; k < kAhead; ++k) P.dq2[k] = desc_load(steps, min(first(k) + kAhead, S - 1), t);
 #pragma unroll
-    for (int k = 0; k <= kAhead; ++k) ix_load(ld_glb(steps + min(k, S - 1)), in.fsrc, ix0[k], t);
+    for (int k = 0; k <= kAhead; ++k) ix0[k] = ix_load(ld_glb(steps + min(k, S - 1)), in.fsrc, t);
 #pragma unroll
-    for (int k = 0; k < kAhead; ++k) ix_load(desc_get(P.dq[k]), in.fsrc, P.ix[k], t);
+    for (int k = 0; k < kAhead; ++k) P.ix[k] = ix_load(desc_get(P.dq[k]), in.fsrc, t);
   }
 #pragma unroll
   for (int k = 0; k < kAhead; ++k)
-    prod_load<G>(ld_glb(steps + min(k, S - 1)), rec, in, ix0[k], P.st[k], P.len[k], P.xlast[k], t);
-  prod_store(L.buf[0], P.st[0], P.len[0], P.xlast[0], t);
-  prod_load<G>(ld_glb(steps + min(kAhead, S - 1)), rec, in, ix0[kAhead], P.st[0], P.len[0], P.xlast[0], t);
+    prod_load<G>(ld_glb(steps + min(k, S - 1)), rec, in, ix0[k], P.st[k], P.len[k], P.nrows[k], t);
+  prod_store(L.buf[0], P.st[0], P.len[0], P.nrows[0], t);
+  prod_load<G>(ld_glb(steps + min(kAhead, S - 1)), rec, in, ix0[kAhead], P.st[0], P.len[0], P.nrows[0], t);
   __syncthreads();
   // full groups of kAhead steps without conditions (exact wait counts),
   // then the remaining steps in straight-line code
