@@ -699,7 +699,8 @@ __device__ __forceinline__ int ix_load(const RecStep &d, const int32_t *__restri
 }
 
 // Streamer: load record k of the sweep and its row inputs into a stage.
-// Loads are clamped to the record / the input segment, never conditional;
+// Lanes past the record's end load nothing (their stage words are never
+// stored), so a short record issues fewer wave-wide loads;
 // records are read once per application, so they are loaded
 // non-temporally.  Each thread loads the three inputs of one row (24
 // contiguous bytes).  A gathered cell value is scaled by the computing
@@ -709,7 +710,9 @@ __device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restr
                                           int ix, Stage &st, int &len, int &nrows, int t) {
 #pragma unroll
   for (int i = 0; i < kStageU4; ++i)
-    st.v[i] = __builtin_nontemporal_load(glb(rec) + d.rec + min(i * 256 + t, d.len - 1));
+    if (i * 256 + t < d.len) st.v[i] = __builtin_nontemporal_load(glb(rec) + d.rec + i * 256 + t);
+  // the row inputs stay clamped: a conditional load here makes the compiler
+  // merge the stage registers at the join and wait for the loads at once
   const int nst = max(d.nrows, 1);
   glb_cdouble *p;
   if constexpr (G) {
