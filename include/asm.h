@@ -185,6 +185,10 @@ typedef struct {
   int64_t sweep_steps;   /* forward + backward sweep steps, all subdomains */
   int64_t reloaded_rows; /* rows whose values are reloaded from global
                             memory (no on-chip slot) during a sweep      */
+  int64_t split_rows;    /* rows (counted once per sweep) whose sum is
+                            computed in pieces over several sweep steps:
+                            too many entries for one record, or too many
+                            reloaded inputs for the reload slots          */
 } asm_precond_stats;
 asm_status asm_precond_get_stats(asm_precond pc, asm_precond_stats *stats_host);
 
@@ -325,7 +329,10 @@ typedef struct {
 } asm_server_state;
 
 asm_status asm_server_create(const asm_server_opts *opts, hipStream_t stream, asm_server *out);
-/* Queues a request (no device work). */
+/* Queues a request (no device work).  Its tag must differ from the tags of
+ * all live requests (queued, running, or completed but not yet returned by
+ * asm_server_poll): ASM_ERR_INVALID otherwise.  A tag is free again once
+ * its completion has been returned. */
 asm_status asm_server_submit(asm_server srv, const asm_request *req);
 /* One scheduling round: admission, one restart cycle of every solve in
  * flight, then up to `max` completions (oldest first) into done_host;

@@ -18,7 +18,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ASM_ORACLE_LIB names another build of oracle.c (the sanitizer test runs
+# the pins against one built with AddressSanitizer and UBSan)
+_LIB = os.environ.get("ASM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, INVALID, OOM, SINGULAR, NONFINITE = 0, 1, -1, -2, -3, -4
 KIND_NONE, KIND_CLASSICAL, KIND_TWO_LEVEL = 0, 1, 2
@@ -116,8 +118,22 @@ class Matrix:
         return self.nx * self.ny * self.nz
 
 
+def _check_sizes(A: Matrix, *vecs) -> None:
+    """Array lengths the C code cannot see: row_ptr of N+1, col_idx and
+    vals of row_ptr[N] blocks, vectors of 3N (INVALID otherwise)."""
+    N = A.N
+    ok = (A.nx > 0 and A.ny > 0 and A.nz > 0 and A.row_ptr.ndim == 1 and A.row_ptr.size == N + 1)
+    if ok:
+        nnzb = int(A.row_ptr[N])
+        ok = (0 <= nnzb and A.col_idx.size == nnzb and A.vals.size == 9 * nnzb)
+    ok = ok and all(v is None or v.size == 3 * N for v in vecs)
+    if not ok:
+        raise OracleError(INVALID, "array sizes do not match the grid")
+
+
 def spmv(A: Matrix, x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
+    _check_sizes(A, x)
     y = np.empty(3 * A.N)
     lib().or_spmv(A.N, _p(A.row_ptr), _p(A.col_idx), _p(A.vals), _p(x), _p(y))
     return y
@@ -144,6 +160,7 @@ class Precond:
                  sx=1, sy=1, overlap=1, near=(2, 2, 2), far=(4, 4, 4),
                  local=LOCAL_ILU0, field=FIELD_NEAR_FAR, coarse=COARSE_NONE, cbox=(4, 4, 4)):
         self.A = A
+        _check_sizes(A)
         o = _Opts(kind, combine, sx, sy, overlap, (C.c_int * 3)(*near),
                   (C.c_int * 3)(*far), local, field, coarse, (C.c_int * 3)(*cbox))
         h = C.c_void_p()
@@ -170,6 +187,7 @@ class Precond:
 
     def apply(self, r: np.ndarray) -> np.ndarray:
         r = np.ascontiguousarray(r, dtype=np.float64)
+        _check_sizes(self.A, r)
         z = np.empty(3 * self.A.N)
         st = lib().or_precond_apply(self._h, _p(r), _p(z))
         if st != OK:
@@ -177,6 +195,8 @@ class Precond:
         return z
 
     def sub(self, s: int) -> Sub:
+        if not 0 <= s < self.nsub:
+            raise OracleError(INVALID, "subdomain out of range")
         n, nf, nc, nnz = (C.c_int(), C.c_int(), C.c_int(), C.c_int())
         lib().or_sub_sizes(self._h, s, C.byref(n), C.byref(nf), C.byref(nc), C.byref(nnz))
         N = self.A.N
@@ -195,6 +215,12 @@ class Precond:
 
     def sub_solve(self, s: int, rh: np.ndarray) -> np.ndarray:
         rh = np.ascontiguousarray(rh, dtype=np.float64)
+        if not 0 <= s < self.nsub:
+            raise OracleError(INVALID, "subdomain out of range")
+        n, nf, nc, nnz = (C.c_int(), C.c_int(), C.c_int(), C.c_int())
+        lib().or_sub_sizes(self._h, s, C.byref(n), C.byref(nf), C.byref(nc), C.byref(nnz))
+        if rh.size != 3 * n.value:
+            raise OracleError(INVALID, "right-hand side of another size")
         xh = np.empty_like(rh)
         lib().or_sub_solve(self._h, s, _p(rh), _p(xh))
         return xh
@@ -216,6 +242,9 @@ def gmres(A: Matrix, P: Precond, b: np.ndarray, x0: np.ndarray | None = None, *,
     """Restarted right-preconditioned GMRES (see or_gmres in oracle.c)."""
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(3 * A.N) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    _check_sizes(A, b, x)
+    if P.A is not A and P.A.N != A.N:
+        raise OracleError(INVALID, "preconditioner of another grid")
     info = _Info()
     hist = np.full(max(max_iters, fixed_iters) + 1, np.nan)
     st = lib().or_gmres(A.nx, A.ny, A.nz, _p(A.row_ptr), _p(A.col_idx), _p(A.vals),

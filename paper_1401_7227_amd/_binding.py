@@ -56,7 +56,8 @@ class PrecondStats(C.Structure):
     _fields_ = [("nsub", C.c_int32), ("ext_rows", C.c_int64), ("coarse_rows", C.c_int64),
                 ("factor_blocks", C.c_int64), ("fine_row_blocks", C.c_int64),
                 ("max_levels", C.c_int32),
-                ("device_bytes", C.c_int64), ("sweep_steps", C.c_int64), ("reloaded_rows", C.c_int64)]
+                ("device_bytes", C.c_int64), ("sweep_steps", C.c_int64), ("reloaded_rows", C.c_int64),
+                ("split_rows", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -422,6 +423,10 @@ class Server:
         xs: lists of float64 device tensors, one per solve (xs hold x0 and
         receive the solutions)."""
         k = len(vals)
+        if tag in self._live:
+            # the library rejects it too; checked here first so the live
+            # request's tensors are never released early
+            raise ValueError(f"tag {tag} is in use by a live request")
         if not (1 <= k <= SERVER_MAX_SOLVES and len(bs) == k and len(xs) == k):
             raise ValueError("one values, b and x tensor per solve, 1..8 solves")
         nb = row_ptr.numel() - 1  # the library checks it against the grid

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <deque>
 #include <future>
+#include <unordered_set>
 
 #include "handles.hpp"
 
@@ -477,6 +478,7 @@ struct asm_server_s {
   std::vector<Request *> running;
   std::vector<Request *> ready;  // next solve of a running request, to join the batch
   std::deque<asm_completion> done;
+  std::unordered_set<int64_t> live_tags;  // tags queued, running or completed but not yet returned
   std::vector<Plan> plans;
   int64_t bytes_in_use = 0;
   int64_t plan_builds = 0, plan_hits = 0;
@@ -798,9 +800,14 @@ asm_status asm_server_submit(asm_server srv, const asm_request *req) {
     if (req->precond.kind == ASM_KIND_NONE) return fail(ASM_ERR_INVALID, "requests need a Schwarz preconditioner");
     if (req->precond.coarse != ASM_COARSE_NONE || req->precond.local != ASM_LOCAL_ILU0)
       return fail(ASM_ERR_INVALID, "coarse corrections and exact local solves are not available in served solves");
+    // a completion names its request by tag: two live requests with one tag
+    // could not be told apart (and the caller's buffers of the first would
+    // be released with the second's completion)
+    if (srv->live_tags.count(req->tag)) return fail(ASM_ERR_INVALID, "tag already in use by a live request");
     std::unique_ptr<Request> r(new (std::nothrow) Request());
     if (!r) return fail(ASM_ERR_OOM, "host allocation failed");
     r->d = *req;
+    srv->live_tags.insert(req->tag);
     srv->queue.push_back(r.get());
     r.release();  // owned by the queue from here
     return ASM_OK;
@@ -892,6 +899,7 @@ asm_status asm_server_poll(asm_server srv, int32_t max, asm_completion *out, int
     // 4. completions
     while (*ndone < max && !srv->done.empty()) {
       out[(*ndone)++] = srv->done.front();
+      srv->live_tags.erase(srv->done.front().tag);
       srv->done.pop_front();
     }
     return ASM_OK;

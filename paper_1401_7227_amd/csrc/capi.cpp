@@ -426,6 +426,7 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   pc->stats.device_bytes = (int64_t)(M.bytes + O.bytes);
   pc->stats.sweep_steps = P.sweep_steps;
   pc->stats.reloaded_rows = P.lds_spilled_rows;
+  pc->stats.split_rows = P.split_rows;
   *out = hold.release();
   return ASM_OK;
 }

@@ -1370,9 +1370,9 @@ __global__ void givens_kernel(int j, int ld, double *H, double *cs, double *sn, 
 
 __global__ void cycle_end_kernel(int ld, const double *H, const double *g, const double *scale, double *coef,
                                  const CycleState *st) {
+  __shared__ double y[kMaxRestart];  // indexed dynamically: LDS, not private (scratch) memory
   if (threadIdx.x != 0) return;
   const int k = st->k;
-  double y[kMaxRestart];
   for (int i = k - 1; i >= 0; --i) {
     double acc = g[i];
     for (int c = i + 1; c < k; ++c) acc -= H[(size_t)c * ld + i] * y[c];

@@ -125,6 +125,7 @@ struct SubLocal {
   std::vector<uint8_t> rl_to32;
   int32_t levels = 0;
   int64_t spilled = 0;
+  int64_t split_rows = 0;  // rows whose sum runs over several sweep steps (pieces)
   int32_t bad_row = -1;  // missing diagonal
 };
 
@@ -487,6 +488,8 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
     for (Chunk &q : split_for_fills(c, true, fslot)) fch.push_back(std::move(q));
   for (const Chunk &c : bch0)
     for (Chunk &q : split_for_fills(c, false, bslot)) bch.push_back(std::move(q));
+  for (const std::vector<Chunk> *ch : {&fch, &bch})
+    for (const Chunk &c : *ch) S.split_rows += (c.piece == kPieceFirst);
   // positions: rows of a step are consecutive, in the step's row order
   std::vector<int32_t> fpos(S.n), bpos(S.n);
   int p = 0;
@@ -1126,6 +1129,7 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     P.max_levels = std::max(P.max_levels, S.levels);
     P.fine_row_entries += S.rp[S.nfine];
     P.lds_spilled_rows += S.spilled;
+    P.split_rows += S.split_rows;
   }
   const int64_t lim = (int64_t)1 << 31;
   if (ext >= lim || ent >= lim || tcount >= lim || asrc >= lim || recb / 4 >= lim || nrl >= lim) {

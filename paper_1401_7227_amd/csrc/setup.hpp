@@ -39,6 +39,7 @@ struct PlanHost {
   int32_t max_levels = 0;
   int64_t sweep_steps = 0;       // forward + backward records
   int64_t lds_spilled_rows = 0;  // rows whose values went through global memory
+  int64_t split_rows = 0;        // rows computed in pieces over several sweep steps
   std::vector<SubDesc> sub;
   // factorisation level steps
   std::vector<Step> fstep;

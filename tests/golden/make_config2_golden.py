@@ -3,10 +3,12 @@
 Calls only the CPU oracle on the seeded generator's input (seed 2, 16x16
 subdomains of 8x8x64, overlap 1, GMRES(30) to rtol 1e-6).  For each
 preconditioner it stores the iteration count, the true relative residual,
-and the solution at a fixed sample of unknowns, so that the GPU tests can
-compare at equal iteration counts without re-running the oracle.  With
+the solution at a fixed sample of unknowns and its per-subdomain
+fingerprint (fingerprint.py: norm, component sums and seeded projections of
+every owned 8x8x64 column block), so that the GPU tests can compare every
+subdomain at equal iteration counts without re-running the oracle.  With
 --apply it stores instead, for every variant, one application z = B^-1 b of
-the preconditioner (the same sample of z and its norm): the check of the
+the preconditioner (the same sample of z, its norm and its fingerprint): the check of the
 Schwarz apply alone at full size, additive combine included.
 
 Usage: python tests/golden/make_config2_golden.py [--apply] [variant ...]
@@ -23,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 import gen  # noqa: E402
 import oracle as O  # noqa: E402
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from fingerprint import fingerprint  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "config2_oracle.json")
 GRID, SEED = (128, 128, 64), 2
@@ -51,7 +55,9 @@ def main(names):
         t2 = time.perf_counter()
         data[name] = dict(status=res.status, iters=res.iters, cycles=res.cycles,
                           rel_res_true=res.rel_res_true, x_norm=float(np.linalg.norm(res.x)),
-                          x_sample=res.x[sample].tolist(), setup_s=t1 - t0, solve_s=t2 - t1,
+                          x_sample=res.x[sample].tolist(),
+                          x_fp=fingerprint(res.x, GRID, SPLIT["sx"], SPLIT["sy"]),
+                          setup_s=t1 - t0, solve_s=t2 - t1,
                           near=list(NEAR), far=list(FAR), **SPLIT)
         print(name, res.status, res.iters, res.rel_res_true, f"setup {t1 - t0:.1f}s solve {t2 - t1:.1f}s",
               flush=True)
@@ -68,7 +74,8 @@ def main_apply(names):
         t0 = time.perf_counter()
         P = O.Precond(A, near=NEAR, far=FAR, **SPLIT, **VARIANTS[name])
         z = P.apply(s.b)
-        app[name] = dict(r="b", z_norm=float(np.linalg.norm(z)), z_sample=z[sample].tolist())
+        app[name] = dict(r="b", z_norm=float(np.linalg.norm(z)), z_sample=z[sample].tolist(),
+                         z_fp=fingerprint(z, GRID, SPLIT["sx"], SPLIT["sy"]))
         print(name, "apply", f"{time.perf_counter() - t0:.1f}s", flush=True)
         json.dump(data, open(OUT, "w"), indent=1)
 

@@ -201,3 +201,51 @@ def test_server_error_statuses(P):
         srv.submit(9, (10, 8, 6), reqs[1]["rp"], reqs[1]["ci"], P.precond_opts(kind=0), reqs[1]["vals"][:1],
                    reqs[1]["bs"][:1], [torch.zeros_like(reqs[1]["bs"][0])])
     srv.close()
+
+
+def test_served_solves_match_oracle(P):
+    """Every solve the server runs (device-drawn inputs, several requests in
+    flight) against the FP64 CPU oracle on the same values: with FP64
+    factors the rtol-stopped iteration count within +-1 of the oracle's and,
+    at the served solve's own iteration count, the solution within a
+    relative 1e-8 of the oracle's; with FP32 factors the count within
+    max(2, 10%) and the solution within 1e-3 (the FP64 true-residual stop
+    still bounds the residual by 1e-6)."""
+    import oracle as O
+    reqs = _requests(P, SPECS)
+    srv = P.Server(restart=30, rtol=1e-6, max_iters=3000, max_active=64)
+    for r in reqs:
+        srv.submit(r["tag"], r["grid"], r["rp"], r["ci"], P.precond_opts(**r["opts"]), r["vals"], r["bs"], r["xs"])
+    done = {}
+    polls = 0
+    while len(done) < len(reqs):
+        for c in srv.poll():
+            done[c["tag"]] = c
+        polls += 1
+        assert polls < 5000
+    srv.close()
+    checked = 0
+    for r in reqs:
+        assert done[r["tag"]]["status"] == P.OK
+        o = r["opts"]
+        fp64 = o["precision"] == 0
+        rp, ci = to_np(r["rp"]).astype(np.int32), to_np(r["ci"]).astype(np.int32)
+        for k, (v, b, x) in enumerate(zip(r["vals"], r["bs"], r["xs"])):
+            A = O.Matrix(*r["grid"], rp, ci, to_np(v).reshape(-1, 3, 3).copy())
+            Bo = O.Precond(A, kind=o["kind"], combine=o["combine"], sx=o["sx"], sy=o["sy"], overlap=o["overlap"],
+                           near=o["near"], far=o["far"])
+            bh = to_np(b)
+            ref = O.gmres(A, Bo, bh, restart=30, rtol=1e-6, max_iters=3000)
+            assert ref.status == O.OK
+            # the served solve's own count (served == solved alone, tested above)
+            G = P.System(*r["grid"], r["rp"], r["ci"], v)
+            _, info = P.solve(G, P.Precond(G, **o), b, restart=30, rtol=1e-6, max_iters=3000)
+            if fp64:
+                assert abs(info.iters - ref.iters) <= 1, (r["tag"], k, info.iters, ref.iters)
+            else:
+                assert abs(info.iters - ref.iters) <= max(2, int(0.1 * ref.iters)), (r["tag"], k)
+            at = O.gmres(A, Bo, bh, restart=30, fixed_iters=info.iters)
+            err = np.linalg.norm(to_np(x) - at.x) / np.linalg.norm(at.x)
+            assert err <= (1e-8 if fp64 else 1e-3), (r["tag"], k, err)
+            checked += 1
+    assert checked == sum(len(r["vals"]) for r in reqs)
