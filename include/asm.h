@@ -224,6 +224,28 @@ typedef struct {
 asm_status asm_solve(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
                      const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
 
+/*
+ * asm_solve_noalloc - asm_solve for callers that cannot allocate memory:
+ * code around HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The same restarted GMRES with the same arithmetic and results
+ * as asm_solve, but every Krylov work array (basis, work vectors, partial
+ * sums, published Hessenberg columns) lives in one fixed device array of the
+ * library, ASM_NOALLOC_SCRATCH_BYTES per device, reserved when the library's
+ * code is loaded on a device and held until the process ends; host-side
+ * state is on the caller's stack.  The call makes no device or pinned-host
+ * allocation (asm_solve allocates the system's workspace on its first call).
+ * Limits: 8 * ((restart+1)*3*nb + 3*3*nb) bytes plus about 360 KiB must fit
+ * the array (at restart 30 about 240,000 unknowns, 80,000 cells); larger
+ * systems return ASM_ERR_INVALID.  The host reads each step's column
+ * synchronously (no step queued ahead), so it is somewhat slower than
+ * asm_solve.  Every call on a device shares that device's array: calls that
+ * overlap on one device (two host threads, or two streams) race and must not
+ * be made.  sys and pc must already exist (their setup allocates).
+ */
+#define ASM_NOALLOC_SCRATCH_BYTES (64 << 20)
+asm_status asm_solve_noalloc(asm_system sys, asm_precond pc, const double *b_dev, double *x_dev,
+                             const asm_solve_opts *opts, hipStream_t stream, asm_solve_info *info);
+
 /* The same solve as asm_solve, with every restart cycle run as one HIP
  * graph: the m Arnoldi steps, the Givens rotations (computed on the device),
  * the triangular solve, the correction x += B^-1 V_k y and the true residual.

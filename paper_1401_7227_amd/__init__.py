@@ -12,5 +12,6 @@ declared in ``include/asm.h``); this package only marshals arguments.
 from ._binding import (  # noqa: F401
     ADDITIVE, COARSE_ADDITIVE, COARSE_NONE, COARSE_TWO_STAGE, ERR_HIP, ERR_INVALID, ERR_NONFINITE,
     ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FIELD_FAR, FIELD_NEAR, FIELD_NEAR_FAR, FP32, FP64,
-    KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, LOCAL_EXACT, LOCAL_ILU0, NOT_CONVERGED, OK, PHASES, RESTRICTED,
+    KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, LOCAL_EXACT, LOCAL_ILU0, NOALLOC_SCRATCH_BYTES, NOT_CONVERGED, OK,
+    PHASES, RESTRICTED,
     AsmError, Info, Precond, Server, System, load, precond_opts, solve, solve_batch)

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libasm_mi355x.so")
 
 OK, NOT_CONVERGED = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ASM_NOALLOC_SCRATCH_BYTES
 ERR_INVALID, ERR_OOM, ERR_SINGULAR_PIVOT, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4, -5
 KIND_NONE, KIND_CLASSICAL, KIND_TWO_LEVEL = 0, 1, 2
 ADDITIVE, RESTRICTED = 0, 1
@@ -30,7 +31,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_OOM",
 
 EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_precond",
             "asm_refactor", "asm_precond_apply", "asm_precond_get_stats",
-            "asm_precond_export_sub", "asm_solve", "asm_solve_graph", "asm_solve_batch", "asm_destroy_precond",
+            "asm_precond_export_sub", "asm_solve", "asm_solve_graph", "asm_solve_noalloc", "asm_solve_batch",
+            "asm_destroy_precond",
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
             "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
             "asm_server_get_state", "asm_server_destroy"]
@@ -351,10 +353,14 @@ class Info:
 
 
 def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6,
-          max_iters=10000, fixed_iters=0, out: torch.Tensor | None = None, graph=False):
+          max_iters=10000, fixed_iters=0, out: torch.Tensor | None = None, graph=False, noalloc=False):
     """Solves A x = b; returns (x, Info).  b, x0: device tensors or arrays.
     graph: every restart cycle runs as one captured HIP graph with the
-    convergence test on the device (asm_solve_graph)."""
+    convergence test on the device (asm_solve_graph).  noalloc: the solve
+    whose work arrays live in the library's fixed device array
+    (asm_solve_noalloc; pass `out` to allocate nothing here either)."""
+    if graph and noalloc:
+        raise ValueError("graph and noalloc are separate entry points")
     n = 3 * system.N
     b = _vec(b, n, "b")
     if out is not None:
@@ -365,7 +371,7 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
         x = torch.zeros_like(b) if x0 is None else _vec(x0, n, "x0").clone()
     o = SolveOpts(restart, rtol, max_iters, fixed_iters)
     info = SolveInfo()
-    fn = load().asm_solve_graph if graph else load().asm_solve
+    fn = load().asm_solve_graph if graph else (load().asm_solve_noalloc if noalloc else load().asm_solve)
     st = _check(fn(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o), _stream(), C.byref(info)))
     return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)
 

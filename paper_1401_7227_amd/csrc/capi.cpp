@@ -34,7 +34,9 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   ASM_HIP(W.mem.alloc(&W.gcs, m + 1));
   ASM_HIP(W.mem.alloc(&W.gsn, m + 1));
   ASM_HIP(W.mem.alloc(&W.gg, m + 1));
-  ASM_HIP(hipHostMalloc((void **)&W.pinned, sizeof(double) * (kPubBase + (size_t)kMaxRestart * kPubStride),
+  // scalars, published columns, then a cycle's solution coefficients
+  ASM_HIP(hipHostMalloc((void **)&W.pinned,
+                        sizeof(double) * (kPubBase + (size_t)kMaxRestart * kPubStride + kMaxRestart + 2),
                         hipHostMallocCoherent));
   ASM_HIP(hipHostGetDevicePointer((void **)&W.pinned_dev, W.pinned, 0));
   for (hipEvent_t &e : W.step_done)
@@ -682,165 +684,293 @@ asm_status asm_precond_export_sub(asm_precond pc, int32_t s, int32_t *n_out, int
   ASM_CATCH_ALL
 }
 
+}  // extern "C"
+
+namespace asmx {
+namespace {
+
+// The Krylov work arrays one solve uses: the system's own workspace
+// (asm_solve), or parts of the library's fixed device array
+// (asm_solve_noalloc).  Each step's last kernel writes the step's Hessenberg
+// column to pub_dev + j*kPubStride.  With events (the workspace's pinned
+// host memory, which pub_dev maps) the host reads it there one step late;
+// without, it copies the column to the host buffer pub_host and waits for it.
+struct KrylovView {
+  double *U = nullptr;
+  int64_t ldu = 0;
+  double *w = nullptr, *z = nullptr, *t = nullptr, *partial = nullptr, *dvec = nullptr, *scale = nullptr,
+         *coef = nullptr, *misc = nullptr;
+  int *flag = nullptr;
+  double *pub_dev = nullptr;   // kMaxRestart columns of kPubStride doubles
+  double *pub_host = nullptr;  // host view of them
+  double *host = nullptr;      // host staging of single scalars (pinned or not)
+  double *coef_host = nullptr; // host staging of a cycle's solution coefficients
+  const hipEvent_t *step_done = nullptr;  // per-step events: read columns one step late
+};
+
+// Doubles the no-allocation solve takes from the fixed array for restart m
+// and n unknowns (each part 256-byte aligned).
+int64_t noalloc_doubles(int m, int64_t n, int64_t *ldu) {
+  auto up = [](int64_t v) { return (v + 31) & ~int64_t(31); };
+  *ldu = (n + 1) & ~int64_t(1);
+  return up((int64_t)(m + 1) * *ldu) + 3 * up(n) + up((int64_t)kReduceBlocks * (kMaxRestart + 2) + 8 * kReduceBlocks) +
+         5 * up(kMaxRestart + 2) + up((int64_t)kMaxRestart * kPubStride) + 32;
+}
+
+asm_status check_nonfinite(const KrylovView &W, const double *v, int64_t n, hipStream_t s, bool *out) {
+  ASM_HIP(launch_fill(1, 0, W.flag, s));
+  ASM_HIP(launch_check_finite(n, v, W.flag, s));
+  int h = 0;
+  ASM_HIP(hipMemcpyAsync(&h, W.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  ASM_HIP(hipStreamSynchronize(s));
+  *out = (h != 0);
+  return ASM_OK;
+}
+
+// Restarted right-preconditioned GMRES (see asm_solve in asm.h) on the work
+// arrays of W.
+asm_status gmres_run(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
+                     hipStream_t s, asm_solve_info *info, const KrylovView &W, Profiler &pf) {
+  const int m = o->restart;
+  const int64_t n = 3 * (int64_t)S->pat.N;
+  asm_status st;
+  bool bad = false;
+  if ((st = check_nonfinite(W, b, n, s, &bad)) != ASM_OK) return st;
+  if (!bad && (st = check_nonfinite(W, x, n, s, &bad)) != ASM_OK) return st;
+  if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
+  const int ld = m + 1;
+  double *hp = W.host;
+  const bool ahead = W.step_done != nullptr;
+  int nb = 0;
+  // ||b||
+  ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
+  ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
+  ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  ASM_HIP(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(hp[0]);
+  if (bnorm == 0.0 && o->fixed_iters == 0) {
+    ASM_HIP(launch_fill(n, 0.0, x, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    return ASM_OK;
+  }
+  const double scl = bnorm > 0.0 ? bnorm : 1.0;
+  const double tol = o->rtol * bnorm;
+  auto true_residual = [&](double *beta) -> asm_status {
+    int nbr = 0;
+    const size_t t0 = pf.mark(ASM_PHASE_RESIDUAL, s);
+    ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
+    pf.span(ASM_PHASE_RESIDUAL, t0, s);
+    const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
+    pf.span(ASM_PHASE_OTHER, t1, s);
+    ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    pf.flush();
+    *beta = hp[0];
+    return ASM_OK;
+  };
+  double beta = 0.0;
+  if ((st = true_residual(&beta)) != ASM_OK) return st;
+  info->rel_res_true = info->rel_res_est = beta / scl;
+  if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
+  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+  // host-side Hessenberg matrix, rotations and coefficients (no heap)
+  double H[(kMaxRestart + 1) * kMaxRestart], cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart],
+      sc[kMaxRestart + 1], coef[kMaxRestart + 1];
+  auto Hh = [&](int i, int j) -> double & { return H[(size_t)j * ld + i]; };
+  asm_status result = ASM_NOT_CONVERGED;
+  // One Arnoldi step on the stream: z = B^-1 v_j, w = A z, CGS projections,
+  // the new basis vector and its norm; the step's Hessenberg column is then
+  // published and (with events) an event marks the step's end.
+  auto enqueue_step = [&](int j) -> asm_status {
+    const double *Uj = W.U + (size_t)j * W.ldu;
+    asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
+    if (e2 != ASM_OK) return e2;
+    size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
+    ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
+    pf.span(ASM_PHASE_SPMV, t0, s);
+    int nbd = 0;
+    t0 = pf.mark(ASM_PHASE_DOTS, s);
+    ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
+    pf.span(ASM_PHASE_DOTS, t0, s);
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    int nbu = 0;
+    t0 = pf.mark(ASM_PHASE_UPDATE, s);
+    ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
+                          &nbu, s));
+    pf.span(ASM_PHASE_UPDATE, t0, s);
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
+    // the Hessenberg column goes to the published area only (the host keeps H)
+    ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.pub_dev + (size_t)j * kPubStride,
+                                 W.scale + j + 1, W.pub_dev + (size_t)j * kPubStride, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    if (ahead) ASM_HIP(hipEventRecord(W.step_done[j], s));
+    return ASM_OK;
+  };
+  while (true) {
+    if (beta == 0.0) { result = ASM_OK; break; }
+    info->cycles++;
+    std::fill(g, g + m + 1, 0.0);
+    g[0] = beta;
+    sc[0] = 1.0 / beta;
+    // steps of this cycle: at most m, and never past the iteration limit
+    const int kmax = std::min(m, limit - info->iters);
+    int k = 0, queued = 0;
+    for (int j = 0; j < kmax; ++j) {
+      // with events, keep the next step queued while step j's column is read
+      while (queued < kmax && queued <= j + (ahead ? 1 : 0)) {
+        if ((st = enqueue_step(queued)) != ASM_OK) return st;
+        ++queued;
+      }
+      const double *col = W.pub_host + (size_t)j * kPubStride;
+      if (ahead) {
+        ASM_HIP(hipEventSynchronize(W.step_done[j]));
+      } else {
+        ASM_HIP(hipMemcpyAsync(W.pub_host + (size_t)j * kPubStride, W.pub_dev + (size_t)j * kPubStride,
+                               sizeof(double) * (j + 3), hipMemcpyDeviceToHost, s));
+        ASM_HIP(hipStreamSynchronize(s));
+      }
+      for (int i = 0; i <= j + 1; ++i) Hh(i, j) = col[i];
+      const double w0 = col[j + 2];
+      const double hn = Hh(j + 1, j);
+      sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+      // previous rotations, then a new one annihilating h_{j+1,j}
+      for (int i = 0; i < j; ++i) {
+        const double a = Hh(i, j), c = Hh(i + 1, j);
+        Hh(i, j) = cs[i] * a + sn[i] * c;
+        Hh(i + 1, j) = -sn[i] * a + cs[i] * c;
+      }
+      const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
+      if (rho == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = Hh(j, j) / rho;
+        sn[j] = Hh(j + 1, j) / rho;
+      }
+      Hh(j, j) = rho;
+      Hh(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      info->rel_res_est = std::fabs(g[j + 1]) / scl;
+      if (hn <= 1e-14 * w0) break;
+      if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
+    }
+    info->iters += k;
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int j = i + 1; j < k; ++j) acc -= Hh(i, j) * y[j];
+      y[i] = acc / Hh(i, i);
+    }
+    for (int i = 0; i < k; ++i) coef[i] = y[i] * sc[i];
+    // coefficients to the device through their staging buffer (pinned: read
+    // by the copy in stream order, not rewritten before the next cycle's
+    // end; pageable: the stream is synchronised at once)
+    std::copy(coef, coef + k, W.coef_host);
+    ASM_HIP(hipMemcpyAsync(W.coef, W.coef_host, k * sizeof(double), hipMemcpyHostToDevice, s));
+    if (!ahead) ASM_HIP(hipStreamSynchronize(s));
+    size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_lincomb(n, k, W.U, W.ldu, W.coef, W.t, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    if ((st = apply_precond(pc, W.t, nullptr, W.z, s, &pf)) != ASM_OK) return st;
+    t0 = pf.mark(ASM_PHASE_OTHER, s);
+    ASM_HIP(launch_axpy(n, W.z, x, s));
+    pf.span(ASM_PHASE_OTHER, t0, s);
+    if ((st = true_residual(&beta)) != ASM_OK) return st;
+    info->rel_res_true = beta / scl;
+    if (o->fixed_iters > 0) {
+      if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
+    } else if (beta <= tol) {
+      result = ASM_OK;
+      break;
+    }
+    if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
+  }
+  ASM_HIP(hipStreamSynchronize(s));
+  return result;
+}
+
+asm_status check_solve_args(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
+                            asm_solve_info *info) {
+  if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
+  if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
+  std::memset(info, 0, sizeof *info);
+  const int m = o->restart;
+  if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
+    return fail(ASM_ERR_INVALID, "bad solver option");
+  return ASM_OK;
+}
+
+}  // namespace
+}  // namespace asmx
+
+extern "C" {
+
 asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                      hipStream_t s, asm_solve_info *info) {
   try {
     g_err.clear();
-    if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
-    if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");
-    std::memset(info, 0, sizeof *info);
-    const int m = o->restart;
-    if (m < 1 || m > kMaxRestart || !(o->rtol >= 0.0) || o->max_iters < 1 || o->fixed_iters < 0)
-      return fail(ASM_ERR_INVALID, "bad solver option");
-    const int64_t n = 3 * (int64_t)S->pat.N;
-    asm_status st = ensure_workspace(S, m, s);
+    asm_status st = check_solve_args(S, pc, b, x, o, info);
     if (st != ASM_OK) return st;
+    if ((st = ensure_workspace(S, o->restart, s)) != ASM_OK) return st;
     Workspace &W = S->ws;
-    Profiler &pf = S->prof;
-    bool bad = false;
-    if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
-    if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
-    if (bad) return fail(ASM_ERR_NONFINITE, "non-finite b or x0");
-    const int ld = m + 1;
-    double *hp = W.pinned;
-    int nb = 0;
-    // ||b||
-    ASM_HIP(launch_norm2(n, b, W.partial, &nb, s));
-    ASM_HIP(launch_reduce_cols(nb, 1, W.partial, W.misc + 2, s));
-    ASM_HIP(hipMemcpyAsync(hp, W.misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(hp[0]);
-    if (bnorm == 0.0 && o->fixed_iters == 0) {
-      ASM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
-      ASM_HIP(hipStreamSynchronize(s));
-      return ASM_OK;
-    }
-    const double scl = bnorm > 0.0 ? bnorm : 1.0;
-    const double tol = o->rtol * bnorm;
-    auto true_residual = [&](double *beta) -> asm_status {
-      int nbr = 0;
-      const size_t t0 = pf.mark(ASM_PHASE_RESIDUAL, s);
-      ASM_HIP(launch_residual(S->sell, x, b, W.U, W.partial, &nbr, s));
-      pf.span(ASM_PHASE_RESIDUAL, t0, s);
-      const size_t t1 = pf.mark(ASM_PHASE_OTHER, s);
-      ASM_HIP(launch_norm_finalize(nbr, W.partial, 0, nullptr, nullptr, W.misc + 1, W.scale, nullptr, s));
-      pf.span(ASM_PHASE_OTHER, t1, s);
-      ASM_HIP(hipMemcpyAsync(hp, W.misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-      ASM_HIP(hipStreamSynchronize(s));
-      pf.flush();
-      *beta = hp[0];
-      return ASM_OK;
+    KrylovView v;
+    v.U = W.U; v.ldu = W.ldu; v.w = W.w; v.z = W.z; v.t = W.t; v.partial = W.partial; v.dvec = W.dvec;
+    v.scale = W.scale; v.coef = W.coef; v.misc = W.misc; v.flag = W.flag;
+    v.pub_dev = W.pinned_dev + kPubBase;
+    v.pub_host = W.pinned + kPubBase;
+    v.host = W.pinned;
+    v.coef_host = W.pinned + kPubBase + (size_t)kMaxRestart * kPubStride;
+    v.step_done = W.step_done;
+    return gmres_run(S, pc, b, x, o, s, info, v, S->prof);
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_solve_noalloc(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
+                             hipStream_t s, asm_solve_info *info) {
+  try {
+    g_err.clear();
+    asm_status st = check_solve_args(S, pc, b, x, o, info);
+    if (st != ASM_OK) return st;
+    int64_t ldu = 0;
+    const int64_t n = 3 * (int64_t)S->pat.N;
+    if (noalloc_doubles(o->restart, n, &ldu) * (int64_t)sizeof(double) > (int64_t)kNoAllocScratchBytes)
+      return fail(ASM_ERR_INVALID, "system too large for the no-allocation solve (ASM_NOALLOC_SCRATCH_BYTES)");
+    void *base = nullptr;
+    ASM_HIP(noalloc_scratch(&base));
+    // carve the fixed array (every part 256-byte aligned)
+    double *p = static_cast<double *>(base);
+    auto take = [&](int64_t count) {
+      double *q = p;
+      p += (count + 31) & ~int64_t(31);
+      return q;
     };
-    double beta = 0.0;
-    if ((st = true_residual(&beta)) != ASM_OK) return st;
-    info->rel_res_true = info->rel_res_est = beta / scl;
-    if (o->fixed_iters == 0 && beta <= tol) return ASM_OK;
-    const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
-    std::vector<double> H((size_t)ld * m), cs(m), sn(m), g(m + 1), y(m), sc(m + 1), coef(m + 1);
-    auto Hh = [&](int i, int j) -> double & { return H[(size_t)j * ld + i]; };
-    asm_status result = ASM_NOT_CONVERGED;
-    // One Arnoldi step on the stream: z = B^-1 v_j, w = A z, CGS projections,
-    // the new basis vector and its norm; the step's Hessenberg column is then
-    // published to pinned memory and an event marks the step's end.
-    auto enqueue_step = [&](int j) -> asm_status {
-      const double *Uj = W.U + (size_t)j * W.ldu;
-      asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
-      if (e2 != ASM_OK) return e2;
-      size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
-      ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
-      pf.span(ASM_PHASE_SPMV, t0, s);
-      int nbd = 0;
-      t0 = pf.mark(ASM_PHASE_DOTS, s);
-      ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
-      pf.span(ASM_PHASE_DOTS, t0, s);
-      t0 = pf.mark(ASM_PHASE_OTHER, s);
-      ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      int nbu = 0;
-      t0 = pf.mark(ASM_PHASE_UPDATE, s);
-      ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
-                            &nbu, s));
-      pf.span(ASM_PHASE_UPDATE, t0, s);
-      t0 = pf.mark(ASM_PHASE_OTHER, s);
-      ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
-                                   W.pinned_dev + kPubBase + (size_t)j * kPubStride, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      ASM_HIP(hipEventRecord(W.step_done[j], s));
-      return ASM_OK;
-    };
-    while (true) {
-      if (beta == 0.0) { result = ASM_OK; break; }
-      info->cycles++;
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
-      sc[0] = 1.0 / beta;
-      // steps of this cycle: at most m, and never past the iteration limit
-      const int kmax = std::min(m, limit - info->iters);
-      int k = 0, queued = 0;
-      if ((st = enqueue_step(0)) != ASM_OK) return st;
-      queued = 1;
-      for (int j = 0; j < kmax; ++j) {
-        // keep the next step queued while step j's column is read back
-        if (queued < kmax) {
-          if ((st = enqueue_step(queued)) != ASM_OK) return st;
-          ++queued;
-        }
-        ASM_HIP(hipEventSynchronize(W.step_done[j]));
-        const double *col = hp + kPubBase + (size_t)j * kPubStride;
-        for (int i = 0; i <= j + 1; ++i) Hh(i, j) = col[i];
-        const double w0 = col[j + 2];
-        const double hn = Hh(j + 1, j);
-        sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-        // previous rotations, then a new one annihilating h_{j+1,j}
-        for (int i = 0; i < j; ++i) {
-          const double a = Hh(i, j), c = Hh(i + 1, j);
-          Hh(i, j) = cs[i] * a + sn[i] * c;
-          Hh(i + 1, j) = -sn[i] * a + cs[i] * c;
-        }
-        const double rho = std::hypot(Hh(j, j), Hh(j + 1, j));
-        if (rho == 0.0) {
-          cs[j] = 1.0;
-          sn[j] = 0.0;
-        } else {
-          cs[j] = Hh(j, j) / rho;
-          sn[j] = Hh(j + 1, j) / rho;
-        }
-        Hh(j, j) = rho;
-        Hh(j + 1, j) = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        k = j + 1;
-        info->rel_res_est = std::fabs(g[j + 1]) / scl;
-        if (hn <= 1e-14 * w0) break;
-        if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
-      }
-      info->iters += k;
-      for (int i = k - 1; i >= 0; --i) {
-        double acc = g[i];
-        for (int j = i + 1; j < k; ++j) acc -= Hh(i, j) * y[j];
-        y[i] = acc / Hh(i, i);
-      }
-      for (int i = 0; i < k; ++i) coef[i] = y[i] * sc[i];
-      ASM_HIP(hipMemcpyAsync(W.coef, coef.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-      size_t t0 = pf.mark(ASM_PHASE_OTHER, s);
-      ASM_HIP(launch_lincomb(n, k, W.U, W.ldu, W.coef, W.t, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      if ((st = apply_precond(pc, W.t, nullptr, W.z, s, &pf)) != ASM_OK) return st;
-      t0 = pf.mark(ASM_PHASE_OTHER, s);
-      ASM_HIP(launch_axpy(n, W.z, x, s));
-      pf.span(ASM_PHASE_OTHER, t0, s);
-      if ((st = true_residual(&beta)) != ASM_OK) return st;
-      info->rel_res_true = beta / scl;
-      if (o->fixed_iters > 0) {
-        if (info->iters >= o->fixed_iters) { result = ASM_OK; break; }
-      } else if (beta <= tol) {
-        result = ASM_OK;
-        break;
-      }
-      if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
-    }
-    ASM_HIP(hipStreamSynchronize(s));
-    return result;
+    KrylovView v;
+    v.ldu = ldu;
+    v.U = take((int64_t)(o->restart + 1) * ldu);
+    v.w = take(n);
+    v.z = take(n);
+    v.t = take(n);
+    v.partial = take((int64_t)kReduceBlocks * (kMaxRestart + 2) + 8 * kReduceBlocks);
+    v.dvec = take(kMaxRestart + 2);
+    v.scale = take(kMaxRestart + 2);
+    v.coef = take(kMaxRestart + 2);
+    v.misc = take(kMaxRestart + 2);
+    v.flag = reinterpret_cast<int *>(take(kMaxRestart + 2));
+    v.pub_dev = take((int64_t)kMaxRestart * kPubStride);
+    // host side: this call's own stack (pageable memory, copied synchronously)
+    double pub_host[kMaxRestart * kPubStride];
+    double host[kMaxRestart + 2], coef_host[kMaxRestart + 2];
+    v.pub_host = pub_host;
+    v.host = host;
+    v.coef_host = coef_host;
+    v.step_done = nullptr;
+    Profiler none;
+    return gmres_run(S, pc, b, x, o, s, info, v, none);
   }
   ASM_CATCH_ALL
 }

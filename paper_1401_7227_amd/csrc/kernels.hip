@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 #include <utility>
 
 #include "kernels.hpp"
@@ -1177,6 +1178,19 @@ __global__ __launch_bounds__(256) void scale_copy_kernel(int64_t n, const double
   scale_copy_body(blockIdx.x, gridDim.x, n, r, scale, z);
 }
 
+// p[0 .. n) = v (also a flag cleared without a memset node).
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(int64_t n, T v, T *__restrict__ p) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p[e] = v;
+}
+
+// Device memory of the no-allocation solve: one fixed array per device,
+// reserved when the code object is loaded on that device and kept until the
+// process ends.  Host code never passes the symbol itself to a kernel (on
+// the host it is only a stand-in); it passes the device address looked up
+// once per device by noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 // ---------------------------------------------------------------- batches
@@ -1688,6 +1702,40 @@ hipError_t launch_batch_axpy(const BatchSys *tab, const BatchSeg &seg, hipStream
   if (seg.total == 0) return hipSuccess;
   batch_axpy_kernel<<<seg.total, 256, 0, s>>>(tab, seg);
   return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double *p, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int grid = std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  fill_kernel<double><<<grid, 256, 0, s>>>(n, v, p);
+  return hipGetLastError();
+}
+hipError_t launch_fill(int64_t n, int v, int *p, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int grid = std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  fill_kernel<int><<<grid, 256, 0, s>>>(n, v, p);
+  return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(void **out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  static std::mutex mu;
+  static void *ptr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    // with this device current: its own copy of the array
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, double *z, hipStream_t s,

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "plan.hpp"
+#include "asm.h"
 
 namespace asmx {
 
@@ -90,6 +91,15 @@ hipError_t launch_lincomb(int64_t n, int nv, const double *U, int64_t ldu, const
 hipError_t launch_axpy(int64_t n, const double *z, double *x, hipStream_t s);
 
 hipError_t launch_check_finite(int64_t n, const double *v, int *flag, hipStream_t s);
+// p[0 .. n) = v.
+hipError_t launch_fill(int64_t n, double v, double *p, hipStream_t s);
+hipError_t launch_fill(int64_t n, int v, int *p, hipStream_t s);
+
+// The fixed device array of the no-allocation solve (asm_solve_noalloc):
+// its address on the current device, looked up on the first call per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)ASM_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(void **out);
 
 // ---------------------------------------------------------------- device-side restart cycles
 // State of a restart cycle that runs on the device (a captured graph): done
