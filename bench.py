@@ -118,22 +118,56 @@ def timed_solves(P, torch, G, B, b, steps, warmup, profile, graph=False):
     return (t1 - t0) / steps * 1e3, info, prof, x
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(s, gpu_iters, budget_steps):
     """The CPU oracle (single thread, FP64) on a bounded sample of the same
     workload: the oracle's setup of the same preconditioner, then a fixed
-    number of GMRES steps, scaled to one solve of the GPU's iteration count."""
+    number of GMRES steps, scaled to one solve of the GPU's iteration count.
+    The calling thread (the one the oracle runs on) is pinned to one core for
+    the leg and released afterwards."""
     import oracle as O
-    A = O.Matrix.from_system(s)
-    t0 = time.perf_counter()
-    Bo = O.Precond(A, kind=O.KIND_TWO_LEVEL, combine=O.RESTRICTED, near=NEAR, far=FAR, **SPLIT)
-    t1 = time.perf_counter()
-    res = O.gmres(A, Bo, s.b, restart=RESTART, fixed_iters=budget_steps)
-    t2 = time.perf_counter()
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        A = O.Matrix.from_system(s)
+        t0 = time.perf_counter()
+        Bo = O.Precond(A, kind=O.KIND_TWO_LEVEL, combine=O.RESTRICTED, near=NEAR, far=FAR, **SPLIT)
+        t1 = time.perf_counter()
+        O.gmres(A, Bo, s.b, restart=RESTART, fixed_iters=budget_steps)
+        t2 = time.perf_counter()
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     per_step = (t2 - t1) / budget_steps
     return {"value": round(per_step * gpu_iters * 1e3, 1), "unit": "ms/solve", "cores": 1, "kind": "oracle",
             "sample": f"oracle setup ({t1 - t0:.1f} s, not in the metric) plus {budget_steps} GMRES steps "
                       f"({t2 - t1:.1f} s) of the same 1M-cell two-level solve, scaled to {gpu_iters} steps",
-            "setup_s": round(t1 - t0, 2), "s_per_step": round(per_step, 3)}
+            "setup_s": round(t1 - t0, 2), "s_per_step": round(per_step, 3),
+            "cpu_model": cpu_model(), "pinned_core": core, "host_cores": os.cpu_count(),
+            "host_cores_allowed": len(allowed),
+            "note": "single-threaded plain C (gcc -O2), pinned to one core with sched_setaffinity"}
+
+
+def oracle_reference():
+    """The FP64 oracle's two-level solution of the benchmark system, stored by
+    tests/golden/make_config2_golden.py (which calls only the oracle): the
+    iteration count and the solution on a fixed sample of unknowns."""
+    path = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d if "two_level_ras" in d else None
 
 
 def batch_systems(gen, np, count=256):
@@ -361,7 +395,7 @@ def run_fifo(P, torch, np, trace, label):
 
 
 def bench_serve(P, gen, torch, np, args):
-    trace = serve_trace(np, count=args.serve_requests)
+    trace = serve_trace(np, count=args.serve_requests, rate=args.serve_rate)
     budget = int(args.serve_budget_gib * (1 << 30))
     prefix = trace[:args.serve_compare]
     # warm-up: one small request through both paths (library load, kernels)
@@ -376,21 +410,53 @@ def bench_serve(P, gen, torch, np, args):
     cells = np.array([t["grid"][0] * t["grid"][1] * t["grid"][2] for t in trace])
     offered = float(np.sum(cells * np.array([t["nsolves"] for t in trace]))) / trace[-1]["t"]
     return {
-        "metric": "served latency p50/p99 ms (Poisson arrivals 200/s, 1e4-1e6 cells, 1-3 solves per request)",
+        "metric": f"served latency p50/p99 ms (Poisson arrivals {args.serve_rate:g}/s, 1e4-1e6 cells, 1-3 solves "
+                  "per request)",
         "value": full["p99_ms"], "unit": "ms (p99)", "higher_is_better": False, "n_gpus": 1,
         "dtype": "f64 (FP32 factors)", "data": "synthetic (seeded generator drawn on the device at arrival)",
-        "config": {"workload": f"{len(trace)} requests, Poisson arrivals at 200/s (trace seed 5), cells "
+        "config": {"workload": f"{len(trace)} requests, Poisson arrivals at {args.serve_rate:g}/s (trace seed 5), cells "
                                "log-uniform in [1e4, 1e6], grid 2nz x 2nz x nz, 1-3 solves each with new values "
                                "on the same pattern; two-level RAS, overlap 1, near 4^3, far 16^3, 16-64 "
                                "subdomains, FP32 factors, GMRES(30) to rtol 1e-6",
                    "hbm_budget_gib": args.serve_budget_gib, "max_active": args.serve_max_active},
         "p50_ms": full["p50_ms"], "p99_ms": full["p99_ms"],
         "offered_cell_solves_per_s": round(offered, 0),
+        "offered_over_served": round(offered / full["cell_solves_per_s"], 3),
+        "arrival_span_s": round(trace[-1]["t"], 2),
         "server_full_trace": full,
         "prefix_comparison": {"requests": len(prefix), "server_fp32": srv_prefix, "fifo_fp64": fifo_prefix,
                               "p50_speedup": round(fifo_prefix["p50_ms"] / srv_prefix["p50_ms"], 2),
                               "p99_speedup": round(fifo_prefix["p99_ms"] / srv_prefix["p99_ms"], 2)},
     }
+
+
+def bench_serve_leg(P, torch, np, args):
+    """The served form inside the default benchmark: a prefix of the serving
+    trace (same seed and mix: 1e4-1e6 cells, 1-3 solves per request) at an
+    arrival rate one GPU sustains, through the request server with FP32
+    factors, against the same requests solved one at a time with FP64
+    factors and the plain calls."""
+    trace = serve_trace(np, count=args.serve_leg_requests, rate=args.serve_leg_rate)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    warm = [{"t": 0.0, "grid": (28, 28, 14), "nsolves": 1, "seed": 1}]
+    run_server(P, torch, np, warm, P.FP32, budget, args.serve_max_active, "warm-up")
+    run_fifo(P, torch, np, warm, "warm-up")
+    srv = run_server(P, torch, np, trace, P.FP32, budget, args.serve_max_active, "leg")
+    torch.cuda.empty_cache()
+    fifo = run_fifo(P, torch, np, trace, "leg")
+    torch.cuda.empty_cache()
+    cells = np.array([t["grid"][0] * t["grid"][1] * t["grid"][2] * t["nsolves"] for t in trace], dtype=float)
+    span = trace[-1]["t"]
+    return {"workload": f"first {len(trace)} requests of the serving trace (seed 5) at {args.serve_leg_rate}/s "
+                        "Poisson arrivals",
+            "offered_cell_solves_per_s": round(float(cells.sum()) / span, 0),
+            "server_fp32": {k: srv[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s",
+                                                "requests_per_s", "cell_solves_per_s", "mean_running",
+                                                "statuses")},
+            "fifo_fp64": {k: fifo[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s", "requests_per_s",
+                                               "statuses")},
+            "p50_speedup": round(fifo["p50_ms"] / srv["p50_ms"], 2),
+            "p99_speedup": round(fifo["p99_ms"] / srv["p99_ms"], 2)}
 
 
 def bench_comparators(P, gen, torch, np, args):
@@ -477,6 +543,11 @@ def main():
                          "serve: a Poisson request trace against the request server, and a prefix of it "
                          "against one-at-a-time FP64 solves; comparators: the iteration-count studies of "
                          "the paper's Section 5 on synthetic systems")
+    ap.add_argument("--no-serve", action="store_true", help="no served leg in the default benchmark")
+    ap.add_argument("--serve-leg-requests", type=int, default=40)
+    ap.add_argument("--serve-leg-rate", type=float, default=6.0,
+                    help="arrivals per second of the served leg (one GPU sustains the trace's mix at this rate)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of --workload serve")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-compare", type=int, default=100, help="trace prefix for the FIFO comparison")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -599,17 +670,44 @@ def main():
             "rel_diff_vs_host_loop_solution": float(np.linalg.norm(xg.cpu().numpy() - x64) / np.linalg.norm(x64))}
         B32 = P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, near=NEAR, far=FAR, precision=P.FP32,
                         **SPLIT)
-        ms32, info32, prof32, x32 = timed_solves(P, torch, G, B32, b, args.steps, args.warmup, profile=None)
-        variants["two_level_fp32_factors"] = {
+        st32 = B32.stats()
+        ms32, info32, prof32, x32 = timed_solves(P, torch, G, B32, b, args.steps, args.warmup,
+                                                 profile=["ilu_apply"])
+        a32 = prof32["ilu_apply"][1] / max(prof32["ilu_apply"][0], 1)
+        alg32 = ilu_apply_bytes(st32, N, fp32=True)
+        v32 = {
             "ms_per_solve": round(ms32, 3), "iters": info32.iters, "rel_res_true": info32.rel_res_true,
             "speedup_vs_fp64": round(ms / ms32, 3),
-            "rel_err_vs_fp64_solution": float(np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64))}
+            "rel_err_vs_fp64_solution": float(np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64)),
+            "roofline": {"bound": "hbm", "kernel": "ilu_apply (FP32 fine-row factors)",
+                         "achieved": round(alg32 / (a32 * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg32 / (a32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                         "alg_bytes_per_launch": int(alg32), "avg_launch_ms": round(a32, 4)}}
+        ref = oracle_reference()
+        if ref is not None:
+            # against the FP64 oracle at the oracle's own iteration count
+            g = ref["two_level_ras"]
+            xf, _ = P.solve(G, B32, b, restart=RESTART, fixed_iters=g["iters"])
+            idx = np.array(ref["sample"])
+            xs, xr = xf.cpu().numpy()[idx], np.array(g["x_sample"])
+            v32["rel_err_vs_oracle"] = float(np.linalg.norm(xs - xr) / np.linalg.norm(xr))
+            v32["oracle_iters"] = g["iters"]
+            v32["rel_err_vs_oracle_note"] = (f"at the oracle's {g['iters']} iterations, on its stored sample of "
+                                             f"{len(idx)} unknowns (tests/golden/config2_oracle.json)")
+            del xf
+        variants["two_level_fp32_factors"] = v32
         del B32
         Bc = P.Precond(G, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, **SPLIT)
         msc, infoc, _, _ = timed_solves(P, torch, G, Bc, b, max(1, args.steps // 2), 1, profile=None)
         variants["classical_ras_fp64"] = {"ms_per_solve": round(msc, 3), "iters": infoc.iters,
                                           "rel_res_true": infoc.rel_res_true}
         del Bc
+        # classical additive Schwarz (eq. (3.3): overlapping contributions summed)
+        Ba = P.Precond(G, kind=P.KIND_CLASSICAL, combine=P.ADDITIVE, **SPLIT)
+        msa, infoa, _, _ = timed_solves(P, torch, G, Ba, b, max(1, args.steps // 4), 1, profile=None)
+        variants["classical_additive_fp64"] = {"ms_per_solve": round(msa, 3), "iters": infoa.iters,
+                                               "rel_res_true": infoa.rel_res_true}
+        del Ba
         # the two-stage global coarse-grid comparator (eq. (3.8)), coarse boxes 16^3
         Bt = P.Precond(G, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, coarse=P.COARSE_TWO_STAGE,
                        cbox=(16, 16, 16), **SPLIT)
@@ -618,6 +716,10 @@ def main():
                                                              "rel_res_true": infot.rel_res_true}
         del Bt
         out["variants"] = variants
+    if not args.no_serve:
+        del G, B
+        torch.cuda.empty_cache()
+        out["served"] = bench_serve_leg(P, torch, np, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, info.iters, args.cpu_steps)
     print(json.dumps(out))
