@@ -30,6 +30,7 @@ NEAR, FAR = (4, 4, 4), (16, 16, 16)
 HBM_PEAK_GBS = 8000.0
 RESTART = 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ilu_apply_two_level_1M_traffic.json")
+TRAFFIC_FILE_FP32 = os.path.join(ROOT, "profiles", "ilu_apply_two_level_fp32_1M_traffic.json")
 # Sources that decide what the sweep kernel reads and writes: the kernel
 # itself and the host code that lays out its records.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_7227_amd", "csrc", f)
@@ -45,13 +46,13 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per sweep launch from the committed counter runs (FETCH_SIZE
     and WRITE_SIZE per dispatch, each scaled by what the same counter reads
     for a copy of known size), or None if the kernel source changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_sha():
         return None
@@ -552,6 +553,8 @@ def main():
     ap.add_argument("--serve-compare", type=int, default=100, help="trace prefix for the FIFO comparison")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     ap.add_argument("--serve-max-active", type=int, default=256)
+    ap.add_argument("--counter-precision", choices=["fp64", "fp32"], default="fp64",
+                    help="factor precision of --counter-workload apply")
     ap.add_argument("--counter-workload", choices=["apply", "copy"], default=None,
                     help="run only a short workload for hardware-counter collection: five preconditioner "
                          "applications of the benchmark configuration, or a plain 1 GiB device copy")
@@ -599,12 +602,18 @@ def main():
     st = B.stats()
     b = torch.from_numpy(s.b).cuda()
     if args.counter_workload == "apply":
+        fp32 = args.counter_precision == "fp32"
+        if fp32:
+            del B
+            B = P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, near=NEAR, far=FAR, precision=P.FP32,
+                          **SPLIT)
+            st = B.stats()
         z = torch.empty_like(b)
         for _ in range(5):
             B.apply(b, out=z)
         torch.cuda.synchronize()
-        print(json.dumps({"counter_workload": "apply", "launches": 5,
-                          "alg_bytes_per_launch": ilu_apply_bytes(st, N)}))
+        print(json.dumps({"counter_workload": "apply", "precision": args.counter_precision, "launches": 5,
+                          "alg_bytes_per_launch": ilu_apply_bytes(st, N, fp32=fp32)}))
         return
 
     # the sweep kernel (the dominant one) is timed by HIP events inside the
@@ -681,7 +690,8 @@ def main():
             "rel_err_vs_fp64_solution": float(np.linalg.norm(x32.cpu().numpy() - x64) / np.linalg.norm(x64)),
             "roofline": {"bound": "hbm", "kernel": "ilu_apply (FP32 fine-row factors)",
                          "achieved": round(alg32 / (a32 * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(alg32 / (a32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(alg32 / (a32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": (lambda t: None if t is None else int(t))(measured_traffic(TRAFFIC_FILE_FP32)),
                          "alg_bytes_per_launch": int(alg32), "avg_launch_ms": round(a32, 4)}}
         ref = oracle_reference()
         if ref is not None:

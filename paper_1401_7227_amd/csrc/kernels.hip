@@ -63,21 +63,6 @@ __device__ __forceinline__ T quad_sum(T v) {
   return v;
 }
 
-__device__ __forceinline__ double readlane64(double v, int lane) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                          __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-
-// Wave-wide sum without LDS: sums within rows of 16 lanes by DPP, then the
-// four row sums in lane order.  All lanes must be active; the result is
-// uniform.
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v = quad_sum(v);
-  v += dpp64<0x141>(v);
-  v += dpp64<0x140>(v);
-  return ((readlane64(v, 0) + readlane64(v, 16)) + readlane64(v, 32)) + readlane64(v, 48);
-}
-
 // Fixed-order block reduction (deterministic): wave butterflies, then the
 // per-wave sums in wave order.  Result valid in thread 0.
 template <int NT>
@@ -392,22 +377,23 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 // backward sweep x = U^-1 y (D^-1 applied per row).  Every level step is a
 // contiguous record (see RecStep) that the streaming waves copy from HBM,
 // together with the step's row inputs (forward: gathered from r and the
-// coarse rows' lumped inputs; backward: the forward results), into one of
-// two LDS buffers (step s is computed from one while step s+1 is written
-// into the other); the loads run several steps ahead in registers.  The computing waves then touch global
-// memory only to store results: vector values live in an LDS slot pool,
-// and values without a slot are reloaded into LDS by "fill" steps.
+// coarse rows' lumped inputs; backward: the forward results), straight into
+// one of three LDS buffers (gfx950's global_load_lds: the data goes from
+// memory to LDS without passing through registers): step s is computed
+// from buffer s % 3 while the records of steps s+1 and s+2 are on their
+// way.  The computing waves touch global memory only to store results:
+// vector values live in an LDS slot pool, and values without a slot are
+// reloaded into LDS by "fill" steps.
 constexpr int kRecU4 = kRecBytes / 16;
-constexpr int kStageU4 = kRecU4 / 256;
+constexpr int kRecBufs = 3;
+constexpr int kRounds = kRecU4 / 256;  // 1 KiB chunk loads per streaming wave and record
 static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
-static_assert(kMaxStepRows <= 256, "row inputs: one row (three doubles) per streaming thread");
+static_assert(kRecChunk == 64 * 16, "a chunk is one wave's 16-byte load");
+static_assert(kMaxStepRows <= 8 * kInRowsPerLoad, "row inputs: two loads of 32 rows per streaming wave");
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 #ifndef ASM_SWEEP_COMPUTE_WAVES
 #define ASM_SWEEP_COMPUTE_WAVES 8
-#endif
-#ifndef ASM_SWEEP_AHEAD
-#define ASM_SWEEP_AHEAD 3
 #endif
 constexpr int kConsumerThreads = 64 * ASM_SWEEP_COMPUTE_WAVES;  // computing waves of the sweep
 constexpr int kSweepThreads = kConsumerThreads + 256;           // plus four streaming waves
@@ -420,6 +406,8 @@ typedef ASMX_LDS double lds_double;
 typedef const ASMX_LDS double lds_cdouble;
 typedef const ASMX_GLB double glb_cdouble;
 typedef ASMX_GLB double glb_double;
+typedef ASMX_LDS void lds_void;
+typedef const ASMX_GLB void glb_cvoid;
 
 // Global memory by its own address space.  A pointer the kernel reads from
 // memory (the batched launches take their plans from a table) is generic
@@ -445,11 +433,6 @@ __device__ __forceinline__ T ld_glb(const T *p) {
   for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = q[i];
   return v;
 }
-
-struct Stage {
-  u32x4 v[kStageU4];
-  double x[3];
-};
 
 template <typename T>
 __device__ __forceinline__ void block9(const T *v, int S, T (&b)[9]) {
@@ -483,68 +466,76 @@ __device__ __forceinline__ void granule9(const float *sec, int S, int q, float (
 }
 
 struct SweepLds {
-  u32x4 buf[2][kRecU4];        // record of step s (read) and of step s+1 (being written)
-  double vec[3 * kVecSlots];    // vector slot pool (top kFillSlots: reloaded values)
-  double part[4];               // partial sum of a split row
+  u32x4 buf[kRecBufs][kRecU4];     // record of step s (read), of steps s+1 and s+2 (arriving)
+  double vec[3 * kVecSlots];       // vector slot pool (top kFillSlots: reloaded values)
+  double part[4];                  // partial sum of a split row
+  int32_t src[2][kMaxStepRows];    // gathering: input sources of the records of steps s+2 and s+3
+  u32x4 trash[64];                 // destination of the loads that carry nothing
 };
+static_assert(sizeof(SweepLds) <= 160 * 1024, "the sweep's LDS must fit one CU");
 
 // Short rows of one section: four threads per row.  Thread r of a row
 // takes the row's entries r and r+4 (jagged diagonals), the four partial
 // sums are combined inside the quad (DPP), and thread r < 3 finishes
-// component r of the result.  Sections with more than 64 rows take
-// several passes.  j0: first step row of the section; n: its rows;
-// koff: its diagonal starts (LDS); dinv rows of the section start at
-// index doff of a plane of dstride rows; sc: the basis scale of the
-// forward inputs flagged as cell values.
+// component r of the result.  Sections with more rows than a quarter of
+// the threads take several passes.  tid, nthr: this thread among the nthr (a multiple of 64)
+// threads given to the section; j0: first step row of the section; n: its rows; q0,
+// q1: the starts of this thread's diagonals r and r+4; dinv rows of the
+// section start at index doff of a plane of dstride rows; sc: the basis
+// scale of the forward inputs flagged as cell values.
+// The critical path is kept to two LDS round trips per pass: the row's
+// header, dependency slots, input, D^-1 row and its first entry's block
+// are read together (the block unconditionally: a thread without that
+// entry reads some other word of LDS and its product is discarded), then
+// the dependency values.
 template <bool FWD, typename T>
 __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
-                                           double *__restrict__ z, int j0, int n, const int32_t *koff, int nslots,
-                                           int vals_off, int dinv_off, int dstride, int doff, int in_off,
+                                           double *__restrict__ z, int tid, int nthr, int j0, int n, int q0, int q1,
+                                           int nslots, int vals_off, int dinv_off, int dstride, int doff, int in_off,
                                            double sc) {
-  constexpr int kRowsPerPass = kConsumerThreads / 4;
+  const int rows_per_pass = nthr / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
-  const int r = threadIdx.x & 3;
+  const int r = tid & 3;
   const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead);
   const T *vals = reinterpret_cast<const T *>(recp + vals_off);
   const double *inb = reinterpret_cast<const double *>(recp + in_off);
-  const int q0 = koff[r], q1 = koff[r + 4];
-  for (int i0 = 0; i0 < n; i0 += kRowsPerPass) {
-    const int i = i0 + (int)(threadIdx.x >> 2);
+  const int rc = r < 3 ? r : 2;
+  for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
+    const int i = i0 + (tid >> 2);
     const bool act = i < n;
-    const int j = j0 + (act ? i : 0);
+    const int ia = act ? i : 0;
+    const int j = j0 + ia;
     const int4 m = hdr[2 * j], dp = hdr[2 * j + 1];
-    // inputs and this lane's row of D^-1 do not depend on earlier steps
-    const int rc = r < 3 ? r : 2;
     T a0, a1, a2, e0 = 0, e1 = 0, e2 = 0;
+    double x = 0.0;
     if (FWD) {
-      const double x = inb[3 * j + rc];
-      a0 = (T)((m.w & 2) ? sc * x : x);  // a cell value of r times the basis scale
+      x = inb[4 * j + rc + (rc >> 1)];
       a1 = a2 = 0;
     } else {
-      a0 = (T)inb[3 * j]; a1 = (T)inb[3 * j + 1]; a2 = (T)inb[3 * j + 2];
-      const T *dv = reinterpret_cast<const T *>(recp + dinv_off) + doff + (j - j0) + 3 * rc * dstride;
+      a0 = (T)inb[4 * j]; a1 = (T)inb[4 * j + 1]; a2 = (T)inb[4 * j + 3];
+      const T *dv = reinterpret_cast<const T *>(recp + dinv_off) + doff + ia + 3 * rc * dstride;
       e0 = dv[0]; e1 = dv[dstride]; e2 = dv[2 * dstride];
     }
+    T b[9];
+    granule9(vals, nslots, q0 + ia, b);
     const int cnt = act ? (m.w >> 8) : 0;
+    if (FWD) a0 = (T)((m.w & 2) ? sc * x : x);  // a cell value of r times the basis scale
     const unsigned w0 = (unsigned)((r < 2) ? dp.x : dp.y), w1 = (unsigned)((r < 2) ? dp.z : dp.w);
     const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
     const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
-    T s0 = 0, s1 = 0, s2 = 0;
-    if (r < cnt) {
-      T b[9];
-      granule9(vals, nslots, q0 + i, b);
-      const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
-      s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
-      s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
-      s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
-    }
+    const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
+    const T t0 = b[0] * u0 + b[1] * u1 + b[2] * u2;
+    const T t1 = b[3] * u0 + b[4] * u1 + b[5] * u2;
+    const T t2 = b[6] * u0 + b[7] * u1 + b[8] * u2;
+    const bool has0 = r < cnt;
+    T s0 = has0 ? t0 : (T)0, s1 = has0 ? t1 : (T)0, s2 = has0 ? t2 : (T)0;
     if (r + 4 < cnt) {
-      T b[9];
-      granule9(vals, nslots, q1 + i, b);
-      const T u0 = (T)vec[3 * d1], u1 = (T)vec[3 * d1 + 1], u2 = (T)vec[3 * d1 + 2];
-      s0 += b[0] * u0 + b[1] * u1 + b[2] * u2;
-      s1 += b[3] * u0 + b[4] * u1 + b[5] * u2;
-      s2 += b[6] * u0 + b[7] * u1 + b[8] * u2;
+      T c[9];
+      granule9(vals, nslots, q1 + i, c);
+      const T v0 = (T)vec[3 * d1], v1 = (T)vec[3 * d1 + 1], v2 = (T)vec[3 * d1 + 2];
+      s0 += c[0] * v0 + c[1] * v1 + c[2] * v2;
+      s1 += c[3] * v0 + c[4] * v1 + c[5] * v2;
+      s2 += c[6] * v0 + c[7] * v1 + c[8] * v2;
     }
     s0 = quad_sum(s0);
     s1 = quad_sum(s1);
@@ -564,54 +555,68 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
   }
 }
 
-// Long rows (FP64): one wavefront per row; lanes stride over its entries.
-// Pieces of a split row carry their partial sum in LDS.
+// Long rows (FP64): sixteen threads (one DPP row) per row, striding over
+// its entries, nthr / 16 rows at a time; the partial sums are combined inside
+// the sixteen threads (DPP), and the first of them finishes the row.
+// Pieces of a split row carry their partial sum in LDS.  The row's header,
+// input and D^-1 are read before the entries, so that they are not on the
+// critical path after the reduction.
+constexpr int kLongLanes = 16;
 template <bool FWD>
 __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
-                                          double *__restrict__ z, int j0, int n, int piece, int deps_off,
-                                          int rptr_off, int vals_off, int dinv_off, int dstride, int doff,
-                                          int in_off, double sc) {
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = kConsumerThreads / kWave;
+                                          double *__restrict__ z, int tid, int nthr, int j0, int n, int piece,
+                                          int deps_off, int rptr_off, int vals_off, int dinv_off, int dstride,
+                                          int doff, int in_off, double sc) {
+  const int groups = nthr / kLongLanes;
+  const int lane = tid % kLongLanes, grp = tid / kLongLanes;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int32_t *deps = reinterpret_cast<const int32_t *>(recp + deps_off);
   const int32_t *rptr = reinterpret_cast<const int32_t *>(recp + rptr_off);
   const double *vals = reinterpret_cast<const double *>(recp + vals_off);
-  for (int i = wv; i < n; i += nw) {
+  // the loop bound is the same for all sixteen threads of a row, and the
+  // DPP reductions stay inside them
+  for (int i = grp; i < n; i += groups) {
+    const int j = j0 + i;
+    const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
+    const int e0 = rptr[i], e1 = rptr[i + 1];
+    double a0, a1, a2;
+    if (piece == kPieceMiddle || piece == kPieceLast) {
+      a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
+    } else {
+      const double *inp = reinterpret_cast<const double *>(recp + in_off) + 4 * j;
+      a0 = inp[0]; a1 = inp[1]; a2 = inp[3];
+    }
+    double dv[9] = {};
+    if (!FWD && (piece == kPieceWhole || piece == kPieceLast)) {
+      const double *dp = reinterpret_cast<const double *>(recp + dinv_off) + doff + i;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) dv[e] = dp[e * dstride];
+    }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int q = rptr[i] + lane; q < rptr[i + 1]; q += kWave) {
+    for (int q = e0 + lane; q < e1; q += kLongLanes) {
       const int d = deps[q];
-      const double y0 = vec[3 * d], y1 = vec[3 * d + 1], y2 = vec[3 * d + 2];
       const double *b = vals + 9 * q;
+      const double y0 = vec[3 * d], y1 = vec[3 * d + 1], y2 = vec[3 * d + 2];
       s0 += b[0] * y0 + b[1] * y1 + b[2] * y2;
       s1 += b[3] * y0 + b[4] * y1 + b[5] * y2;
       s2 += b[6] * y0 + b[7] * y1 + b[8] * y2;
     }
-    s0 = wave_sum_dpp(s0);
-    s1 = wave_sum_dpp(s1);
-    s2 = wave_sum_dpp(s2);
+    // sums over the sixteen threads: quads, then halves, then the row
+    s0 = quad_sum(s0); s1 = quad_sum(s1); s2 = quad_sum(s2);
+    s0 += dpp64<0x141>(s0); s1 += dpp64<0x141>(s1); s2 += dpp64<0x141>(s2);
+    s0 += dpp64<0x140>(s0); s1 += dpp64<0x140>(s1); s2 += dpp64<0x140>(s2);
     if (lane == 0) {
-      const int j = j0 + i;
-      const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
-      double a0, a1, a2;
-      if (piece == kPieceMiddle || piece == kPieceLast) {
-        a0 = L.part[0]; a1 = L.part[1]; a2 = L.part[2];
-      } else {
-        const double *inp = reinterpret_cast<const double *>(recp + in_off) + 3 * j;
-        a0 = inp[0]; a1 = inp[1]; a2 = inp[2];
-        if (FWD && (m.w & 2)) {
-          a0 = sc * a0; a1 = sc * a1; a2 = sc * a2;
-        }
+      if (FWD && (m.w & 2) && !(piece == kPieceMiddle || piece == kPieceLast)) {
+        a0 = sc * a0; a1 = sc * a1; a2 = sc * a2;
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
       if (piece == kPieceFirst || piece == kPieceMiddle) {
         L.part[0] = a0; L.part[1] = a1; L.part[2] = a2;
       } else {
         if (!FWD) {
-          const double *dv = reinterpret_cast<const double *>(recp + dinv_off) + doff + i;
-          const int S = dstride;
-          const double x0 = dv[0] * a0 + dv[S] * a1 + dv[2 * S] * a2;
-          const double x1 = dv[3 * S] * a0 + dv[4 * S] * a1 + dv[5 * S] * a2;
-          const double x2 = dv[6 * S] * a0 + dv[7 * S] * a1 + dv[8 * S] * a2;
+          const double x0 = dv[0] * a0 + dv[1] * a1 + dv[2] * a2;
+          const double x1 = dv[3] * a0 + dv[4] * a1 + dv[5] * a2;
+          const double x2 = dv[6] * a0 + dv[7] * a1 + dv[8] * a2;
           a0 = x0; a1 = x1; a2 = x2;
         }
         lds_double *w = (lds_double *)L.vec;
@@ -645,13 +650,24 @@ __device__ __forceinline__ void fill_values(const RecHead &h, const char *recp, 
 
 // The sweep runs with wave-specialised roles.  The first
 // ASM_SWEEP_COMPUTE_WAVES waves compute the steps; the last four waves
-// only stream: each streaming thread
-// keeps kAhead future records (and their row inputs) in registers and
-// moves the next one into LDS every step, so several steps are in flight
-// while the computing waves work.  Both roles execute the same sequence of
-// barriers.
-constexpr int kAhead = ASM_SWEEP_AHEAD;
-static_assert(kAhead == 3 || kAhead == 4, "three or four records in flight per streaming thread");
+// only stream.  Both roles execute the same sequence of barriers.
+//
+// Streaming, per step s (every load goes straight to LDS):
+//   1. the step three ahead, s+3, is read from record s's head (in LDS
+//      since the last barrier); gathering, its rows' input sources are
+//      loaded into one of two source slots;
+//   2. record s+2 is loaded into buffer (s+2) % 3, which step s-1 has left,
+//      and its rows' inputs behind it (gathering: through the sources
+//      loaded one step earlier);
+//   3. each streaming wave waits until everything it issued before this
+//      step's record loads has landed (record s+1 and the sources of s+3:
+//      loads complete in issue order) and joins the barrier that starts
+//      step s+1.
+// Every streaming wave issues the same number of loads per step whatever
+// the record's length (chunks past a record's end, and the loads of
+// records past the sweep's end, go to a trash area), so the wait count is
+// a compile-time constant; no load of the streaming waves writes a
+// register.
 
 // Where the streaming waves take a sweep's row inputs from.  Backward: the
 // forward results, contiguous at the step's positions (src).  Forward
@@ -666,162 +682,140 @@ struct SweepIn {
   const double *r, *crs;
 };
 
-template <bool G>
-struct Producer {
-  Stage st[kAhead];
-  int len[kAhead];
-  int nrows[kAhead];         // rows of the staged record (at least 1): the threads that store inputs
-  int dq[kAhead];            // descriptor of the record stage k loads next (one word per lane)
-  int dq2[G ? kAhead : 1];   // gathering: the descriptor kAhead records after that
-  int ix[G ? kAhead : 1];    // gathering: source of this thread's row of record dq[k]
-};
+// An LDS array of the sweep's shared struct by its own address space.
+__device__ __forceinline__ ASMX_LDS u32x4 *lds(u32x4 *p) { return (ASMX_LDS u32x4 *)p; }
+__device__ __forceinline__ ASMX_LDS int32_t *lds(int32_t *p) { return (ASMX_LDS int32_t *)p; }
 
-// Descriptor of step k by a vector load, lane l holding word l % 4.  The
-// wait for the LDS stores before each barrier also waits for every scalar
-// load in flight, so a descriptor fetched by a scalar load would put its
-// full latency on every step; a vector load issued kAhead steps before use
-// completes together with the record loads issued after it.
-__device__ __forceinline__ int desc_load(const RecStep *__restrict__ steps, int k, int t) {
-  return glb(reinterpret_cast<const int32_t *>(steps + k))[t & 3];
-}
-__device__ __forceinline__ RecStep desc_get(int v) {
+// Wave-uniform copy of a step descriptor held in LDS (a record's head).
+__device__ __forceinline__ RecStep desc_lds(const RecStep *p) {
+  const ASMX_LDS int32_t *q = (const ASMX_LDS int32_t *)p;
   RecStep d;
-  d.rec = __builtin_amdgcn_readlane(v, 0);
-  d.len = __builtin_amdgcn_readlane(v, 1);
-  d.pos = __builtin_amdgcn_readlane(v, 2);
-  d.nrows = __builtin_amdgcn_readlane(v, 3);
+  d.rec = __builtin_amdgcn_readfirstlane(q[0]);
+  d.len = __builtin_amdgcn_readfirstlane(q[1]);
+  d.pos = __builtin_amdgcn_readfirstlane(q[2]);
+  d.nrows = __builtin_amdgcn_readfirstlane(q[3]);
   return d;
 }
 
-// Source of this thread's row (row t of the step, clamped) of the step
-// described by d.
-__device__ __forceinline__ int ix_load(const RecStep &d, const int32_t *__restrict__ fsrc, int t) {
-  return __builtin_nontemporal_load(glb(fsrc) + d.pos + min(t, max(d.nrows, 1) - 1));
+// Cache policy of the record loads: non-temporal (gfx950 cache-policy
+// bit); records are read once per application.
+constexpr int kNontemporalAux = 2;
+
+// Loads record d (live: a step of the sweep) into LDS buffer dst: chunk i
+// of streaming wave w holds 16-byte words i*256 + w*64 .. +63.  Chunks
+// wholly past the record's end, and every chunk of a dead record, go to
+// the trash area; lanes past the end within the last chunk load its last
+// word (the input area starts at the next chunk).
+__device__ __forceinline__ void dma_record(const RecStep &d, bool live, const u32x4 *__restrict__ rec,
+                                           ASMX_LDS u32x4 *dst, ASMX_LDS u32x4 *trash, int w, int l) {
+#pragma unroll
+  for (int i = 0; i < kRounds; ++i) {
+    const int base = i * 256 + w * 64;
+    const bool on = live && base < d.len;  // uniform over the wave
+    const u32x4 *g = on ? rec + d.rec + min(base + l, d.len - 1) : rec;
+    ASMX_LDS u32x4 *dl = on ? dst + base : trash;
+    __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 16, 0, kNontemporalAux);
+  }
 }
 
-// Streamer: load record k of the sweep and its row inputs into a stage.
-// Lanes past the record's end load nothing (their stage words are never
-// stored), so a short record issues fewer wave-wide loads;
-// records are read once per application, so they are loaded
-// non-temporally.  Each thread loads the three inputs of one row (24
-// contiguous bytes).  A gathered cell value is scaled by the computing
-// waves (row flag bit 1), so that nothing here waits on the loads it issues.
+// Gathering: the input sources of record d's rows (fsrc at its positions)
+// into a source slot; streaming wave w loads entries 64w .. 64w+63, rows
+// past the end repeat the last one.
+__device__ __forceinline__ void dma_sources(const RecStep &d, bool live, const int32_t *__restrict__ fsrc,
+                                            const void *dummy, ASMX_LDS int32_t *dst, ASMX_LDS u32x4 *trash, int w,
+                                            int l) {
+  const bool on = live && d.nrows > 64 * w;  // uniform over the wave
+  const int32_t *g = on ? fsrc + d.pos + min(64 * w + l, d.nrows - 1) : static_cast<const int32_t *>(dummy);
+  ASMX_LDS void *dl = on ? (ASMX_LDS void *)(dst + 64 * w) : (ASMX_LDS void *)trash;
+  __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 4, 0, 0);
+}
+
+// Row inputs: load k of a record covers rows 32k .. 32k+31 (streaming wave
+// w issues loads k = w and k = w + 4); lane l carries doubles (0, 1) of
+// row 32k + (l >> 1) if l is even, doubles (1, 2) if odd, so row j's input
+// lands as 32 bytes at kInRowBytes * j, component c at double 4j + c +
+// (c >> 1).  Rows past the record's end repeat its last row.
 template <bool G>
-__device__ __forceinline__ void prod_load(const RecStep &d, const u32x4 *__restrict__ rec, const SweepIn &in,
-                                          int ix, Stage &st, int &len, int &nrows, int t) {
+__device__ __forceinline__ void dma_inputs(const RecStep &d, bool live, const ASMX_LDS int32_t *srcs,
+                                           const SweepIn &in, const void *dummy, ASMX_LDS u32x4 *dst,
+                                           ASMX_LDS u32x4 *trash, int w, int l) {
+  ASMX_LDS char *area = reinterpret_cast<ASMX_LDS char *>(dst) + rec_in_offset((int64_t)d.len * 16);
 #pragma unroll
-  for (int i = 0; i < kStageU4; ++i)
-    if (i * 256 + t < d.len) st.v[i] = __builtin_nontemporal_load(glb(rec) + d.rec + i * 256 + t);
-  // the row inputs stay clamped: a conditional load here makes the compiler
-  // merge the stage registers at the join and wait for the loads at once
-  const int nst = max(d.nrows, 1);
-  glb_cdouble *p;
-  if constexpr (G) {
-    p = ix >= 0 ? glb(in.r) + 3 * (size_t)ix : glb(in.crs) + 3 * (size_t)(-ix - 1);
-  } else {
-    p = glb(in.src) + 3 * ((size_t)d.pos + min(t, nst - 1));
-  }
-  st.x[0] = p[0];
-  st.x[1] = p[1];
-  st.x[2] = p[2];
-  len = d.len;
-  nrows = nst;
-}
-
-// Stores a stage into an LDS buffer: the record words, then the inputs
-// right behind the record.
-__device__ __forceinline__ void prod_store(u32x4 *dst, const Stage &st, int len, int nrows, int t) {
-#pragma unroll
-  for (int i = 0; i < kStageU4; ++i)
-    if (i * 256 + t < len) dst[i * 256 + t] = st.v[i];
-  double *xd = reinterpret_cast<double *>(dst + len);
-  if (t < nrows) {
-    xd[3 * t] = st.x[0];
-    xd[3 * t + 1] = st.x[1];
-    xd[3 * t + 2] = st.x[2];
+  for (int q = 0; q < 2; ++q) {
+    const int k = w + 4 * q;
+    const bool on = live && d.nrows > kInRowsPerLoad * k;  // uniform over the wave
+    const int row = min(kInRowsPerLoad * k + (l >> 1), max(d.nrows, 1) - 1);
+    const double *p;
+    if constexpr (G) {
+      const int c = srcs[row];
+      p = c >= 0 ? in.r + 3 * (size_t)c : in.crs + 3 * (size_t)(-c - 1);
+    } else {
+      p = in.src + 3 * ((size_t)d.pos + row);
+    }
+    const void *g = on ? static_cast<const void *>(p + (l & 1)) : dummy;
+    ASMX_LDS char *dl = on ? area + k * (kInRowsPerLoad * kInRowBytes) : reinterpret_cast<ASMX_LDS char *>(trash);
+    __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 16, 0, 0);
   }
 }
 
-template <bool G, int K>
-__device__ __forceinline__ void prod_iter(int s, int S, const RecStep *__restrict__ steps,
-                                          const u32x4 *__restrict__ rec, const SweepIn &in, SweepLds &L,
-                                          Producer<G> &P, int t) {
-  // record s+1 is in stage (s+1) % kAhead == K; move it to LDS, then reuse
-  // the stage for record s+1+kAhead, whose descriptor dq[K] was loaded
-  // kAhead steps ago.  Gathering, the sources of that record's inputs
-  // (ix[K]) were loaded kAhead steps ago too; once the gathers are issued,
-  // ix[K] takes the sources of record s+1+2*kAhead (descriptor dq2[K], also
-  // kAhead steps old) and dq2[K] the descriptor of s+1+3*kAhead.  Each ring
-  // register is overwritten in place, after its last use: a copy of a value
-  // still in flight would wait for it.
-  prod_store(L.buf[(s + 1) & 1], P.st[K], P.len[K], P.nrows[K], t);
-  const RecStep d = desc_get(P.dq[K]);
-  if constexpr (G) {
-    const RecStep d2 = desc_get(P.dq2[K]);
-    P.dq[K] = P.dq2[K];
-    P.dq2[K] = desc_load(steps, min(s + 1 + 3 * kAhead, S - 1), t);
-    prod_load<G>(d, rec, in, P.ix[K], P.st[K], P.len[K], P.nrows[K], t);
-    P.ix[K] = ix_load(d2, in.fsrc, t);
-  } else {
-    P.dq[K] = desc_load(steps, min(s + 1 + 2 * kAhead, S - 1), t);
-    prod_load<G>(d, rec, in, 0, P.st[K], P.len[K], P.nrows[K], t);
-  }
-  __syncthreads();
-}
+// vmcnt(n) alone (the other counters at their maximum), gfx9 encoding.
+constexpr int vmcnt_imm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
+
+// Loads of one streaming step after (and including) the record loads.
+constexpr int kRecordLoads = kRounds + 2;
+
+// Keeps the compiler from moving memory operations across this point.
+__device__ __forceinline__ void mem_order() { __asm__ __volatile__("" ::: "memory"); }
 
 template <bool G>
 __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
                                                const u32x4 *__restrict__ rec, const SweepIn &in, SweepLds &L) {
   if (S == 0) return;
-  const int t = threadIdx.x - kConsumerThreads;
-  Producer<G> P;
-  // iteration s with (s+1) % kAhead == k reloads stage k with record
-  // s+1+kAhead: dq[k] starts with its descriptor (and, gathering, ix[k] with
-  // its input sources, dq2[k] with the descriptor kAhead records later)
-  auto first = [&](int k) { return min(kAhead + (k == 0 ? kAhead : k), S - 1); };
-#pragma unroll
-  for (int k = 0; k < kAhead; ++k) P.dq[k] = desc_load(steps, first(k), t);
-  // gathering: the sources of the first kAhead+1 records' inputs and of
-  // those the first iterations load, ahead of the first records, so that
-  // the loop finds them as old as in its steady state
-  int ix0[kAhead + 1] = {};
+  const int t = threadIdx.x - kConsumerThreads, w = t >> 6, l = t & 63;
+  ASMX_LDS u32x4 *trash = lds(L.trash);
+  const RecStep d0 = ld_glb(steps), d1 = ld_glb(steps + min(1, S - 1));
+  RecStep dcur = ld_glb(steps + min(2, S - 1));
+  // sources of records 0 and 1, visible to all streaming waves after the
+  // sweep's first barrier
   if constexpr (G) {
-#pragma unroll
-    for (int k = 0; k < kAhead; ++k) P.dq2[k] = desc_load(steps, min(first(k) + kAhead, S - 1), t);
-#pragma unroll
-    for (int k = 0; k <= kAhead; ++k) ix0[k] = ix_load(ld_glb(steps + min(k, S - 1)), in.fsrc, t);
-#pragma unroll
-    for (int k = 0; k < kAhead; ++k) P.ix[k] = ix_load(desc_get(P.dq[k]), in.fsrc, t);
+    dma_sources(d0, true, in.fsrc, rec, lds(L.src[0]), trash, w, l);
+    dma_sources(d1, S > 1, in.fsrc, rec, lds(L.src[1]), trash, w, l);
   }
-#pragma unroll
-  for (int k = 0; k < kAhead; ++k)
-    prod_load<G>(ld_glb(steps + min(k, S - 1)), rec, in, ix0[k], P.st[k], P.len[k], P.nrows[k], t);
-  prod_store(L.buf[0], P.st[0], P.len[0], P.nrows[0], t);
-  prod_load<G>(ld_glb(steps + min(kAhead, S - 1)), rec, in, ix0[kAhead], P.st[0], P.len[0], P.nrows[0], t);
-  __syncthreads();
-  // full groups of kAhead steps without conditions (exact wait counts),
-  // then the remaining steps in straight-line code
-  int s = 0;
-  if constexpr (kAhead == 4) {
-    for (; s + 4 <= S; s += 4) {
-      prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
-      prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
-      prod_iter<G, 3>(s + 2, S, steps, rec, in, L, P, t);
-      prod_iter<G, 0>(s + 3, S, steps, rec, in, L, P, t);
-    }
-    if (s < S) prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
-    if (s + 1 < S) prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
-    if (s + 2 < S) prod_iter<G, 3>(s + 2, S, steps, rec, in, L, P, t);
-  } else {
-    for (; s + 3 <= S; s += 3) {
-      prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
-      prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
-      prod_iter<G, 0>(s + 2, S, steps, rec, in, L, P, t);
-    }
-    if (s < S) prod_iter<G, 1>(s, S, steps, rec, in, L, P, t);
-    if (s + 1 < S) prod_iter<G, 2>(s + 1, S, steps, rec, in, L, P, t);
+  mem_order();
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+  __builtin_amdgcn_s_barrier();
+  mem_order();
+  dma_record(d0, true, rec, lds(L.buf[0]), trash, w, l);
+  dma_inputs<G>(d0, true, lds(L.src[0]), in, rec, lds(L.buf[0]), trash, w, l);
+  mem_order();
+  if constexpr (G) dma_sources(dcur, S > 2, in.fsrc, rec, lds(L.src[0]), trash, w, l);
+  mem_order();
+  dma_record(d1, S > 1, rec, lds(L.buf[1]), trash, w, l);
+  dma_inputs<G>(d1, S > 1, lds(L.src[1]), in, rec, lds(L.buf[1]), trash, w, l);
+  mem_order();
+  // record 0 (and the sources of record 2) landed: only record 1 in flight
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(kRecordLoads));
+  __builtin_amdgcn_s_barrier();
+  for (int s = 0; s < S; ++s) {
+    mem_order();
+    const RecStep dn = desc_lds(&reinterpret_cast<const RecHead *>(L.buf[s % kRecBufs])->ahead);
+    if constexpr (G) dma_sources(dn, s + 3 < S, in.fsrc, rec, lds(L.src[(s + 3) & 1]), trash, w, l);
+    mem_order();
+    const bool live = s + 2 < S;
+    ASMX_LDS u32x4 *dst = lds(L.buf[(s + 2) % kRecBufs]);
+    dma_record(dcur, live, rec, dst, trash, w, l);
+    dma_inputs<G>(dcur, live, lds(L.src[(s + 2) & 1]), in, rec, dst, trash, w, l);
+    mem_order();
+    dcur = dn;
+    // everything issued before this step's record loads has landed
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(kRecordLoads));
+    __builtin_amdgcn_s_barrier();
   }
-  __syncthreads();  // matches the computing waves' final epilogue barrier
+  mem_order();
+  // the loads of the records past the end (trash) complete before the
+  // next sweep starts; matches the computing waves' final barrier
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+  __builtin_amdgcn_s_barrier();
 }
 
 // Computing iteration for step s: step s from LDS (or the reloads of a
@@ -829,19 +823,30 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
 template <bool FWD>
 __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict__ yx, double *__restrict__ z,
                                           double sc) {
-  const char *recp = reinterpret_cast<const char *>(L.buf[s & 1]);
+  const char *recp = reinterpret_cast<const char *>(L.buf[s % kRecBufs]);
   const RecHead *hp = reinterpret_cast<const RecHead *>(recp);
   const RecHead h = *hp;
-  const int nlong = h.nrows - h.n32 - h.n64;
-  if (h.n32 > 0)
-    short_rows<FWD, float>(recp, L, yx, z, 0, h.n32, hp->koff32, h.nslots32, h.vals32, h.dinv32, h.n32, 0, h.in,
-                           sc);
-  if (h.n64 > 0)
-    short_rows<FWD, double>(recp, L, yx, z, h.n32, h.n64, hp->koff64, h.nslots64, h.vals64, h.dinv64,
-                            h.n64 + nlong, 0, h.in, sc);
-  if (nlong > 0)
-    long_rows<FWD>(recp, L, yx, z, h.n32 + h.n64, nlong, h.piece, h.ldeps, h.lrptr, h.lvals, h.dinv64,
-                   h.n64 + nlong, h.n64, h.in, sc);
+  // this thread's diagonal starts, read with the head
+  const int r = threadIdx.x & 3;
+  const int q32a = hp->koff32[r], q32b = hp->koff32[r + 4], q64a = hp->koff64[r], q64b = hp->koff64[r + 4];
+  const int nlong = h.nrows - h.n32 - h.n64, nshort = h.n32 + h.n64;
+  // a step with both kinds runs them side by side: the long rows on the
+  // last waves (four rows per wave, at most half of the waves), the short
+  // rows on the others
+  const int wlong = nlong == 0 ? 0 : (nshort == 0 ? kConsumerThreads / 64 : min(kConsumerThreads / 128, (nlong + 3) / 4));
+  const int tshort = kConsumerThreads - 64 * wlong;
+  const int tid = (int)threadIdx.x;
+  if (tid < tshort) {
+    if (h.n32 > 0)
+      short_rows<FWD, float>(recp, L, yx, z, tid, tshort, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
+                             h.n32, 0, h.in, sc);
+    if (h.n64 > 0)
+      short_rows<FWD, double>(recp, L, yx, z, tid, tshort, h.n32, h.n64, q64a, q64b, h.nslots64, h.vals64,
+                              h.dinv64, h.n64 + nlong, 0, h.in, sc);
+  } else {
+    long_rows<FWD>(recp, L, yx, z, tid - tshort, kConsumerThreads - tshort, nshort, nlong, h.piece, h.ldeps, h.lrptr,
+                   h.lvals, h.dinv64, h.n64 + nlong, h.n64, h.in, sc);
+  }
   if (h.nfill > 0) fill_values(h, recp, L, yx);
   __syncthreads();
 }
@@ -850,6 +855,9 @@ template <bool FWD>
 __device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__restrict__ yx, double *__restrict__ z,
                                                double sc) {
   if (S == 0) return;
+  // the streaming waves' two opening barriers: sources of the first
+  // records, then the first record
+  __syncthreads();
   __syncthreads();
   for (int s = 0; s < S; ++s) cons_iter<FWD>(s, L, yx, z, sc);
   __syncthreads();  // matches the streaming waves' final barrier

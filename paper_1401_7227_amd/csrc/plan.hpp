@@ -5,6 +5,7 @@
 // global CSR (entries sorted by local column) from which the factors are
 // computed, and re-laid out per level step for the triangular solves.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 namespace asmx {
@@ -29,6 +30,25 @@ constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
 static_assert(kVecSlots <= 65536, "slots are stored as 16-bit indices");
 constexpr int kMaxJdsWidth = 8;    // mode-0 rows have at most this many entries
 constexpr int kMaxStepRows = 256;  // rows per step
+// The streaming waves copy a record into LDS in chunks of 1 KiB (64 lanes x
+// 16 bytes per wave and load); lanes past the record's end still write
+// their chunk, so a record's row inputs start at the next chunk boundary.
+// A row's input (3 doubles) arrives as two 16-byte loads, doubles (0, 1)
+// and (1, 2), so in LDS row j's input takes 32 bytes, component c at
+// double 4j + c + (c >> 1); 32 rows per load, the input area is sized in
+// whole groups of 32 rows.
+constexpr int kRecChunk = 1024;
+constexpr int kInRowsPerLoad = 32;
+constexpr int kInRowBytes = 32;
+constexpr int32_t rec_in_offset(int64_t stored_bytes) {
+  return (int32_t)((stored_bytes + kRecChunk - 1) / kRecChunk * kRecChunk);
+}
+constexpr int32_t rec_in_bytes(int nrows) {
+  return (int32_t)(((nrows > 1 ? nrows : 1) + kInRowsPerLoad - 1) / kInRowsPerLoad * kInRowsPerLoad * kInRowBytes);
+}
+// A record's head names the record kHeadAhead steps later in its sweep (the
+// last one past the end): the streaming waves read it there.
+constexpr int kHeadAhead = 3;
 static_assert(kMaxStepRows * kMaxJdsWidth < 65536, "section entries are packed in 16 bits");
 
 #ifndef ASM_FILL_SLOTS
@@ -69,29 +89,18 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 //   fill    int2 per value {global position, slot}: values of the NEXT step
 //           that have no LDS slot of their own, reloaded from the global
 //           vector into the fill slots (only in empty "fill" steps).
-// The stored record ends there (len 16-byte units); in LDS it is followed
-// by the "in" section, 3 doubles per row (at least one row): the rows'
-// inputs, which the streaming waves fetch (forward: gathered from r and
-// the coarse rows' lumped inputs through the position's source; backward:
-// the forward results at the step's positions).
+// The stored record ends there (len 16-byte units); in LDS it is followed,
+// from the next 1 KiB boundary (rec_in_offset), by the "in" section, 32
+// bytes per row (see kInRowBytes): the rows' inputs, which the streaming waves fetch
+// (forward: gathered from r and the coarse rows' lumped inputs through the
+// position's source; backward: the forward results at the step's
+// positions).  Record, padding and input area (rec_in_bytes) fit one
+// buffer of kRecBytes.
 // A long row whose record would not fit one LDS buffer is split into
 // pieces in consecutive one-row steps that carry the partial sum in LDS.
 // A value reloaded by a fill step is produced at least two steps before
 // it (the host inserts empty steps where needed).
 enum { kPieceWhole = 0, kPieceFirst = 1, kPieceMiddle = 2, kPieceLast = 3 };
-
-struct RecHead {
-  int32_t nrows, n32, n64, piece;
-  int32_t nslots32, nslots64, pos, in;
-  int32_t vals32, vals64, lvals, ldeps;
-  int32_t lrptr, dinv32, dinv64, nfill;
-  int32_t fill, pad0, pad1, pad2;
-  int32_t koff32[kMaxJdsWidth + 1];  // first entry of each jagged diagonal
-  int32_t koff64[kMaxJdsWidth + 1];
-  int32_t pad3[2];
-};
-constexpr int kRecHead = (int)sizeof(RecHead);
-static_assert(kRecHead % 16 == 0, "record head must keep 16-byte alignment");
 
 struct RecStep {
   int32_t rec;    // record start, in 16-byte units
@@ -99,6 +108,21 @@ struct RecStep {
   int32_t pos;    // position of the step's first row (forward / backward order)
   int32_t nrows;
 };
+
+struct RecHead {
+  int32_t nrows, n32, n64, piece;
+  int32_t nslots32, nslots64, pos, in;
+  int32_t vals32, vals64, lvals, ldeps;
+  int32_t lrptr, dinv32, dinv64, nfill;
+  RecStep ahead;                     // the step kHeadAhead later (16-byte aligned)
+  int32_t fill, pad0, pad1, pad2;
+  int32_t koff32[kMaxJdsWidth + 1];  // first entry of each jagged diagonal
+  int32_t koff64[kMaxJdsWidth + 1];
+  int32_t pad3[2];
+};
+constexpr int kRecHead = (int)sizeof(RecHead);
+static_assert(kRecHead % 16 == 0, "record head must keep 16-byte alignment");
+static_assert(offsetof(RecHead, ahead) % 16 == 0, "the step ahead is read as one 16-byte word");
 
 struct ApplyPlan {
   int32_t nsub;

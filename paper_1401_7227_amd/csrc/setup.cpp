@@ -241,7 +241,6 @@ struct RecLayout {
   int32_t ldeps, lrptr, vals32, vals64, lvals, dinv32, dinv64, total, lds;
 };
 
-inline int32_t in_bytes(int nrows) { return align16((int64_t)24 * std::max(nrows, 1)); }
 
 RecLayout rec_layout(const StepShape &k, bool fwd) {
   RecLayout L{};
@@ -262,7 +261,7 @@ RecLayout rec_layout(const StepShape &k, bool fwd) {
   if (!fwd) at += align16((int64_t)72 * (k.n64 + k.nlong));
   const int64_t lim = (int64_t)1 << 30;
   L.total = (int32_t)std::min(at, lim);
-  L.lds = (int32_t)std::min(at + in_bytes(k.nrows()), lim);
+  L.lds = (int32_t)std::min((int64_t)rec_in_offset(at) + rec_in_bytes(k.nrows()), lim);
   return L;
 }
 
@@ -563,7 +562,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         while ((int32_t)out.size() < newest + 2) {
           RecHead e{};
           e.pos = out.empty() ? pos0 : out.back().pos;
-          e.in = kRecHead;
+          e.in = rec_in_offset(kRecHead);
           push_record(e, kRecHead, e.pos, 0);
         }
         RecHead f{};
@@ -571,7 +570,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         f.nfill = (int32_t)fills.size();
         f.fill = kRecHead;
         const int32_t total = kRecHead + align16((int64_t)8 * fills.size());
-        f.in = total;
+        f.in = rec_in_offset(total);
         uint8_t *fb = push_record(f, total, f.pos, 0);
         int32_t *fl = reinterpret_cast<int32_t *>(fb + kRecHead);
         for (size_t q = 0; q < fills.size(); ++q) {
@@ -588,7 +587,7 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       h.nslots32 = shp.e32;
       h.nslots64 = shp.e64;
       h.pos = pos0;
-      h.in = L.total;
+      h.in = rec_in_offset(L.total);
       h.vals32 = L.vals32;
       h.vals64 = L.vals64;
       h.lvals = L.lvals;
@@ -1203,6 +1202,19 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     };
     place(S.rf, P.rf, o_rf[s]);
     place(S.rb, P.rb, o_rb[s]);
+    // each record names the one kHeadAhead steps later in its sweep (the
+    // last one past the end), where the streaming waves look it up
+    auto link = [&](const std::vector<RecStep> &loc, const std::vector<RecStep> &glob, int64_t off) {
+      const size_t n = loc.size();
+      for (size_t k = 0; k < n; ++k) {
+        RecHead h;
+        std::memcpy(&h, rb + loc[k].rec, sizeof h);
+        h.ahead = glob[off + std::min(k + kHeadAhead, n - 1)];
+        std::memcpy(rb + loc[k].rec, &h, sizeof h);
+      }
+    };
+    link(S.rf, P.rf, o_rf[s]);
+    link(S.rb, P.rb, o_rb[s]);
     for (size_t t = 0; t < S.rl_src.size(); ++t) {
       const int sz = (S.rl_to32[t] & 1) ? 4 : 8;
       P.rl.src[o_rl[s] + t] = (int32_t)(o_ent[s] + S.rl_src[t]);

@@ -14,6 +14,7 @@
 //                      nearx neary nearz farx fary farz precision field
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -68,10 +69,13 @@ static void check_steps(const PlanHost &P, const std::vector<RecStep> &steps, co
     std::memcpy(&h, P.rec.data() + b0, sizeof h);
     CHECK(h.nrows == d.nrows, "%s step %zu: head rows %d, step rows %d", which, k, h.nrows, d.nrows);
     CHECK(d.nrows >= 0 && d.nrows <= kMaxStepRows, "%s step %zu: %d rows", which, k, d.nrows);
-    const int64_t in = 24 * (int64_t)(d.nrows > 0 ? d.nrows : 1);
-    CHECK(len + ((in + 15) & ~15LL) <= kRecBytes, "%s step %zu: %lld record bytes + inputs exceed the buffer", which,
-          k, (long long)len);
-    CHECK(h.in == len, "%s step %zu: inputs at %d, record length %lld", which, k, h.in, (long long)len);
+    // inputs from the 1 KiB chunk after the record, whole groups of 32 rows
+    const int64_t in_off = (len + 1023) / 1024 * 1024;
+    const int64_t in = ((d.nrows > 1 ? d.nrows : 1) + 31) / 32 * 32 * 32;
+
+    CHECK(in_off + in <= kRecBytes, "%s step %zu: %lld record bytes + inputs exceed the buffer", which, k,
+          (long long)len);
+    CHECK(h.in == in_off, "%s step %zu: inputs at %d, record length %lld", which, k, h.in, (long long)len);
     CHECK(h.n32 >= 0 && h.n64 >= 0 && h.n32 + h.n64 <= h.nrows, "%s step %zu: sections", which, k);
     CHECK(d.pos >= 0 && d.pos + d.nrows <= P.total_pos, "%s step %zu: positions", which, k);
     const int32_t offs[] = {h.vals32, h.vals64, h.lvals, h.ldeps, h.lrptr, h.dinv32, h.dinv64};
@@ -133,6 +137,19 @@ int main(int argc, char **argv) {
   CHECK((int64_t)P.arp.size() == P.total_ext + 1 && P.arp.back() == P.total_entries, "factor CSR");
   check_steps(P, P.rf, "forward");
   check_steps(P, P.rb, "backward");
+  // each head names the step kHeadAhead later in its subdomain's sweep (or the last)
+  for (int s = 0; s < P.nsub; ++s)
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      const std::vector<RecStep> &st = sweep ? P.rb : P.rf;
+      const int a = sweep ? P.sub[s].rb0 : P.sub[s].rf0, b = sweep ? P.sub[s].rb1 : P.sub[s].rf1;
+      for (int k = a; k < b; ++k) {
+        RecHead h;
+        std::memcpy(&h, P.rec.data() + (int64_t)st[k].rec * 16, sizeof h);
+        const RecStep &ah = st[std::min(k + kHeadAhead, b - 1)];
+        CHECK(h.ahead.rec == ah.rec && h.ahead.len == ah.len && h.ahead.pos == ah.pos && h.ahead.nrows == ah.nrows,
+              "sub %d sweep %d step %d: step ahead", s, sweep, k - a);
+      }
+    }
   // factor slots of the record buffer
   const int64_t rbytes = (int64_t)P.rec.size();
   for (size_t t = 0; t < P.rl.src.size(); ++t) {
