@@ -39,15 +39,17 @@ __device__ inline double wave_sum(double v) {
 // Cross-lane moves inside the VALU (DPP), no LDS traffic.  CTRL is a DPP
 // control: quad_perm 0xB1 (lanes xor 1), 0x4E (xor 2), 0x141 row half
 // mirror (lane i <-> 7-i within 8), 0x140 row mirror (i <-> 15-i within 16).
+// Every source lane of these controls is inside the same row of 16 lanes,
+// so no lane reads outside the row (bound_ctrl set: no old value needed).
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_any(double v) { return dpp64<CTRL>(v); }
@@ -474,11 +476,28 @@ struct SweepLds {
 };
 static_assert(sizeof(SweepLds) <= 160 * 1024, "the sweep's LDS must fit one CU");
 
+// A record row's header (see RecHead): the result's LDS slot (-1: none),
+// flags, entry count, and the index word (forward: the row's backward
+// position; backward: the output cell or -1).
+struct RowHead {
+  int slot, flags, cnt, idx;
+};
+__device__ __forceinline__ RowHead row_head(int2 m) {
+  RowHead r;
+  const unsigned w = (unsigned)m.x;
+  const int sl = (int)(w & 0xffff);
+  r.slot = sl == kRecNoSlot ? -1 : sl;
+  r.flags = (int)((w >> 16) & 3);
+  r.cnt = (int)(w >> 18);
+  r.idx = m.y;
+  return r;
+}
+
 // Short rows of one section: four threads per row.  Thread r of a row
 // takes the row's entries r and r+4 (jagged diagonals), the four partial
 // sums are combined inside the quad (DPP), and thread r < 3 finishes
 // component r of the result.  Sections with more rows than a quarter of
-// the threads take several passes.  tid, nthr: this thread among the nthr (a multiple of 64)
+// the threads take several passes; waves without a row in a pass skip it.  tid, nthr: this thread among the nthr (a multiple of 64)
 // threads given to the section; j0: first step row of the section; n: its rows; q0,
 // q1: the starts of this thread's diagonals r and r+4; dinv rows of the
 // section start at index doff of a plane of dstride rows; sc: the basis
@@ -490,22 +509,25 @@ static_assert(sizeof(SweepLds) <= 160 * 1024, "the sweep's LDS must fit one CU")
 // the dependency values.
 template <bool FWD, typename T>
 __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
-                                           double *__restrict__ z, int tid, int nthr, int j0, int n, int q0, int q1,
-                                           int nslots, int vals_off, int dinv_off, int dstride, int doff, int in_off,
-                                           double sc) {
+                                           double *__restrict__ z, int tid, int nthr, int spos, int j0, int n, int q0,
+                                           int q1, int nslots, int vals_off, int dinv_off, int dstride, int doff,
+                                           int in_off, double sc) {
   const int rows_per_pass = nthr / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int r = tid & 3;
-  const int4 *hdr = reinterpret_cast<const int4 *>(recp + kRecHead);
+  const char *rows = recp + kRecHead;
   const T *vals = reinterpret_cast<const T *>(recp + vals_off);
   const double *inb = reinterpret_cast<const double *>(recp + in_off);
   const int rc = r < 3 ? r : 2;
   for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
+    if (i0 + ((tid & ~63) >> 2) >= n) break;  // no row of this wave in the pass (uniform)
     const int i = i0 + (tid >> 2);
     const bool act = i < n;
     const int ia = act ? i : 0;
     const int j = j0 + ia;
-    const int4 m = hdr[2 * j], dp = hdr[2 * j + 1];
+    const RowHead m = row_head(*reinterpret_cast<const int2 *>(rows + kRecRowBytes * j));
+    const int2 dpa = *reinterpret_cast<const int2 *>(rows + kRecRowBytes * j + 8);
+    const int2 dpb = *reinterpret_cast<const int2 *>(rows + kRecRowBytes * j + 16);
     T a0, a1, a2, e0 = 0, e1 = 0, e2 = 0;
     double x = 0.0;
     if (FWD) {
@@ -518,9 +540,10 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     }
     T b[9];
     granule9(vals, nslots, q0 + ia, b);
-    const int cnt = act ? (m.w >> 8) : 0;
-    if (FWD) a0 = (T)((m.w & 2) ? sc * x : x);  // a cell value of r times the basis scale
-    const unsigned w0 = (unsigned)((r < 2) ? dp.x : dp.y), w1 = (unsigned)((r < 2) ? dp.z : dp.w);
+    const int cnt = act ? m.cnt : 0;
+    if (FWD) a0 = (T)((m.flags & 2) ? sc * x : x);  // a cell value of r times the basis scale
+    // slots of entries r and r+4: half r & 1 of words r / 2 and 2 + r / 2
+    const unsigned w0 = (unsigned)((r < 2) ? dpa.x : dpa.y), w1 = (unsigned)((r < 2) ? dpb.x : dpb.y);
     const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
     const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
     const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
@@ -548,9 +571,9 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
         o = e0 * (a0 - s0) + e1 * (a1 - s1) + e2 * (a2 - s2);
       }
       const double od = (double)o;
-      if (m.x >= 0) ((lds_double *)L.vec)[3 * m.x + r] = od;
-      if (m.w & 1) glb(yx)[3 * (size_t)m.y + r] = od;
-      if (m.z >= 0) glb(z)[3 * (size_t)m.z + r] = od;
+      if (m.slot >= 0) ((lds_double *)L.vec)[3 * m.slot + r] = od;
+      if (m.flags & 1) glb(yx)[3 * (size_t)(FWD ? m.idx : spos + j) + r] = od;
+      if (!FWD && m.idx >= 0) glb(z)[3 * (size_t)m.idx + r] = od;
     }
   }
 }
@@ -564,9 +587,9 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
 constexpr int kLongLanes = 16;
 template <bool FWD>
 __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
-                                          double *__restrict__ z, int tid, int nthr, int j0, int n, int piece,
-                                          int deps_off, int rptr_off, int vals_off, int dinv_off, int dstride,
-                                          int doff, int in_off, double sc) {
+                                          double *__restrict__ z, int tid, int nthr, int spos, int j0, int n,
+                                          int piece, int deps_off, int rptr_off, int vals_off, int dinv_off,
+                                          int dstride, int doff, int in_off, double sc) {
   const int groups = nthr / kLongLanes;
   const int lane = tid % kLongLanes, grp = tid / kLongLanes;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
@@ -577,7 +600,7 @@ __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double 
   // DPP reductions stay inside them
   for (int i = grp; i < n; i += groups) {
     const int j = j0 + i;
-    const int4 m = reinterpret_cast<const int4 *>(recp + kRecHead)[2 * j];
+    const RowHead m = row_head(*reinterpret_cast<const int2 *>(recp + kRecHead + kRecRowBytes * j));
     const int e0 = rptr[i], e1 = rptr[i + 1];
     double a0, a1, a2;
     if (piece == kPieceMiddle || piece == kPieceLast) {
@@ -606,7 +629,7 @@ __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double 
     s0 += dpp64<0x141>(s0); s1 += dpp64<0x141>(s1); s2 += dpp64<0x141>(s2);
     s0 += dpp64<0x140>(s0); s1 += dpp64<0x140>(s1); s2 += dpp64<0x140>(s2);
     if (lane == 0) {
-      if (FWD && (m.w & 2) && !(piece == kPieceMiddle || piece == kPieceLast)) {
+      if (FWD && (m.flags & 2) && !(piece == kPieceMiddle || piece == kPieceLast)) {
         a0 = sc * a0; a1 = sc * a1; a2 = sc * a2;
       }
       a0 -= s0; a1 -= s1; a2 -= s2;
@@ -620,13 +643,13 @@ __device__ __forceinline__ void long_rows(const char *recp, SweepLds &L, double 
           a0 = x0; a1 = x1; a2 = x2;
         }
         lds_double *w = (lds_double *)L.vec;
-        if (m.x >= 0) { w[3 * m.x] = a0; w[3 * m.x + 1] = a1; w[3 * m.x + 2] = a2; }
-        if (m.w & 1) {
-          glb_double *g = glb(yx) + 3 * (size_t)m.y;
+        if (m.slot >= 0) { w[3 * m.slot] = a0; w[3 * m.slot + 1] = a1; w[3 * m.slot + 2] = a2; }
+        if (m.flags & 1) {
+          glb_double *g = glb(yx) + 3 * (size_t)(FWD ? m.idx : spos + j);
           g[0] = a0; g[1] = a1; g[2] = a2;
         }
-        if (m.z >= 0) {
-          glb_double *g = glb(z) + 3 * (size_t)m.z;
+        if (!FWD && m.idx >= 0) {
+          glb_double *g = glb(z) + 3 * (size_t)m.idx;
           g[0] = a0; g[1] = a1; g[2] = a2;
         }
       }
@@ -838,13 +861,13 @@ __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict
   const int tid = (int)threadIdx.x;
   if (tid < tshort) {
     if (h.n32 > 0)
-      short_rows<FWD, float>(recp, L, yx, z, tid, tshort, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
+      short_rows<FWD, float>(recp, L, yx, z, tid, tshort, h.pos, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
                              h.n32, 0, h.in, sc);
     if (h.n64 > 0)
-      short_rows<FWD, double>(recp, L, yx, z, tid, tshort, h.n32, h.n64, q64a, q64b, h.nslots64, h.vals64,
+      short_rows<FWD, double>(recp, L, yx, z, tid, tshort, h.pos, h.n32, h.n64, q64a, q64b, h.nslots64, h.vals64,
                               h.dinv64, h.n64 + nlong, 0, h.in, sc);
   } else {
-    long_rows<FWD>(recp, L, yx, z, tid - tshort, kConsumerThreads - tshort, nshort, nlong, h.piece, h.ldeps, h.lrptr,
+    long_rows<FWD>(recp, L, yx, z, tid - tshort, kConsumerThreads - tshort, h.pos, nshort, nlong, h.piece, h.ldeps, h.lrptr,
                    h.lvals, h.dinv64, h.n64 + nlong, h.n64, h.in, sc);
   }
   if (h.nfill > 0) fill_values(h, recp, L, yx);

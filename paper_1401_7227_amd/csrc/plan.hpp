@@ -37,6 +37,8 @@ constexpr int kMaxStepRows = 256;  // rows per step
 // and (1, 2), so in LDS row j's input takes 32 bytes, component c at
 // double 4j + c + (c >> 1); 32 rows per load, the input area is sized in
 // whole groups of 32 rows.
+constexpr int kRecRowBytes = 24;  // per-row header of a record
+constexpr int kRecNoSlot = 0xffff;
 constexpr int kRecChunk = 1024;
 constexpr int kInRowsPerLoad = 32;
 constexpr int kInRowBytes = 32;
@@ -67,13 +69,16 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 // long row takes a whole wavefront.  Record sections (byte offsets from the
 // record start, each 16-byte aligned):
 //   head    RecHead (kRecHead bytes).
-//   rows    32 bytes per row: int4 {LDS slot or -1, own position, output
-//           cell or -1, flags}, flags bit 0 = store the value to the global
-//           vector at the own position (always in the forward sweep), bit 1
-//           = the row's input is a cell value of r, to be multiplied by the
-//           basis scale (forward fine rows), bits 8.. = the row's entry
-//           count; then (short rows) the LDS slots of the row's
-//           dependencies, 8 x uint16.
+//   rows    kRecRowBytes (24) per row: int2 {slot | flags << 16 | count
+//           << 18, index}: the LDS slot of the result (0xffff: none);
+//           flags bit 0 = store the value to the global vector (always in
+//           the forward sweep), bit 1 = the row's input is a cell value of
+//           r, to be multiplied by the basis scale (forward fine rows); the
+//           row's entry count; index = forward sweep: the row's backward
+//           position (where its value goes in the global vector), backward
+//           sweep: the output cell or -1 (the row's own position is the
+//           step's position plus its index in the step); then (short rows)
+//           the LDS slots of the row's dependencies, 8 x uint16.
 //   ldeps   long rows: int per entry, the LDS slot of the dependency.
 //   lrptr   long rows: relative entry offsets (nlong+1).
 //   vals32, vals64  short rows: jagged diagonals; entry q = koff[k] + i for

@@ -244,7 +244,7 @@ struct RecLayout {
 
 RecLayout rec_layout(const StepShape &k, bool fwd) {
   RecLayout L{};
-  int64_t at = kRecHead + 32 * (int64_t)k.nrows();
+  int64_t at = align16(kRecHead + (int64_t)kRecRowBytes * k.nrows());
   L.ldeps = (int32_t)at;
   at += align16((int64_t)4 * k.elong);
   L.lrptr = (int32_t)at;
@@ -610,29 +610,27 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       diag_starts(c.n32, c.n32 + c.n64, h.koff64);
       uint8_t *base = push_record(h, L.total, h.pos, nr);
       const int32_t rec0 = out.back().rec;
-      int32_t *meta = reinterpret_cast<int32_t *>(base + kRecHead);
       int32_t *ldeps = reinterpret_cast<int32_t *>(base + L.ldeps);
       int32_t *lrptr = reinterpret_cast<int32_t *>(base + L.lrptr);
       auto dep_of = [&](int col) { return slot[col] >= 0 ? slot[col] : kVecSlots - kFillSlots + fill_of[col]; };
       for (int j = 0; j < nr; ++j) {
         const int i = c.rows[j];
-        int32_t *m = meta + 8 * j;
-        m[0] = slot[i];
-        m[1] = bpos[i];
+        int32_t *m = reinterpret_cast<int32_t *>(base + kRecHead + (int64_t)kRecRowBytes * j);
         // flags: bit 0 = store to the global vector, bit 1 = the input is a
-        // cell value of r (forward fine rows: scaled by the basis scale),
-        // bits 8.. = entry count
+        // cell value of r (forward fine rows: scaled by the basis scale)
+        int flags;
         if (fwd) {
-          m[2] = -1;
-          m[3] = 1 | (i < S.nfine ? 2 : 0);
+          flags = 1 | (i < S.nfine ? 2 : 0);
+          m[1] = bpos[i];
         } else {
           const bool fine = i < S.nfine;
-          m[2] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
-          m[3] = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
+          m[1] = (restricted && fine && owner[S.cells[i]] == sub) ? S.cells[i] : -1;
+          flags = ((slot[i] < 0 && last[i] >= 0) || (!restricted && fine)) ? 1 : 0;
         }
-        m[3] |= (int32_t)ent[j].size() << 8;
+        m[0] = (int32_t)((uint32_t)(slot[i] >= 0 ? slot[i] : kRecNoSlot) | ((uint32_t)flags << 16) |
+                         ((uint32_t)ent[j].size() << 18));
         if (j < c.n32 + c.n64) {
-          uint16_t *dp = reinterpret_cast<uint16_t *>(m + 4);
+          uint16_t *dp = reinterpret_cast<uint16_t *>(m + 2);
           for (size_t k = 0; k < ent[j].size(); ++k) dp[k] = (uint16_t)dep_of(S.ci[ent[j][k]]);
         }
         if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
@@ -1184,13 +1182,16 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
     // records: shift positions (rows and reloads) by the subdomain offset
     uint8_t *rb = P.rec.data() + o_rec[s];
     std::copy(S.rec.begin(), S.rec.end(), rb);
-    auto place = [&](const std::vector<RecStep> &loc, std::vector<RecStep> &glob, int64_t off) {
+    auto place = [&](const std::vector<RecStep> &loc, std::vector<RecStep> &glob, int64_t off, bool fwd) {
       for (size_t k = 0; k < loc.size(); ++k) {
         RecStep st = loc[k];
         RecHead h;
         std::memcpy(&h, rb + st.rec, sizeof h);
-        int32_t *meta = reinterpret_cast<int32_t *>(rb + st.rec + kRecHead);
-        for (int j = 0; j < h.nrows; ++j) meta[8 * j + 1] += pos_off;
+        // forward rows name their backward position (backward rows an
+        // output cell, already global)
+        if (fwd)
+          for (int j = 0; j < h.nrows; ++j)
+            reinterpret_cast<int32_t *>(rb + st.rec + kRecHead + (int64_t)kRecRowBytes * j)[1] += pos_off;
         int32_t *fl = reinterpret_cast<int32_t *>(rb + st.rec + h.fill);
         for (int q = 0; q < h.nfill; ++q) fl[2 * q] += pos_off;
         h.pos += pos_off;
@@ -1200,8 +1201,8 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
         glob[off + k] = st;
       }
     };
-    place(S.rf, P.rf, o_rf[s]);
-    place(S.rb, P.rb, o_rb[s]);
+    place(S.rf, P.rf, o_rf[s], true);
+    place(S.rb, P.rb, o_rb[s], false);
     // each record names the one kHeadAhead steps later in its sweep (the
     // last one past the end), where the streaming waves look it up
     auto link = [&](const std::vector<RecStep> &loc, const std::vector<RecStep> &glob, int64_t off) {

@@ -91,11 +91,15 @@ static void check_steps(const PlanHost &P, const std::vector<RecStep> &steps, co
     }
     CHECK(h.piece >= kPieceWhole && h.piece <= kPieceLast, "%s step %zu: piece %d", which, k, h.piece);
     if (h.piece != kPieceWhole) CHECK(h.nrows == 1 && h.n32 + h.n64 == 0, "%s step %zu: a piece is one long row", which, k);
-    // row headers: LDS slot, own position, output cell, flags
-    const int32_t *m = reinterpret_cast<const int32_t *>(P.rec.data() + b0 + kRecHead);
-    for (int j = 0; j < h.nrows && kRecHead + 32LL * (j + 1) <= len; ++j) {
-      CHECK(m[8 * j] >= -1 && m[8 * j] < kVecSlots - kFillSlots, "%s step %zu row %d: slot %d", which, k, j, m[8 * j]);
-      CHECK(m[8 * j + 2] >= -1, "%s step %zu row %d: output cell", which, k, j);
+    // row headers: slot | flags | count, then backward position (forward
+    // sweep) or output cell (backward sweep)
+    const bool fwd = which[0] == 'f';
+    for (int j = 0; j < h.nrows && kRecHead + (int64_t)kRecRowBytes * (j + 1) <= len; ++j) {
+      const int32_t *m = reinterpret_cast<const int32_t *>(P.rec.data() + b0 + kRecHead + (int64_t)kRecRowBytes * j);
+      const int slot = m[0] & 0xffff;
+      CHECK(slot == kRecNoSlot || slot < kVecSlots - kFillSlots, "%s step %zu row %d: slot %d", which, k, j, slot);
+      if (fwd) CHECK(m[1] >= 0 && m[1] < P.total_pos, "%s step %zu row %d: position %d", which, k, j, m[1]);
+      else CHECK(m[1] >= -1, "%s step %zu row %d: output cell", which, k, j);
     }
   }
 }
