@@ -668,6 +668,7 @@ def main():
                        "with every phase timed",
         "solve_alg_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
         "roofline": roofline,
+        "tuning": G.tuning(),
     }
     if not args.no_variants:
         variants = {}

@@ -87,7 +87,8 @@ asm_status asm_create_system(const asm_grid *grid, int32_t nb, int64_t nnzb,
  * refreshed with asm_refactor. */
 asm_status asm_update_values(asm_system sys, const double *vals_dev, hipStream_t stream);
 
-/* y = A x (device vectors of 3*nb doubles). */
+/* y = A x (device vectors of 3*nb doubles), with the system's SpMV
+ * launch shape (see asm_tuning; every shape sums in the same order). */
 asm_status asm_spmv(asm_system sys, const double *x_dev, double *y_dev, hipStream_t stream);
 
 /*
@@ -390,6 +391,53 @@ typedef struct {
 } asm_profile;
 asm_status asm_profile_enable(asm_system sys, int32_t phase_mask);
 asm_status asm_profile_read(asm_system sys, asm_profile *out_host, int32_t reset);
+
+/* Launch-shape tuning of a system's Krylov kernels (no passage of the
+ * paper: a choice of this implementation).  Two runtime choices:
+ *   spmv_rows   block rows per thread of the SpMV w = A z: 1, 2 or 4.  The
+ *               same sums in the same order whatever the choice.
+ *   red_blocks  partial-sum blocks of the Gram-Schmidt kernels (V^T w and
+ *               w - V h with its norm): 512, 1024, 2048 or 4096.  The
+ *               choice fixes the order of the dot products' sums, so it
+ *               changes results in the last bits (not beyond the rounding
+ *               bound of a dot product).
+ * The first asm_solve, asm_solve_graph or asm_solve_batch on an untuned
+ * system times every candidate on the system's own matrix and work arrays
+ * (HIP events, a few milliseconds for a 1M-cell system) and keeps the
+ * fastest; a candidate replaces the default (1 row, 1024 blocks) only when
+ * it is at least 3% faster.  The choice is cached per process, device,
+ * size class (block rows rounded up to a power of two) and restart length:
+ * later systems of the same class take it without timing (source
+ * ASM_TUNE_CACHED), so one process makes one choice per class.  The
+ * environment variable ASM_TUNE=0 turns timing off (defaults are used);
+ * asm_tuning_set fixes a choice (for reproducible summation orders across
+ * processes).  asm_solve_noalloc never times: it uses the system's current
+ * choice.  A batch uses each system's choice, so batched and single solves
+ * stay identical. */
+enum {
+  ASM_TUNE_DEFAULT = 0,  /* not tuned: default choice                      */
+  ASM_TUNE_TIMED = 1,    /* timed on this system                           */
+  ASM_TUNE_CACHED = 2,   /* taken from an earlier system of its size class */
+  ASM_TUNE_SET = 3       /* fixed by asm_tuning_set                        */
+};
+typedef struct {
+  int32_t spmv_rows;     /* 1, 2 or 4                                      */
+  int32_t red_blocks;    /* 512, 1024, 2048 or 4096                        */
+  int32_t source;        /* ASM_TUNE_*                                     */
+  int32_t restart;       /* restart length the Krylov timing used          */
+  double spmv_us[3];     /* one SpMV with 1, 2, 4 rows per thread (timed
+                            choices; else 0)                               */
+  double krylov_us[4];   /* Gram-Schmidt kernels per Arnoldi step, mean over
+                            a restart cycle (1 .. restart columns), with
+                            512, 1024, 2048, 4096 blocks                   */
+} asm_tuning;
+/* The system's current choice and the timings it was made from. */
+asm_status asm_tuning_get(asm_system sys, asm_tuning *out_host);
+/* Fixes the choice (source becomes ASM_TUNE_SET; timings are cleared).
+ * spmv_rows = red_blocks = 0 returns the system to untuned: the next solve
+ * times again, bypassing the cache.  INVALID for any other value outside
+ * the lists above. */
+asm_status asm_tuning_set(asm_system sys, int32_t spmv_rows, int32_t red_blocks);
 
 /* Frees a handle and its device memory.  A system's preconditioners are
  * destroyed before the system. */

@@ -35,7 +35,7 @@ EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_pre
             "asm_destroy_precond",
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
             "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
-            "asm_server_get_state", "asm_server_destroy"]
+            "asm_server_get_state", "asm_server_destroy", "asm_tuning_get", "asm_tuning_set"]
 
 SERVER_MAX_SOLVES = 8
 SERVER_MAX_ACTIVE = 1024
@@ -74,6 +74,14 @@ class SolveInfo(C.Structure):
 
 class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * 8), ("ms", C.c_double * 8)]
+
+
+TUNE_SOURCES = {0: "default", 1: "timed", 2: "cached", 3: "set"}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("spmv_rows", C.c_int32), ("red_blocks", C.c_int32), ("source", C.c_int32),
+                ("restart", C.c_int32), ("spmv_us", C.c_double * 3), ("krylov_us", C.c_double * 4)]
 
 
 class ServerOpts(C.Structure):
@@ -128,6 +136,8 @@ def load() -> C.CDLL:
     L.asm_profile_enable.argtypes = [V, C.c_int32]
     L.asm_profile_read.argtypes = [V, C.POINTER(Profile), C.c_int32]
     L.asm_precond_clone.argtypes = [V, V, V, C.POINTER(V)]
+    L.asm_tuning_get.argtypes = [V, C.POINTER(Tuning)]
+    L.asm_tuning_set.argtypes = [V, C.c_int32, C.c_int32]
     L.asm_server_create.argtypes = [C.POINTER(ServerOpts), V, C.POINTER(V)]
     L.asm_server_submit.argtypes = [V, C.POINTER(Request)]
     L.asm_server_poll.argtypes = [V, C.c_int32, C.POINTER(Completion), C.POINTER(C.c_int32)]
@@ -248,6 +258,22 @@ class System:
         p = Profile()
         _check(load().asm_profile_read(self._h, C.byref(p), 1 if reset else 0))
         return {name: (int(p.launches[k]), float(p.ms[k])) for k, name in enumerate(PHASES)}
+
+    def tuning(self) -> dict:
+        """The system's launch-shape choice: SpMV rows per thread, Krylov
+        partial-sum blocks, where the choice came from, and the candidate
+        timings (microseconds) it was made from."""
+        t = Tuning()
+        _check(load().asm_tuning_get(self._h, C.byref(t)))
+        return {"spmv_rows": int(t.spmv_rows), "red_blocks": int(t.red_blocks),
+                "source": TUNE_SOURCES.get(int(t.source), str(t.source)), "restart": int(t.restart),
+                "spmv_us": {r: float(t.spmv_us[k]) for k, r in enumerate((1, 2, 4))},
+                "krylov_us": {b: float(t.krylov_us[k]) for k, b in enumerate((512, 1024, 2048, 4096))}}
+
+    def set_tuning(self, spmv_rows: int = 0, red_blocks: int = 0):
+        """Fixes the launch-shape choice; (0, 0) makes the next solve time
+        the candidates again."""
+        _check(load().asm_tuning_set(self._h, int(spmv_rows), int(red_blocks)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

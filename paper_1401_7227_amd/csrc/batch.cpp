@@ -101,6 +101,7 @@ class BatchEngine {
       slots[a] = sl;
       fresh.push_back(sl);
       asm_status st = ensure_workspace(E.S, m_, s_);
+      if (st == ASM_OK) st = ensure_tuned(E.S, m_, s_);
       if (st != ASM_OK) return st;
       fill_table(sl);
     }
@@ -307,6 +308,7 @@ class BatchEngine {
     T.ldu = W.ldu;
     T.U = W.U; T.w = W.w; T.z = W.z; T.t = W.t;
     T.partial = W.partial; T.dvec = W.dvec; T.H = W.H; T.scale = W.scale; T.misc = W.misc;
+    T.red_blocks = S->tune.red_blocks;
     T.pub = pin_dev_ + region_ * i + 1;
     T.coefh = pin_dev_ + region_ * i + 1 + (size_t)m_ * kPubStride;
     T.b = E.b;
@@ -417,7 +419,7 @@ int64_t system_bytes(asm_system S) { return (int64_t)(S->mem.bytes + S->ws.mem.b
 // Device bytes of a system's Krylov workspace for restart m.
 int64_t workspace_bytes(int64_t N, int m) {
   const int64_t n = 3 * N, ldu = (n + 1) & ~(int64_t)1;
-  return 8 * ((m + 1) * ldu + 3 * n + (int64_t)kReduceBlocks * (kMaxRestart + 10) + (kMaxRestart + 2) +
+  return 8 * ((m + 1) * ldu + 3 * n + partial_doubles(N) + (kMaxRestart + 2) +
               (m + 1) * m + 2 * (m + 1) + 8) + 4;
 }
 

@@ -1,6 +1,9 @@
 // C ABI: system and preconditioner handles, numeric setup on the device, and
 // the restarted right-preconditioned GMRES driver.
 #include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "handles.hpp"
 
@@ -23,7 +26,7 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   ASM_HIP(W.mem.alloc(&W.w, n));
   ASM_HIP(W.mem.alloc(&W.z, n));
   ASM_HIP(W.mem.alloc(&W.t, n));
-  ASM_HIP(W.mem.alloc(&W.partial, (size_t)kReduceBlocks * (kMaxRestart + 2) + 8 * (size_t)kReduceBlocks));
+  ASM_HIP(W.mem.alloc(&W.partial, (size_t)partial_doubles(S->pat.N)));
   ASM_HIP(W.mem.alloc(&W.dvec, kMaxRestart + 2));
   ASM_HIP(W.mem.alloc(&W.H, (size_t)(m + 1) * m));
   ASM_HIP(W.mem.alloc(&W.scale, m + 1));
@@ -43,6 +46,131 @@ asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
     if (!e) ASM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   W.m = m;
   (void)s;
+  return ASM_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+namespace {
+
+struct TuneKey {
+  int device, size_class, restart;
+  bool operator<(const TuneKey &o) const {
+    if (device != o.device) return device < o.device;
+    if (size_class != o.size_class) return size_class < o.size_class;
+    return restart < o.restart;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuning> g_tune_cache;
+
+int size_class(int64_t N) {
+  int c = 0;
+  while (((int64_t)1 << c) < N) ++c;
+  return c;
+}
+
+bool tuning_enabled() {
+  const char *e = std::getenv("ASM_TUNE");
+  return !(e && e[0] == '0' && e[1] == 0);
+}
+
+// Device milliseconds per call of f (one untimed call first, then reps).
+template <class F>
+asm_status time_calls(F &&f, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t s, double *us) {
+  ASM_HIP(f());
+  ASM_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) ASM_HIP(f());
+  ASM_HIP(hipEventRecord(e1, s));
+  ASM_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  ASM_HIP(hipEventElapsedTime(&ms, e0, e1));
+  *us = 1e3 * (double)ms / reps;
+  return ASM_OK;
+}
+
+// Times every candidate on the system's own matrix and work arrays (which
+// the solve then overwrites): the SpMV z -> w, and the Gram-Schmidt kernels
+// (V^T w, its reduction, then the update and its norm) of one whole restart
+// cycle, over 1, 2, ..., restart columns as the solve runs them (the best
+// block count differs between few and many columns).  A candidate replaces
+// the default only when it is at least 3% faster.
+asm_status time_candidates(asm_system S, int m, hipStream_t s, Tuning *t) {
+  Workspace &W = S->ws;
+  const int64_t n = 3 * (int64_t)S->pat.N;
+  ASM_HIP(launch_fill(n, 1.0, W.z, s));
+  ASM_HIP(launch_fill((int64_t)(m + 1) * W.ldu, 1.0, W.U, s));
+  ASM_HIP(launch_fill(m + 2, 0.0, W.dvec, s));
+  ASM_HIP(launch_fill(m + 1, 0.0, W.scale, s));  // zero projections: the columns stay bounded
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ASM_HIP(hipEventCreate(&e0));
+  hipError_t ec = hipEventCreate(&e1);
+  if (ec != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ASM_ERR_HIP, hipGetErrorString(ec));
+  }
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } guard{e0, e1};
+  static const int rows[3] = {1, 2, 4};
+  static const int blocks[4] = {512, 1024, 2048, 4096};
+  for (int k = 0; k < 3; ++k) {
+    asm_status st = time_calls([&] { return launch_spmv(S->sell, W.z, W.w, s, nullptr, rows[k]); }, 6, e0, e1, s,
+                               &t->spmv_us[k]);
+    if (st != ASM_OK) return st;
+  }
+  for (int k = 0; k < 4; ++k) {
+    auto pair = [&](int nv) -> hipError_t {
+      int nb = 0;
+      hipError_t e = launch_multidot(n, nv, W.U, W.ldu, W.w, W.partial, &nb, s, nullptr, blocks[k]);
+      if (e == hipSuccess) e = launch_reduce_cols(nb, nv + 1, W.partial, W.dvec, s);
+      if (e != hipSuccess) return e;
+      return launch_update(n, nv, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)nv * W.ldu, W.partial, &nb, s,
+                           nullptr, blocks[k]);
+    };
+    ASM_HIP(pair(1));  // untimed
+    ASM_HIP(hipEventRecord(e0, s));
+    for (int nv = 1; nv <= m; ++nv) ASM_HIP(pair(nv));
+    ASM_HIP(hipEventRecord(e1, s));
+    ASM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ASM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    t->krylov_us[k] = 1e3 * (double)ms / m;  // per step
+  }
+  t->spmv_rows = 1;
+  double best = t->spmv_us[0];
+  for (int k = 1; k < 3; ++k)
+    if (t->spmv_us[k] < 0.97 * t->spmv_us[0] && t->spmv_us[k] < best) { best = t->spmv_us[k]; t->spmv_rows = rows[k]; }
+  t->red_blocks = kReduceBlocks;
+  best = t->krylov_us[1];
+  for (int k = 0; k < 4; ++k)
+    if (k != 1 && t->krylov_us[k] < 0.97 * t->krylov_us[1] && t->krylov_us[k] < best) {
+      best = t->krylov_us[k];
+      t->red_blocks = blocks[k];
+    }
+  return ASM_OK;
+}
+
+}  // namespace
+
+asm_status ensure_tuned(asm_system S, int m, hipStream_t s) {
+  Tuning &t = S->tune;
+  if (t.source != ASM_TUNE_DEFAULT || !tuning_enabled()) return ASM_OK;
+  const TuneKey key{S->device, size_class(S->pat.N), m};
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end() && !t.retime) {
+    t = it->second;
+    t.source = ASM_TUNE_CACHED;
+    return ASM_OK;
+  }
+  Tuning nt;
+  asm_status st = time_candidates(S, m, s, &nt);
+  if (st != ASM_OK) return st;
+  nt.source = ASM_TUNE_TIMED;
+  nt.restart = m;
+  t = nt;
+  g_tune_cache[key] = nt;
   return ASM_OK;
 }
 
@@ -508,7 +636,7 @@ asm_status asm_spmv(asm_system S, const double *x_dev, double *y_dev, hipStream_
   try {
     g_err.clear();
     if (!S || !x_dev || !y_dev) return fail(ASM_ERR_INVALID, "NULL argument");
-    ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream));
+    ASM_HIP(launch_spmv(S->sell, x_dev, y_dev, stream, nullptr, S->tune.spmv_rows));
     return ASM_OK;
   }
   ASM_CATCH_ALL
@@ -713,7 +841,7 @@ struct KrylovView {
 int64_t noalloc_doubles(int m, int64_t n, int64_t *ldu) {
   auto up = [](int64_t v) { return (v + 31) & ~int64_t(31); };
   *ldu = (n + 1) & ~int64_t(1);
-  return up((int64_t)(m + 1) * *ldu) + 3 * up(n) + up((int64_t)kReduceBlocks * (kMaxRestart + 2) + 8 * kReduceBlocks) +
+  return up((int64_t)(m + 1) * *ldu) + 3 * up(n) + up(partial_doubles(n / 3)) +
          5 * up(kMaxRestart + 2) + up((int64_t)kMaxRestart * kPubStride) + 32;
 }
 
@@ -787,11 +915,11 @@ asm_status gmres_run(asm_system S, asm_precond pc, const double *b, double *x, c
     asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &pf);
     if (e2 != ASM_OK) return e2;
     size_t t0 = pf.mark(ASM_PHASE_SPMV, s);
-    ASM_HIP(launch_spmv(S->sell, W.z, W.w, s));
+    ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, nullptr, S->tune.spmv_rows));
     pf.span(ASM_PHASE_SPMV, t0, s);
     int nbd = 0;
     t0 = pf.mark(ASM_PHASE_DOTS, s);
-    ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s));
+    ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, nullptr, S->tune.red_blocks));
     pf.span(ASM_PHASE_DOTS, t0, s);
     t0 = pf.mark(ASM_PHASE_OTHER, s);
     ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s));
@@ -799,7 +927,7 @@ asm_status gmres_run(asm_system S, asm_precond pc, const double *b, double *x, c
     int nbu = 0;
     t0 = pf.mark(ASM_PHASE_UPDATE, s);
     ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
-                          &nbu, s));
+                          &nbu, s, nullptr, S->tune.red_blocks));
     pf.span(ASM_PHASE_UPDATE, t0, s);
     t0 = pf.mark(ASM_PHASE_OTHER, s);
     // the Hessenberg column goes to the published area only (the host keeps H)
@@ -809,18 +937,24 @@ asm_status gmres_run(asm_system S, asm_precond pc, const double *b, double *x, c
     if (ahead) ASM_HIP(hipEventRecord(W.step_done[j], s));
     return ASM_OK;
   };
+  // Residual estimate and its last one-step reduction factor: when the
+  // estimate after the next step is predicted within 4 tol, the step after
+  // it is not queued ahead (it would be wasted at convergence).
+  double ratio = 1.0;
   while (true) {
     if (beta == 0.0) { result = ASM_OK; break; }
     info->cycles++;
     std::fill(g, g + m + 1, 0.0);
     g[0] = beta;
     sc[0] = 1.0 / beta;
+    double est = beta;
     // steps of this cycle: at most m, and never past the iteration limit
     const int kmax = std::min(m, limit - info->iters);
     int k = 0, queued = 0;
     for (int j = 0; j < kmax; ++j) {
       // with events, keep the next step queued while step j's column is read
-      while (queued < kmax && queued <= j + (ahead ? 1 : 0)) {
+      const bool near_tol = o->fixed_iters == 0 && est * ratio <= 4.0 * tol;
+      while (queued < kmax && queued <= j + (ahead && !near_tol ? 1 : 0)) {
         if ((st = enqueue_step(queued)) != ASM_OK) return st;
         ++queued;
       }
@@ -856,6 +990,8 @@ asm_status gmres_run(asm_system S, asm_precond pc, const double *b, double *x, c
       g[j] = cs[j] * g[j];
       k = j + 1;
       info->rel_res_est = std::fabs(g[j + 1]) / scl;
+      ratio = est > 0.0 ? std::fabs(g[j + 1]) / est : 0.0;
+      est = std::fabs(g[j + 1]);
       if (hn <= 1e-14 * w0) break;
       if (o->fixed_iters == 0 && std::fabs(g[j + 1]) <= tol) break;
     }
@@ -916,6 +1052,7 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
     asm_status st = check_solve_args(S, pc, b, x, o, info);
     if (st != ASM_OK) return st;
     if ((st = ensure_workspace(S, o->restart, s)) != ASM_OK) return st;
+    if ((st = ensure_tuned(S, o->restart, s)) != ASM_OK) return st;
     Workspace &W = S->ws;
     KrylovView v;
     v.U = W.U; v.ldu = W.ldu; v.w = W.w; v.z = W.z; v.t = W.t; v.partial = W.partial; v.dvec = W.dvec;
@@ -955,7 +1092,7 @@ asm_status asm_solve_noalloc(asm_system S, asm_precond pc, const double *b, doub
     v.w = take(n);
     v.z = take(n);
     v.t = take(n);
-    v.partial = take((int64_t)kReduceBlocks * (kMaxRestart + 2) + 8 * kReduceBlocks);
+    v.partial = take(partial_doubles(S->pat.N));
     v.dvec = take(kMaxRestart + 2);
     v.scale = take(kMaxRestart + 2);
     v.coef = take(kMaxRestart + 2);
@@ -1003,6 +1140,7 @@ asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double
     hipStream_t s = W.gstream;
     ASM_HIP(hipEventRecord(W.gready, user_stream));
     ASM_HIP(hipStreamWaitEvent(s, W.gready, 0));
+    if ((st = ensure_tuned(S, m, s)) != ASM_OK) return st;
     bool bad = false;
     if ((st = any_nonfinite(S, b, n, s, &bad)) != ASM_OK) return st;
     if (!bad && (st = any_nonfinite(S, x, n, s, &bad)) != ASM_OK) return st;
@@ -1057,12 +1195,12 @@ asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double
           const double *Uj = W.U + (size_t)j * W.ldu;
           asm_status e2 = apply_precond(pc, Uj, W.scale + j, W.z, s, &none, skip);
           if (e2 != ASM_OK) return e2;
-          ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, skip));
+          ASM_HIP(launch_spmv(S->sell, W.z, W.w, s, skip, S->tune.spmv_rows));
           int nbd = 0, nbu = 0;
-          ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, skip));
+          ASM_HIP(launch_multidot(n, j + 1, W.U, W.ldu, W.w, W.partial, &nbd, s, skip, S->tune.red_blocks));
           ASM_HIP(launch_reduce_cols(nbd, j + 2, W.partial, W.dvec, s, skip));
           ASM_HIP(launch_update(n, j + 1, W.U, W.ldu, W.dvec, W.scale, W.w, W.U + (size_t)(j + 1) * W.ldu, W.partial,
-                                &nbu, s, skip));
+                                &nbu, s, skip, S->tune.red_blocks));
           ASM_HIP(launch_norm_finalize(nbu, W.partial, j + 1, W.dvec, W.scale, W.H + (size_t)j * ld, W.scale + j + 1,
                                        nullptr, s, skip));
           ASM_HIP(launch_givens(j, ld, W.H, W.gcs, W.gsn, W.gg, W.dvec, W.cst, s));
@@ -1117,6 +1255,45 @@ asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double
       if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
     }
     return result;
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_tuning_get(asm_system S, asm_tuning *out) {
+  try {
+    g_err.clear();
+    if (!S || !out) return fail(ASM_ERR_INVALID, "NULL argument");
+    const Tuning &t = S->tune;
+    std::memset(out, 0, sizeof *out);
+    out->spmv_rows = t.spmv_rows;
+    out->red_blocks = t.red_blocks;
+    out->source = t.source;
+    out->restart = t.restart;
+    for (int k = 0; k < 3; ++k) out->spmv_us[k] = t.spmv_us[k];
+    for (int k = 0; k < 4; ++k) out->krylov_us[k] = t.krylov_us[k];
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_tuning_set(asm_system S, int32_t spmv_rows, int32_t red_blocks) {
+  try {
+    g_err.clear();
+    if (!S) return fail(ASM_ERR_INVALID, "NULL argument");
+    Tuning t;
+    if (spmv_rows == 0 && red_blocks == 0) {
+      t.retime = true;  // untuned: the next solve times again
+    } else {
+      if (spmv_rows != 1 && spmv_rows != 2 && spmv_rows != 4) return fail(ASM_ERR_INVALID, "spmv_rows must be 1, 2 or 4");
+      if (red_blocks != 512 && red_blocks != 1024 && red_blocks != 2048 && red_blocks != 4096)
+        return fail(ASM_ERR_INVALID, "red_blocks must be 512, 1024, 2048 or 4096");
+      t.spmv_rows = spmv_rows;
+      t.red_blocks = red_blocks;
+      t.source = ASM_TUNE_SET;
+    }
+    S->ws.drop_graph();  // a captured cycle holds the old launch shapes
+    S->tune = t;
+    return ASM_OK;
   }
   ASM_CATCH_ALL
 }

@@ -211,6 +211,9 @@ constexpr int kPubBase = 16, kPubStride = kMaxRestart + 4;
 // Krylov workspace of a system (allocated on first use), the batched-solve
 // helpers and the preconditioner application shared by the solvers.
 asm_status ensure_workspace(asm_system S, int m, hipStream_t s);
+// Times the launch-shape candidates of an untuned system (or takes the
+// process-wide cached choice of its size class); needs the workspace.
+asm_status ensure_tuned(asm_system S, int m, hipStream_t s);
 // Structure checks of asm_create_system (host copy of the pattern).
 asm_status validate_pattern(const HostPattern &P);
 // Option checks of asm_setup_precond against a pattern, and its device part:
@@ -225,8 +228,22 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
 
 }  // namespace asmx
 
+namespace asmx {
+// The launch-shape choices of a system's Krylov kernels (see asm_tuning).
+struct Tuning {
+  int spmv_rows = 1;
+  int red_blocks = kReduceBlocks;
+  int source = ASM_TUNE_DEFAULT;
+  int restart = 0;
+  bool retime = false;  // asm_tuning_set(0, 0): time again, bypass the cache
+  double spmv_us[3] = {};
+  double krylov_us[4] = {};
+};
+}  // namespace asmx
+
 struct asm_system_s {
   int device = 0;
+  asmx::Tuning tune;
   asmx::HostPattern pat;
   asmx::DevMem mem;
   int32_t *rp = nullptr, *ci = nullptr;

@@ -143,6 +143,54 @@ __device__ __forceinline__ void spmv_body(int bid, int N, int nlogical, const in
   }
 }
 
+// R block rows per thread: thread t of logical block lb takes rows
+// lb*256*R + k*256 + t, k < R (independent sums, more loads in flight per
+// thread); every row's sum runs in the same order whatever R.
+template <int R>
+__global__ __launch_bounds__(256) void spmv_rows_kernel(int N, int nlogical, const int32_t *__restrict__ sptr,
+                                                        const int32_t *__restrict__ cols,
+                                                        const double *__restrict__ vals,
+                                                        const double *__restrict__ x, double *__restrict__ y,
+                                                        const int *__restrict__ skip) {
+  if (skip && *skip) return;  // a graph-mode cycle that has ended
+  const int lb = xcd_logical_block(nlogical, blockIdx.x);
+  if (lb >= nlogical) return;
+  int row[R], g0[R], g1[R];
+  double a[R][3];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    row[k] = (lb * R + k) * 256 + (int)threadIdx.x;
+    const int sl = (row[k] < N ? row[k] : 0) >> 6;
+    g0[k] = row[k] < N ? sptr[sl] : 0;
+    g1[k] = row[k] < N ? sptr[sl + 1] : 0;
+    a[k][0] = a[k][1] = a[k][2] = 0.0;
+  }
+  int gmax = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) gmax = max(gmax, g1[k] - g0[k]);
+  for (int q = 0; q < gmax; ++q) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (q < g1[k] - g0[k]) {
+        const int g = g0[k] + q, lane = row[k] & 63;
+        const int c = ld_stream(cols + (size_t)g * 64 + lane);
+        const double *v = vals + (size_t)g * 576 + lane;
+        const double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
+        a[k][0] += ld_stream(v) * x0 + ld_stream(v + 64) * x1 + ld_stream(v + 128) * x2;
+        a[k][1] += ld_stream(v + 192) * x0 + ld_stream(v + 256) * x1 + ld_stream(v + 320) * x2;
+        a[k][2] += ld_stream(v + 384) * x0 + ld_stream(v + 448) * x1 + ld_stream(v + 512) * x2;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (row[k] < N) {
+      y[3 * (size_t)row[k]] = a[k][0];
+      y[3 * (size_t)row[k] + 1] = a[k][1];
+      y[3 * (size_t)row[k] + 2] = a[k][2];
+    }
+}
+
 template <bool RESID>
 __global__ __launch_bounds__(256) void spmv_kernel(int N, int nlogical, const int32_t *__restrict__ sptr,
                                                    const int32_t *__restrict__ cols,
@@ -1323,7 +1371,7 @@ __global__ __launch_bounds__(256) void batch_multidot_kernel(const BatchSys *__r
 __device__ __forceinline__ int red_blocks(const BatchSys &S, int src) {
   if (src == 1) return (((int)((S.N + 255) / 256) + 7) >> 3) << 3;
   const int64_t b = (S.n / 2 + 255) / 256;
-  return (int)(b < 1 ? 1 : (b > kReduceBlocks ? kReduceBlocks : b));
+  return (int)(b < 1 ? 1 : (b > S.red_blocks ? S.red_blocks : b));
 }
 
 __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchSys *__restrict__ tab, BatchSeg g, int ncols,
@@ -1480,7 +1528,15 @@ hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip) {
+hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip, int rows) {
+  if (rows == 2 || rows == 4) {
+    const int nlog = blocks_for(A.N, 256 * rows);
+    if (rows == 2)
+      spmv_rows_kernel<2><<<xcd_grid(nlog), 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, y, skip);
+    else
+      spmv_rows_kernel<4><<<xcd_grid(nlog), 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, y, skip);
+    return hipGetLastError();
+  }
   const int nlog = blocks_for(A.N, 256);
   spmv_kernel<false><<<xcd_grid(nlog), 256, 0, s>>>(A.N, nlog, A.sptr, A.cols, A.vals, x, nullptr, y, nullptr, skip);
   return hipGetLastError();
@@ -1566,8 +1622,9 @@ static bool multidot_dispatch(int nv, int64_t n, const double *U, int64_t ldu, c
 }
 
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w, double *partial,
-                           int *nblocks_out, hipStream_t s, const int *skip) {
-  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
+                           int *nblocks_out, hipStream_t s, const int *skip, int max_blocks) {
+  if (max_blocks < 1 || max_blocks > kMaxReduceBlocks) return hipErrorInvalidValue;
+  const int grid = std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > 32) return hipErrorInvalidValue;
   multidot_dispatch(nv, n, U, ldu, w, partial, grid, s, skip, std::make_integer_sequence<int, 32>{});
   *nblocks_out = grid;
@@ -1600,8 +1657,9 @@ static bool update_dispatch(int nv, int64_t n, const double *U, int64_t ldu, con
 
 hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d, const double *scale,
                          const double *w, double *unew, double *partial, int *nblocks_out, hipStream_t s,
-                         const int *skip) {
-  const int grid = std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
+                         const int *skip, int max_blocks) {
+  if (max_blocks < 1 || max_blocks > kMaxReduceBlocks) return hipErrorInvalidValue;
+  const int grid = std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
   if (nv < 1 || nv > kMaxRestart) return hipErrorInvalidValue;
   update_dispatch(nv, n, U, ldu, d, scale, w, unew, partial, grid, s, skip,
                   std::make_integer_sequence<int, kMaxRestart>{});
@@ -1652,7 +1710,7 @@ int batch_blocks(BatchKernel k, const BatchSys &s) {
     case kBkCombine: return blocks_for(s.N, 256);
     case kBkCopy: return (int)std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
     case kBkSpmv: return xcd_grid(blocks_for(s.N, 256));
-    case kBkRed: return (int)std::min<int64_t>(kReduceBlocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
+    case kBkRed: return (int)std::min<int64_t>(s.red_blocks, std::max<int64_t>(1, (n / 2 + 255) / 256));
     case kBkVec: return (int)std::min<int64_t>(4 * kReduceBlocks, std::max<int64_t>(1, (n + 255) / 256));
     case kBkOne: return 1;
     default: return 0;

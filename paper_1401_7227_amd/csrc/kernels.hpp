@@ -20,15 +20,26 @@ struct SellDev {
   double *vals = nullptr;    // [ngroups*9*64]
 };
 
-constexpr int kReduceBlocks = 1024;  // partial-sum blocks of the Krylov kernels
+constexpr int kReduceBlocks = 1024;     // partial-sum blocks of the Krylov kernels (default)
+constexpr int kMaxReduceBlocks = 4096;  // largest choice of the tuner (buffers are sized for it)
 constexpr int kMaxRestart = 32;
+// Doubles of a system's partial-sum buffer for N block rows: the Krylov
+// kernels' (restart + 2 columns of at most kMaxReduceBlocks blocks) or the
+// residual SpMV's (one per 256-row block, rounded up to 8).
+inline int64_t partial_doubles(int64_t N) {
+  const int64_t krylov = (int64_t)kMaxReduceBlocks * (kMaxRestart + 2);
+  const int64_t resid = ((N + 255) / 256 + 7) / 8 * 8;
+  return krylov > resid ? krylov : resid;
+}
 
 // The launchers of the kernels an Arnoldi step runs take an optional skip
 // flag (device): a kernel whose flag is set returns at once.  A restart
 // cycle captured as one graph sets it when the cycle ends on the device.
 
 hipError_t launch_sell_fill(const SellDev &A, const double *csr_vals, hipStream_t s);
-hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip = nullptr);
+// rows: block rows per thread (1, 2 or 4; the same results, a tuning choice).
+hipError_t launch_spmv(const SellDev &A, const double *x, double *y, hipStream_t s, const int *skip = nullptr,
+                       int rows = 1);
 // r = b - A x; partial[kReduceBlocks-sized region] receives per-block sums of r.r
 hipError_t launch_residual(const SellDev &A, const double *x, const double *b, double *r,
                            double *partial, int *nblocks_out, hipStream_t s);
@@ -71,15 +82,19 @@ hipError_t launch_additive_combine(int N, const int32_t *cptr, const int32_t *ci
 
 // Krylov kernels (n = scalar length).
 // U columns (stride ldu, even) and w must be 16-byte aligned.
+// max_blocks: the partial-sum block count (at most kMaxReduceBlocks; a
+// tuning choice that decides the summation order).
 hipError_t launch_multidot(int64_t n, int nv, const double *U, int64_t ldu, const double *w,
-                           double *partial, int *nblocks_out, hipStream_t s, const int *skip = nullptr);
+                           double *partial, int *nblocks_out, hipStream_t s, const int *skip = nullptr,
+                           int max_blocks = kReduceBlocks);
 hipError_t launch_reduce_cols(int nblocks, int ncols, const double *partial, double *out,
                               hipStream_t s, const int *skip = nullptr);
 // unew = w - sum_{i<nv} (scale[i] d[i]) scale[i] U_i, d the reduced
 // projections of the step; per-block partial sums of ||unew||^2.
 hipError_t launch_update(int64_t n, int nv, const double *U, int64_t ldu, const double *d,
                          const double *scale, const double *w, double *unew, double *partial,
-                         int *nblocks_out, hipStream_t s, const int *skip = nullptr);
+                         int *nblocks_out, hipStream_t s, const int *skip = nullptr,
+                         int max_blocks = kReduceBlocks);
 // One block: h = sqrt(sum of partial[0..nblocks)) into hcol[nv], 1/h (0 if
 // h = 0) into *scale_out, hcol[i] = scale[i]*d[i] for i < nv; if pub is not
 // NULL, hcol[0..nv] and sqrt(d[nv]) are also written to pub[0..nv+1].
@@ -136,6 +151,7 @@ hipError_t launch_scale_copy(int64_t n, const double *r, const double *scale, do
 // table, one entry per system).  Vectors are the system's own workspace.
 struct BatchSys {
   int64_t n, ldu;
+  int32_t red_blocks, pad_;  // partial-sum blocks of the Krylov kernels (the system's tuned choice)
   double *U, *w, *z, *t, *partial, *dvec, *H, *scale, *misc;
   double *pub;          // pinned (device view): published Hessenberg columns
   const double *coefh;  // pinned (device view): [0] = k, [1..k] = solution coefficients
