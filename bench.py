@@ -211,11 +211,17 @@ def bench_batch(P, gen, torch, np, args):
     xs, infos = P.solve_batch(systems, preconds, bs, **kw)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    seq = [P.solve(G, B, b, **kw) for G, B, b in zip(systems, preconds, bs)]
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    identical = all(bool(torch.equal(x, x1)) and i.iters == i1.iters for x, i, (x1, i1) in zip(xs, infos, seq))
+    order = P.batch_tuning_last()
+    if args.batch_no_sequential:  # (a traced run: the batched solves only)
+        seq, t_seq = None, float("nan")
+        identical = None
+    else:
+        t0 = time.perf_counter()
+        seq = [P.solve(G, B, b, **kw) for G, B, b in zip(systems, preconds, bs)]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        identical = all(bool(torch.equal(x, x1)) and i.iters == i1.iters
+                        for x, i, (x1, i1) in zip(xs, infos, seq))
     iters = [i.iters for i in infos]
     return {
         "metric": "batch of 256 independent solves to rtol 1e-6 (FP32 preconditioner, FP64 GMRES(30))",
@@ -225,11 +231,42 @@ def bench_batch(P, gen, torch, np, args):
                                "each, two-level RAS, overlap 1, near 4^3, far 16^3, FP32 factors",
                    "cells": cells, "systems": len(specs)},
         "systems_per_s": round(len(specs) / t_batch, 1),
-        "sequential_ms": round(t_seq * 1e3, 1), "speedup_vs_sequential": round(t_seq / t_batch, 2),
+        "sequential_ms": None if seq is None else round(t_seq * 1e3, 1),
+        "speedup_vs_sequential": None if seq is None else round(t_seq / t_batch, 2),
         "identical_to_sequential": identical, "converged": sum(i.status == P.OK for i in infos),
         "iters": {"min": min(iters), "median": int(np.median(iters)), "max": max(iters)},
         "setup_s": round(t_setup, 1),
+        "batch_order": order,
+        "tuning_by_size_class": tuning_classes(systems),
     }
+
+
+def tuning_classes(systems):
+    """The launch-shape choice of each size class among the systems (one
+    representative per class)."""
+    out = {}
+    for G in systems:
+        t = G.tuning()
+        k = f"N<={1 << max(0, int(G.N - 1).bit_length())}"
+        if k not in out:
+            out[k] = {"spmv_rows": t["spmv_rows"], "red_blocks": t["red_blocks"], "source": t["source"]}
+    return dict(sorted(out.items(), key=lambda kv: int(kv[0][3:])))
+
+
+def bench_tuning(P, gen, torch, np, args):
+    """The tuner's choice per size class: one system per class (grid 2nz x
+    2nz x nz, classical RAS), timed on its first solve."""
+    rows = []
+    for nz in (6, 10, 16, 25, 40, 64):
+        grid = (2 * nz, 2 * nz, nz)
+        s = gen.generate(*grid, seed=7)
+        G = P.System.from_generated(s)
+        B = P.Precond(G, kind=P.KIND_CLASSICAL, combine=P.RESTRICTED, sx=4, sy=4, overlap=1)
+        P.solve(G, B, torch.from_numpy(s.b).cuda(), restart=RESTART, fixed_iters=2)
+        t = G.tuning()
+        rows.append({"grid": list(grid), "block_rows": s.N, **t})
+        del B, G
+    return {"metric": "launch-shape tuner choices by size class", "restart": RESTART, "classes": rows}
 
 
 def serve_trace(np, count=1000, rate=200.0, seed=5):
@@ -309,10 +346,14 @@ def run_server(P, torch, np, trace, precision, budget, max_active, label):
     n = len(trace)
     front, done, arrived = deque(), {}, 0
     running_sum, polls, status = 0, 0, {}
+    busy_s, tprev, busy = 0.0, 0.0, False  # time with a request queued or in flight
     t0 = time.perf_counter()
     last = t0
     while len(done) < n:
         now = time.perf_counter() - t0
+        if busy:
+            busy_s += now - tprev
+        tprev = now
         while arrived < n and trace[arrived]["t"] <= now:
             front.append(arrived)
             arrived += 1
@@ -324,12 +365,15 @@ def run_server(P, torch, np, trace, precision, budget, max_active, label):
                        vals, bs, xs)
             st["queued"] += 1
         if st["running"] == 0 and st["queued"] == 0 and not front and arrived < n:
+            busy = False
             time.sleep(max(0.0, trace[arrived]["t"] - (time.perf_counter() - t0)))
             continue
         for c in srv.poll():
             done[c["tag"]] = (time.perf_counter() - t0, c)
             status[c["status"]] = status.get(c["status"], 0) + 1
-        running_sum += srv.state()["running"]
+        st = srv.state()
+        running_sum += st["running"]
+        busy = st["running"] > 0 or st["queued"] > 0 or bool(front)
         polls += 1
         if time.perf_counter() - last > 15.0:
             last = time.perf_counter()
@@ -347,6 +391,7 @@ def run_server(P, torch, np, trace, precision, budget, max_active, label):
                 "solves_per_s": round(sum(t["nsolves"] for t in trace) / wall, 2),
                 "cell_solves_per_s": round(cells / wall, 0),
                 "mean_running": round(running_sum / max(polls, 1), 1), "polls": polls,
+                "busy_frac": round(busy_s / wall, 3),
                 "plan_builds": st["plan_builds"], "plan_hits": st["plan_hits"],
                 "statuses": {str(k): v for k, v in status.items()},
                 "iters_total": sum(done[r][1]["iters"] for r in range(n))})
@@ -405,9 +450,12 @@ def bench_serve(P, gen, torch, np, args):
     run_fifo(P, torch, np, warm, "warm-up")
     full = run_server(P, torch, np, trace, P.FP32, budget, args.serve_max_active, "full")
     torch.cuda.empty_cache()
-    srv_prefix = run_server(P, torch, np, prefix, P.FP32, budget, args.serve_max_active, "prefix")
-    torch.cuda.empty_cache()
-    fifo_prefix = run_fifo(P, torch, np, prefix, "prefix")
+    if len(prefix) < len(trace):
+        srv_prefix = run_server(P, torch, np, prefix, P.FP32, budget, args.serve_max_active, "prefix")
+        torch.cuda.empty_cache()
+    else:  # the comparison covers the whole trace
+        srv_prefix = full
+    fifo_prefix = run_fifo(P, torch, np, prefix, "prefix" if len(prefix) < len(trace) else "full")
     cells = np.array([t["grid"][0] * t["grid"][1] * t["grid"][2] for t in trace])
     offered = float(np.sum(cells * np.array([t["nsolves"] for t in trace]))) / trace[-1]["t"]
     return {
@@ -425,6 +473,10 @@ def bench_serve(P, gen, torch, np, args):
         "offered_over_served": round(offered / full["cell_solves_per_s"], 3),
         "arrival_span_s": round(trace[-1]["t"], 2),
         "server_full_trace": full,
+        "utilisation": {"server_busy_frac": full["busy_frac"],
+                        "offered_over_saturated_capacity": round(offered / args.serve_capacity, 3),
+                        "saturated_capacity_cell_solves_per_s": args.serve_capacity,
+                        "run_length_s": full["wall_s"]},
         "prefix_comparison": {"requests": len(prefix), "server_fp32": srv_prefix, "fifo_fp64": fifo_prefix,
                               "p50_speedup": round(fifo_prefix["p50_ms"] / srv_prefix["p50_ms"], 2),
                               "p99_speedup": round(fifo_prefix["p99_ms"] / srv_prefix["p99_ms"], 2)},
@@ -453,7 +505,7 @@ def bench_serve_leg(P, torch, np, args):
             "offered_cell_solves_per_s": round(float(cells.sum()) / span, 0),
             "server_fp32": {k: srv[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s",
                                                 "requests_per_s", "cell_solves_per_s", "mean_running",
-                                                "statuses")},
+                                                "busy_frac", "statuses")},
             "fifo_fp64": {k: fifo[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s", "requests_per_s",
                                                "statuses")},
             "p50_speedup": round(fifo["p50_ms"] / srv["p50_ms"], 2),
@@ -538,17 +590,23 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--workload", choices=["solve1m", "batch256", "serve", "comparators"], default="solve1m",
+    ap.add_argument("--workload", choices=["solve1m", "batch256", "serve", "comparators", "tuning"],
+                    default="solve1m",
                     help="solve1m: the 1M-cell solve (default); batch256: 256 independent systems of "
                          "2k-295k cells solved as one batch, against solving them one after another; "
                          "serve: a Poisson request trace against the request server, and a prefix of it "
                          "against one-at-a-time FP64 solves; comparators: the iteration-count studies of "
                          "the paper's Section 5 on synthetic systems")
     ap.add_argument("--no-serve", action="store_true", help="no served leg in the default benchmark")
+    ap.add_argument("--batch-no-sequential", action="store_true",
+                    help="batch256: skip the one-after-another comparison (for traced runs)")
     ap.add_argument("--serve-leg-requests", type=int, default=40)
-    ap.add_argument("--serve-leg-rate", type=float, default=6.0,
+    ap.add_argument("--serve-leg-rate", type=float, default=4.0,
                     help="arrivals per second of the served leg (one GPU sustains the trace's mix at this rate)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of --workload serve")
+    ap.add_argument("--serve-capacity", type=float, default=5.26e6,
+                    help="saturated server throughput (cell-solves/s, from the 200/s run) the offered load is "
+                         "stated against")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-compare", type=int, default=100, help="trace prefix for the FIFO comparison")
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
@@ -572,6 +630,9 @@ def main():
     import paper_1401_7227_amd as P
 
     torch.cuda.set_device(0)
+    if args.workload == "tuning":
+        print(json.dumps(bench_tuning(P, gen, torch, np, args)))
+        return
     if args.workload == "batch256":
         print(json.dumps(bench_batch(P, gen, torch, np, args)))
         return

@@ -439,6 +439,40 @@ asm_status asm_tuning_get(asm_system sys, asm_tuning *out_host);
  * the lists above. */
 asm_status asm_tuning_set(asm_system sys, int32_t spmv_rows, int32_t red_blocks);
 
+/* Order of the systems in the launches of asm_solve_batch (a choice of
+ * this implementation; results do not depend on it):
+ *   ASM_BATCH_ORDER_SUBMITTED      as passed;
+ *   ASM_BATCH_ORDER_LARGEST_FIRST  systems with more block rows first, so a
+ *                                  launch's workgroups for the small
+ *                                  systems fill in at its end;
+ *   ASM_BATCH_ORDER_TUNE           (default) the first batch of a size class
+ *                                  (device, count and total block rows, each
+ *                                  rounded up to a power of two) runs its
+ *                                  first restart cycle in the submitted
+ *                                  order and its second largest first, timed
+ *                                  on the host per block row and Arnoldi
+ *                                  step; the second order is kept, for the
+ *                                  rest of that batch and for later batches
+ *                                  of the class, only if at least 3% faster.
+ *                                  ASM_TUNE=0 keeps the submitted order.
+ * asm_batch_order_set sets the process-wide choice (INVALID for other
+ * values); asm_batch_tuning_last reports what the calling thread's last
+ * asm_solve_batch used (source: ASM_TUNE_*; the timings of the two orders,
+ * nanoseconds per block row and step, where they were timed, else the
+ * cached ones or 0). */
+enum {
+  ASM_BATCH_ORDER_TUNE = -1,
+  ASM_BATCH_ORDER_SUBMITTED = 0,
+  ASM_BATCH_ORDER_LARGEST_FIRST = 1
+};
+typedef struct {
+  int32_t order;
+  int32_t source;
+  double ns_per_row_step[2]; /* submitted, largest first */
+} asm_batch_tuning;
+asm_status asm_batch_order_set(int32_t order);
+asm_status asm_batch_tuning_last(asm_batch_tuning *out_host);
+
 /* Frees a handle and its device memory.  A system's preconditioners are
  * destroyed before the system. */
 void asm_destroy_precond(asm_precond pc);

@@ -13,5 +13,6 @@ from ._binding import (  # noqa: F401
     ADDITIVE, COARSE_ADDITIVE, COARSE_NONE, COARSE_TWO_STAGE, ERR_HIP, ERR_INVALID, ERR_NONFINITE,
     ERR_OOM, ERR_SINGULAR_PIVOT, EXPORTED, FIELD_FAR, FIELD_NEAR, FIELD_NEAR_FAR, FP32, FP64,
     KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, LOCAL_EXACT, LOCAL_ILU0, NOALLOC_SCRATCH_BYTES, NOT_CONVERGED, OK,
-    PHASES, RESTRICTED,
-    AsmError, Info, Precond, Server, System, load, precond_opts, solve, solve_batch)
+    PHASES, RESTRICTED, BATCH_ORDER_TUNE, BATCH_ORDER_SUBMITTED, BATCH_ORDER_LARGEST_FIRST,
+    AsmError, Info, Precond, Server, System, batch_order_set, batch_tuning_last, load, precond_opts, solve,
+    solve_batch)

@@ -35,7 +35,8 @@ EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_pre
             "asm_destroy_precond",
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
             "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
-            "asm_server_get_state", "asm_server_destroy", "asm_tuning_get", "asm_tuning_set"]
+            "asm_server_get_state", "asm_server_destroy", "asm_tuning_get", "asm_tuning_set",
+            "asm_batch_order_set", "asm_batch_tuning_last"]
 
 SERVER_MAX_SOLVES = 8
 SERVER_MAX_ACTIVE = 1024
@@ -82,6 +83,13 @@ TUNE_SOURCES = {0: "default", 1: "timed", 2: "cached", 3: "set"}
 class Tuning(C.Structure):
     _fields_ = [("spmv_rows", C.c_int32), ("red_blocks", C.c_int32), ("source", C.c_int32),
                 ("restart", C.c_int32), ("spmv_us", C.c_double * 3), ("krylov_us", C.c_double * 4)]
+
+
+BATCH_ORDER_TUNE, BATCH_ORDER_SUBMITTED, BATCH_ORDER_LARGEST_FIRST = -1, 0, 1
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("order", C.c_int32), ("source", C.c_int32), ("ns_per_row_step", C.c_double * 2)]
 
 
 class ServerOpts(C.Structure):
@@ -138,6 +146,8 @@ def load() -> C.CDLL:
     L.asm_precond_clone.argtypes = [V, V, V, C.POINTER(V)]
     L.asm_tuning_get.argtypes = [V, C.POINTER(Tuning)]
     L.asm_tuning_set.argtypes = [V, C.c_int32, C.c_int32]
+    L.asm_batch_order_set.argtypes = [C.c_int32]
+    L.asm_batch_tuning_last.argtypes = [C.POINTER(BatchTuning)]
     L.asm_server_create.argtypes = [C.POINTER(ServerOpts), V, C.POINTER(V)]
     L.asm_server_submit.argtypes = [V, C.POINTER(Request)]
     L.asm_server_poll.argtypes = [V, C.c_int32, C.POINTER(Completion), C.POINTER(C.c_int32)]
@@ -400,6 +410,23 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
     fn = load().asm_solve_graph if graph else (load().asm_solve_noalloc if noalloc else load().asm_solve)
     st = _check(fn(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o), _stream(), C.byref(info)))
     return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)
+
+
+def batch_order_set(order: int):
+    """Order of the systems in batched launches: BATCH_ORDER_TUNE (default),
+    BATCH_ORDER_SUBMITTED or BATCH_ORDER_LARGEST_FIRST (process-wide)."""
+    _check(load().asm_batch_order_set(int(order)))
+
+
+def batch_tuning_last() -> dict:
+    """The order this thread's last solve_batch used, where the choice came
+    from and the timings (ns per block row and step) of both orders."""
+    t = BatchTuning()
+    _check(load().asm_batch_tuning_last(C.byref(t)))
+    return {"order": "largest_first" if t.order == BATCH_ORDER_LARGEST_FIRST else "submitted",
+            "source": TUNE_SOURCES.get(int(t.source), str(t.source)),
+            "ns_per_row_step": {"submitted": float(t.ns_per_row_step[0]),
+                                "largest_first": float(t.ns_per_row_step[1])}}
 
 
 def solve_batch(systems, preconds, bs, x0s=None, *, restart=30, rtol=1e-6, max_iters=10000, fixed_iters=0):

@@ -4,8 +4,12 @@
 // asm_solve_batch and the request server are built on it.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <deque>
 #include <future>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <unordered_set>
 
 #include "handles.hpp"
@@ -167,13 +171,24 @@ class BatchEngine {
     return ASM_OK;
   }
 
+  // Order of the solves in every launch of the next cycles: as placed, or
+  // the largest systems first (their workgroups start first, so the launch
+  // ends with the small ones).  Results do not depend on it.
+  void set_largest_first(bool on) { largest_first_ = on; }
+  // Work of the last cycle: block rows summed over the steps each solve ran.
+  double last_cycle_work() const { return last_work_; }
+
   // One restart cycle of every iterating solve; solves that end (converged,
   // iteration limit) stop iterating and keep their slot until released.
   asm_status cycle() {
     std::vector<int> active;
     for (int i = 0; i < cap_; ++i)
       if (ent_[i].iterating) active.push_back(i);
+    last_work_ = 0.0;
     if (active.empty()) return ASM_OK;
+    if (largest_first_)
+      std::stable_sort(active.begin(), active.end(),
+                       [&](int a, int b) { return ent_[a].S->pat.N > ent_[b].S->pat.N; });
     asm_status st;
     int K = 0;
     for (int i : active) {
@@ -195,7 +210,10 @@ class BatchEngine {
     auto enqueue_step = [&](int j) -> asm_status {
       std::vector<int> act;
       for (int i : active)
-        if (ent_[i].in_cycle && ent_[i].kmax > j) act.push_back(i);
+        if (ent_[i].in_cycle && ent_[i].kmax > j) {
+          act.push_back(i);
+          last_work_ += (double)ent_[i].S->pat.N;
+        }
       ran[j] = act;
       if (act.empty()) return ASM_OK;
       BatchSeg seg[kBkCount];
@@ -396,6 +414,8 @@ class BatchEngine {
 
   asm_solve_opts o_{};
   hipStream_t s_ = nullptr;
+  bool largest_first_ = false;
+  double last_work_ = 0.0;
   int cap_ = 0, m_ = 0, ld_ = 0, limit_ = 0;
   size_t region_ = 0;  // pinned doubles per slot: [beta][m published columns][1 + m coefficients]
   std::vector<BatchEntry> ent_;
@@ -728,12 +748,92 @@ void solve_ended(asm_server srv, Request *r) {
 
 }  // namespace
 
+namespace asmx {
+namespace {
+
+// The order of the systems in batched launches (see asm_batch_order_set):
+// the process-wide setting, the choices made per size class (device, log2
+// of the system count, log2 of the total block rows), and this thread's
+// record of its last batched solve.
+std::mutex g_order_mu;
+int g_order_setting = ASM_BATCH_ORDER_TUNE;
+std::map<std::tuple<int, int, int>, asm_batch_tuning> g_order_cache;
+thread_local asm_batch_tuning t_last_batch{};
+
+int log2_ceil(int64_t v) {
+  int c = 0;
+  while (((int64_t)1 << c) < v) ++c;
+  return c;
+}
+
+// Runs the batch's restart cycles to the end.  Tuning: the first two cycles
+// run in each order, timed on the host (each cycle ends in a synchronised
+// residual) per block row and step; the faster order, if at least 3%
+// faster, is kept for the rest of the batch and for later batches of the
+// same size class.
+asm_status batch_cycles(BatchEngine &eng, int count, int64_t cells, int device) {
+  asm_batch_tuning rec{};
+  int setting;
+  {
+    std::lock_guard<std::mutex> lock(g_order_mu);
+    setting = g_order_setting;
+  }
+  const char *env = std::getenv("ASM_TUNE");
+  const bool tune_off = env && env[0] == '0' && env[1] == 0;
+  const auto key = std::make_tuple(device, log2_ceil(count), log2_ceil(cells));
+  bool timing = false;
+  if (setting != ASM_BATCH_ORDER_TUNE) {
+    rec.order = setting;
+    rec.source = ASM_TUNE_SET;
+  } else if (tune_off || count < 2) {
+    rec.order = ASM_BATCH_ORDER_SUBMITTED;
+    rec.source = ASM_TUNE_DEFAULT;
+  } else {
+    std::lock_guard<std::mutex> lock(g_order_mu);
+    auto it = g_order_cache.find(key);
+    if (it != g_order_cache.end()) {
+      rec = it->second;
+      rec.source = ASM_TUNE_CACHED;
+    } else {
+      timing = true;
+      rec.order = ASM_BATCH_ORDER_SUBMITTED;
+      rec.source = ASM_TUNE_DEFAULT;
+    }
+  }
+  int timed = 0;
+  while (eng.iterating() > 0) {
+    const int order = timing ? timed : rec.order;
+    eng.set_largest_first(order == ASM_BATCH_ORDER_LARGEST_FIRST);
+    const auto t0 = std::chrono::steady_clock::now();
+    asm_status st = eng.cycle();
+    if (st != ASM_OK) return st;
+    if (!timing) continue;
+    const double ns = std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
+    const double work = eng.last_cycle_work();
+    rec.ns_per_row_step[timed] = work > 0.0 ? ns / work : 0.0;
+    if (++timed == 2) {
+      timing = false;
+      rec.order = rec.ns_per_row_step[1] < 0.97 * rec.ns_per_row_step[0] ? ASM_BATCH_ORDER_LARGEST_FIRST
+                                                                         : ASM_BATCH_ORDER_SUBMITTED;
+      rec.source = ASM_TUNE_TIMED;
+      std::lock_guard<std::mutex> lock(g_order_mu);
+      g_order_cache[key] = rec;
+    }
+  }
+  t_last_batch = rec;
+  return ASM_OK;
+}
+
+}  // namespace
+}  // namespace asmx
+
 extern "C" {
 
 asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_precond *preconds,
                            const double *const *b, double *const *x, const asm_solve_opts *o, hipStream_t s,
                            asm_solve_info *infos, int32_t *status) {
   try {
+    TraceRange range_("asm_solve_batch");
     g_err.clear();
     if (count < 1 || !systems || !preconds || !b || !x || !o || !infos || !status)
       return fail(ASM_ERR_INVALID, "NULL argument or empty batch");
@@ -756,8 +856,9 @@ asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_p
     for (int i = 0; i < count; ++i)
       if (eng.entry(slots[i]).status == ASM_ERR_NONFINITE)
         return fail(ASM_ERR_NONFINITE, "non-finite b or x0 in batch entry " + std::to_string(i));
-    while (eng.iterating() > 0)
-      if ((st = eng.cycle()) != ASM_OK) return st;
+    int64_t cells = 0;
+    for (int i = 0; i < count; ++i) cells += systems[i]->pat.N;
+    if ((st = batch_cycles(eng, count, cells, systems[0]->device)) != ASM_OK) return st;
     ASM_HIP(hipStreamSynchronize(s));
     asm_status result = ASM_OK;
     for (int i = 0; i < count; ++i) {
@@ -767,6 +868,28 @@ asm_status asm_solve_batch(int32_t count, const asm_system *systems, const asm_p
       if (E.status != ASM_OK) result = ASM_NOT_CONVERGED;
     }
     return result;
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_batch_order_set(int32_t order) {
+  try {
+    g_err.clear();
+    if (order != ASM_BATCH_ORDER_TUNE && order != ASM_BATCH_ORDER_SUBMITTED && order != ASM_BATCH_ORDER_LARGEST_FIRST)
+      return fail(ASM_ERR_INVALID, "unknown batch order");
+    std::lock_guard<std::mutex> lock(g_order_mu);
+    g_order_setting = order;
+    return ASM_OK;
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_batch_tuning_last(asm_batch_tuning *out) {
+  try {
+    g_err.clear();
+    if (!out) return fail(ASM_ERR_INVALID, "NULL argument");
+    *out = t_last_batch;
+    return ASM_OK;
   }
   ASM_CATCH_ALL
 }

@@ -644,6 +644,7 @@ asm_status asm_spmv(asm_system S, const double *x_dev, double *y_dev, hipStream_
 
 asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_t stream, asm_precond *out) {
   try {
+    TraceRange range_("asm_setup_precond");
     g_err.clear();
     if (!S || !o || !out) return fail(ASM_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -663,6 +664,7 @@ asm_status asm_setup_precond(asm_system S, const asm_precond_opts *o, hipStream_
 
 asm_status asm_refactor(asm_precond pc, hipStream_t stream) {
   try {
+    TraceRange range_("asm_refactor");
     g_err.clear();
     if (!pc) return fail(ASM_ERR_INVALID, "NULL argument");
     if (pc->opts.kind == ASM_KIND_NONE) return ASM_OK;
@@ -756,6 +758,7 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
 
 asm_status asm_precond_apply(asm_precond pc, const double *r_dev, double *z_dev, hipStream_t stream) {
   try {
+    TraceRange range_("asm_precond_apply");
     g_err.clear();
     if (!pc || !r_dev || !z_dev) return fail(ASM_ERR_INVALID, "NULL argument");
     return apply_precond(pc, r_dev, nullptr, z_dev, stream);
@@ -1048,6 +1051,7 @@ extern "C" {
 asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                      hipStream_t s, asm_solve_info *info) {
   try {
+    TraceRange range_("asm_solve");
     g_err.clear();
     asm_status st = check_solve_args(S, pc, b, x, o, info);
     if (st != ASM_OK) return st;
@@ -1070,6 +1074,7 @@ asm_status asm_solve(asm_system S, asm_precond pc, const double *b, double *x, c
 asm_status asm_solve_noalloc(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                              hipStream_t s, asm_solve_info *info) {
   try {
+    TraceRange range_("asm_solve_noalloc");
     g_err.clear();
     asm_status st = check_solve_args(S, pc, b, x, o, info);
     if (st != ASM_OK) return st;
@@ -1119,6 +1124,7 @@ asm_status asm_solve_noalloc(asm_system S, asm_precond pc, const double *b, doub
 asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double *x, const asm_solve_opts *o,
                            hipStream_t user_stream, asm_solve_info *info) {
   try {
+    TraceRange range_("asm_solve_graph");
     g_err.clear();
     if (!S || !pc || !b || !x || !o || !info) return fail(ASM_ERR_INVALID, "NULL argument");
     if (pc->sys != S) return fail(ASM_ERR_INVALID, "preconditioner belongs to another system");

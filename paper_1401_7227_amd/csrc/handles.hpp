@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/asm.h"
 #include "dense.hpp"
 #include "kernels.hpp"
@@ -229,6 +231,15 @@ asm_status apply_precond(asm_precond pc, const double *r, const double *scale, d
 }  // namespace asmx
 
 namespace asmx {
+// A named roctx range over one library call (seen by rocprofv3
+// --marker-trace; a no-op without a profiler).
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // The launch-shape choices of a system's Krylov kernels (see asm_tuning).
 struct Tuning {
   int spmv_rows = 1;

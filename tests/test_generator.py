@@ -101,3 +101,14 @@ def test_redraw_keeps_pattern_and_rock():
     assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col_idx, b.col_idx)
     assert np.array_equal(a.perm, b.perm)
     assert not np.array_equal(a.vals, b.vals)
+
+
+def test_config2_permeability_contrast():
+    """The 128x128x64 benchmark system (seed 2): log-normal permeability
+    (sigma 1) over 1,048,576 cells spans between three and five decades
+    (realised: about 4.7); the 10x10x5 system spans less."""
+    big = gen.generate(128, 128, 64, seed=2)
+    assert 3.0 <= big.contrast_decades <= 5.0
+    assert abs(big.contrast_decades - 4.68) < 0.01
+    small = gen.generate(10, 10, 5, seed=1)
+    assert 1.0 <= small.contrast_decades < big.contrast_decades

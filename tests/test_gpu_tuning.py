@@ -183,3 +183,47 @@ def test_batch_keeps_each_systems_choice(P):
     x3, _ = P.solve(G, preconds[0], bs[0], restart=30, fixed_iters=40)
     a, b = to_np(single[0][0]), to_np(x3)
     assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_batch_order_choices_give_identical_results(P):
+    """Every order of the systems in batched launches gives each system
+    exactly its single-solve result; the tuned order is timed on the first
+    batch of its size class (two restart cycles) and taken from the cache
+    afterwards."""
+    import torch
+    cases = [((24, 20, 12), 11), ((9, 9, 6), 12), ((30, 26, 10), 13), ((13, 11, 7), 14)]
+    systems, preconds, bs = [], [], []
+    for grid, seed in cases:
+        s = gen.generate(*grid, seed=seed)
+        G = P.System.from_generated(s)
+        systems.append(G)
+        preconds.append(P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, sx=2, sy=2, overlap=1,
+                                  near=(2, 2, 2), far=(4, 4, 4)))
+        bs.append(torch.from_numpy(s.b).cuda())
+    kw = dict(restart=10, fixed_iters=35)
+    single = [to_np(P.solve(G, B, b, **kw)[0]) for G, B, b in zip(systems, preconds, bs)]
+    try:
+        for order, name in [(P.BATCH_ORDER_SUBMITTED, "submitted"), (P.BATCH_ORDER_LARGEST_FIRST, "largest_first")]:
+            P.batch_order_set(order)
+            xs, infos = P.solve_batch(systems, preconds, bs, **kw)
+            t = P.batch_tuning_last()
+            assert t["order"] == name and t["source"] == "set"
+            for x1, x2, i in zip(single, xs, infos):
+                assert i.iters == 35 and np.array_equal(x1, to_np(x2))
+        P.batch_order_set(P.BATCH_ORDER_TUNE)
+        xs, _ = P.solve_batch(systems, preconds, bs, **kw)
+        t = P.batch_tuning_last()
+        assert t["source"] in ("timed", "cached")
+        if t["source"] == "timed":
+            assert t["ns_per_row_step"]["submitted"] > 0 and t["ns_per_row_step"]["largest_first"] > 0
+        for x1, x2 in zip(single, xs):
+            assert np.array_equal(x1, to_np(x2))
+        xs, _ = P.solve_batch(systems, preconds, bs, **kw)
+        t2 = P.batch_tuning_last()
+        assert t2["source"] == "cached" and t2["order"] == t["order"]
+        for x1, x2 in zip(single, xs):
+            assert np.array_equal(x1, to_np(x2))
+        with pytest.raises(P.AsmError):
+            P.batch_order_set(7)
+    finally:
+        P.batch_order_set(P.BATCH_ORDER_TUNE)
