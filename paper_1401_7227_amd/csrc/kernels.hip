@@ -907,13 +907,19 @@ __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict
   const int wlong = nlong == 0 ? 0 : (nshort == 0 ? kConsumerThreads / 64 : min(kConsumerThreads / 128, (nlong + 3) / 4));
   const int tshort = kConsumerThreads - 64 * wlong;
   const int tid = (int)threadIdx.x;
+  // a step holding both short sections runs them side by side when the
+  // FP32 rows fit one pass on fewer waves than the short rows have: the
+  // FP32 rows on the first waves, the FP64 rows on the rest
+  const int w32 = (h.n32 + 15) / 16;
+  const bool side = h.n32 > 0 && h.n64 > 0 && 64 * w32 < tshort;
+  const int t32 = side ? 64 * w32 : tshort;
   if (tid < tshort) {
-    if (h.n32 > 0)
-      short_rows<FWD, float>(recp, L, yx, z, tid, tshort, h.pos, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
+    if (h.n32 > 0 && tid < t32)
+      short_rows<FWD, float>(recp, L, yx, z, tid, t32, h.pos, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
                              h.n32, 0, h.in, sc);
-    if (h.n64 > 0)
-      short_rows<FWD, double>(recp, L, yx, z, tid, tshort, h.pos, h.n32, h.n64, q64a, q64b, h.nslots64, h.vals64,
-                              h.dinv64, h.n64 + nlong, 0, h.in, sc);
+    if (h.n64 > 0 && (!side || tid >= t32))
+      short_rows<FWD, double>(recp, L, yx, z, side ? tid - t32 : tid, side ? tshort - t32 : tshort, h.pos, h.n32,
+                              h.n64, q64a, q64b, h.nslots64, h.vals64, h.dinv64, h.n64 + nlong, 0, h.in, sc);
   } else {
     long_rows<FWD>(recp, L, yx, z, tid - tshort, kConsumerThreads - tshort, h.pos, nshort, nlong, h.piece, h.ldeps, h.lrptr,
                    h.lvals, h.dinv64, h.n64 + nlong, h.n64, h.in, sc);
