@@ -29,6 +29,7 @@
 #ifndef ASM_MI355X_H
 #define ASM_MI355X_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -472,6 +473,21 @@ typedef struct {
 } asm_batch_tuning;
 asm_status asm_batch_order_set(int32_t order);
 asm_status asm_batch_tuning_last(asm_batch_tuning *out_host);
+
+/* Device-memory hooks, for callers whose framework owns device memory (a
+ * caching allocator): with hooks set, every device array a handle keeps
+ * (matrix, factors, plans, Krylov work arrays) comes from
+ * alloc(bytes, device, ctx), which returns NULL on failure (the call then
+ * fails with ASM_ERR_OOM) and a pointer aligned to 256 bytes, and goes back
+ * through free_fn(ptr, bytes, device, ctx) when the handle is destroyed
+ * (after a device synchronisation, so no kernel still uses it).  A handle
+ * keeps the hooks that were set when it was created.  Both NULL: hipMalloc
+ * and hipFree (the default).  The small per-call tables of batched and
+ * served solves, the pinned host buffers and the no-allocation solve's
+ * fixed array do not use the hooks.  INVALID if only one is NULL. */
+typedef void *(*asm_alloc_fn)(size_t bytes, int32_t device, void *ctx);
+typedef void (*asm_free_fn)(void *ptr, size_t bytes, int32_t device, void *ctx);
+asm_status asm_set_allocator(asm_alloc_fn alloc, asm_free_fn free_fn, void *ctx);
 
 /* Frees a handle and its device memory.  A system's preconditioners are
  * destroyed before the system. */

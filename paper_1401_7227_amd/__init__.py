@@ -15,4 +15,4 @@ from ._binding import (  # noqa: F401
     KIND_CLASSICAL, KIND_NONE, KIND_TWO_LEVEL, LIB_PATH, LOCAL_EXACT, LOCAL_ILU0, NOALLOC_SCRATCH_BYTES, NOT_CONVERGED, OK,
     PHASES, RESTRICTED, BATCH_ORDER_TUNE, BATCH_ORDER_SUBMITTED, BATCH_ORDER_LARGEST_FIRST,
     AsmError, Info, Precond, Server, System, batch_order_set, batch_tuning_last, load, precond_opts, solve,
-    solve_batch)
+    solve_batch, use_torch_allocator)

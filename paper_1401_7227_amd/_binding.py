@@ -36,7 +36,7 @@ EXPORTED = ["asm_create_system", "asm_update_values", "asm_spmv", "asm_setup_pre
             "asm_destroy_system", "asm_last_error", "asm_profile_enable", "asm_profile_read",
             "asm_precond_clone", "asm_server_create", "asm_server_submit", "asm_server_poll",
             "asm_server_get_state", "asm_server_destroy", "asm_tuning_get", "asm_tuning_set",
-            "asm_batch_order_set", "asm_batch_tuning_last"]
+            "asm_batch_order_set", "asm_batch_tuning_last", "asm_set_allocator"]
 
 SERVER_MAX_SOLVES = 8
 SERVER_MAX_ACTIVE = 1024
@@ -115,6 +115,9 @@ class ServerState(C.Structure):
 
 
 _lib = None
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p)
+_alloc_hooks = None  # the registered callbacks (kept alive while set)
 
 
 def load() -> C.CDLL:
@@ -147,6 +150,7 @@ def load() -> C.CDLL:
     L.asm_tuning_get.argtypes = [V, C.POINTER(Tuning)]
     L.asm_tuning_set.argtypes = [V, C.c_int32, C.c_int32]
     L.asm_batch_order_set.argtypes = [C.c_int32]
+    L.asm_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, V]
     L.asm_batch_tuning_last.argtypes = [C.POINTER(BatchTuning)]
     L.asm_server_create.argtypes = [C.POINTER(ServerOpts), V, C.POINTER(V)]
     L.asm_server_submit.argtypes = [V, C.POINTER(Request)]
@@ -410,6 +414,31 @@ def solve(system: System, precond: Precond, b, x0=None, *, restart=30, rtol=1e-6
     fn = load().asm_solve_graph if graph else (load().asm_solve_noalloc if noalloc else load().asm_solve)
     st = _check(fn(system.handle, precond.handle, _ptr(b), _ptr(x), C.byref(o), _stream(), C.byref(info)))
     return x, Info(st, info.iters, info.cycles, info.rel_res_true, info.rel_res_est)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Routes the device arrays of handles created from now on through
+    torch's caching allocator (enable=False: back to hipMalloc/hipFree).
+    Handles keep the allocator they were created with."""
+    global _alloc_hooks
+    L = load()
+    if not enable:
+        _check(L.asm_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        _alloc_hooks = None
+        return
+
+    def _alloc(nbytes, device, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device))
+        except Exception:  # out of memory: the library reports ASM_ERR_OOM
+            return None
+
+    def _free(ptr, nbytes, device, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(L.asm_set_allocator(hooks[0], hooks[1], None))
+    _alloc_hooks = hooks
 
 
 def batch_order_set(order: int):

@@ -11,6 +11,16 @@ namespace asmx {
 
 thread_local std::string g_err;
 
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_allocator;
+}  // namespace
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_allocator;
+}
+
 asm_status ensure_workspace(asm_system S, int m, hipStream_t s) {
   Workspace &W = S->ws;
   if (W.m >= m && W.U) return ASM_OK;
@@ -1261,6 +1271,19 @@ asm_status asm_solve_graph(asm_system S, asm_precond pc, const double *b, double
       if (info->iters >= limit) { result = ASM_NOT_CONVERGED; break; }
     }
     return result;
+  }
+  ASM_CATCH_ALL
+}
+
+asm_status asm_set_allocator(asm_alloc_fn alloc, asm_free_fn free_fn, void *ctx) {
+  try {
+    g_err.clear();
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(ASM_ERR_INVALID, "set both hooks or neither");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_allocator.alloc = alloc;
+    g_allocator.free = free_fn;
+    g_allocator.ctx = alloc ? ctx : nullptr;
+    return ASM_OK;
   }
   ASM_CATCH_ALL
 }

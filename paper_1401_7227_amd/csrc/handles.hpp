@@ -52,13 +52,32 @@ inline asm_status fail(asm_status st, const std::string &msg) {
                           std::string(#call) + ": " + hipGetErrorString(e_));                \
   } while (0)
 
-// Owner of device allocations; frees everything on destruction.
+// Device-memory hooks (asm_set_allocator): NULL functions mean
+// hipMalloc / hipFree.
+struct Allocator {
+  asm_alloc_fn alloc = nullptr;
+  asm_free_fn free = nullptr;
+  void *ctx = nullptr;
+};
+Allocator current_allocator();
+
+// Owner of device allocations; frees everything on destruction, through
+// the allocator that was current when it was created.
 struct DevMem {
-  std::vector<void *> ptrs;
+  Allocator a = current_allocator();
+  std::vector<std::pair<void *, size_t>> ptrs;
   size_t bytes = 0;
   ~DevMem() { release(); }
   void release() {
-    for (void *p : ptrs) (void)hipFree(p);
+    if (a.free && !ptrs.empty()) {
+      // hooked memory returns to its owner at once: no kernel may still use it
+      (void)hipDeviceSynchronize();
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      for (auto &q : ptrs) a.free(q.first, q.second, dev, a.ctx);
+    } else {
+      for (auto &q : ptrs) (void)hipFree(q.first);
+    }
     ptrs.clear();
     bytes = 0;
   }
@@ -67,10 +86,23 @@ struct DevMem {
     *out = nullptr;
     if (n == 0) n = 1;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) return e;
-    ptrs.push_back(p);
-    bytes += n * sizeof(T);
+    const size_t nb = n * sizeof(T);
+    if (a.alloc) {
+      int dev = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e != hipSuccess) return e;
+      p = a.alloc(nb, dev, a.ctx);
+      if (!p) return hipErrorOutOfMemory;
+      if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {  // the kernels' 16-byte loads need less; keep hipMalloc's
+        a.free(p, nb, dev, a.ctx);
+        return hipErrorInvalidValue;
+      }
+    } else {
+      hipError_t e = hipMalloc(&p, nb);
+      if (e != hipSuccess) return e;
+    }
+    ptrs.emplace_back(p, nb);
+    bytes += nb;
     *out = static_cast<T *>(p);
     return hipSuccess;
   }
