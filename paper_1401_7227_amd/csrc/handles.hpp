@@ -64,19 +64,33 @@ Allocator current_allocator();
 // Owner of device allocations; frees everything on destruction, through
 // the allocator that was current when it was created.
 struct DevMem {
+  struct Block {
+    void *p;
+    size_t bytes;
+    int dev;
+  };
   Allocator a = current_allocator();
-  std::vector<std::pair<void *, size_t>> ptrs;
+  std::vector<Block> ptrs;
   size_t bytes = 0;
   ~DevMem() { release(); }
   void release() {
     if (a.free && !ptrs.empty()) {
-      // hooked memory returns to its owner at once: no kernel may still use it
-      (void)hipDeviceSynchronize();
-      int dev = 0;
-      (void)hipGetDevice(&dev);
-      for (auto &q : ptrs) a.free(q.first, q.second, dev, a.ctx);
+      // hooked memory returns to its owner at once: no kernel on its device
+      // may still use it
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      int synced = -1;
+      for (const Block &q : ptrs) {
+        if (q.dev != synced) {
+          if (q.dev != cur) (void)hipSetDevice(q.dev);
+          (void)hipDeviceSynchronize();
+          synced = q.dev;
+        }
+        a.free(q.p, q.bytes, q.dev, a.ctx);
+      }
+      if (synced != cur) (void)hipSetDevice(cur);
     } else {
-      for (auto &q : ptrs) (void)hipFree(q.first);
+      for (const Block &q : ptrs) (void)hipFree(q.p);
     }
     ptrs.clear();
     bytes = 0;
@@ -87,10 +101,10 @@ struct DevMem {
     if (n == 0) n = 1;
     void *p = nullptr;
     const size_t nb = n * sizeof(T);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
     if (a.alloc) {
-      int dev = 0;
-      hipError_t e = hipGetDevice(&dev);
-      if (e != hipSuccess) return e;
       p = a.alloc(nb, dev, a.ctx);
       if (!p) return hipErrorOutOfMemory;
       if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {  // the kernels' 16-byte loads need less; keep hipMalloc's
@@ -98,10 +112,10 @@ struct DevMem {
         return hipErrorInvalidValue;
       }
     } else {
-      hipError_t e = hipMalloc(&p, nb);
+      e = hipMalloc(&p, nb);
       if (e != hipSuccess) return e;
     }
-    ptrs.emplace_back(p, nb);
+    ptrs.push_back(Block{p, nb, dev});
     bytes += nb;
     *out = static_cast<T *>(p);
     return hipSuccess;
