@@ -489,7 +489,7 @@ asm_status setup_from_plan(asm_system S, const asm_precond_opts *o, std::shared_
   // gathered inputs in sweep order: only the dense local solves read them
   const size_t nrs = o->local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0;
   double *yx, *rs, *fact;
-  if ((e = ALLOC(&yx, (size_t)P.total_pos * 3)) != hipSuccess || (e = ALLOC(&rs, nrs)) != hipSuccess ||
+  if ((e = ALLOC(&yx, ((size_t)P.total_pos + kPosPad) * 3)) != hipSuccess || (e = ALLOC(&rs, nrs)) != hipSuccess ||
       (e = ALLOC(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess ||
       (e = ALLOC(&pc->bad, 1)) != hipSuccess)
@@ -719,7 +719,7 @@ asm_status asm_precond_clone(asm_precond src, asm_system S, hipStream_t stream, 
     hipError_t e = hipSuccess;
     uint8_t *rec = nullptr;
     double *yx = nullptr, *rs = nullptr, *fact = nullptr;
-    if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, (size_t)P.total_pos * 3)) != hipSuccess ||
+    if ((e = O.alloc(&rec, pc->rec_bytes)) != hipSuccess || (e = O.alloc(&yx, ((size_t)P.total_pos + kPosPad) * 3)) != hipSuccess ||
         (e = O.alloc(&rs, pc->opts.local == ASM_LOCAL_EXACT ? (size_t)P.total_pos * 3 : 0)) != hipSuccess ||
         (e = O.alloc(&fact, (size_t)P.total_entries * 9)) != hipSuccess ||
         (e = O.alloc(&pc->aval, (size_t)P.total_entries * 9)) != hipSuccess || (e = O.alloc(&pc->bad, 1)) != hipSuccess)

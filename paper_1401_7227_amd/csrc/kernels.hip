@@ -772,60 +772,107 @@ __device__ __forceinline__ RecStep desc_lds(const RecStep *p) {
 // bit); records are read once per application.
 constexpr int kNontemporalAux = 2;
 
+// The streaming waves address memory through buffer resources built per
+// step in scalar registers: a load's per-lane offset is a constant of the
+// lane and its per-load offset a scalar, so issuing a load costs no vector
+// instructions (the streaming waves share their SIMDs with computing waves,
+// and every vector instruction of theirs delays a step).  Raw resource (no
+// stride, no swizzle) over nbytes at p, gfx9 data-format word.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t buf_rsrc(const void *p, int nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, nbytes, 0x00020000);
+}
+// A value every lane holds, in a scalar register (the compiler may form a
+// clamp of scalars with a vector instruction; a buffer resource built from
+// a vector register would need a loop over distinct values).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A pointer every lane holds, in scalar registers (a plan read through a
+// generic pointer arrives in vector registers).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v), hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<T *>(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ RecStep uniform_step(const RecStep &d) {
+  RecStep u;
+  u.rec = __builtin_amdgcn_readfirstlane(d.rec);
+  u.len = __builtin_amdgcn_readfirstlane(d.len);
+  u.pos = __builtin_amdgcn_readfirstlane(d.pos);
+  u.nrows = __builtin_amdgcn_readfirstlane(d.nrows);
+  return u;
+}
+
+// Per-lane byte offsets of the streaming loads.
+struct LaneOff {
+  unsigned rec;  // 16 * lane: record chunks
+  unsigned src;  // 4 * lane: input sources
+  unsigned in;   // backward inputs: 24 * (lane >> 1) + 8 * (lane & 1)
+  int row, odd;  // forward inputs: lane >> 1, lane & 1
+};
+
 // Loads record d (live: a step of the sweep) into LDS buffer dst: chunk i
-// of streaming wave w holds 16-byte words i*256 + w*64 .. +63.  Chunks
-// wholly past the record's end, and every chunk of a dead record, go to
-// the trash area; lanes past the end within the last chunk load its last
-// word (the input area starts at the next chunk).
-__device__ __forceinline__ void dma_record(const RecStep &d, bool live, const u32x4 *__restrict__ rec,
-                                           ASMX_LDS u32x4 *dst, ASMX_LDS u32x4 *trash, int w, int l) {
+// of streaming wave w holds 16-byte words i*256 + w*64 .. +63.  Each chunk
+// has a resource of its own that ends with the record, so lanes past the
+// end fetch nothing (they write zeros into the rest of the record's last
+// chunk); chunks wholly past the end, and every chunk of a dead record,
+// have an empty resource and go to the trash area.
+__device__ __forceinline__ void dma_record(const RecStep &d, bool live, const u32x4 *rec, ASMX_LDS u32x4 *dst,
+                                           ASMX_LDS u32x4 *trash, int w, const LaneOff &lo) {
+  // bytes of the record from this wave's first chunk on (integer
+  // arithmetic only: every chunk's range and destination follow from it)
+  const int rb = live ? 16 * (d.len - 64 * w) : 0;
+  const u32x4 *r0 = rec + d.rec + 64 * w;
 #pragma unroll
   for (int i = 0; i < kRounds; ++i) {
-    const int base = i * 256 + w * 64;
-    const bool on = live && base < d.len;  // uniform over the wave
-    const u32x4 *g = on ? rec + d.rec + min(base + l, d.len - 1) : rec;
-    ASMX_LDS u32x4 *dl = on ? dst + base : trash;
-    __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 16, 0, kNontemporalAux);
+    const int nb = uniform(min(max(rb - 4096 * i, 0), 1024));
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(buf_rsrc(r0 + 256 * i, nb),
+                                             (lds_void *)(nb > 0 ? dst + (i * 256 + w * 64) : trash), 16, lo.rec, 0, 0,
+                                             kNontemporalAux);
   }
 }
 
 // Gathering: the input sources of record d's rows (fsrc at its positions)
-// into a source slot; streaming wave w loads entries 64w .. 64w+63, rows
-// past the end repeat the last one.
-__device__ __forceinline__ void dma_sources(const RecStep &d, bool live, const int32_t *__restrict__ fsrc,
-                                            const void *dummy, ASMX_LDS int32_t *dst, ASMX_LDS u32x4 *trash, int w,
-                                            int l) {
-  const bool on = live && d.nrows > 64 * w;  // uniform over the wave
-  const int32_t *g = on ? fsrc + d.pos + min(64 * w + l, d.nrows - 1) : static_cast<const int32_t *>(dummy);
-  ASMX_LDS void *dl = on ? (ASMX_LDS void *)(dst + 64 * w) : (ASMX_LDS void *)trash;
-  __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 4, 0, 0);
+// into a source slot; streaming wave w loads entries 64w .. 64w+63 (lanes
+// past the step's rows fetch nothing).
+__device__ __forceinline__ void dma_sources(const RecStep &d, bool live, const int32_t *fsrc, ASMX_LDS int32_t *dst,
+                                            ASMX_LDS u32x4 *trash, int w, const LaneOff &lo) {
+  const int nb = uniform(live ? min(max(4 * (d.nrows - 64 * w), 0), 256) : 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(buf_rsrc(fsrc + d.pos + 64 * w, nb),
+                                           nb > 0 ? (lds_void *)(dst + 64 * w) : (lds_void *)trash, 4, lo.src, 0, 0, 0);
 }
 
 // Row inputs: load k of a record covers rows 32k .. 32k+31 (streaming wave
 // w issues loads k = w and k = w + 4); lane l carries doubles (0, 1) of
 // row 32k + (l >> 1) if l is even, doubles (1, 2) if odd, so row j's input
 // lands as 32 bytes at kInRowBytes * j, component c at double 4j + c +
-// (c >> 1).  Rows past the record's end repeat its last row.
+// (c >> 1).  Rows past the record's end: the gathering repeats the last
+// row; the backward loads' resources end with the step's rows.
 template <bool G>
 __device__ __forceinline__ void dma_inputs(const RecStep &d, bool live, const ASMX_LDS int32_t *srcs,
-                                           const SweepIn &in, const void *dummy, ASMX_LDS u32x4 *dst,
-                                           ASMX_LDS u32x4 *trash, int w, int l) {
+                                           const SweepIn &in, ASMX_LDS u32x4 *dst, ASMX_LDS u32x4 *trash, int w,
+                                           const LaneOff &lo) {
   ASMX_LDS char *area = reinterpret_cast<ASMX_LDS char *>(dst) + rec_in_offset((int64_t)d.len * 16);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int k = w + 4 * q;
-    const bool on = live && d.nrows > kInRowsPerLoad * k;  // uniform over the wave
-    const int row = min(kInRowsPerLoad * k + (l >> 1), max(d.nrows, 1) - 1);
-    const double *p;
     if constexpr (G) {
-      const int c = srcs[row];
-      p = c >= 0 ? in.r + 3 * (size_t)c : in.crs + 3 * (size_t)(-c - 1);
+      const bool on = live && d.nrows > kInRowsPerLoad * k;  // scalar
+      ASMX_LDS char *dl = on ? area + k * (kInRowsPerLoad * kInRowBytes) : reinterpret_cast<ASMX_LDS char *>(trash);
+      // a dead load reads row 0 of r (its source slot may hold anything)
+      int c = srcs[min(kInRowsPerLoad * k + lo.row, max(d.nrows, 1) - 1)];
+      c = on ? c : 0;
+      const double *p = c >= 0 ? in.r + 3 * (size_t)c : in.crs + 3 * (size_t)(-c - 1);
+      __builtin_amdgcn_global_load_lds((glb_cvoid *)(p + lo.odd), (lds_void *)dl, 16, 0, 0);
     } else {
-      p = in.src + 3 * ((size_t)d.pos + row);
+      const int r0 = kInRowsPerLoad * k;
+      const int nb = uniform(live ? min(max(24 * (d.nrows - r0), 0), 24 * kInRowsPerLoad) : 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(buf_rsrc(in.src + 3 * ((size_t)d.pos + r0), nb),
+                                               nb > 0 ? (lds_void *)(area + k * (kInRowsPerLoad * kInRowBytes))
+                                                      : (lds_void *)trash,
+                                               16, lo.in, 0, 0, 0);
     }
-    const void *g = on ? static_cast<const void *>(p + (l & 1)) : dummy;
-    ASMX_LDS char *dl = on ? area + k * (kInRowsPerLoad * kInRowBytes) : reinterpret_cast<ASMX_LDS char *>(trash);
-    __builtin_amdgcn_global_load_lds((glb_cvoid *)g, (lds_void *)dl, 16, 0, 0);
   }
 }
 
@@ -840,29 +887,35 @@ __device__ __forceinline__ void mem_order() { __asm__ __volatile__("" ::: "memor
 
 template <bool G>
 __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
-                                               const u32x4 *__restrict__ rec, const SweepIn &in, SweepLds &L) {
+                                               const u32x4 *__restrict__ rec_in, const SweepIn &in_v, SweepLds &L) {
   if (S == 0) return;
-  const int t = threadIdx.x - kConsumerThreads, w = t >> 6, l = t & 63;
+  const int t = threadIdx.x - kConsumerThreads, l = t & 63;
+  // the wave index, pointers and step descriptors in scalar registers, so
+  // that every resource, LDS address and per-load offset below is scalar
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const LaneOff lo{16u * l, 4u * l, 24u * (l >> 1) + 8u * (l & 1), l >> 1, l & 1};
+  const u32x4 *rec = uniform_ptr(rec_in);
+  const SweepIn in{uniform_ptr(in_v.src), uniform_ptr(in_v.fsrc), uniform_ptr(in_v.r), uniform_ptr(in_v.crs)};
   ASMX_LDS u32x4 *trash = lds(L.trash);
-  const RecStep d0 = ld_glb(steps), d1 = ld_glb(steps + min(1, S - 1));
-  RecStep dcur = ld_glb(steps + min(2, S - 1));
+  const RecStep d0 = uniform_step(ld_glb(steps)), d1 = uniform_step(ld_glb(steps + min(1, S - 1)));
+  RecStep dcur = uniform_step(ld_glb(steps + min(2, S - 1)));
   // sources of records 0 and 1, visible to all streaming waves after the
   // sweep's first barrier
   if constexpr (G) {
-    dma_sources(d0, true, in.fsrc, rec, lds(L.src[0]), trash, w, l);
-    dma_sources(d1, S > 1, in.fsrc, rec, lds(L.src[1]), trash, w, l);
+    dma_sources(d0, true, in.fsrc, lds(L.src[0]), trash, w, lo);
+    dma_sources(d1, S > 1, in.fsrc, lds(L.src[1]), trash, w, lo);
   }
   mem_order();
   __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
   __builtin_amdgcn_s_barrier();
   mem_order();
-  dma_record(d0, true, rec, lds(L.buf[0]), trash, w, l);
-  dma_inputs<G>(d0, true, lds(L.src[0]), in, rec, lds(L.buf[0]), trash, w, l);
+  dma_record(d0, true, rec, lds(L.buf[0]), trash, w, lo);
+  dma_inputs<G>(d0, true, lds(L.src[0]), in, lds(L.buf[0]), trash, w, lo);
   mem_order();
-  if constexpr (G) dma_sources(dcur, S > 2, in.fsrc, rec, lds(L.src[0]), trash, w, l);
+  if constexpr (G) dma_sources(dcur, S > 2, in.fsrc, lds(L.src[0]), trash, w, lo);
   mem_order();
-  dma_record(d1, S > 1, rec, lds(L.buf[1]), trash, w, l);
-  dma_inputs<G>(d1, S > 1, lds(L.src[1]), in, rec, lds(L.buf[1]), trash, w, l);
+  dma_record(d1, S > 1, rec, lds(L.buf[1]), trash, w, lo);
+  dma_inputs<G>(d1, S > 1, lds(L.src[1]), in, lds(L.buf[1]), trash, w, lo);
   mem_order();
   // record 0 (and the sources of record 2) landed: only record 1 in flight
   __builtin_amdgcn_s_waitcnt(vmcnt_imm(kRecordLoads));
@@ -870,12 +923,12 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   for (int s = 0; s < S; ++s) {
     mem_order();
     const RecStep dn = desc_lds(&reinterpret_cast<const RecHead *>(L.buf[s % kRecBufs])->ahead);
-    if constexpr (G) dma_sources(dn, s + 3 < S, in.fsrc, rec, lds(L.src[(s + 3) & 1]), trash, w, l);
+    if constexpr (G) dma_sources(dn, s + 3 < S, in.fsrc, lds(L.src[(s + 3) & 1]), trash, w, lo);
     mem_order();
     const bool live = s + 2 < S;
     ASMX_LDS u32x4 *dst = lds(L.buf[(s + 2) % kRecBufs]);
-    dma_record(dcur, live, rec, dst, trash, w, l);
-    dma_inputs<G>(dcur, live, lds(L.src[(s + 2) & 1]), in, rec, dst, trash, w, l);
+    dma_record(dcur, live, rec, dst, trash, w, lo);
+    dma_inputs<G>(dcur, live, lds(L.src[(s + 2) & 1]), in, dst, trash, w, lo);
     mem_order();
     dcur = dn;
     // everything issued before this step's record loads has landed

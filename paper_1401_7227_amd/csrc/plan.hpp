@@ -48,6 +48,13 @@ constexpr int32_t rec_in_offset(int64_t stored_bytes) {
 constexpr int32_t rec_in_bytes(int nrows) {
   return (int32_t)(((nrows > 1 ? nrows : 1) + kInRowsPerLoad - 1) / kInRowsPerLoad * kInRowsPerLoad * kInRowBytes);
 }
+// The streaming loads read whole chunks and whole groups of rows: up to one
+// chunk past a record's end, 64 input sources past a step's last position
+// and 32 input rows past it.  The arrays they read are padded by that much
+// (the sources' padding holds zeros: cell 0, a valid gather).
+constexpr int kRecPadBytes = kRecChunk;
+constexpr int kSrcPad = 64;
+constexpr int kPosPad = kInRowsPerLoad;
 // A record's head names the record kHeadAhead steps later in its sweep (the
 // last one past the end): the streaming waves read it there.
 constexpr int kHeadAhead = 3;

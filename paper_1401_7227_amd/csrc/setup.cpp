@@ -1142,8 +1142,8 @@ asm_status build_plan(const HostPattern &A, const asm_precond_opts &o, PlanHost 
   P.frow.resize(ext);
   P.rf.resize(nrf);
   P.rb.resize(nrb);
-  P.rec.assign(recb, 0);
-  P.fsrc.resize(ext);
+  P.rec.assign(recb + kRecPadBytes, 0);
+  P.fsrc.assign(ext + kSrcPad, 0);
   P.rhs_src.resize(ext);
   P.arp.resize(ext + 1);
   P.aci.resize(ent);

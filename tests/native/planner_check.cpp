@@ -78,6 +78,13 @@ static void check_steps(const PlanHost &P, const std::vector<RecStep> &steps, co
     CHECK(h.in == in_off, "%s step %zu: inputs at %d, record length %lld", which, k, h.in, (long long)len);
     CHECK(h.n32 >= 0 && h.n64 >= 0 && h.n32 + h.n64 <= h.nrows, "%s step %zu: sections", which, k);
     CHECK(d.pos >= 0 && d.pos + d.nrows <= P.total_pos, "%s step %zu: positions", which, k);
+    // the streaming loads read whole chunks past the record (the record
+    // array's padding), 64 sources and 32 input rows past the step's rows
+    // (the padding of the sources and of the work vector)
+    CHECK(b0 + len + kRecPadBytes <= rbytes, "%s step %zu: no record padding after it", which, k);
+    const int64_t rows = d.nrows > 1 ? d.nrows : 1;
+    CHECK(d.pos + (rows + 63) / 64 * 64 <= P.total_pos + kSrcPad, "%s step %zu: source loads", which, k);
+    CHECK(d.pos + (rows + 31) / 32 * 32 <= P.total_pos + kPosPad, "%s step %zu: input loads", which, k);
     const int32_t offs[] = {h.vals32, h.vals64, h.lvals, h.ldeps, h.lrptr, h.dinv32, h.dinv64};
     if (h.nrows > 0)
       for (int32_t o : offs) CHECK(o >= kRecHead && o <= len && o % 16 == 0, "%s step %zu: section at %d", which, k, o);
@@ -136,8 +143,9 @@ int main(int argc, char **argv) {
     CHECK(d.fstep0 <= d.fstep1 && d.fstep1 <= (int)P.fstep.size(), "sub %d factorisation steps", s);
   }
   CHECK(ext == P.total_ext, "extended rows %lld vs %lld", (long long)ext, (long long)P.total_ext);
-  CHECK((int64_t)P.fsrc.size() == P.total_pos, "forward sources");
+  CHECK((int64_t)P.fsrc.size() == P.total_pos + kSrcPad, "forward sources");
   for (int32_t f : P.fsrc) CHECK(f < A.N && -f - 1 < P.total_coarse, "forward source %d", f);
+  for (int q = 0; q < kSrcPad; ++q) CHECK(P.fsrc[P.total_pos + q] == 0, "source padding %d", q);
   CHECK((int64_t)P.arp.size() == P.total_ext + 1 && P.arp.back() == P.total_entries, "factor CSR");
   check_steps(P, P.rf, "forward");
   check_steps(P, P.rb, "backward");
