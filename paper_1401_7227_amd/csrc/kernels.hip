@@ -428,16 +428,14 @@ __global__ __launch_bounds__(256) void relayout_kernel(int nslots, const int32_t
 // contiguous record (see RecStep) that the streaming waves copy from HBM,
 // together with the step's row inputs (forward: gathered from r and the
 // coarse rows' lumped inputs; backward: the forward results), straight into
-// one of three LDS buffers (gfx950's global_load_lds: the data goes from
-// memory to LDS without passing through registers): step s is computed
-// from buffer s % 3 while the records of steps s+1 and s+2 are on their
-// way.  The computing waves touch global memory only to store results:
-// vector values live in an LDS slot pool, and values without a slot are
-// reloaded into LDS by "fill" steps.
+// one of kRecBufs LDS buffers (gfx950's buffer loads to LDS: the data goes
+// from memory to LDS without passing through registers): step s is
+// computed from buffer s % kRecBufs while the records of the next
+// kRecBufs - 1 steps are on their way.  The computing waves touch global
+// memory only to store results: vector values live in an LDS slot pool, and
+// values without a slot are reloaded into LDS by "fill" steps.
 constexpr int kRecU4 = kRecBytes / 16;
-constexpr int kRecBufs = 3;
-constexpr int kRounds = kRecU4 / 256;  // 1 KiB chunk loads per streaming wave and record
-static_assert(kRecU4 % 256 == 0, "record buffer must split evenly over 256 threads");
+constexpr int kRounds = (kRecU4 + 255) / 256;  // 1 KiB chunk loads per streaming wave and record
 static_assert(kRecChunk == 64 * 16, "a chunk is one wave's 16-byte load");
 static_assert(kMaxStepRows <= 8 * kInRowsPerLoad, "row inputs: two loads of 32 rows per streaming wave");
 
@@ -516,10 +514,10 @@ __device__ __forceinline__ void granule9(const float *sec, int S, int q, float (
 }
 
 struct SweepLds {
-  u32x4 buf[kRecBufs][kRecU4];     // record of step s (read), of steps s+1 and s+2 (arriving)
+  u32x4 buf[kRecBufs][kRecU4];     // record of step s (read), of the next steps (arriving)
   double vec[3 * kVecSlots];       // vector slot pool (top kFillSlots: reloaded values)
   double part[4];                  // partial sum of a split row
-  int32_t src[2][kMaxStepRows];    // gathering: input sources of the records of steps s+2 and s+3
+  int32_t src[3][kMaxStepRows];    // gathering: input sources of three records (record k in slot k % 3)
   u32x4 trash[64];                 // destination of the loads that carry nothing
 };
 static_assert(sizeof(SweepLds) <= 160 * 1024, "the sweep's LDS must fit one CU");
@@ -881,14 +879,29 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 <
 
 // Loads of one streaming step after (and including) the record loads.
 constexpr int kRecordLoads = kRounds + 2;
+// At the end of step s the record of step s+1 and the input sources of
+// record s + kRecBufs (issued first in step s-1) must have landed.  With
+// three buffers the record came last in step s-1, so only step s's own
+// loads may still be in flight; with more, step s-1's record loads may be
+// too.
+constexpr int kStepWait = kRecBufs == 3 ? kRecordLoads + 1 : 2 * kRecordLoads + 1;
+// Barriers before a sweep's first step (the computing waves match them).
+constexpr int kOpenBarriers = kRecBufs;
 
 // Keeps the compiler from moving memory operations across this point.
 __device__ __forceinline__ void mem_order() { __asm__ __volatile__("" ::: "memory"); }
 
+// Streaming waves of one sweep.  Step s (after the barrier that ends step
+// s-1, which frees buffer (s-1) % kRecBufs) issues, in this order: the
+// input sources of record s + kRecBufs + 1 (its descriptor read from the
+// head of record s), then record s + kRecBufs - 1 with its inputs (gathered
+// through the sources loaded two steps earlier).  Source slots are reused
+// only after a barrier has followed the last gather that read them.
 template <bool G>
 __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps, int S,
                                                const u32x4 *__restrict__ rec_in, const SweepIn &in_v, SweepLds &L) {
   if (S == 0) return;
+  constexpr int NB = kRecBufs;
   const int t = threadIdx.x - kConsumerThreads, l = t & 63;
   // the wave index, pointers and step descriptors in scalar registers, so
   // that every resource, LDS address and per-load offset below is scalar
@@ -897,42 +910,49 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   const u32x4 *rec = uniform_ptr(rec_in);
   const SweepIn in{uniform_ptr(in_v.src), uniform_ptr(in_v.fsrc), uniform_ptr(in_v.r), uniform_ptr(in_v.crs)};
   ASMX_LDS u32x4 *trash = lds(L.trash);
-  const RecStep d0 = uniform_step(ld_glb(steps)), d1 = uniform_step(ld_glb(steps + min(1, S - 1)));
-  RecStep dcur = uniform_step(ld_glb(steps + min(2, S - 1)));
-  // sources of records 0 and 1, visible to all streaming waves after the
+  RecStep dd[NB + 1];  // steps 0 .. NB (the last step for those past it)
+#pragma unroll
+  for (int k = 0; k <= NB; ++k) dd[k] = uniform_step(ld_glb(steps + min(k, S - 1)));
+  // sources of records 0, 1 and 2, visible to all streaming waves after the
   // sweep's first barrier
   if constexpr (G) {
-    dma_sources(d0, true, in.fsrc, lds(L.src[0]), trash, w, lo);
-    dma_sources(d1, S > 1, in.fsrc, lds(L.src[1]), trash, w, lo);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dma_sources(dd[k], k < S, in.fsrc, lds(L.src[k]), trash, w, lo);
   }
   mem_order();
   __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
   __builtin_amdgcn_s_barrier();
+  // records 0 .. NB-2; the sources of records 3 .. NB into the slots just read
+#pragma unroll
+  for (int k = 0; k + 1 < NB; ++k) {
+    mem_order();
+    dma_record(dd[k], k < S, rec, lds(L.buf[k]), trash, w, lo);
+    dma_inputs<G>(dd[k], k < S, lds(L.src[k % 3]), in, lds(L.buf[k]), trash, w, lo);
+    if (k + 3 <= NB) {
+      mem_order();
+      __builtin_amdgcn_s_barrier();
+      mem_order();
+      if constexpr (G) dma_sources(dd[k + 3], k + 3 < S, in.fsrc, lds(L.src[k % 3]), trash, w, lo);
+    }
+  }
   mem_order();
-  dma_record(d0, true, rec, lds(L.buf[0]), trash, w, lo);
-  dma_inputs<G>(d0, true, lds(L.src[0]), in, lds(L.buf[0]), trash, w, lo);
-  mem_order();
-  if constexpr (G) dma_sources(dcur, S > 2, in.fsrc, lds(L.src[0]), trash, w, lo);
-  mem_order();
-  dma_record(d1, S > 1, rec, lds(L.buf[1]), trash, w, lo);
-  dma_inputs<G>(d1, S > 1, lds(L.src[1]), in, lds(L.buf[1]), trash, w, lo);
-  mem_order();
-  // record 0 (and the sources of record 2) landed: only record 1 in flight
-  __builtin_amdgcn_s_waitcnt(vmcnt_imm(kRecordLoads));
+  // record 0 and the sources of record NB-1 landed
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(kStepWait));
   __builtin_amdgcn_s_barrier();
+  RecStep da = dd[NB - 1], db = dd[NB];  // the records loaded at steps s and s+1
   for (int s = 0; s < S; ++s) {
     mem_order();
-    const RecStep dn = desc_lds(&reinterpret_cast<const RecHead *>(L.buf[s % kRecBufs])->ahead);
-    if constexpr (G) dma_sources(dn, s + 3 < S, in.fsrc, lds(L.src[(s + 3) & 1]), trash, w, lo);
+    const RecStep dn = desc_lds(&reinterpret_cast<const RecHead *>(L.buf[s % NB])->ahead);
+    if constexpr (G) dma_sources(dn, s + NB + 1 < S, in.fsrc, lds(L.src[(s + NB + 1) % 3]), trash, w, lo);
     mem_order();
-    const bool live = s + 2 < S;
-    ASMX_LDS u32x4 *dst = lds(L.buf[(s + 2) % kRecBufs]);
-    dma_record(dcur, live, rec, dst, trash, w, lo);
-    dma_inputs<G>(dcur, live, lds(L.src[(s + 2) & 1]), in, dst, trash, w, lo);
+    const bool live = s + NB - 1 < S;
+    ASMX_LDS u32x4 *dst = lds(L.buf[(s + NB - 1) % NB]);
+    dma_record(da, live, rec, dst, trash, w, lo);
+    dma_inputs<G>(da, live, lds(L.src[(s + NB - 1) % 3]), in, dst, trash, w, lo);
     mem_order();
-    dcur = dn;
-    // everything issued before this step's record loads has landed
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm(kRecordLoads));
+    da = db;
+    db = dn;
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(kStepWait));
     __builtin_amdgcn_s_barrier();
   }
   mem_order();
@@ -985,10 +1005,9 @@ template <bool FWD>
 __device__ __forceinline__ void consumer_sweep(int S, SweepLds &L, double *__restrict__ yx, double *__restrict__ z,
                                                double sc) {
   if (S == 0) return;
-  // the streaming waves' two opening barriers: sources of the first
-  // records, then the first record
-  __syncthreads();
-  __syncthreads();
+  // the streaming waves' opening barriers (sources of the first records,
+  // source slots freed, the first record landed)
+  for (int k = 0; k < kOpenBarriers; ++k) __syncthreads();
   for (int s = 0; s < S; ++s) cons_iter<FWD>(s, L, yx, z, sc);
   __syncthreads();  // matches the streaming waves' final barrier
 }

@@ -19,12 +19,27 @@ struct Step {
 
 // Apply-sweep layout: every level step of a sweep is one contiguous record
 // in a global buffer, streamed into LDS ahead of its use.
+#ifndef ASM_REC_BUFS
+#define ASM_REC_BUFS 3
+#endif
 #ifndef ASM_REC_BYTES
+#if ASM_REC_BUFS == 4
+#define ASM_REC_BYTES 27584
+#else
 #define ASM_REC_BYTES 36864
 #endif
-constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer (2 buffers)
+#endif
+constexpr int kRecBufs = ASM_REC_BUFS;    // LDS record buffers of a sweep
+constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer
+static_assert(kRecBufs >= 3 && kRecBytes % 16 == 0, "three or more buffers of whole 16-byte words");
 #ifndef ASM_VEC_SLOTS
+// what the record buffers, three source slots and the trash area leave of a
+// CU's 160 KiB of LDS
+#if ASM_REC_BUFS == 3 && ASM_REC_BYTES == 36864
+#define ASM_VEC_SLOTS 2046
+#else
 #define ASM_VEC_SLOTS 2048
+#endif
 #endif
 constexpr int kVecSlots = ASM_VEC_SLOTS;  // LDS vector slots (3 doubles each)
 static_assert(kVecSlots <= 65536, "slots are stored as 16-bit indices");
@@ -56,8 +71,10 @@ constexpr int kRecPadBytes = kRecChunk;
 constexpr int kSrcPad = 64;
 constexpr int kPosPad = kInRowsPerLoad;
 // A record's head names the record kHeadAhead steps later in its sweep (the
-// last one past the end): the streaming waves read it there.
-constexpr int kHeadAhead = 3;
+// last one past the end): the streaming waves read it there and load that
+// record's input sources, two steps before they load the record itself
+// into the buffer that frees up last.
+constexpr int kHeadAhead = kRecBufs + 1;
 static_assert(kMaxStepRows * kMaxJdsWidth < 65536, "section entries are packed in 16 bits");
 
 #ifndef ASM_FILL_SLOTS
