@@ -68,3 +68,28 @@ def test_server_request_tensors_are_checked(P):
         srv.submit(1, grid, rp, ci, popts, [v.float()], [b], [torch.zeros_like(b)])
     assert srv.state()["queued"] == 0
     srv.close()
+
+
+def test_solves_after_freed_systems_are_unchanged(P):
+    """Each system's solver workspace holds pinned host memory through which
+    the host reads the Hessenberg columns; the runtime hands freed pinned
+    memory out again with the old contents still in it.  Systems created
+    after others were freed must solve exactly as the first one did."""
+    import gc
+    import torch
+    s = gen.generate(12, 10, 6, seed=4)
+    o = dict(kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, sx=3, sy=2, overlap=1, near=(2, 2, 2), far=(4, 4, 4))
+    b = torch.from_numpy(s.b).cuda()
+    ref = None
+    for rep in range(4):
+        G = P.System.from_generated(s)
+        B = P.Precond(G, **o)
+        x, info = P.solve(G, B, b, restart=8, rtol=1e-8)
+        got = (info.status, info.iters, info.cycles, x.cpu().numpy().copy())
+        if ref is None:
+            ref = got
+        else:
+            assert got[:3] == ref[:3]
+            assert np.array_equal(got[3], ref[3])
+        del G, B, x
+        gc.collect()
