@@ -879,12 +879,18 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 <
 
 // Loads of one streaming step after (and including) the record loads.
 constexpr int kRecordLoads = kRounds + 2;
-// At the end of step s the record of step s+1 and the input sources of
-// record s + kRecBufs (issued first in step s-1) must have landed.  With
-// three buffers the record came last in step s-1, so only step s's own
-// loads may still be in flight; with more, step s-1's record loads may be
-// too.
-constexpr int kStepWait = kRecBufs == 3 ? kRecordLoads + 1 : 2 * kRecordLoads + 1;
+// Loads that may still be in flight at the end of step s, when the record
+// of step s+1 and (gathering) the input sources of record s + kRecBufs,
+// issued first in step s-1, must have landed.  Gathering, a step issues
+// one source load and then a record's loads: with three buffers record s+1
+// came last in step s-1, so only step s's own loads may be in flight; with
+// four, step s-1's record loads may be too.  Without sources (backward),
+// the records of steps s+2 .. s + kRecBufs - 1 may be.
+template <bool G>
+constexpr int step_wait() {
+  static_assert(kRecBufs == 3 || kRecBufs == 4, "three or four record buffers");
+  return G ? (kRecBufs == 3 ? kRecordLoads + 1 : 2 * kRecordLoads + 1) : (kRecBufs - 2) * kRecordLoads;
+}
 // Barriers before a sweep's first step (the computing waves match them).
 constexpr int kOpenBarriers = kRecBufs;
 
@@ -937,7 +943,7 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
   }
   mem_order();
   // record 0 and the sources of record NB-1 landed
-  __builtin_amdgcn_s_waitcnt(vmcnt_imm(kStepWait));
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(step_wait<G>()));
   __builtin_amdgcn_s_barrier();
   RecStep da = dd[NB - 1], db = dd[NB];  // the records loaded at steps s and s+1
   for (int s = 0; s < S; ++s) {
@@ -952,7 +958,7 @@ __device__ __forceinline__ void producer_sweep(const RecStep *__restrict__ steps
     mem_order();
     da = db;
     db = dn;
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm(kStepWait));
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(step_wait<G>()));
     __builtin_amdgcn_s_barrier();
   }
   mem_order();

@@ -31,7 +31,7 @@ struct Step {
 #endif
 constexpr int kRecBufs = ASM_REC_BUFS;    // LDS record buffers of a sweep
 constexpr int kRecBytes = ASM_REC_BYTES;  // LDS bytes of one record buffer
-static_assert(kRecBufs >= 3 && kRecBytes % 16 == 0, "three or more buffers of whole 16-byte words");
+static_assert((kRecBufs == 3 || kRecBufs == 4) && kRecBytes % 16 == 0, "three or four buffers of whole 16-byte words");
 #ifndef ASM_VEC_SLOTS
 // what the record buffers, three source slots and the trash area leave of a
 // CU's 160 KiB of LDS

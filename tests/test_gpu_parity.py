@@ -477,6 +477,37 @@ def test_solve_batch_matches_oracle(P):
             assert err <= (1e-8 if prec == 0 else 1e-3), (grid, fixed, err)
 
 
+# systems of the 256-system benchmark batch whose backward steps carry more
+# than 128 rows with FP32 factors (a step's second input load per streaming
+# wave): grid, seed, subdomains (sx, sy)
+BIG_STEP_CASES = [((94, 26, 27), 1008, (8, 2)), ((81, 91, 14), 1023, (5, 5)), ((51, 83, 24), 1025, (4, 6)),
+                  ((74, 94, 28), 1026, (6, 8)), ((88, 85, 32), 1040, (8, 7)), ((93, 59, 31), 1045, (8, 5))]
+
+
+def test_big_steps_deterministic_in_batches(P):
+    """Systems whose level steps hold more than 128 rows, two-level with FP32
+    factors, solved in one batch twice and one at a time: every result is
+    bit-identical (a step's inputs must all have landed before its rows are
+    computed, whatever the load on the memory system)."""
+    import torch
+    systems, preconds, bs = [], [], []
+    for grid, seed, (sx, sy) in BIG_STEP_CASES:
+        s = gen.generate(*grid, seed=seed)
+        G = P.System.from_generated(s)
+        systems.append(G)
+        preconds.append(P.Precond(G, kind=P.KIND_TWO_LEVEL, combine=P.RESTRICTED, sx=sx, sy=sy, overlap=1,
+                                  near=(4, 4, 4), far=(16, 16, 16), precision=P.FP32))
+        bs.append(torch.from_numpy(s.b).cuda())
+    kw = dict(restart=30, fixed_iters=90)
+    runs = [P.solve_batch(systems, preconds, bs, **kw) for _ in range(3)]
+    single = [P.solve(G, B, b, **kw) for G, B, b in zip(systems, preconds, bs)]
+    for k in range(len(systems)):
+        ref = to_np(single[k][0])
+        for xs, infos in runs:
+            assert infos[k].iters == 90
+            assert np.array_equal(to_np(xs[k]), ref), BIG_STEP_CASES[k]
+
+
 def test_solve_batch_with_x0_and_errors(P):
     import torch
     systems, preconds, bs = _batch_setup(P)
