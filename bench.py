@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,11 +39,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_7227_amd", "csrc", f)
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
+def _code_only(text):
+    """Source text without comments, trailing blanks and empty lines: an
+    edit of the comments leaves the measured kernel what it was."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line.strip())
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
+        with open(path, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

@@ -721,17 +721,17 @@ __device__ __forceinline__ void fill_values(const RecHead &h, const char *recp, 
 // ASM_SWEEP_COMPUTE_WAVES waves compute the steps; the last four waves
 // only stream.  Both roles execute the same sequence of barriers.
 //
-// Streaming, per step s (every load goes straight to LDS):
-//   1. the step three ahead, s+3, is read from record s's head (in LDS
+// Streaming, per step s (every load goes straight to LDS; three record
+// buffers shown, kRecBufs in general):
+//   1. the step four ahead, s+4, is read from record s's head (in LDS
 //      since the last barrier); gathering, its rows' input sources are
-//      loaded into one of two source slots;
+//      loaded into one of three source slots;
 //   2. record s+2 is loaded into buffer (s+2) % 3, which step s-1 has left,
 //      and its rows' inputs behind it (gathering: through the sources
-//      loaded one step earlier);
-//   3. each streaming wave waits until everything it issued before this
-//      step's record loads has landed (record s+1 and the sources of s+3:
-//      loads complete in issue order) and joins the barrier that starts
-//      step s+1.
+//      loaded two steps earlier);
+//   3. each streaming wave waits until record s+1 and (gathering) the
+//      sources of record s+3 have landed (loads complete in issue order)
+//      and joins the barrier that starts step s+1.
 // Every streaming wave issues the same number of loads per step whatever
 // the record's length (chunks past a record's end, and the loads of
 // records past the sweep's end, go to a trash area), so the wait count is
