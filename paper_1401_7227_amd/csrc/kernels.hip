@@ -545,7 +545,8 @@ __device__ __forceinline__ RowHead row_head(int2 m) {
 // component r of the result.  Sections with more rows than a quarter of
 // the threads take several passes; waves without a row in a pass skip it.  tid, nthr: this thread among the nthr (a multiple of 64)
 // threads given to the section; j0: first step row of the section; n: its rows; q0,
-// q1: the starts of this thread's diagonals r and r+4; dinv rows of the
+// q1: the starts of this thread's diagonals r and r+4 (in the section's
+// values and in its dependency slots at slots_off alike); dinv rows of the
 // section start at index doff of a plane of dstride rows; sc: the basis
 // scale of the forward inputs flagged as cell values.
 // The critical path is kept to two LDS round trips per pass: the row's
@@ -556,13 +557,15 @@ __device__ __forceinline__ RowHead row_head(int2 m) {
 template <bool FWD, typename T>
 __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double *__restrict__ yx,
                                            double *__restrict__ z, int tid, int nthr, int spos, int j0, int n, int q0,
-                                           int q1, int nslots, int vals_off, int dinv_off, int dstride, int doff,
-                                           int in_off, double sc) {
+                                           int q1, int nslots, int slots_off, int vals_off, int dinv_off, int dstride,
+                                           int doff, int in_off, double sc) {
   const int rows_per_pass = nthr / 4;
   lds_cdouble *vec = (lds_cdouble *)L.vec;
   const int r = tid & 3;
   const char *rows = recp + kRecHead;
   const T *vals = reinterpret_cast<const T *>(recp + vals_off);
+  const ASMX_LDS uint16_t *sl = (const ASMX_LDS uint16_t *)(recp + slots_off);
+  const int qmax = max(nslots - 1, 0);
   const double *inb = reinterpret_cast<const double *>(recp + in_off);
   const int rc = r < 3 ? r : 2;
   for (int i0 = 0; i0 < n; i0 += rows_per_pass) {
@@ -572,8 +575,9 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     const int ia = act ? i : 0;
     const int j = j0 + ia;
     const RowHead m = row_head(*reinterpret_cast<const int2 *>(rows + kRecRowBytes * j));
-    const int2 dpa = *reinterpret_cast<const int2 *>(rows + kRecRowBytes * j + 8);
-    const int2 dpb = *reinterpret_cast<const int2 *>(rows + kRecRowBytes * j + 16);
+    // the dependency slot of entry r (any word of the array for a thread
+    // without that entry: its product is discarded)
+    const int da = sl[min(q0 + ia, qmax)];
     T a0, a1, a2, e0 = 0, e1 = 0, e2 = 0;
     double x = 0.0;
     if (FWD) {
@@ -588,17 +592,15 @@ __device__ __forceinline__ void short_rows(const char *recp, SweepLds &L, double
     granule9(vals, nslots, q0 + ia, b);
     const int cnt = act ? m.cnt : 0;
     if (FWD) a0 = (T)((m.flags & 2) ? sc * x : x);  // a cell value of r times the basis scale
-    // slots of entries r and r+4: half r & 1 of words r / 2 and 2 + r / 2
-    const unsigned w0 = (unsigned)((r < 2) ? dpa.x : dpa.y), w1 = (unsigned)((r < 2) ? dpb.x : dpb.y);
-    const int d0 = (r & 1) ? (int)(w0 >> 16) : (int)(w0 & 0xffff);
-    const int d1 = (r & 1) ? (int)(w1 >> 16) : (int)(w1 & 0xffff);
+    const bool has0 = r < cnt;
+    const int d0 = has0 ? da : 0;
     const T u0 = (T)vec[3 * d0], u1 = (T)vec[3 * d0 + 1], u2 = (T)vec[3 * d0 + 2];
     const T t0 = b[0] * u0 + b[1] * u1 + b[2] * u2;
     const T t1 = b[3] * u0 + b[4] * u1 + b[5] * u2;
     const T t2 = b[6] * u0 + b[7] * u1 + b[8] * u2;
-    const bool has0 = r < cnt;
     T s0 = has0 ? t0 : (T)0, s1 = has0 ? t1 : (T)0, s2 = has0 ? t2 : (T)0;
     if (r + 4 < cnt) {
+      const int d1 = sl[q1 + i];
       T c[9];
       granule9(vals, nslots, q1 + i, c);
       const T v0 = (T)vec[3 * d1], v1 = (T)vec[3 * d1 + 1], v2 = (T)vec[3 * d1 + 2];
@@ -994,11 +996,12 @@ __device__ __forceinline__ void cons_iter(int s, SweepLds &L, double *__restrict
   const int t32 = side ? 64 * w32 : tshort;
   if (tid < tshort) {
     if (h.n32 > 0 && tid < t32)
-      short_rows<FWD, float>(recp, L, yx, z, tid, t32, h.pos, 0, h.n32, q32a, q32b, h.nslots32, h.vals32, h.dinv32,
-                             h.n32, 0, h.in, sc);
+      short_rows<FWD, float>(recp, L, yx, z, tid, t32, h.pos, 0, h.n32, q32a, q32b, h.nslots32, h.slots32, h.vals32,
+                             h.dinv32, h.n32, 0, h.in, sc);
     if (h.n64 > 0 && (!side || tid >= t32))
       short_rows<FWD, double>(recp, L, yx, z, side ? tid - t32 : tid, side ? tshort - t32 : tshort, h.pos, h.n32,
-                              h.n64, q64a, q64b, h.nslots64, h.vals64, h.dinv64, h.n64 + nlong, 0, h.in, sc);
+                              h.n64, q64a, q64b, h.nslots64, h.slots64, h.vals64, h.dinv64, h.n64 + nlong, 0, h.in,
+                              sc);
   } else {
     long_rows<FWD>(recp, L, yx, z, tid - tshort, kConsumerThreads - tshort, h.pos, nshort, nlong, h.piece, h.ldeps, h.lrptr,
                    h.lvals, h.dinv64, h.n64 + nlong, h.n64, h.in, sc);

@@ -52,7 +52,7 @@ constexpr int kMaxStepRows = 256;  // rows per step
 // and (1, 2), so in LDS row j's input takes 32 bytes, component c at
 // double 4j + c + (c >> 1); 32 rows per load, the input area is sized in
 // whole groups of 32 rows.
-constexpr int kRecRowBytes = 24;  // per-row header of a record
+constexpr int kRecRowBytes = 8;  // per-row header of a record
 constexpr int kRecNoSlot = 0xffff;
 constexpr int kRecChunk = 1024;
 constexpr int kInRowsPerLoad = 32;
@@ -93,7 +93,7 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 // long row takes a whole wavefront.  Record sections (byte offsets from the
 // record start, each 16-byte aligned):
 //   head    RecHead (kRecHead bytes).
-//   rows    kRecRowBytes (24) per row: int2 {slot | flags << 16 | count
+//   rows    kRecRowBytes (8) per row: int2 {slot | flags << 16 | count
 //           << 18, index}: the LDS slot of the result (0xffff: none);
 //           flags bit 0 = store the value to the global vector (always in
 //           the forward sweep), bit 1 = the row's input is a cell value of
@@ -101,8 +101,10 @@ constexpr int kFillSlots = ASM_FILL_SLOTS;  // top slots of the pool: values rel
 //           row's entry count; index = forward sweep: the row's backward
 //           position (where its value goes in the global vector), backward
 //           sweep: the output cell or -1 (the row's own position is the
-//           step's position plus its index in the step); then (short rows)
-//           the LDS slots of the row's dependencies, 8 x uint16.
+//           step's position plus its index in the step).
+//   slots32, slots64  short rows: the LDS slot of each entry's dependency,
+//           uint16, in the order of the section's values (entry q = koff[k]
+//           + i, below).
 //   ldeps   long rows: int per entry, the LDS slot of the dependency.
 //   lrptr   long rows: relative entry offsets (nlong+1).
 //   vals32, vals64  short rows: jagged diagonals; entry q = koff[k] + i for
@@ -144,7 +146,7 @@ struct RecHead {
   int32_t vals32, vals64, lvals, ldeps;
   int32_t lrptr, dinv32, dinv64, nfill;
   RecStep ahead;                     // the step kHeadAhead later (16-byte aligned)
-  int32_t fill, pad0, pad1, pad2;
+  int32_t fill, slots32, slots64, pad2;
   int32_t koff32[kMaxJdsWidth + 1];  // first entry of each jagged diagonal
   int32_t koff64[kMaxJdsWidth + 1];
   int32_t pad3[2];

@@ -238,13 +238,17 @@ struct StepShape {
   int nrows() const { return n32 + n64 + nlong; }
 };
 struct RecLayout {
-  int32_t ldeps, lrptr, vals32, vals64, lvals, dinv32, dinv64, total, lds;
+  int32_t slots32, slots64, ldeps, lrptr, vals32, vals64, lvals, dinv32, dinv64, total, lds;
 };
 
 
 RecLayout rec_layout(const StepShape &k, bool fwd) {
   RecLayout L{};
   int64_t at = align16(kRecHead + (int64_t)kRecRowBytes * k.nrows());
+  L.slots32 = (int32_t)at;
+  at += align16((int64_t)2 * k.e32);
+  L.slots64 = (int32_t)at;
+  at += align16((int64_t)2 * k.e64);
   L.ldeps = (int32_t)at;
   at += align16((int64_t)4 * k.elong);
   L.lrptr = (int32_t)at;
@@ -588,6 +592,8 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
       h.nslots64 = shp.e64;
       h.pos = pos0;
       h.in = rec_in_offset(L.total);
+      h.slots32 = L.slots32;
+      h.slots64 = L.slots64;
       h.vals32 = L.vals32;
       h.vals64 = L.vals64;
       h.lvals = L.lvals;
@@ -630,8 +636,12 @@ void build_sweeps(SubLocal &S, const std::vector<int32_t> &lf, int maxf, const s
         m[0] = (int32_t)((uint32_t)(slot[i] >= 0 ? slot[i] : kRecNoSlot) | ((uint32_t)flags << 16) |
                          ((uint32_t)ent[j].size() << 18));
         if (j < c.n32 + c.n64) {
-          uint16_t *dp = reinterpret_cast<uint16_t *>(m + 2);
-          for (size_t k = 0; k < ent[j].size(); ++k) dp[k] = (uint16_t)dep_of(S.ci[ent[j][k]]);
+          // dependency slots in the order of the section's values
+          const bool f32 = j < c.n32;
+          const int32_t *koff = f32 ? h.koff32 : h.koff64;
+          uint16_t *dp = reinterpret_cast<uint16_t *>(base + (f32 ? L.slots32 : L.slots64));
+          const int i_sec = f32 ? j : j - c.n32;
+          for (size_t k = 0; k < ent[j].size(); ++k) dp[koff[k] + i_sec] = (uint16_t)dep_of(S.ci[ent[j][k]]);
         }
         if (c.piece == kPieceWhole || c.piece == kPieceLast) made[i] = (int)out.size() - 1;
       }

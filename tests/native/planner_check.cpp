@@ -85,7 +85,7 @@ static void check_steps(const PlanHost &P, const std::vector<RecStep> &steps, co
     const int64_t rows = d.nrows > 1 ? d.nrows : 1;
     CHECK(d.pos + (rows + 63) / 64 * 64 <= P.total_pos + kSrcPad, "%s step %zu: source loads", which, k);
     CHECK(d.pos + (rows + 31) / 32 * 32 <= P.total_pos + kPosPad, "%s step %zu: input loads", which, k);
-    const int32_t offs[] = {h.vals32, h.vals64, h.lvals, h.ldeps, h.lrptr, h.dinv32, h.dinv64};
+    const int32_t offs[] = {h.slots32, h.slots64, h.vals32, h.vals64, h.lvals, h.ldeps, h.lrptr, h.dinv32, h.dinv64};
     if (h.nrows > 0)
       for (int32_t o : offs) CHECK(o >= kRecHead && o <= len && o % 16 == 0, "%s step %zu: section at %d", which, k, o);
     if (h.nfill > 0) {
@@ -107,6 +107,17 @@ static void check_steps(const PlanHost &P, const std::vector<RecStep> &steps, co
       CHECK(slot == kRecNoSlot || slot < kVecSlots - kFillSlots, "%s step %zu row %d: slot %d", which, k, j, slot);
       if (fwd) CHECK(m[1] >= 0 && m[1] < P.total_pos, "%s step %zu row %d: position %d", which, k, j, m[1]);
       else CHECK(m[1] >= -1, "%s step %zu row %d: output cell", which, k, j);
+    }
+    // short rows' dependency slots: one per entry, inside the record, each
+    // a slot of the pool
+    if (h.nrows > 0) {
+      const int32_t so[2] = {h.slots32, h.slots64}, ns[2] = {h.nslots32, h.nslots64};
+      for (int q = 0; q < 2; ++q) {
+        CHECK(so[q] + 2LL * ns[q] <= len, "%s step %zu: slot array %d past the record", which, k, q);
+        if (so[q] + 2LL * ns[q] > len) continue;
+        const uint16_t *sl = reinterpret_cast<const uint16_t *>(P.rec.data() + b0 + so[q]);
+        for (int e = 0; e < ns[q]; ++e) CHECK(sl[e] < kVecSlots, "%s step %zu: dependency slot %d", which, k, sl[e]);
+      }
     }
   }
 }
