@@ -48,6 +48,20 @@ def planner(tmp_path_factory):
     return exe
 
 
+@pytest.fixture(scope="module")
+def planner_nb4(tmp_path_factory):
+    """The planner check built for four record buffers (no sanitizers)."""
+    if not _gxx_ok():
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("nb4") / "planner_check_nb4")
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-DASM_REC_BUFS=4", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           f"-I{os.path.join(ROOT, 'include')}", os.path.join(ROOT, "tests", "native", "planner_check.cpp"),
+           os.path.join(CSRC, "setup.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
 PLANS = [
     # grid, kind, combine, sx, sy, overlap, near, far, precision, field
     ((10, 10, 5), 1, 0, 4, 1, 1, (2, 2, 2), (5, 5, 5), 0, 0),
@@ -137,3 +151,24 @@ def test_device_code_uses_no_scratch(tmp_path):
     assert not bad, bad
     sweeps = [k for k in allres if "ilu_apply" in k]
     assert sweeps and all(allres[k]["ScratchSize [bytes/lane]"] == 0 for k in sweeps)
+
+
+def test_four_buffer_sweep_builds(tmp_path, planner_nb4):
+    """The sweep's other compile-time shape (four 27,584-byte record buffers,
+    ASM_REC_BUFS=4): the kernels compile for gfx950 without scratch or
+    spills, and two-level plans of 48x48x32 cells (FP64 and FP32 factors)
+    pass every check (the records fit the smaller buffers, each head names
+    the step five ahead)."""
+    sys.path.insert(0, ROOT)
+    from paper_1401_7227_amd import build as B
+    cmd = [B.HIPCC, *B.COMMON, "-DASM_REC_BUFS=4", "-x", "hip", *B.DEVICE, B.REMARKS, "--cuda-device-only", "-c",
+           os.path.join(CSRC, "kernels.hip"), "-o", str(tmp_path / "kernels4.o")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    res = B.parse_resources(r.stderr)
+    sweeps = [k for k in res if "apply_kernel" in k]
+    assert sweeps and all(res[k]["ScratchSize [bytes/lane]"] == 0 and res[k].get("VGPRs Spill", 0) == 0
+                          for k in sweeps)
+    for prec in (0, 1):
+        st = _run_planner(planner_nb4, ((48, 48, 32), 2, 1, 6, 6, 1, (4, 4, 4), (16, 16, 16), prec, 0))
+        assert st["fails"] == 0
