@@ -815,9 +815,9 @@ struct LaneOff {
 // Loads record d (live: a step of the sweep) into LDS buffer dst: chunk i
 // of streaming wave w holds 16-byte words i*256 + w*64 .. +63.  Each chunk
 // has a resource of its own that ends with the record, so lanes past the
-// end fetch nothing (they write zeros into the rest of the record's last
-// chunk); chunks wholly past the end, and every chunk of a dead record,
-// have an empty resource and go to the trash area.
+// end fetch nothing (whatever they write lands in the rest of the record's
+// last chunk, before the inputs); chunks wholly past the end, and every
+// chunk of a dead record, have an empty resource and go to the trash area.
 __device__ __forceinline__ void dma_record(const RecStep &d, bool live, const u32x4 *rec, ASMX_LDS u32x4 *dst,
                                            ASMX_LDS u32x4 *trash, int w, const LaneOff &lo) {
   // bytes of the record from this wave's first chunk on (integer
