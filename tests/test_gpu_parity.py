@@ -508,6 +508,23 @@ def test_big_steps_deterministic_in_batches(P):
             assert np.array_equal(to_np(xs[k]), ref), BIG_STEP_CASES[k]
 
 
+@pytest.mark.parametrize("k", [0, 1])
+def test_big_steps_apply_matches_oracle(P, k):
+    """One application on a system whose backward steps hold more than 128
+    rows (FP32 factors) against the FP64 oracle: FP64 factors within 1e-10,
+    FP32 factors within the factors' rounding (1e-4)."""
+    import torch
+    grid, seed, (sx, sy) = BIG_STEP_CASES[k]
+    s = gen.generate(*grid, seed=seed)
+    o = dict(kind=2, combine=1, sx=sx, sy=sy, overlap=1, near=(4, 4, 4), far=(16, 16, 16))
+    r = np.random.default_rng(11).standard_normal(s.n)
+    zo = oracle_precond(s, o).apply(r)
+    G = P.System.from_generated(s)
+    for prec, bar in ((0, 1e-10), (1, 1e-4)):
+        z = to_np(gpu_precond(P, G, o, precision=prec).apply(torch.from_numpy(r).cuda()))
+        assert rel(z, zo) <= bar, (grid, prec, rel(z, zo))
+
+
 def test_solve_batch_with_x0_and_errors(P):
     import torch
     systems, preconds, bs = _batch_setup(P)
